@@ -1,0 +1,163 @@
+/*
+ * swkb.h -- C ABI of the screened-WKB (S-WKB) propagation library for AMD
+ * MI355X (gfx950).
+ *
+ * The library carries a time-harmonic field across a sequence of planar
+ * screens for the 2D Helmholtz problem  Delta u + k^2 eps(x,z) u = 0
+ * (Bruno & Maas, "WKB across caustics: the screened-WKB method", Sec. 2,
+ * eq. helmholtz_3D), x the range and z the height.  One screen step
+ * (Algorithm 1, "Screened WKB") is:
+ *   1. a vertical FFT of the field on screen x_q (Sec. 2.1.1, eqs. fft_eq,
+ *      ifft_eq, fourier_psi), keeping the M modes n in [-M/2, M/2);
+ *   2. per mode, WKB across the screen: RK4 rays of the characteristic
+ *      system for the eikonal phase and the transport amplitude
+ *      (Sec. 2.1.2 and Appendix A, eqs. charsys, charsys_s), marched in x;
+ *   3. interpolation of phase and amplitude onto the grid of screen x_{q+1}
+ *      (Sec. 2.1.2) and
+ *   4. the sum over modes (eq. ray_bundle_q_plus_1), then the next screen.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named "device" are HIP device pointers; "host" pointers are
+ *     ordinary CPU memory.  Complex data are interleaved (re, im) doubles
+ *     (complex128), contiguous.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued asynchronously unless the description says "synchronises".
+ *   - The caller owns every buffer it passes; the library never frees
+ *     caller memory.  The plan lives in a caller-provided device workspace.
+ *   - Every call returns swkb_status; no C++ exception crosses the ABI.
+ *     swkb_last_error() gives a message for the last failure on the
+ *     calling thread.
+ */
+#ifndef SWKB_H
+#define SWKB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum swkb_status {
+  SWKB_OK = 0,
+  SWKB_ERR_ARG = 1,     /* invalid parameter, size or pointer                     */
+  SWKB_ERR_NOMEM = 2,   /* workspace smaller than swkb_workspace_bytes()          */
+  SWKB_ERR_DEVICE = 3,  /* a HIP runtime call or kernel launch failed             */
+  SWKB_ERR_CAUSTIC = 4, /* a mode above caustic_tol crossed a caustic in a screen */
+  SWKB_ERR_STATE = 5    /* call out of order (e.g. continue without a field)      */
+} swkb_status;
+
+enum { SWKB_FP64 = 0, SWKB_MIXED = 1 };
+enum { SWKB_BC_PERIODIC = 0, SWKB_BC_DIRICHLET = 1, SWKB_BC_NEUMANN = 2 };
+enum {
+  SWKB_MEDIUM_LINEAR = 0,   /* params [eps0, g]:          eps = eps0 + g z                       */
+  SWKB_MEDIUM_EXPGAUSS = 1, /* params [eps0, a, b, zc]:   eps = eps0 + a exp(-b (z-zc)^2)
+                               (the exponential permittivity model of the paper, Sec. 3)       */
+  SWKB_MEDIUM_GAUSSSUM = 2, /* params [n_g, (a, s, cx, cz) x n_g]:
+                               n = 1 + sum a exp(-((x-cx)^2 + (z-cz)^2) / (2 s^2)), terms with
+                               (x-cx)^2 + (z-cz)^2 > 64 s^2 dropped, eps = n^2                   */
+  SWKB_MEDIUM_MPROFILE = 3  /* params [M0, g1, g2, d, w, scale]: modified refractivity
+                               M = M0 + g1 z + (g2-g1) w log(1 + exp((z-d)/w)),
+                               n = 1 + scale M, eps = n^2 (surface duct, corner smoothed)         */
+};
+
+/* Problem and numerical parameters of one propagation problem. */
+typedef struct swkb_params {
+  double k;                 /* wavenumber 2 pi / lambda                                     */
+  double z_a, z_b;          /* screen extent; grid z_m = z_a + m h, h = (z_b - z_a) / n_z   */
+  int32_t n_z;              /* grid points N: a power of two, 64 <= N <= 32768              */
+  int32_t n_modes;          /* kept modes M: even, 2 <= M <= P (P = N, or 2N with a mirror) */
+  double x0, dx;            /* first screen x_0 and screen spacing; x_q = x0 + q dx        */
+  int32_t n_screens;        /* screens reachable by this plan: q in [0, n_screens]          */
+  int32_t rk4_steps;        /* RK4 steps S per screen, >= 1                                 */
+  int32_t ray_stride;       /* ray launch spacing rho in grid cells, >= 1                   */
+  int32_t launch_ext_cells; /* launch extension E in cells: rays start at
+                               s_r = z_a + (r rho - E) h, r = 0..R-1,
+                               R = ceil((N + 2E) / rho) + 1                                 */
+  double p2_floor;          /* a ray with p^2 = eps - q^2 <= p2_floor is dead               */
+  int32_t bc;               /* SWKB_BC_*: ground mirror about z_a (Sec. 2.3)                */
+  int32_t medium_kind;      /* SWKB_MEDIUM_*                                                 */
+  double absorber_bot;      /* cos^2 taper thickness at z_a (0 = none)                       */
+  double absorber_top;      /* cos^2 taper thickness at z_b (0 = none)                       */
+  const double* medium_params; /* host; copied by swkb_plan                                  */
+  int32_t n_medium_params;
+  int32_t precision;        /* SWKB_FP64 or SWKB_MIXED                                       */
+  double eps_ref;           /* reference permittivity of the phase split (bookkeeping only) */
+  double caustic_tol;       /* SWKB_ERR_CAUSTIC when a mode with |c_n| > caustic_tol max|c|
+                               has a caustic (Z_s <= 0) or crossing rays in a screen          */
+} swkb_params;
+
+/* Device-side health counters, summed over all screens propagated so far. */
+typedef struct swkb_counters {
+  int64_t caustic_rays; /* rays with Z_s <= 0 at some RK4 stage (dropped)              */
+  int64_t dead_rays;    /* rays with p^2 <= p2_floor at launch or on the way (dropped) */
+  int64_t folded_modes; /* modes whose live arrivals were not increasing in z (dropped) */
+  int64_t significant;  /* caustic or folded modes with |c_n| > caustic_tol max|c|     */
+  int64_t screens;      /* screen steps executed                                         */
+} swkb_counters;
+
+typedef struct swkb_plan_s* swkb_plan_t;
+
+/* Bytes of device workspace a plan for *p needs (0 if *p is invalid).
+ * Host only. */
+size_t swkb_workspace_bytes(const swkb_params* p);
+
+/* Build a plan: validates *p (SWKB_ERR_ARG with a message otherwise),
+ * derives the mode tables (xi_n = 2 pi n / (k P h), Sec. 2.1.1-2.1.2), the
+ * FFT twiddles and, for SWKB_MEDIUM_GAUSSSUM, the per-screen lists of
+ * Gaussians whose 8-sigma disc meets the screen, and uploads them into
+ * workspace (device, >= swkb_workspace_bytes(p) bytes, 256-byte aligned)
+ * on hip_stream.  The workspace must stay allocated until swkb_destroy.
+ * *out receives a host handle. */
+swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_bytes,
+                      void* hip_stream, swkb_plan_t* out);
+
+/* Propagate screens q_begin .. q_end-1 (Algorithm 1 per screen).
+ * u_in: device complex128[N], the field on screen q_begin; NULL continues
+ * from the plan's current field, which must then be on screen q_begin.
+ * history: device complex128[(q_end - q_begin) * N] receiving the field on
+ * screens q_begin+1 .. q_end, or NULL.  Afterwards the plan's current
+ * field is the one on screen q_end.  0 <= q_begin <= q_end <= n_screens.
+ * Asynchronous on hip_stream; caustics are reported by swkb_diagnostics. */
+swkb_status swkb_propagate(swkb_plan_t plan, const void* u_in, int32_t q_begin, int32_t q_end,
+                           void* history, void* hip_stream);
+
+/* Copy the plan's current field (device complex128[N]) into out (device).
+ * Returns SWKB_ERR_STATE before the first swkb_propagate. */
+swkb_status swkb_field(swkb_plan_t plan, void* out, void* hip_stream);
+
+/* Current screen index of the plan's field (-1 before the first propagate). */
+int32_t swkb_current_screen(swkb_plan_t plan);
+
+/* Synchronises hip_stream, copies the counters to *out (host) and returns
+ * SWKB_ERR_CAUSTIC if out->significant > 0, else SWKB_OK. */
+swkb_status swkb_diagnostics(swkb_plan_t plan, void* hip_stream, swkb_counters* out);
+
+/* Release the host handle (the caller frees the workspace). */
+void swkb_destroy(swkb_plan_t plan);
+
+const char* swkb_status_string(swkb_status s);
+const char* swkb_last_error(void);
+
+/* ---- stage entry points, for checking each step on its own ---------- */
+
+/* Step 1 only: c (device complex128[M], c[j] for n = j - M/2) = the DFT of
+ * the (mirror-extended) field u (device complex128[N]) divided by P. */
+swkb_status swkb_stage_modes(swkb_plan_t plan, const void* u, void* c, void* hip_stream);
+
+/* Step 2 only, for screen q: arrival records of all M x R rays, row-major
+ * [mode j][ray r], written as doubles to device arrays Z (arrival height),
+ * psi (full phase psi, length units), qz (psi_z at arrival), amp (transport
+ * factor sqrt(p0 / (p Z_s))), and int32 flag (0 live, 1 dead at launch,
+ * 2 dead on the way, 3 caustic).  R = swkb_num_rays(plan). */
+swkb_status swkb_stage_rays(swkb_plan_t plan, int32_t q, void* Z, void* psi, void* qz, void* amp,
+                            void* flag, void* hip_stream);
+
+/* Rays per mode R of the plan. */
+int32_t swkb_num_rays(swkb_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWKB_H */

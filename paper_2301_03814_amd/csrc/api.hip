@@ -1,0 +1,388 @@
+// Host side of the C ABI declared in include/swkb.h: argument validation,
+// workspace layout, plan tables and the per-screen launch sequence.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "swkb_internal.h"
+
+namespace swkb {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int waves_per_mode(const Geometry& g);
+
+namespace {
+
+bool is_pow2(long long x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int expected_params(const swkb_params* p) {
+  switch (p->medium_kind) {
+    case SWKB_MEDIUM_LINEAR: return 2;
+    case SWKB_MEDIUM_EXPGAUSS: return 4;
+    case SWKB_MEDIUM_MPROFILE: return 6;
+    case SWKB_MEDIUM_GAUSSSUM:
+      if (p->n_medium_params < 1 || !p->medium_params) return -1;
+      return 1 + 4 * (int)p->medium_params[0];
+    default: return -1;
+  }
+}
+
+// Returns an empty string when *p is acceptable.
+std::string validate(const swkb_params* p) {
+  if (!p) return "params is NULL";
+  if (!(p->k > 0.0) || !std::isfinite(p->k)) return "k must be positive and finite";
+  if (!(p->z_b > p->z_a)) return "z_b must exceed z_a";
+  if (!is_pow2(p->n_z) || p->n_z < 64 || p->n_z > 32768) return "n_z must be a power of two in [64, 32768]";
+  const int P = p->bc == SWKB_BC_PERIODIC ? p->n_z : 2 * p->n_z;
+  if (p->n_modes < 2 || (p->n_modes & 1) || p->n_modes > P) return "n_modes must be even and in [2, P]";
+  if (!(p->dx > 0.0) || !std::isfinite(p->x0)) return "dx must be positive";
+  if (p->n_screens < 1) return "n_screens must be >= 1";
+  if (p->rk4_steps < 1 || p->rk4_steps > 4096) return "rk4_steps must be in [1, 4096]";
+  if (p->ray_stride < 1 || p->ray_stride > p->n_z) return "ray_stride must be in [1, n_z]";
+  if (p->launch_ext_cells < 0 || p->launch_ext_cells > 4 * p->n_z) return "launch_ext_cells must be in [0, 4 n_z]";
+  if (!(p->p2_floor >= 0.0)) return "p2_floor must be >= 0";
+  if (p->bc < 0 || p->bc > 2) return "bc must be SWKB_BC_PERIODIC, _DIRICHLET or _NEUMANN";
+  if (p->precision != SWKB_FP64 && p->precision != SWKB_MIXED) return "precision must be SWKB_FP64 or SWKB_MIXED";
+  const double L = p->z_b - p->z_a;
+  if (!(p->absorber_bot >= 0.0 && p->absorber_top >= 0.0 && p->absorber_bot + p->absorber_top <= L))
+    return "absorber thicknesses must be >= 0 and fit in [z_a, z_b]";
+  if (!(p->caustic_tol >= 0.0)) return "caustic_tol must be >= 0";
+  if (!(p->eps_ref > 0.0)) return "eps_ref must be positive";
+  const int np = expected_params(p);
+  if (np < 0) return "unknown medium_kind or missing parameters";
+  if (p->n_medium_params != np || !p->medium_params) return "n_medium_params does not match medium_kind";
+  for (int i = 0; i < np; ++i)
+    if (!std::isfinite(p->medium_params[i])) return "medium_params must be finite";
+  if (p->medium_kind == SWKB_MEDIUM_GAUSSSUM) {
+    const int ng = (int)p->medium_params[0];
+    if (ng < 0 || (double)ng != p->medium_params[0]) return "GAUSSSUM count must be a non-negative integer";
+    for (int j = 0; j < ng; ++j)
+      if (!(p->medium_params[2 + 4 * j] > 0.0)) return "GAUSSSUM widths must be positive";
+  }
+  if (p->medium_kind == SWKB_MEDIUM_MPROFILE && !(p->medium_params[4] > 0.0)) return "MPROFILE w must be > 0";
+  return "";
+}
+
+Geometry geometry(const swkb_params* p) {
+  Geometry g;
+  g.N = p->n_z;
+  g.M = p->n_modes;
+  g.bc = p->bc;
+  g.P = g.bc == SWKB_BC_PERIODIC ? g.N : 2 * g.N;
+  g.rho = p->ray_stride;
+  g.E = p->launch_ext_cells;
+  g.R = (g.N + 2 * g.E + g.rho - 1) / g.rho + 1;
+  g.T = g.N / kTile;
+  g.S = p->rk4_steps;
+  int lp = 0;
+  while ((1 << lp) < g.P) ++lp;
+  g.P1 = 1 << (lp / 2);
+  g.P2 = g.P / g.P1;
+  g.z_a = p->z_a;
+  g.z_b = p->z_b;
+  g.h = (p->z_b - p->z_a) / p->n_z;
+  g.k = p->k;
+  g.lam = 2.0 * M_PI / p->k;
+  g.dx = p->dx;
+  g.p2_floor = p->p2_floor;
+  return g;
+}
+
+// Per-screen candidate Gaussians: bump j can reach the screen strip
+// [x_q, x_q + dx] only if |x - cx_j| <= 8 s_j somewhere in it.
+std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
+  std::vector<int> list;
+  off->assign(p->n_screens + 2, 0);
+  if (p->medium_kind != SWKB_MEDIUM_GAUSSSUM) return list;
+  const int ng = (int)p->medium_params[0];
+  for (int q = 0; q <= p->n_screens; ++q) {
+    (*off)[q] = (int)list.size();
+    if (q == p->n_screens) break;
+    const double xa = p->x0 + q * p->dx, xb = xa + p->dx;
+    for (int j = 0; j < ng; ++j) {
+      const double s = p->medium_params[2 + 4 * j], cx = p->medium_params[3 + 4 * j];
+      const double slack = 1e-9 * (std::fabs(cx) + std::fabs(xb) + 1.0);
+      const double near = cx < xa ? xa : (cx > xb ? xb : cx);
+      if (std::fabs(near - cx) <= 8.0 * s + slack) list.push_back(j);
+    }
+  }
+  (*off)[p->n_screens + 1] = (int)list.size();
+  return list;
+}
+
+struct Layout {
+  size_t xi, pbar, e1r, frac, tw, mprm, glist, u, Y, c, D, Pp, G, A, key, tstart, mflag, mcaus, mdead, counters;
+  size_t total;
+};
+
+Layout layout(const swkb_params* p, const Geometry& g, size_t nlist) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    size_t at = o;
+    o += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t MR = (size_t)g.M * g.R;
+  const size_t ts = p->precision == SWKB_FP64 ? sizeof(double) : sizeof(float);
+  L.xi = take(sizeof(double) * g.M);
+  L.pbar = take(sizeof(double) * g.M);
+  L.e1r = take(sizeof(double) * g.M);
+  L.frac = take(sizeof(double) * g.M);
+  L.tw = take(sizeof(double2) * g.P);
+  L.mprm = take(sizeof(double) * p->n_medium_params);
+  L.glist = take(sizeof(int) * (nlist ? nlist : 1));
+  L.u = take(sizeof(double2) * g.N);
+  L.Y = take(sizeof(double2) * g.P);
+  L.c = take(sizeof(double2) * g.M);
+  L.D = take(ts * MR);
+  L.Pp = take(ts * MR);
+  L.G = take(ts * MR);
+  L.A = take(ts * MR);
+  L.key = take(sizeof(double) * MR);
+  L.tstart = take(sizeof(int) * (size_t)g.M * (g.T + 1));
+  L.mflag = take(sizeof(int) * g.M);
+  L.mcaus = take(sizeof(int) * g.M);
+  L.mdead = take(sizeof(int) * ((size_t)g.M + 2 * (size_t)g.M * waves_per_mode(g)));
+  L.counters = take(sizeof(unsigned long long) * 8);
+  L.total = o;
+  return L;
+}
+
+swkb_status fail(swkb_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+swkb_status hip_fail(hipError_t e, const char* what) {
+  return fail(SWKB_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+}  // namespace swkb
+
+using namespace swkb;
+
+extern "C" {
+
+size_t swkb_workspace_bytes(const swkb_params* p) {
+  if (!validate(p).empty()) return 0;
+  const Geometry g = geometry(p);
+  std::vector<int> off;
+  const std::vector<int> list = gauss_lists(p, &off);
+  return layout(p, g, list.size()).total;
+}
+
+swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_bytes, void* hip_stream,
+                      swkb_plan_t* out) {
+  if (!out) return fail(SWKB_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  const std::string why = validate(p);
+  if (!why.empty()) return fail(SWKB_ERR_ARG, why);
+  if (!workspace) return fail(SWKB_ERR_ARG, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail(SWKB_ERR_ARG, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)hip_stream;
+  swkb_plan_s* pl = new (std::nothrow) swkb_plan_s();
+  if (!pl) return fail(SWKB_ERR_NOMEM, "host allocation failed");
+  try {
+    pl->p = *p;
+    pl->mparams.assign(p->medium_params, p->medium_params + p->n_medium_params);
+    pl->p.medium_params = pl->mparams.data();
+    pl->g = geometry(p);
+    pl->precision = p->precision;
+    pl->x_invariant = p->medium_kind != SWKB_MEDIUM_GAUSSSUM;
+    pl->march_valid_q = -1;
+    pl->cur_q = -1;
+    const Geometry& g = pl->g;
+    const std::vector<int> list = gauss_lists(p, &pl->goff);
+    const Layout L = layout(p, g, list.size());
+    if (workspace_bytes < L.total) {
+      delete pl;
+      return fail(SWKB_ERR_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    }
+    char* ws = static_cast<char*>(workspace);
+    pl->xi = reinterpret_cast<double*>(ws + L.xi);
+    pl->pbar = reinterpret_cast<double*>(ws + L.pbar);
+    pl->e1r = reinterpret_cast<double*>(ws + L.e1r);
+    pl->frac = reinterpret_cast<double*>(ws + L.frac);
+    pl->tw = reinterpret_cast<double2*>(ws + L.tw);
+    pl->mprm = reinterpret_cast<double*>(ws + L.mprm);
+    pl->glist = reinterpret_cast<int*>(ws + L.glist);
+    pl->u = reinterpret_cast<double2*>(ws + L.u);
+    pl->Y = reinterpret_cast<double2*>(ws + L.Y);
+    pl->c = reinterpret_cast<double2*>(ws + L.c);
+    pl->rec.D = ws + L.D;
+    pl->rec.Pp = ws + L.Pp;
+    pl->rec.G = ws + L.G;
+    pl->rec.A = ws + L.A;
+    pl->rec.key = reinterpret_cast<double*>(ws + L.key);
+    pl->rec.tstart = reinterpret_cast<int*>(ws + L.tstart);
+    pl->rec.mflag = reinterpret_cast<int*>(ws + L.mflag);
+    pl->rec.mcaus = reinterpret_cast<int*>(ws + L.mcaus);
+    pl->rec.mdead = reinterpret_cast<int*>(ws + L.mdead);
+    pl->counters = reinterpret_cast<unsigned long long*>(ws + L.counters);
+
+    // mode tables: xi_n = 2 pi n / (k P h); reference pbar and range phase
+    std::vector<double> xi(g.M), pbar(g.M), e1r(g.M), frac(g.M);
+    for (int j = 0; j < g.M; ++j) {
+      const int n = j - g.M / 2;
+      xi[j] = 2.0 * M_PI * n / (g.k * (double)g.P * g.h);
+      const double pb2 = p->eps_ref - xi[j] * xi[j];
+      if (pb2 >= p->p2_floor && pb2 > 0.0) {
+        pbar[j] = std::sqrt(pb2);
+        e1r[j] = p->eps_ref - 1.0;
+      } else {
+        const double f = p->p2_floor > 0.0 ? p->p2_floor : 1e-2;
+        pbar[j] = std::sqrt(f);
+        e1r[j] = (f + xi[j] * xi[j]) - 1.0;
+      }
+      const long double turns = (long double)pbar[j] * (long double)g.dx * (long double)g.k / (2.0L * M_PIl);
+      frac[j] = (double)(turns - floorl(turns));
+    }
+    std::vector<double2> tw(g.P);
+    for (int t = 0; t < g.P; ++t) {
+      const long double a = 2.0L * M_PIl * (long double)t / (long double)g.P;
+      tw[t] = make_double2((double)cosl(a), (double)-sinl(a));
+    }
+    hipError_t e = hipSuccess;
+    auto put = [&](void* dst, const void* src, size_t n) {
+      if (e == hipSuccess && n) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
+    };
+    put(pl->xi, xi.data(), sizeof(double) * g.M);
+    put(pl->pbar, pbar.data(), sizeof(double) * g.M);
+    put(pl->e1r, e1r.data(), sizeof(double) * g.M);
+    put(pl->frac, frac.data(), sizeof(double) * g.M);
+    put(pl->tw, tw.data(), sizeof(double2) * g.P);
+    put(pl->mprm, pl->mparams.data(), sizeof(double) * p->n_medium_params);
+    put(pl->glist, list.data(), sizeof(int) * list.size());
+    if (e == hipSuccess) e = hipMemsetAsync(pl->counters, 0, sizeof(unsigned long long) * 8, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // host tables go out of scope
+    if (e != hipSuccess) {
+      delete pl;
+      return hip_fail(e, "swkb_plan upload");
+    }
+  } catch (const std::exception& ex) {
+    delete pl;
+    return fail(SWKB_ERR_NOMEM, std::string("swkb_plan: ") + ex.what());
+  }
+  *out = pl;
+  return SWKB_OK;
+}
+
+static swkb_status ensure_rays(swkb_plan_s* pl, int q, hipStream_t st) {
+  if (pl->x_invariant ? pl->march_valid_q == -2 : pl->march_valid_q == q) return SWKB_OK;
+  hipError_t e = launch_march(*pl, q, st);
+  if (e == hipSuccess) e = launch_scan(*pl, st);
+  if (e != hipSuccess) {
+    pl->march_valid_q = -1;
+    return hip_fail(e, "ray march launch");
+  }
+  pl->march_valid_q = pl->x_invariant ? -2 : q;
+  return SWKB_OK;
+}
+
+swkb_status swkb_propagate(swkb_plan_t pl, const void* u_in, int32_t q_begin, int32_t q_end, void* history,
+                           void* hip_stream) {
+  if (!pl) return fail(SWKB_ERR_ARG, "plan is NULL");
+  if (q_begin < 0 || q_end < q_begin || q_end > pl->p.n_screens)
+    return fail(SWKB_ERR_ARG, "need 0 <= q_begin <= q_end <= n_screens");
+  if (!u_in && pl->cur_q != q_begin)
+    return fail(SWKB_ERR_STATE, "u_in is NULL but the plan's field is not on screen q_begin");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const Geometry& g = pl->g;
+  const double2* src = u_in ? static_cast<const double2*>(u_in) : pl->u;
+  if (q_end == q_begin) {
+    if (u_in) {
+      hipError_t e = hipMemcpyAsync(pl->u, u_in, sizeof(double2) * g.N, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "field copy");
+    }
+    pl->cur_q = q_begin;
+    return SWKB_OK;
+  }
+  for (int q = q_begin; q < q_end; ++q) {
+    swkb_status s = ensure_rays(pl, q, st);
+    if (s != SWKB_OK) return s;
+    hipError_t e = launch_fft_modes(*pl, src, st);
+    if (e != hipSuccess) return hip_fail(e, "fft launch");
+    double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * g.N : nullptr;
+    e = launch_superpose(*pl, pl->u, hist, st);
+    if (e != hipSuccess) return hip_fail(e, "superposition launch");
+    src = pl->u;
+    pl->cur_q = q + 1;
+  }
+  return SWKB_OK;
+}
+
+swkb_status swkb_field(swkb_plan_t pl, void* out, void* hip_stream) {
+  if (!pl || !out) return fail(SWKB_ERR_ARG, "plan or out is NULL");
+  if (pl->cur_q < 0) return fail(SWKB_ERR_STATE, "no field yet: call swkb_propagate first");
+  hipError_t e = hipMemcpyAsync(out, pl->u, sizeof(double2) * pl->g.N, hipMemcpyDeviceToDevice,
+                                (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "field copy");
+  return SWKB_OK;
+}
+
+int32_t swkb_current_screen(swkb_plan_t pl) { return pl ? pl->cur_q : -1; }
+
+swkb_status swkb_diagnostics(swkb_plan_t pl, void* hip_stream, swkb_counters* out) {
+  if (!pl || !out) return fail(SWKB_ERR_ARG, "plan or out is NULL");
+  unsigned long long h[8];
+  hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+  if (e == hipSuccess) e = hipMemcpy(h, pl->counters, sizeof(h), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics");
+  out->caustic_rays = (int64_t)h[0];
+  out->dead_rays = (int64_t)h[1];
+  out->folded_modes = (int64_t)h[2];
+  out->significant = (int64_t)h[3];
+  out->screens = (int64_t)h[4];
+  if (out->significant > 0) return fail(SWKB_ERR_CAUSTIC, "a significant mode met a caustic inside a screen");
+  return SWKB_OK;
+}
+
+void swkb_destroy(swkb_plan_t pl) { delete pl; }
+
+const char* swkb_status_string(swkb_status s) {
+  switch (s) {
+    case SWKB_OK: return "ok";
+    case SWKB_ERR_ARG: return "invalid argument";
+    case SWKB_ERR_NOMEM: return "workspace too small or out of memory";
+    case SWKB_ERR_DEVICE: return "HIP runtime error";
+    case SWKB_ERR_CAUSTIC: return "caustic inside a screen";
+    case SWKB_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* swkb_last_error(void) { return g_err.c_str(); }
+
+swkb_status swkb_stage_modes(swkb_plan_t pl, const void* u, void* c, void* hip_stream) {
+  if (!pl || !u || !c) return fail(SWKB_ERR_ARG, "NULL argument");
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = launch_fft_modes(*pl, static_cast<const double2*>(u), st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c, pl->c, sizeof(double2) * pl->g.M, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "stage modes");
+  return SWKB_OK;
+}
+
+swkb_status swkb_stage_rays(swkb_plan_t pl, int32_t q, void* Z, void* psi, void* qz, void* amp, void* flag,
+                            void* hip_stream) {
+  if (!pl || !Z || !psi || !qz || !amp || !flag) return fail(SWKB_ERR_ARG, "NULL argument");
+  if (q < 0 || q >= pl->p.n_screens) return fail(SWKB_ERR_ARG, "q out of range");
+  hipStream_t st = (hipStream_t)hip_stream;
+  swkb_status s = ensure_rays(pl, q, st);
+  if (s != SWKB_OK) return s;
+  hipError_t e = launch_export_rays(*pl, q, static_cast<double*>(Z), static_cast<double*>(psi),
+                                    static_cast<double*>(qz), static_cast<double*>(amp), static_cast<int*>(flag), st);
+  if (e != hipSuccess) return hip_fail(e, "stage rays");
+  return SWKB_OK;
+}
+
+int32_t swkb_num_rays(swkb_plan_t pl) { return pl ? pl->g.R : 0; }
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Step 1 of a screen: vertical DFT of the screen field and selection of the
+// kept modes (Sec. 2.1.1, eqs. fft_eq / ifft_eq; the 1/P of the inverse
+// transform is folded into the mode amplitudes).
+//
+// Four-step FFT of length P = P1 * P2 (input index i = P2 m1 + m2, output
+// index n = n1 + P1 n2):
+//   fft_cols: for each column m2, a length-P1 FFT over m1 in LDS, then the
+//             twiddle e^{-2 pi i n1 m2 / P}; writes Y[n1][m2];
+//   fft_rows: for each row n1, a length-P2 FFT over m2 in LDS; writes only
+//             the M kept bins n in [-M/2, M/2), scaled by 1/P.
+// Both sub-FFTs are in-place radix-2 (bit-reversed load) in LDS, several
+// short sequences per workgroup so that global loads and stores move
+// contiguous runs.  The ground-mirror extension of the field (Sec. 2.3) is
+// applied on the fly in fft_cols' loads.
+#include "swkb_internal.h"
+
+namespace swkb {
+namespace {
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ inline int bitrev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
+
+// Element i in [0, P) of the periodic vector whose DFT gives the modes.
+// Mirror: v[N+m] = u[m]; v[N-m] = -/+ u[m] (Dirichlet / Neumann);
+// v[0] = 0; v[N] = 0 for Dirichlet.
+__device__ inline double2 extended(const double2* __restrict__ u, int i, int N, int bc) {
+  if (bc == SWKB_BC_PERIODIC) return u[i];
+  if (i > N) return u[i - N];
+  if (i == N) return bc == SWKB_BC_DIRICHLET ? make_double2(0.0, 0.0) : u[0];
+  if (i == 0) return make_double2(0.0, 0.0);
+  double2 x = u[N - i];
+  return bc == SWKB_BC_DIRICHLET ? make_double2(-x.x, -x.y) : x;
+}
+
+// nb sequences of length len (power of two) stored at L[b * len + i] in
+// bit-reversed order; in-place radix-2 decimation in time.  The twiddle of
+// butterfly k at half-size hs is e^{-2 pi i k / (2 hs)} = tw[k * P / (2 hs)].
+__device__ void lds_fft(double2* L, int nb, int len, const double2* __restrict__ tw, int P) {
+  const int half = len >> 1;
+  const int nbf = nb * half;
+  for (int hs = 1; hs < len; hs <<= 1) {
+    const int tstride = P / (2 * hs);
+    for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
+      const int seq = b / half, bb = b - seq * half;
+      const int grp = bb / hs, kk = bb - grp * hs;
+      const int i0 = seq * len + grp * 2 * hs + kk, i1 = i0 + hs;
+      const double2 w = tw[kk * tstride];
+      const double2 x0 = L[i0];
+      const double2 x1 = cmul(L[i1], w);
+      L[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
+      L[i1] = make_double2(x0.x - x1.x, x0.y - x1.y);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) fft_cols(const double2* __restrict__ u, double2* __restrict__ Y,
+                                                const double2* __restrict__ tw, int N, int bc, int P, int P1,
+                                                int P2, int logP1, int CA) {
+  extern __shared__ double2 L[];  // CA sequences of length P1
+  const int c0 = blockIdx.x * CA;
+  for (int idx = threadIdx.x; idx < CA * P1; idx += blockDim.x) {
+    const int cc = idx % CA, m1 = idx / CA;
+    L[cc * P1 + bitrev(m1, logP1)] = extended(u, P2 * m1 + c0 + cc, N, bc);
+  }
+  __syncthreads();
+  lds_fft(L, CA, P1, tw, P);
+  for (int idx = threadIdx.x; idx < CA * P1; idx += blockDim.x) {
+    const int cc = idx % CA, n1 = idx / CA, m2 = c0 + cc;
+    Y[n1 * P2 + m2] = cmul(L[cc * P1 + n1], tw[n1 * m2]);  // n1 m2 < P
+  }
+}
+
+__global__ void __launch_bounds__(256) fft_rows(const double2* __restrict__ Y, double2* __restrict__ c,
+                                                const double2* __restrict__ tw, int P, int P1, int P2,
+                                                int logP2, int RB, int M) {
+  extern __shared__ double2 L[];  // RB sequences of length P2
+  const int r0 = blockIdx.x * RB;
+  for (int idx = threadIdx.x; idx < RB * P2; idx += blockDim.x) {
+    const int rr = idx / P2, m2 = idx - rr * P2;
+    L[rr * P2 + bitrev(m2, logP2)] = Y[(r0 + rr) * P2 + m2];
+  }
+  __syncthreads();
+  lds_fft(L, RB, P2, tw, P);
+  const double inv = 1.0 / (double)P;  // exact: P is a power of two
+  const int halfM = M >> 1;
+  for (int idx = threadIdx.x; idx < RB * P2; idx += blockDim.x) {
+    const int rr = idx / P2, n2 = idx - rr * P2;
+    const int n = (r0 + rr) + P1 * n2;
+    int j = -1;
+    if (n < halfM) j = n + halfM;
+    else if (n >= P - halfM) j = n - P + halfM;
+    if (j >= 0) {
+      const double2 x = L[rr * P2 + n2];
+      c[j] = make_double2(x.x * inv, x.y * inv);
+    }
+  }
+}
+
+int ilog2(int x) {
+  int l = 0;
+  while ((1 << l) < x) ++l;
+  return l;
+}
+
+}  // namespace
+
+hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, hipStream_t st) {
+  const Geometry& g = pl.g;
+  const int CA = g.P2 < 16 ? g.P2 : 16;
+  int RB = 2048 / g.P2;
+  if (RB < 1) RB = 1;
+  if (RB > g.P1) RB = g.P1;
+  hipLaunchKernelGGL(fft_cols, dim3(g.P2 / CA), dim3(256), sizeof(double2) * CA * g.P1, st, u, pl.Y, pl.tw,
+                     g.N, g.bc, g.P, g.P1, g.P2, ilog2(g.P1), CA);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fft_rows, dim3(g.P1 / RB), dim3(256), sizeof(double2) * RB * g.P2, st, pl.Y, pl.c, pl.tw,
+                     g.P, g.P1, g.P2, ilog2(g.P2), RB, g.M);
+  return hipGetLastError();
+}
+
+}  // namespace swkb

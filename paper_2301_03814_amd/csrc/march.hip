@@ -1,0 +1,318 @@
+// Step 2 of a screen: WKB across the screen, one ray per (mode, launch
+// point), and the per-mode bookkeeping the interpolation needs.
+//
+// Rays follow the characteristic system of the eikonal and transport
+// equations (Appendix A, eqs. charsys, charsys_s), reparametrised by the
+// range x (dt = dx / (2 psi_x); Sec. 2.1.2 admits any eikonal/transport
+// solver) and marched with S classical RK4 steps so that every ray lands
+// on x_{q+1}.  With p = psi_x = sqrt(eps - q^2), q = psi_z:
+//   dz/dx = q/p,   dq/dx = eps_z / (2p),
+//   dZs/dx = (eps Qs - q eps_z Zs / 2) / p^3,
+//   dQs/dx = (eps_zz / (2p) - eps_z^2 / (4p^3)) Zs + q eps_z / (2p^3) Qs,
+// where Zs = dz/ds, Qs = dq/ds at fixed x carry the ray-tube width.  The
+// transport amplitude on arrival is a = sqrt(p0 / (p Zs)) (the Jacobian
+// J = X_t Z_s - Z_t X_s of Appendix A with A = A0 sqrt(J0/J)).
+//
+// Phase split: psi = xi (z - z0') + pbar (x - x_q) + dpsi.  The first term
+// is exact on the grid (an integer number of 1/P turns), the second is one
+// FP64 number per mode, and only the small deviation dpsi is marched:
+//   d dpsi/dx = ((eps - eps_ref_n) - (q - xi)(q + xi)) / (p + pbar) + q (q - xi) / p
+// (= eps/p - xi q/p - pbar, written in small quantities).  State per ray:
+// dz = z - s, dq = q - xi, dpsi in T; Zs, Qs always in FP64.
+//
+// Ray r of mode n starts at s_r = z_a + (r rho - E) h with q = xi_n
+// (Sec. 2.1.2 initial conditions), Zs = 1, Qs = 0.  A ray is dead when
+// p^2 <= p2_floor at launch or at any stage, caustic when Zs <= 0 at any
+// stage; dead and caustic rays do not contribute.
+#include "medium.h"
+
+namespace swkb {
+namespace {
+
+struct ModeC {
+  double xi, omx2;  // xi, 1 - xi^2
+  double pbar, e1r; // reference p and eps - 1 of the mode
+};
+
+template <typename T>
+struct Deriv {
+  T dz, dq, dps;
+  double Zs, Qs;
+};
+
+enum { kLive = 0, kDeadLaunch = 1, kDead = 2, kCaustic = 3 };
+
+// Right-hand side at (x, state).  Returns kLive, kDead or kCaustic.
+template <typename T>
+__device__ inline int rhs(const DevMedium& md, const ModeC& mc, double x, double s, T dz, T dq, double Zs,
+                         double Qs, double p2_floor, Deriv<T>& d) {
+  if (!(Zs > 0.0)) return kCaustic;
+  const Med<T> m = medium_eval<T>(md, x, s, dz);
+  const T xi = (T)mc.xi;
+  const T q = xi + dq;
+  const T p2 = (T)mc.omx2 + m.e1 - dq * (T(2) * xi + dq);
+  if (!(p2 > (T)p2_floor)) return kDead;
+  const T p = sqrt(p2);
+  const T ip = T(1) / p;
+  const T pbar = (T)mc.pbar;
+  d.dz = q * ip;
+  d.dq = T(0.5) * m.ez * ip;
+  d.dps = ((m.e1 - (T)mc.e1r) - dq * (q + xi)) / (p + pbar) + q * dq * ip;
+  // ray-tube variations in FP64
+  const double pd = (double)p, ipd = 1.0 / pd;
+  const double ip3 = ipd * ipd * ipd;
+  const double eps = 1.0 + (double)m.e1;
+  const double qe = (double)q * (double)m.ez * 0.5 * ip3;  // q eps_z / (2 p^3)
+  const double ez = (double)m.ez;
+  d.Zs = eps * ip3 * Qs - qe * Zs;
+  d.Qs = (0.5 * (double)m.ezz * ipd - 0.25 * ez * ez * ip3) * Zs + qe * Qs;
+  return kLive;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, DevModes modes, DevRecords rec,
+                                                    int* __restrict__ wcount, double x_q, int waves_per_mode) {
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const int j = wave / waves_per_mode;
+  if (j >= g.M) return;  // uniform per wavefront
+  const int w = wave - j * waves_per_mode;
+  const int r = w * 64 + lane;
+  const bool active = r < g.R;
+
+  ModeC mc;
+  mc.xi = modes.xi[j];
+  mc.omx2 = 1.0 - mc.xi * mc.xi;
+  mc.pbar = modes.pbar[j];
+  mc.e1r = modes.e1r[j];
+
+  const double s = g.z_a + (double)(r * g.rho - g.E) * g.h;
+  int st = kLive;
+  T dz = T(0), dq = T(0), dps = T(0);
+  double Zs = 1.0, Qs = 0.0;
+  double amp = 0.0;
+  if (active) {
+    const Med<T> m0 = medium_eval<T>(md, x_q, s, T(0));
+    const T p02 = (T)mc.omx2 + m0.e1;
+    if (!(p02 > (T)g.p2_floor)) {
+      st = kDeadLaunch;
+    } else {
+      const double p0 = (double)sqrt(p02);
+      const double hx = g.dx / g.S;
+      Deriv<T> k1, k2, k3, k4;
+      for (int i = 0; i < g.S && st == kLive; ++i) {
+        const double x = x_q + i * hx;
+        const T hh = (T)(0.5 * hx);
+        if ((st = rhs<T>(md, mc, x, s, dz, dq, Zs, Qs, g.p2_floor, k1))) break;
+        if ((st = rhs<T>(md, mc, x + 0.5 * hx, s, dz + hh * k1.dz, dq + hh * k1.dq, Zs + 0.5 * hx * k1.Zs,
+                         Qs + 0.5 * hx * k1.Qs, g.p2_floor, k2)))
+          break;
+        if ((st = rhs<T>(md, mc, x + 0.5 * hx, s, dz + hh * k2.dz, dq + hh * k2.dq, Zs + 0.5 * hx * k2.Zs,
+                         Qs + 0.5 * hx * k2.Qs, g.p2_floor, k3)))
+          break;
+        const T hf = (T)hx;
+        if ((st = rhs<T>(md, mc, x + hx, s, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hx * k3.Zs, Qs + hx * k3.Qs,
+                         g.p2_floor, k4)))
+          break;
+        const T h6 = (T)(hx / 6.0);
+        dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
+        dq += h6 * (k1.dq + T(2) * k2.dq + T(2) * k3.dq + k4.dq);
+        dps += h6 * (k1.dps + T(2) * k2.dps + T(2) * k3.dps + k4.dps);
+        const double hd6 = hx / 6.0;
+        Zs += hd6 * (k1.Zs + 2.0 * k2.Zs + 2.0 * k3.Zs + k4.Zs);
+        Qs += hd6 * (k1.Qs + 2.0 * k2.Qs + 2.0 * k3.Qs + k4.Qs);
+      }
+      if (st == kLive) {
+        if (!(Zs > 0.0)) {
+          st = kCaustic;
+        } else {
+          const Med<T> m1 = medium_eval<T>(md, x_q + g.dx, s, dz);
+          const T xi = (T)mc.xi;
+          const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
+          if (!(p2 > (T)g.p2_floor)) st = kDead;
+          else amp = sqrt(p0 / ((double)sqrt(p2) * Zs));
+        }
+      }
+    }
+    const size_t o = (size_t)j * g.R + r;
+    static_cast<T*>(rec.D)[o] = dz;
+    static_cast<T*>(rec.Pp)[o] = dps;
+    static_cast<T*>(rec.G)[o] = dq;
+    static_cast<T*>(rec.A)[o] = st == kLive ? (T)amp : (T)(-st);
+  }
+  // per-wave counts (summed per mode by the scan kernel; no atomics)
+  const unsigned long long bc = __ballot(active && st == kCaustic);
+  const unsigned long long bd = __ballot(active && (st == kDead || st == kDeadLaunch));
+  if (lane == 0) {
+    wcount[2 * ((size_t)j * waves_per_mode + w)] = __popcll(bc);
+    wcount[2 * ((size_t)j * waves_per_mode + w) + 1] = __popcll(bd);
+  }
+}
+
+// One workgroup per mode: running maximum of live arrivals (search keys),
+// the fold test (live arrivals must increase strictly), the per-tile search
+// windows and the mode's ray counts.
+template <typename T>
+__global__ void __launch_bounds__(256) scan_kernel(Geometry g, DevRecords rec, const int* __restrict__ wcount,
+                                                   int waves_per_mode) {
+  __shared__ double sh[256];
+  __shared__ int sfold;
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x;
+  const size_t base = (size_t)j * g.R;
+  int* __restrict__ ts = rec.tstart + (size_t)j * (g.T + 1);
+  const double tileh = (double)kTile * g.h;
+  if (tid == 0) sfold = 0;
+  double carry = -INFINITY;
+  for (int c0 = 0; c0 < g.R; c0 += 256) {
+    const int r = c0 + tid;
+    double Z = -INFINITY;
+    bool live = false;
+    if (r < g.R) {
+      const T a = static_cast<const T*>(rec.A)[base + r];
+      live = a > T(0);
+      if (live) Z = (g.z_a + (double)(r * g.rho - g.E) * g.h) + (double)static_cast<const T*>(rec.D)[base + r];
+    }
+    sh[tid] = Z;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const double v = tid >= off ? sh[tid - off] : -INFINITY;
+      __syncthreads();
+      sh[tid] = fmax(sh[tid], v);
+      __syncthreads();
+    }
+    const double incl = fmax(carry, sh[tid]);
+    const double prev = fmax(carry, tid > 0 ? sh[tid - 1] : -INFINITY);  // key of ray r-1
+    if (live && !(Z > prev)) sfold = 1;
+    if (r < g.R) {
+      rec.key[base + r] = incl;
+      // tiles whose first point z_t satisfies key_{r-1} <= z_t < key_r get window start r-1
+      if (incl > prev) {
+        int t = prev == -INFINITY ? 0 : (int)floor((prev - g.z_a) / tileh) - 1;
+        if (t < 0) t = 0;
+        for (; t <= g.T; ++t) {
+          const double zt = g.z_a + (double)(t * kTile) * g.h;
+          if (!(zt < incl)) break;
+          if (prev <= zt) ts[t] = r - 1;
+        }
+      }
+    }
+    carry = fmax(carry, sh[255]);
+    __syncthreads();
+  }
+  // tiles at or above the last key start at the last ray
+  for (int t = tid; t <= g.T; t += 256) {
+    const double zt = g.z_a + (double)(t * kTile) * g.h;
+    if (carry <= zt) ts[t] = g.R - 1;
+  }
+  // counts
+  if (tid < 64) {
+    int nc = 0, nd = 0;
+    for (int w = tid; w < waves_per_mode; w += 64) {
+      nc += wcount[2 * ((size_t)j * waves_per_mode + w)];
+      nd += wcount[2 * ((size_t)j * waves_per_mode + w) + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      nc += __shfl_down(nc, off);
+      nd += __shfl_down(nd, off);
+    }
+    if (tid == 0) {
+      rec.mcaus[j] = nc;
+      rec.mdead[j] = nd;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) rec.mflag[j] = (sfold ? 1 : 0) | (rec.mcaus[j] > 0 ? 2 : 0);
+}
+
+// Full records in FP64 for the stage entry point.
+template <typename T>
+__global__ void export_kernel(Geometry g, DevModes modes, DevRecords rec, double* __restrict__ Z,
+                              double* __restrict__ psi, double* __restrict__ qz, double* __restrict__ amp,
+                              int* __restrict__ flag, double z0p) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)g.M * g.R) return;
+  const int j = (int)(i / g.R), r = (int)(i - (size_t)j * g.R);
+  const double xi = modes.xi[j];
+  const double s = g.z_a + (double)(r * g.rho - g.E) * g.h;
+  const double zz = s + (double)static_cast<const T*>(rec.D)[i];
+  const double a = (double)static_cast<const T*>(rec.A)[i];
+  Z[i] = zz;
+  psi[i] = xi * (zz - z0p) + modes.pbar[j] * g.dx + (double)static_cast<const T*>(rec.Pp)[i];
+  qz[i] = xi + (double)static_cast<const T*>(rec.G)[i];
+  amp[i] = a > 0.0 ? a : 0.0;
+  flag[i] = a > 0.0 ? 0 : (int)(-a);
+}
+
+DevMedium medium_for(const swkb_plan_s& pl, int q) {
+  DevMedium md;
+  md.kind = pl.p.medium_kind;
+  md.mirror = pl.g.bc != SWKB_BC_PERIODIC;
+  md.z_a = pl.g.z_a;
+  md.prm = pl.mprm;
+  md.list = nullptr;
+  md.nlist = 0;
+  if (md.kind == SWKB_MEDIUM_GAUSSSUM) {
+    md.list = pl.glist + pl.goff[q];
+    md.nlist = pl.goff[q + 1] - pl.goff[q];
+  }
+  return md;
+}
+
+DevModes modes_of(const swkb_plan_s& pl) {
+  DevModes m;
+  m.xi = pl.xi;
+  m.pbar = pl.pbar;
+  m.e1r = pl.e1r;
+  m.frac = pl.frac;
+  return m;
+}
+
+}  // namespace
+
+int waves_per_mode(const Geometry& g) { return (g.R + 63) / 64; }
+
+hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
+  const Geometry& g = pl.g;
+  const int wpm = waves_per_mode(g);
+  const long long waves = (long long)wpm * g.M;
+  const dim3 grid((unsigned)((waves + 3) / 4));
+  const double x_q = pl.p.x0 + q * pl.p.dx;
+  int* wcount = pl.rec.mdead + g.M;  // scratch after the per-mode arrays
+  if (pl.precision == SWKB_FP64)
+    hipLaunchKernelGGL(march_kernel<double>, grid, dim3(256), 0, st, g, medium_for(pl, q), modes_of(pl), pl.rec,
+                       wcount, x_q, wpm);
+  else
+    hipLaunchKernelGGL(march_kernel<float>, grid, dim3(256), 0, st, g, medium_for(pl, q), modes_of(pl), pl.rec,
+                       wcount, x_q, wpm);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st) {
+  const Geometry& g = pl.g;
+  const int wpm = waves_per_mode(g);
+  const int* wcount = pl.rec.mdead + g.M;
+  if (pl.precision == SWKB_FP64)
+    hipLaunchKernelGGL(scan_kernel<double>, dim3(g.M), dim3(256), 0, st, g, pl.rec, wcount, wpm);
+  else
+    hipLaunchKernelGGL(scan_kernel<float>, dim3(g.M), dim3(256), 0, st, g, pl.rec, wcount, wpm);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_rays(const swkb_plan_s& pl, int q, double* Z, double* psi, double* qz, double* amp,
+                              int* flag, hipStream_t st) {
+  (void)q;
+  const Geometry& g = pl.g;
+  const size_t n = (size_t)g.M * g.R;
+  const double z0p = g.bc == SWKB_BC_PERIODIC ? g.z_a : g.z_a - (g.z_b - g.z_a);
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (pl.precision == SWKB_FP64)
+    hipLaunchKernelGGL(export_kernel<double>, grid, dim3(256), 0, st, g, modes_of(pl), pl.rec, Z, psi, qz, amp,
+                       flag, z0p);
+  else
+    hipLaunchKernelGGL(export_kernel<float>, grid, dim3(256), 0, st, g, modes_of(pl), pl.rec, Z, psi, qz, amp,
+                       flag, z0p);
+  return hipGetLastError();
+}
+
+}  // namespace swkb

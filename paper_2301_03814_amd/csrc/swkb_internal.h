@@ -1,0 +1,88 @@
+// Internal declarations shared by the HIP translation units of libswkb.
+// Not part of the C ABI (include/swkb.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/swkb.h"
+
+namespace swkb {
+
+// Points per superposition tile (one wavefront lane per grid point).
+constexpr int kTile = 64;
+
+// Device view of the medium for one screen.
+struct DevMedium {
+  int kind;            // SWKB_MEDIUM_*
+  int mirror;          // nonzero: eps reflected about z_a (ground mirror)
+  double z_a;
+  const double* prm;   // raw parameter array (device)
+  const int* list;     // GAUSSSUM: candidate Gaussians of this screen (device)
+  int nlist;
+};
+
+// Per-mode constants (device arrays of length M).
+struct DevModes {
+  const double* xi;    // vertical slowness xi_n = 2 pi n / (k P h)
+  const double* pbar;  // reference horizontal slowness of the phase split
+  const double* e1r;   // pbar^2 + xi^2 - 1 (reference eps - 1 of the mode)
+  const double* frac;  // frac(pbar dx / lambda): range phase in turns, mod 1
+};
+
+// Arrival records, row-major [mode][ray].  T = double (FP64) or float (mixed).
+struct DevRecords {
+  void* D;        // arrival height minus launch height, T
+  void* Pp;       // phase deviation delta psi, T
+  void* G;        // q - xi at arrival, T
+  void* A;        // transport factor a (> 0 live); -flag otherwise, T
+  double* key;    // running maximum of live arrival heights (search keys)
+  int* tstart;    // [mode][tile 0..T]: largest r with key_r <= z of the tile's first point
+  int* mflag;     // per mode: bit0 folded, bit1 has caustic rays
+  int* mcaus;     // per mode: caustic rays this march
+  int* mdead;     // per mode: dead rays this march
+};
+
+struct Geometry {
+  int N, M, P, R, T, S, rho, E, bc, P1, P2;
+  double z_a, z_b, h, k, lam, dx, p2_floor;
+};
+
+}  // namespace swkb
+
+struct swkb_plan_s {
+  swkb_params p;
+  std::vector<double> mparams;
+  swkb::Geometry g;
+  int precision;
+  int x_invariant;
+  int march_valid_q;   // screen whose rays the records hold (-1 none; -2 any, x-invariant)
+  int cur_q;
+  // device pointers inside the caller's workspace
+  double *xi, *pbar, *e1r, *frac;
+  double2* tw;         // e^{-2 pi i t / P}, t in [0, P)
+  double* mprm;
+  int* glist;          // concatenated per-screen Gaussian lists
+  std::vector<int> goff;  // host offsets into glist per screen (n_screens + 1)
+  double2 *u, *Y, *c;
+  swkb::DevRecords rec;
+  unsigned long long* counters;  // caustic, dead, folded, significant, screens
+};
+
+namespace swkb {
+
+void set_error(const std::string& msg);
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, hipStream_t st);
+hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st);
+hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st);
+hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, hipStream_t st);
+hipError_t launch_export_rays(const swkb_plan_s& pl, int q, double* Z, double* psi, double* qz,
+                              double* amp, int* flag, hipStream_t st);
+
+}  // namespace swkb

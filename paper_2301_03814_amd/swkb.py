@@ -1,0 +1,216 @@
+"""Python binding of libswkb (include/swkb.h): argument marshalling only.
+
+Every step of the propagation runs in the library's HIP kernels; PyTorch
+provides device memory (the plan workspace, fields, history) and the
+stream.  There is no CPU fallback: without the built library, or without a
+GPU, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswkb.so")
+
+SWKB_OK, SWKB_ERR_ARG, SWKB_ERR_NOMEM, SWKB_ERR_DEVICE, SWKB_ERR_CAUSTIC, SWKB_ERR_STATE = range(6)
+FP64, MIXED = 0, 1
+BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
+MEDIUM_LINEAR, MEDIUM_EXPGAUSS, MEDIUM_GAUSSSUM, MEDIUM_MPROFILE = 0, 1, 2, 3
+
+EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", "swkb_current_screen",
+           "swkb_diagnostics", "swkb_destroy", "swkb_status_string", "swkb_last_error",
+           "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays"]
+
+
+class Params(C.Structure):
+    """Mirror of swkb_params (include/swkb.h), field for field."""
+    _fields_ = [
+        ("k", C.c_double), ("z_a", C.c_double), ("z_b", C.c_double),
+        ("n_z", C.c_int32), ("n_modes", C.c_int32),
+        ("x0", C.c_double), ("dx", C.c_double),
+        ("n_screens", C.c_int32), ("rk4_steps", C.c_int32), ("ray_stride", C.c_int32),
+        ("launch_ext_cells", C.c_int32),
+        ("p2_floor", C.c_double),
+        ("bc", C.c_int32), ("medium_kind", C.c_int32),
+        ("absorber_bot", C.c_double), ("absorber_top", C.c_double),
+        ("medium_params", C.POINTER(C.c_double)),
+        ("n_medium_params", C.c_int32), ("precision", C.c_int32),
+        ("eps_ref", C.c_double), ("caustic_tol", C.c_double),
+    ]
+
+
+class Counters(C.Structure):
+    _fields_ = [("caustic_rays", C.c_int64), ("dead_rays", C.c_int64), ("folded_modes", C.c_int64),
+                ("significant", C.c_int64), ("screens", C.c_int64)]
+
+
+class SwkbError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"swkb error {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libswkb.so (built by paper_2301_03814_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libswkb.so not built ({path}); run paper_2301_03814_amd.build.build()")
+    lib = C.CDLL(path)
+    vp, i32, pp = C.c_void_p, C.c_int32, C.POINTER(Params)
+    lib.swkb_workspace_bytes.argtypes = [pp]
+    lib.swkb_workspace_bytes.restype = C.c_size_t
+    lib.swkb_plan.argtypes = [pp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.swkb_propagate.argtypes = [vp, vp, i32, i32, vp, vp]
+    lib.swkb_field.argtypes = [vp, vp, vp]
+    lib.swkb_current_screen.argtypes = [vp]
+    lib.swkb_current_screen.restype = i32
+    lib.swkb_diagnostics.argtypes = [vp, vp, C.POINTER(Counters)]
+    lib.swkb_destroy.argtypes = [vp]
+    lib.swkb_destroy.restype = None
+    lib.swkb_status_string.argtypes = [C.c_int]
+    lib.swkb_status_string.restype = C.c_char_p
+    lib.swkb_last_error.restype = C.c_char_p
+    lib.swkb_stage_modes.argtypes = [vp, vp, vp, vp]
+    lib.swkb_stage_rays.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.swkb_num_rays.argtypes = [vp]
+    lib.swkb_num_rays.restype = i32
+    for name in ("swkb_plan", "swkb_propagate", "swkb_field", "swkb_diagnostics", "swkb_stage_modes",
+                 "swkb_stage_rays"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != SWKB_OK:
+        raise SwkbError(status, _lib.swkb_last_error().decode())
+
+
+def make_params(cfg, precision=FP64):
+    """swkb_params from a workload dict (keys as in the workloads module)."""
+    mp = np.ascontiguousarray(cfg["medium_params"], dtype=np.float64)
+    p = Params(
+        k=cfg["k"], z_a=cfg["z_a"], z_b=cfg["z_b"], n_z=cfg["n_z"], n_modes=cfg["n_modes"],
+        x0=cfg["x0"], dx=cfg["dx"], n_screens=cfg["n_screens"], rk4_steps=cfg["rk4_steps"],
+        ray_stride=cfg["ray_stride"], launch_ext_cells=cfg["launch_ext_cells"], p2_floor=cfg["p2_floor"],
+        bc=cfg["bc"], medium_kind=cfg["medium_kind"], absorber_bot=cfg["absorber_bot"],
+        absorber_top=cfg["absorber_top"], medium_params=mp.ctypes.data_as(C.POINTER(C.c_double)),
+        n_medium_params=mp.size, precision=int(precision), eps_ref=cfg["eps_ref"],
+        caustic_tol=cfg["caustic_tol"])
+    p._keep = mp
+    return p
+
+
+def workspace_bytes(cfg, precision=FP64) -> int:
+    return int(load().swkb_workspace_bytes(C.byref(make_params(cfg, precision))))
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor with {numel} elements")
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One propagation problem resident on the GPU (workspace owned here)."""
+
+    def __init__(self, cfg, precision=FP64, device="cuda", stream=None):
+        import torch
+        lib = load()
+        self.cfg = cfg
+        self.precision = precision
+        self._params = make_params(cfg, precision)
+        nbytes = lib.swkb_workspace_bytes(C.byref(self._params))
+        if nbytes == 0:
+            raise SwkbError(SWKB_ERR_ARG, "invalid parameters")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        self.device = self.workspace.device
+        h = C.c_void_p()
+        _check(lib.swkb_plan(C.byref(self._params), C.c_void_p(self.workspace.data_ptr()), nbytes,
+                             _stream_handle(stream), C.byref(h)))
+        self._h = h
+        self.n_z = cfg["n_z"]
+        self.n_modes = cfg["n_modes"]
+        self.num_rays = int(lib.swkb_num_rays(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.swkb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def current_screen(self) -> int:
+        return int(_lib.swkb_current_screen(self._h))
+
+    def propagate(self, u0=None, q_begin=0, q_end=None, history=True, out=None, stream=None):
+        """Screens q_begin..q_end-1.  Returns the history [q_end-q_begin, N]
+        (complex128, device) when history is True, else None."""
+        import torch
+        if q_end is None:
+            q_end = self.cfg["n_screens"]
+        up = C.c_void_p(0) if u0 is None else _dev_ptr(u0, torch.complex128, self.n_z, "u0")
+        hist = None
+        hp = C.c_void_p(0)
+        if out is not None:
+            hist = out
+            hp = _dev_ptr(out, torch.complex128, (q_end - q_begin) * self.n_z, "out")
+        elif history:
+            hist = torch.empty((q_end - q_begin, self.n_z), dtype=torch.complex128, device=self.device)
+            hp = C.c_void_p(hist.data_ptr())
+        _check(_lib.swkb_propagate(self._h, up, int(q_begin), int(q_end), hp, _stream_handle(stream)))
+        return hist
+
+    def field(self, stream=None):
+        import torch
+        out = torch.empty(self.n_z, dtype=torch.complex128, device=self.device)
+        _check(_lib.swkb_field(self._h, C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def diagnostics(self, stream=None, raise_on_caustic=False):
+        cnt = Counters()
+        st = _lib.swkb_diagnostics(self._h, _stream_handle(stream), C.byref(cnt))
+        if st not in (SWKB_OK, SWKB_ERR_CAUSTIC) or (raise_on_caustic and st != SWKB_OK):
+            _check(st)
+        return {f: int(getattr(cnt, f)) for f, _ in Counters._fields_}
+
+    def stage_modes(self, u, stream=None):
+        import torch
+        c = torch.empty(self.n_modes, dtype=torch.complex128, device=self.device)
+        _check(_lib.swkb_stage_modes(self._h, _dev_ptr(u, torch.complex128, self.n_z, "u"),
+                                     C.c_void_p(c.data_ptr()), _stream_handle(stream)))
+        return c
+
+    def stage_rays(self, q, stream=None):
+        import torch
+        n = self.n_modes * self.num_rays
+        shape = (self.n_modes, self.num_rays)
+        arrs = {k: torch.empty(shape, dtype=torch.float64, device=self.device) for k in ("Z", "psi", "q", "a")}
+        arrs["flag"] = torch.empty(shape, dtype=torch.int32, device=self.device)
+        _check(_lib.swkb_stage_rays(self._h, int(q), *(C.c_void_p(arrs[k].data_ptr())
+                                                          for k in ("Z", "psi", "q", "a", "flag")),
+                                    _stream_handle(stream)))
+        del n
+        return arrs

@@ -1,0 +1,107 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol,
+its struct layout matches the header, and host-only argument validation
+works.  No kernel is launched here."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swkb.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2301_03814_amd import swkb
+    if not os.path.exists(swkb.LIB_PATH):
+        from paper_2301_03814_amd import build
+        build.build()
+    return swkb.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(swkb_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    from paper_2301_03814_amd import swkb
+    assert sorted(swkb.EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_params_struct_layout_matches_header(tmp_path):
+    from paper_2301_03814_amd.swkb import Counters, Params
+    fields = [f for f, _ in Params._fields_]
+    src = ['#include <stddef.h>', '#include <stdio.h>', f'#include "{HEADER}"', 'int main(void){',
+           'printf("%zu\\n", sizeof(swkb_params));', 'printf("%zu\\n", sizeof(swkb_counters));']
+    src += [f'printf("%zu\\n", offsetof(swkb_params, {f}));' for f in fields]
+    src += ['return 0;}']
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-o", str(exe), str(c)])
+    out = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert out[0] == C.sizeof(Params) and out[1] == C.sizeof(Counters)
+    assert out[2:] == [getattr(Params, f).offset for f in fields]
+
+
+def test_workspace_bytes_validates_arguments(lib):
+    from paper_2301_03814_amd import swkb
+    good = W.linear_caustic()
+    n = swkb.workspace_bytes(good)
+    assert n > 0
+    # grows with the precision's record size and with the problem
+    assert swkb.workspace_bytes(good, swkb.MIXED) < n
+    assert swkb.workspace_bytes(W.random_medium()) > n
+    bad = [
+        dict(n_z=100), dict(n_z=32), dict(n_modes=7), dict(n_modes=0), dict(n_modes=1024),
+        dict(rk4_steps=0), dict(ray_stride=0), dict(launch_ext_cells=-1), dict(dx=0.0),
+        dict(z_b=0.0), dict(medium_params=[1.0]), dict(medium_kind=9), dict(bc=3),
+        dict(absorber_top=60.0), dict(eps_ref=0.0), dict(n_screens=0),
+    ]
+    for kw in bad:
+        assert swkb.workspace_bytes(W.with_overrides(good, **kw)) == 0, kw
+    # mirror doubles the FFT length: n_modes may then reach 2N
+    assert swkb.workspace_bytes(W.with_overrides(good, bc=W.BC_DIRICHLET, n_modes=1024)) > 0
+    # Gaussian sum: the parameter count must match the declared count
+    gp = W.gaussian_sum_params(1, 3, (0, 100), (0, 64))
+    assert swkb.workspace_bytes(W.with_overrides(good, medium_kind=W.MEDIUM_GAUSSSUM, medium_params=gp)) > 0
+    assert swkb.workspace_bytes(W.with_overrides(good, medium_kind=W.MEDIUM_GAUSSSUM,
+                                                 medium_params=gp[:-1])) == 0
+
+
+def test_status_strings_and_missing_library(lib):
+    from paper_2301_03814_amd import swkb
+    lib.swkb_status_string.restype = C.c_char_p
+    assert lib.swkb_status_string(0) == b"ok"
+    assert b"caustic" in lib.swkb_status_string(4)
+    old = swkb._lib
+    try:
+        swkb._lib = None
+        with pytest.raises(RuntimeError):
+            swkb.load(os.path.join(ROOT, "no_such_libswkb.so"))
+    finally:
+        swkb._lib = old
+
+
+def test_plan_rejects_bad_arguments_on_host(lib):
+    from paper_2301_03814_amd import swkb
+    p = swkb.make_params(W.with_overrides(W.linear_caustic(), n_z=100))
+    h = C.c_void_p()
+    st = lib.swkb_plan(C.byref(p), C.c_void_p(256), 1 << 20, None, C.byref(h))
+    assert st == swkb.SWKB_ERR_ARG and not h.value
+    assert b"power of two" in lib.swkb_last_error()
+    p = swkb.make_params(W.linear_caustic())
+    st = lib.swkb_plan(C.byref(p), C.c_void_p(256), 16, None, C.byref(h))
+    assert st == swkb.SWKB_ERR_NOMEM
+    st = lib.swkb_plan(C.byref(p), C.c_void_p(257), 1 << 30, None, C.byref(h))
+    assert st == swkb.SWKB_ERR_ARG

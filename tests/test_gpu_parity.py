@@ -1,0 +1,242 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+FP64 runs must match the oracle to a relative L2 error of 1e-10 over all
+screens, mixed-precision runs to 1e-3.  Stage entry points are checked on
+their own (modes, ray arrivals) so that a failure names its step.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def swkb():
+    import paper_2301_03814_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def small_random(n_screens=12, n_z=1024, n_modes=256, seed=7):
+    cfg = W.random_medium(n_screens=n_screens, n_z=n_z, n_modes=n_modes, height=125.0, seed=seed,
+                          n_gauss=12, x_len=n_screens * 10.0)
+    return cfg
+
+
+def small_duct(bc=W.BC_DIRICHLET, n_screens=4):
+    return W.surface_duct(n_screens=n_screens, n_z=2048, n_modes=512, height=60.0, bc=bc, ext_m=4.0)
+
+
+CASES = {
+    "linear_caustic_N512": lambda: W.linear_caustic(),
+    "random_medium_N1024": lambda: small_random(),
+    "duct_dirichlet_N2048": lambda: small_duct(),
+    "duct_neumann_N2048": lambda: small_duct(bc=W.BC_NEUMANN),
+    "expgauss_N64_M2": lambda: W.with_overrides(
+        W.linear_caustic(n_screens=3), n_z=64, n_modes=2, medium_kind=W.MEDIUM_EXPGAUSS,
+        medium_params=[1.0, 0.05, 0.01, 32.0], launch_ext_cells=8, ray_stride=3),
+    "expgauss_N64_allmodes": lambda: W.with_overrides(
+        W.linear_caustic(n_screens=3), n_z=64, n_modes=64, medium_kind=W.MEDIUM_EXPGAUSS,
+        medium_params=[1.0, 0.05, 0.01, 32.0], launch_ext_cells=8, ray_stride=1),
+    "linear_M6_ragged": lambda: W.with_overrides(W.linear_caustic(n_screens=5), n_z=256, n_modes=6,
+                                                 ray_stride=5, launch_ext_cells=37),
+}
+
+
+@pytest.fixture(scope="module")
+def oracle_runs():
+    import oracle
+    oracle.build()
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            cfg = CASES[name]()
+            u0 = W.incident_field(cfg)
+            hist, cnt = oracle.run(cfg, u0)
+            cache[name] = (cfg, u0, hist, cnt)
+        return cache[name]
+    return get
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_propagation_matches_oracle(torch_dev, swkb, oracle_runs, name, prec):
+    torch, dev = torch_dev
+    cfg, u0, ref, cnt = oracle_runs(name)
+    say(f"[parity] {name} {prec} N={cfg['n_z']} M={cfg['n_modes']} Q={cfg['n_screens']}")
+    plan = swkb.Plan(cfg, precision=swkb.FP64 if prec == "fp64" else swkb.MIXED, device=dev)
+    hist = plan.propagate(torch.from_numpy(u0).to(dev), 0, cfg["n_screens"])
+    got = hist.cpu().numpy()
+    diag = plan.diagnostics()
+    err = rel(got, ref)
+    say(f"[parity] {name} {prec} rel_l2={err:.3e} diag={diag} oracle={cnt}")
+    assert err <= (FP64_TOL if prec == "fp64" else MIXED_TOL)
+    assert diag["screens"] == cfg["n_screens"]
+    if prec == "fp64":
+        # discrete decisions (dead / caustic rays, folded modes) agree with the oracle
+        assert diag["caustic_rays"] == cnt["caustic_rays"]
+        assert diag["dead_rays"] == cnt["dead_rays"]
+        assert diag["folded_modes"] == cnt["folded_modes"]
+        assert diag["significant"] == cnt["significant"]
+    # the last field equals the last history row
+    assert torch.equal(plan.field(), hist[-1])
+    plan.close()
+
+
+@pytest.mark.parametrize("bc", [W.BC_PERIODIC, W.BC_DIRICHLET, W.BC_NEUMANN])
+def test_stage_modes_match_oracle(torch_dev, swkb, bc):
+    import oracle
+    torch, dev = torch_dev
+    for n_z, n_modes in ((64, 2), (512, 128), (4096, 1024), (16384, 4096)):
+        cfg = W.with_overrides(W.linear_caustic(), n_z=n_z, n_modes=n_modes, bc=bc)
+        rng = np.random.default_rng(n_z)
+        u = rng.normal(size=n_z) + 1j * rng.normal(size=n_z)
+        plan = swkb.Plan(cfg, device=dev)
+        c = plan.stage_modes(torch.from_numpy(u).to(dev)).cpu().numpy()
+        ref = oracle.modes(cfg, u)
+        err = rel(c, ref)
+        say(f"[modes] bc={bc} N={n_z} M={n_modes} rel={err:.2e}")
+        assert err < 1e-13
+        plan.close()
+
+
+@pytest.mark.parametrize("name", ["linear_caustic_N512", "random_medium_N1024", "duct_dirichlet_N2048"])
+def test_stage_rays_match_oracle(torch_dev, swkb, name):
+    import oracle
+    torch, dev = torch_dev
+    cfg = CASES[name]()
+    plan = swkb.Plan(cfg, device=dev)
+    q = 1
+    rays = {k: v.cpu().numpy() for k, v in plan.stage_rays(q).items()}
+    M = cfg["n_modes"]
+    for j in sorted({0, 1, M // 4, M // 2 - 1, M // 2, M // 2 + 3, 3 * M // 4, M - 1}):
+        ref = oracle.march_mode(cfg, q, j)
+        # liveness and caustics agree exactly; "dead at launch" and "dead on the
+        # way" may trade places for a ray launched exactly at p^2 = p2_floor
+        assert np.array_equal(rays["flag"][j] == 0, ref["flag"] == 0), f"liveness differs in mode {j}"
+        assert np.array_equal(rays["flag"][j] == 3, ref["flag"] == 3), f"caustics differ in mode {j}"
+        live = ref["flag"] == 0
+        scale = max(1.0, abs(cfg["z_b"]))
+        assert np.abs(rays["Z"][j][live] - ref["Z"][live]).max(initial=0) < 1e-12 * scale
+        assert np.abs(rays["q"][j][live] - ref["q"][live]).max(initial=0) < 1e-12
+        psi_scale = max(1.0, np.abs(ref["psi"][live]).max(initial=1.0))
+        assert np.abs(rays["psi"][j][live] - ref["psi"][live]).max(initial=0) < 1e-12 * psi_scale
+        assert np.abs(rays["a"][j][live] - ref["a"][live]).max(initial=0) < 1e-11
+    say(f"[rays] {name} ok R={plan.num_rays}")
+    plan.close()
+
+
+def test_resume_and_determinism(torch_dev, swkb):
+    """Resuming from screen q equals an uninterrupted run bit for bit, and
+    two runs are bitwise identical (fixed-order reductions, no atomics on
+    the field)."""
+    torch, dev = torch_dev
+    cfg = small_random()
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    Q = cfg["n_screens"]
+    a = swkb.Plan(cfg, device=dev)
+    full = a.propagate(u0, 0, Q)
+    b = swkb.Plan(cfg, device=dev)
+    h1 = b.propagate(u0, 0, 5)
+    h2 = b.propagate(None, 5, Q)
+    assert torch.equal(torch.cat([h1, h2]), full)
+    again = a.propagate(u0, 0, Q)
+    assert torch.equal(again, full)
+    # restart from a stored screen through u_in
+    c = swkb.Plan(cfg, device=dev)
+    h3 = c.propagate(full[6].contiguous(), 7, Q)
+    assert torch.equal(h3, full[7:])
+    for p in (a, b, c):
+        p.close()
+
+
+def test_zero_screens_and_state_errors(torch_dev, swkb):
+    torch, dev = torch_dev
+    cfg = W.linear_caustic()
+    plan = swkb.Plan(cfg, device=dev)
+    with pytest.raises(swkb.SwkbError):
+        plan.field()
+    with pytest.raises(swkb.SwkbError):
+        plan.propagate(None, 0, 2)  # no field yet
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    h = plan.propagate(u0, 3, 3)
+    assert h.shape == (0, cfg["n_z"])
+    assert torch.equal(plan.field(), u0) and plan.current_screen == 3
+    with pytest.raises(swkb.SwkbError):
+        plan.propagate(u0, 0, cfg["n_screens"] + 1)
+    plan.close()
+
+
+def test_caustic_is_reported(torch_dev, swkb):
+    """A screen much wider than the caustic-free spacing makes significant
+    modes cross; the library drops those rays and reports SWKB_ERR_CAUSTIC."""
+    torch, dev = torch_dev
+    cfg = W.with_overrides(W.linear_caustic(n_screens=1), dx=300.0, rk4_steps=64, absorber_top=0.0,
+                           absorber_bot=0.0, caustic_tol=1e-3)
+    plan = swkb.Plan(cfg, device=dev)
+    plan.propagate(torch.from_numpy(W.incident_field(cfg)).to(dev), 0, 1)
+    d = plan.diagnostics()
+    assert d["significant"] > 0
+    with pytest.raises(swkb.SwkbError) as ei:
+        plan.diagnostics(raise_on_caustic=True)
+    assert ei.value.status == swkb.swkb.SWKB_ERR_CAUSTIC
+    plan.close()
+
+
+@pytest.mark.slow
+def test_random_medium_full_size_sampled_screens(torch_dev, swkb):
+    """Full random-medium workload (N = 8192, M = 2048, 400 screens) in the
+    launch configuration the benchmark times: the oracle recomputes sampled
+    screens from the GPU's own input field on that screen; the mixed run is
+    held against the FP64 run over all 400 screens."""
+    import oracle
+    torch, dev = torch_dev
+    cfg = W.random_medium()
+    u0 = W.incident_field(cfg)
+    u0_d = torch.from_numpy(u0).to(dev)
+    Q = cfg["n_screens"]
+    p64 = swkb.Plan(cfg, precision=swkb.FP64, device=dev)
+    h64 = p64.propagate(u0_d, 0, Q)
+    d64 = p64.diagnostics()
+    say(f"[full] fp64 done diag={d64}")
+    hist = h64.cpu().numpy()
+    for q in (0, 211):
+        uin = u0 if q == 0 else hist[q - 1]
+        ref, cnt = oracle.screen(cfg, q, uin)
+        err = rel(hist[q], ref)
+        say(f"[full] screen {q} fp64 vs oracle rel={err:.3e}")
+        assert err <= FP64_TOL
+    p32 = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
+    h32 = p32.propagate(u0_d, 0, Q).cpu().numpy()
+    err = rel(h32, hist)
+    say(f"[full] mixed vs fp64 over {Q} screens rel={err:.3e}")
+    assert err <= MIXED_TOL
+    assert d64["significant"] == 0
+    p64.close()
+    p32.close()

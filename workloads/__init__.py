@@ -129,7 +129,7 @@ def random_medium(n_screens=400, n_z=8192, n_modes=2048, height=1000.0, seed=230
     h = height / n_z
     ext = int(math.ceil(32.0 / h / 8.0)) * 8
     return _base(lam=1.0, z_a=0.0, z_b=height, n_z=n_z, n_modes=n_modes, x0=0.0,
-                 dx=x_len / 400.0, n_screens=n_screens, rk4_steps=8, ray_stride=8,
+                 dx=10.0, n_screens=n_screens, rk4_steps=8, ray_stride=8,
                  launch_ext_cells=ext, bc=BC_PERIODIC, absorber_bot=50.0, absorber_top=50.0,
                  medium_kind=MEDIUM_GAUSSSUM,
                  medium_params=gaussian_sum_params(seed, n_gauss, (0.0, x_len), (0.0, height)),
@@ -211,7 +211,6 @@ def serving_stream(seed=5, rate=20.0, duration=60.0):
             cfg = random_medium(n_screens=int(round(x_len / 10.0)), n_z=nz, n_modes=nz // 4,
                                 height=height, seed=int(rng.integers(1 << 31)), n_gauss=n_g,
                                 x_len=x_len)
-            cfg["dx"] = 10.0
         reqs.append((t, cfg))
     return reqs
 
