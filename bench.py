@@ -1,0 +1,214 @@
+"""Throughput of the screened-WKB screen step on one MI355X.
+
+Workload: the smooth random medium (lambda = 1; 200 seeded Gaussian index
+bumps; 1000 x 4000 wavelengths; N = 8192 grid points, M = 2048 modes,
+400 screens of width 10).  One step = one full propagation across all 400
+screens (FFT, ray march, interpolation and superposition per screen), input
+field resident on the device.  The mixed-precision path (FP32 march,
+interpolation and phase evaluation; FP64 ray-tube variations and phase
+bookkeeping) is the reported value; the plain FP64 path is timed beside it
+and the mixed result is checked against it.
+
+Prints one JSON line.  --gpus must be 1: the propagation runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "mode×point evals/s; range km/s at 1e-3 rel err vs FP64 plain; p50/p99 latency"
+
+# Algorithmic flops of the ray march (transcendentals, divisions and square
+# roots count as one flop each; a fused multiply-add as two):
+#   per RK4 stage evaluation of the ray system                      55
+#     (39 in the right-hand side, 16 in the stage/step combinations)
+#   per evaluation of eps, eps_z, eps_zz from the index deviation     9
+#   per Gaussian term inside its cutoff (distance, exp, 3 sums)      22
+FLOPS_PER_RHS = 55
+FLOPS_PER_MEDIUM = 9
+FLOPS_PER_TERM = 22
+PEAK_FP32_VECTOR = 157.3e12   # MI355X published dense FP32 vector FLOP/s
+PEAK_FP64_VECTOR = 78.6e12
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("march.hip", "medium.h"):
+        with open(os.path.join(ROOT, "paper_2301_03814_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(precision):
+    """HBM bytes per launch of the march kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "march_random_medium_N8192_pmc.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    rec = d.get(precision)
+    return None if rec is None else rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy kernel over BYTES bytes (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)  # reads and writes BYTES bytes
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 3}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the screened-WKB path is "
+              "measured on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2301_03814_amd import FP64, MIXED, Plan
+
+    cfg = W.random_medium()
+    N, M, Q = cfg["n_z"], cfg["n_modes"], cfg["n_screens"]
+    dev = torch.device("cuda:0")
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    plans = {"mixed": Plan(cfg, precision=MIXED, device=dev), "fp64": Plan(cfg, precision=FP64, device=dev)}
+    hists = {k: torch.empty((Q, N), dtype=torch.complex128, device=dev) for k in plans}
+
+    def step(name):
+        plans[name].propagate(u0, 0, Q, out=hists[name])
+
+    for _ in range(args.warmup):
+        for name in plans:
+            step(name)
+    torch.cuda.synchronize()
+
+    res = {}
+    for name, plan in plans.items():
+        plan.diagnostics()
+        base = plan.diagnostics()
+        plan.profile(True)
+        plan.profile_read()
+        lat = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            step(name)
+            e1.record()
+            lat.append((e0, e1))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = plan.profile_read()
+        plan.profile(False)
+        diag = plan.diagnostics()
+        work = {k: diag[k] - base[k] for k in ("rhs_evals", "medium_evals", "medium_terms", "screens")}
+        res[name] = dict(seconds=t1 - t0, prof=prof, work=work, diag=diag,
+                         lat_ms=sorted(a.elapsed_time(b) for a, b in lat))
+        print(f"[bench] {name}: {1e3 * (t1 - t0) / args.steps:.1f} ms/step {prof}", file=sys.stderr, flush=True)
+
+    hm, hd = hists["mixed"].cpu().numpy(), hists["fp64"].cpu().numpy()
+    err_mixed = float(np.linalg.norm(hm - hd) / np.linalg.norm(hd))
+
+    mp_per_step = M * N * Q
+    rm = res["mixed"]
+    ms_step = 1e3 * rm["seconds"] / args.steps
+    value = mp_per_step * args.steps / rm["seconds"]
+    fp64_ms = 1e3 * res["fp64"]["seconds"] / args.steps
+
+    def roof(r, peak, prec):
+        w, p = r["work"], r["prof"]
+        flops = FLOPS_PER_RHS * w["rhs_evals"] + FLOPS_PER_MEDIUM * w["medium_evals"] + \
+            FLOPS_PER_TERM * w["medium_terms"]
+        launches = max(1, p["march_launches"])
+        avg_s = p["march_ms"] * 1e-3 / launches
+        per_launch = flops / launches
+        achieved = per_launch / avg_s / 1e12
+        t = traffic_from_profiles(prec)
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
+                "frac": round(achieved * 1e12 / peak, 4), "traffic": t,
+                "kernel": f"march_kernel<{'float' if prec == 'mixed' else 'double'}>",
+                "flops_per_launch": per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
+
+    roof_m = roof(rm, PEAK_FP32_VECTOR, "mixed")
+    roof_d = roof(res["fp64"], PEAK_FP64_VECTOR, "fp64")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        threads = oracle.max_threads()
+        samples = (0, Q // 2)
+        t0 = time.perf_counter()
+        errs = []
+        for q in samples:
+            uin = W.incident_field(cfg) if q == 0 else hd[q - 1]
+            ref, _ = oracle.screen(cfg, q, uin)
+            errs.append(float(np.linalg.norm(hd[q] - ref) / np.linalg.norm(ref)))
+        tc = time.perf_counter() - t0
+        cpu = {"value": M * N * len(samples) / tc, "unit": "mode-point evals/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"screens {list(samples)} of the same workload (FP64 oracle, OpenMP over modes, "
+                         f"{threads} threads), each started from the GPU FP64 field on that screen",
+               "seconds": round(tc, 2), "fp64_gpu_vs_oracle_rel_l2_max": max(errs)}
+
+    p50 = float(np.percentile(rm["lat_ms"], 50))
+    p99 = float(np.percentile(rm["lat_ms"], 99))
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "mode-point evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "random_medium: lambda=1, 200 Gaussian index bumps (seed 2301), 1000x4000 "
+                               "wavelengths, N_z=8192, 2048 modes, 400 screens of 10, RK4 S=8, ray stride 8",
+                   "n_z": N, "n_modes": M, "n_screens": Q, "rays_per_mode": plans["mixed"].num_rays,
+                   "precision": "mixed (FP32 march/interp/sincos, FP64 ray-tube and phase bookkeeping)"},
+        "range_wavelengths_per_s": 4000.0 * args.steps / rm["seconds"],
+        "rel_err_mixed_vs_fp64": err_mixed,
+        "latency_ms_p50": p50,
+        "latency_ms_p99": p99,
+        "fp64": {"value": mp_per_step * args.steps / res["fp64"]["seconds"], "ms_per_step": fp64_ms,
+                 "roofline": roof_d},
+        "speedup_mixed_vs_fp64": fp64_ms / ms_step,
+        "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in rm["prof"].items() if k.endswith("_ms")},
+        "roofline": roof_m,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    for p in plans.values():
+        p.close()
+
+
+if __name__ == "__main__":
+    main()

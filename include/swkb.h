@@ -94,7 +94,18 @@ typedef struct swkb_counters {
   int64_t folded_modes; /* modes whose live arrivals were not increasing in z (dropped) */
   int64_t significant;  /* caustic or folded modes with |c_n| > caustic_tol max|c|     */
   int64_t screens;      /* screen steps executed                                         */
+  /* work of the method, per screen step summed (for throughput accounting):          */
+  int64_t rhs_evals;    /* RK4 stage evaluations of the ray system by live rays          */
+  int64_t medium_evals; /* evaluations of eps, eps_z, eps_zz (stages, launch, arrival)   */
+  int64_t medium_terms; /* Gaussian terms inside their cutoff evaluated (GAUSSSUM)        */
 } swkb_counters;
+
+/* Device time per kernel class, from HIP events recorded on the launch
+ * stream around each kernel while profiling is enabled. */
+typedef struct swkb_timing {
+  double march_ms, scan_ms, fft_ms, superpose_ms;
+  int64_t march_launches, scan_launches, fft_launches, superpose_launches;
+} swkb_timing;
 
 typedef struct swkb_plan_s* swkb_plan_t;
 
@@ -132,6 +143,14 @@ int32_t swkb_current_screen(swkb_plan_t plan);
 /* Synchronises hip_stream, copies the counters to *out (host) and returns
  * SWKB_ERR_CAUSTIC if out->significant > 0, else SWKB_OK. */
 swkb_status swkb_diagnostics(swkb_plan_t plan, void* hip_stream, swkb_counters* out);
+
+/* Enable (1) or disable (0) event timing of every kernel the plan launches.
+ * Host only; events are recorded on the stream of each launch. */
+swkb_status swkb_profile(swkb_plan_t plan, int32_t enable);
+
+/* Synchronises hip_stream, writes the accumulated device times to *out
+ * (host) and clears them. */
+swkb_status swkb_profile_read(swkb_plan_t plan, void* hip_stream, swkb_timing* out);
 
 /* Release the host handle (the caller frees the workspace). */
 void swkb_destroy(swkb_plan_t plan);

@@ -117,7 +117,8 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, tw, mprm, glist, u, Y, c, D, Pp, G, A, key, tstart, mflag, mcaus, mdead, counters;
+  size_t xi, pbar, e1r, frac, tw, mprm, glist, u, Y, c, D, Pp, G, A, key, tstart, mflag, mcaus, mdead, mwork,
+      wcount, counters;
   size_t total;
 };
 
@@ -149,7 +150,9 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist) {
   L.tstart = take(sizeof(int) * (size_t)g.M * (g.T + 1));
   L.mflag = take(sizeof(int) * g.M);
   L.mcaus = take(sizeof(int) * g.M);
-  L.mdead = take(sizeof(int) * ((size_t)g.M + 2 * (size_t)g.M * waves_per_mode(g)));
+  L.mdead = take(sizeof(int) * g.M);
+  L.mwork = take(sizeof(int) * 3 * (size_t)g.M);
+  L.wcount = take(sizeof(int) * kWaveCounts * (size_t)g.M * waves_per_mode(g));
   L.counters = take(sizeof(unsigned long long) * 8);
   L.total = o;
   return L;
@@ -168,6 +171,43 @@ swkb_status hip_fail(hipError_t e, const char* what) {
 }  // namespace swkb
 
 using namespace swkb;
+
+// Event timing: an event is recorded on the launch stream before and after
+// each kernel (class 0 march, 1 scan, 2 fft, 3 superposition).
+enum { kProfMarch = 0, kProfScan = 1, kProfFft = 2, kProfSuper = 3 };
+
+static int prof_mark(swkb_plan_s* pl, hipStream_t st) {
+  if (pl->ev_used == pl->ev_pool.size()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return -1;
+    pl->ev_pool.push_back(ev);
+  }
+  const int i = (int)pl->ev_used++;
+  if (hipEventRecord(pl->ev_pool[i], st) != hipSuccess) return -1;
+  return i;
+}
+
+template <typename F>
+static hipError_t timed(swkb_plan_s* pl, int cls, hipStream_t st, F&& launch) {
+  if (!pl->prof_on) return launch();
+  const int a = prof_mark(pl, st);
+  hipError_t e = launch();
+  const int b = prof_mark(pl, st);
+  if (a >= 0 && b >= 0) pl->marks.push_back({cls, a, b});
+  return e;
+}
+
+static swkb_status ensure_rays(swkb_plan_s* pl, int q, hipStream_t st) {
+  if (pl->x_invariant ? pl->march_valid_q == -2 : pl->march_valid_q == q) return SWKB_OK;
+  hipError_t e = timed(pl, kProfMarch, st, [&] { return launch_march(*pl, q, st); });
+  if (e == hipSuccess) e = timed(pl, kProfScan, st, [&] { return launch_scan(*pl, st); });
+  if (e != hipSuccess) {
+    pl->march_valid_q = -1;
+    return hip_fail(e, "ray march launch");
+  }
+  pl->march_valid_q = pl->x_invariant ? -2 : q;
+  return SWKB_OK;
+}
 
 extern "C" {
 
@@ -226,6 +266,10 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->rec.mflag = reinterpret_cast<int*>(ws + L.mflag);
     pl->rec.mcaus = reinterpret_cast<int*>(ws + L.mcaus);
     pl->rec.mdead = reinterpret_cast<int*>(ws + L.mdead);
+    pl->rec.mwork = reinterpret_cast<int*>(ws + L.mwork);
+    pl->wcount = reinterpret_cast<int*>(ws + L.wcount);
+    pl->prof_on = 0;
+    pl->ev_used = 0;
     pl->counters = reinterpret_cast<unsigned long long*>(ws + L.counters);
 
     // mode tables: xi_n = 2 pi n / (k P h); reference pbar and range phase
@@ -275,18 +319,6 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
   return SWKB_OK;
 }
 
-static swkb_status ensure_rays(swkb_plan_s* pl, int q, hipStream_t st) {
-  if (pl->x_invariant ? pl->march_valid_q == -2 : pl->march_valid_q == q) return SWKB_OK;
-  hipError_t e = launch_march(*pl, q, st);
-  if (e == hipSuccess) e = launch_scan(*pl, st);
-  if (e != hipSuccess) {
-    pl->march_valid_q = -1;
-    return hip_fail(e, "ray march launch");
-  }
-  pl->march_valid_q = pl->x_invariant ? -2 : q;
-  return SWKB_OK;
-}
-
 swkb_status swkb_propagate(swkb_plan_t pl, const void* u_in, int32_t q_begin, int32_t q_end, void* history,
                            void* hip_stream) {
   if (!pl) return fail(SWKB_ERR_ARG, "plan is NULL");
@@ -308,10 +340,10 @@ swkb_status swkb_propagate(swkb_plan_t pl, const void* u_in, int32_t q_begin, in
   for (int q = q_begin; q < q_end; ++q) {
     swkb_status s = ensure_rays(pl, q, st);
     if (s != SWKB_OK) return s;
-    hipError_t e = launch_fft_modes(*pl, src, st);
+    hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, st); });
     if (e != hipSuccess) return hip_fail(e, "fft launch");
     double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * g.N : nullptr;
-    e = launch_superpose(*pl, pl->u, hist, st);
+    e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->u, hist, st); });
     if (e != hipSuccess) return hip_fail(e, "superposition launch");
     src = pl->u;
     pl->cur_q = q + 1;
@@ -341,11 +373,51 @@ swkb_status swkb_diagnostics(swkb_plan_t pl, void* hip_stream, swkb_counters* ou
   out->folded_modes = (int64_t)h[2];
   out->significant = (int64_t)h[3];
   out->screens = (int64_t)h[4];
+  out->rhs_evals = (int64_t)h[5];
+  out->medium_evals = (int64_t)h[6];
+  out->medium_terms = (int64_t)h[7];
   if (out->significant > 0) return fail(SWKB_ERR_CAUSTIC, "a significant mode met a caustic inside a screen");
   return SWKB_OK;
 }
 
-void swkb_destroy(swkb_plan_t pl) { delete pl; }
+swkb_status swkb_profile(swkb_plan_t pl, int32_t enable) {
+  if (!pl) return fail(SWKB_ERR_ARG, "plan is NULL");
+  pl->prof_on = enable ? 1 : 0;
+  return SWKB_OK;
+}
+
+swkb_status swkb_profile_read(swkb_plan_t pl, void* hip_stream, swkb_timing* out) {
+  if (!pl || !out) return fail(SWKB_ERR_ARG, "plan or out is NULL");
+  hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "profile read");
+  double ms[4] = {0, 0, 0, 0};
+  int64_t n[4] = {0, 0, 0, 0};
+  for (const auto& mk : pl->marks) {
+    float t = 0.f;
+    e = hipEventSynchronize(pl->ev_pool[mk.b]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, pl->ev_pool[mk.a], pl->ev_pool[mk.b]);
+    if (e != hipSuccess) return hip_fail(e, "profile read");
+    ms[mk.cls] += t;
+    n[mk.cls] += 1;
+  }
+  pl->marks.clear();
+  pl->ev_used = 0;
+  out->march_ms = ms[kProfMarch];
+  out->scan_ms = ms[kProfScan];
+  out->fft_ms = ms[kProfFft];
+  out->superpose_ms = ms[kProfSuper];
+  out->march_launches = n[kProfMarch];
+  out->scan_launches = n[kProfScan];
+  out->fft_launches = n[kProfFft];
+  out->superpose_launches = n[kProfSuper];
+  return SWKB_OK;
+}
+
+void swkb_destroy(swkb_plan_t pl) {
+  if (!pl) return;
+  for (hipEvent_t ev : pl->ev_pool) (void)hipEventDestroy(ev);
+  delete pl;
+}
 
 const char* swkb_status_string(swkb_status s) {
   switch (s) {

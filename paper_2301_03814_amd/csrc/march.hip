@@ -45,9 +45,10 @@ enum { kLive = 0, kDeadLaunch = 1, kDead = 2, kCaustic = 3 };
 // Right-hand side at (x, state).  Returns kLive, kDead or kCaustic.
 template <typename T>
 __device__ inline int rhs(const DevMedium& md, const ModeC& mc, double x, double s, T dz, T dq, double Zs,
-                         double Qs, double p2_floor, Deriv<T>& d) {
+                         double Qs, double p2_floor, Deriv<T>& d, int& nterms, int& nmed) {
   if (!(Zs > 0.0)) return kCaustic;
-  const Med<T> m = medium_eval<T>(md, x, s, dz);
+  const Med<T> m = medium_eval<T>(md, x, s, dz, nterms);
+  ++nmed;
   const T xi = (T)mc.xi;
   const T q = xi + dq;
   const T p2 = (T)mc.omx2 + m.e1 - dq * (T(2) * xi + dq);
@@ -91,8 +92,10 @@ __global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, De
   T dz = T(0), dq = T(0), dps = T(0);
   double Zs = 1.0, Qs = 0.0;
   double amp = 0.0;
+  int nterms = 0, nmed = 0, nrhs = 0;
   if (active) {
-    const Med<T> m0 = medium_eval<T>(md, x_q, s, T(0));
+    const Med<T> m0 = medium_eval<T>(md, x_q, s, T(0), nterms);
+    ++nmed;
     const T p02 = (T)mc.omx2 + m0.e1;
     if (!(p02 > (T)g.p2_floor)) {
       st = kDeadLaunch;
@@ -103,17 +106,18 @@ __global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, De
       for (int i = 0; i < g.S && st == kLive; ++i) {
         const double x = x_q + i * hx;
         const T hh = (T)(0.5 * hx);
-        if ((st = rhs<T>(md, mc, x, s, dz, dq, Zs, Qs, g.p2_floor, k1))) break;
+        if ((st = rhs<T>(md, mc, x, s, dz, dq, Zs, Qs, g.p2_floor, k1, nterms, nmed))) break;
         if ((st = rhs<T>(md, mc, x + 0.5 * hx, s, dz + hh * k1.dz, dq + hh * k1.dq, Zs + 0.5 * hx * k1.Zs,
-                         Qs + 0.5 * hx * k1.Qs, g.p2_floor, k2)))
+                         Qs + 0.5 * hx * k1.Qs, g.p2_floor, k2, nterms, nmed)))
           break;
         if ((st = rhs<T>(md, mc, x + 0.5 * hx, s, dz + hh * k2.dz, dq + hh * k2.dq, Zs + 0.5 * hx * k2.Zs,
-                         Qs + 0.5 * hx * k2.Qs, g.p2_floor, k3)))
+                         Qs + 0.5 * hx * k2.Qs, g.p2_floor, k3, nterms, nmed)))
           break;
         const T hf = (T)hx;
         if ((st = rhs<T>(md, mc, x + hx, s, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hx * k3.Zs, Qs + hx * k3.Qs,
-                         g.p2_floor, k4)))
+                         g.p2_floor, k4, nterms, nmed)))
           break;
+        nrhs += 4;
         const T h6 = (T)(hx / 6.0);
         dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
         dq += h6 * (k1.dq + T(2) * k2.dq + T(2) * k3.dq + k4.dq);
@@ -126,7 +130,8 @@ __global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, De
         if (!(Zs > 0.0)) {
           st = kCaustic;
         } else {
-          const Med<T> m1 = medium_eval<T>(md, x_q + g.dx, s, dz);
+          const Med<T> m1 = medium_eval<T>(md, x_q + g.dx, s, dz, nterms);
+          ++nmed;
           const T xi = (T)mc.xi;
           const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
           if (!(p2 > (T)g.p2_floor)) st = kDead;
@@ -143,9 +148,18 @@ __global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, De
   // per-wave counts (summed per mode by the scan kernel; no atomics)
   const unsigned long long bc = __ballot(active && st == kCaustic);
   const unsigned long long bd = __ballot(active && (st == kDead || st == kDeadLaunch));
+  for (int off = 32; off > 0; off >>= 1) {
+    nrhs += __shfl_xor(nrhs, off);
+    nmed += __shfl_xor(nmed, off);
+    nterms += __shfl_xor(nterms, off);
+  }
   if (lane == 0) {
-    wcount[2 * ((size_t)j * waves_per_mode + w)] = __popcll(bc);
-    wcount[2 * ((size_t)j * waves_per_mode + w) + 1] = __popcll(bd);
+    int* wc = wcount + kWaveCounts * ((size_t)j * waves_per_mode + w);
+    wc[0] = __popcll(bc);
+    wc[1] = __popcll(bd);
+    wc[2] = nrhs;
+    wc[3] = nmed;
+    wc[4] = nterms;
   }
 }
 
@@ -207,18 +221,17 @@ __global__ void __launch_bounds__(256) scan_kernel(Geometry g, DevRecords rec, c
   }
   // counts
   if (tid < 64) {
-    int nc = 0, nd = 0;
-    for (int w = tid; w < waves_per_mode; w += 64) {
-      nc += wcount[2 * ((size_t)j * waves_per_mode + w)];
-      nd += wcount[2 * ((size_t)j * waves_per_mode + w) + 1];
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      nc += __shfl_down(nc, off);
-      nd += __shfl_down(nd, off);
-    }
+    int v[kWaveCounts] = {0, 0, 0, 0, 0};
+    for (int w = tid; w < waves_per_mode; w += 64)
+      for (int k = 0; k < kWaveCounts; ++k) v[k] += wcount[kWaveCounts * ((size_t)j * waves_per_mode + w) + k];
+    for (int off = 32; off > 0; off >>= 1)
+      for (int k = 0; k < kWaveCounts; ++k) v[k] += __shfl_down(v[k], off);
     if (tid == 0) {
-      rec.mcaus[j] = nc;
-      rec.mdead[j] = nd;
+      rec.mcaus[j] = v[0];
+      rec.mdead[j] = v[1];
+      rec.mwork[3 * j] = v[2];
+      rec.mwork[3 * j + 1] = v[3];
+      rec.mwork[3 * j + 2] = v[4];
     }
   }
   __syncthreads();
@@ -278,7 +291,7 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
   const long long waves = (long long)wpm * g.M;
   const dim3 grid((unsigned)((waves + 3) / 4));
   const double x_q = pl.p.x0 + q * pl.p.dx;
-  int* wcount = pl.rec.mdead + g.M;  // scratch after the per-mode arrays
+  int* wcount = pl.wcount;
   if (pl.precision == SWKB_FP64)
     hipLaunchKernelGGL(march_kernel<double>, grid, dim3(256), 0, st, g, medium_for(pl, q), modes_of(pl), pl.rec,
                        wcount, x_q, wpm);
@@ -291,7 +304,7 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
 hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st) {
   const Geometry& g = pl.g;
   const int wpm = waves_per_mode(g);
-  const int* wcount = pl.rec.mdead + g.M;
+  const int* wcount = pl.wcount;
   if (pl.precision == SWKB_FP64)
     hipLaunchKernelGGL(scan_kernel<double>, dim3(g.M), dim3(256), 0, st, g, pl.rec, wcount, wpm);
   else

@@ -51,8 +51,10 @@ __device__ inline T rel(double s, double zref, T dz) {
   return (T)(s - zref) + dz;
 }
 
+// nterms is incremented by the number of Gaussian terms evaluated inside
+// their cutoff (work accounting only).
 template <typename T>
-__device__ inline Med<T> medium_eval(const DevMedium& md, double x, double s, T dz) {
+__device__ inline Med<T> medium_eval(const DevMedium& md, double x, double s, T dz, int& nterms) {
   // reflection about the ground
   bool flip = false;
   if (md.mirror) {
@@ -95,6 +97,7 @@ __device__ inline Med<T> medium_eval(const DevMedium& md, double x, double s, T 
         const T r2 = ddx * ddx + ddz * ddz;
         const T s2 = sg * sg;
         if (r2 > T(64) * s2) continue;
+        ++nterms;
         const T is2 = T(1) / s2;
         const T gg = a * dev_exp<T>(-r2 * T(0.5) * is2);
         dn += gg;

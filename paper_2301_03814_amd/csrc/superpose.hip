@@ -167,38 +167,37 @@ __global__ void __launch_bounds__(1024) superpose_kernel(Geometry g, DevModes mo
   // screen diagnostics, once per screen (block 0): ray counts of the march,
   // folded modes, and caustic/folded modes whose weight exceeds the tolerance
   if (t == 0) {
-    __shared__ unsigned long long cnt[4];
+    __shared__ unsigned long long cnt[7];
     double* sm = reinterpret_cast<double*>(red);
     __syncthreads();
     double cmax = 0.0;
     for (int j = threadIdx.x; j < g.M; j += blockDim.x) cmax = fmax(cmax, hypot(c[j].x, c[j].y));
     sm[threadIdx.x] = cmax;
-    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 7) cnt[threadIdx.x] = 0;
     __syncthreads();
     for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
       if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
       __syncthreads();
     }
     cmax = sm[0];
-    unsigned long long ncaus = 0, ndead = 0, nfold = 0, nsig = 0;
+    unsigned long long v[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
       const int f = rec.mflag[j];
-      ncaus += rec.mcaus[j];
-      ndead += rec.mdead[j];
-      nfold += f & 1;
-      if (f && hypot(c[j].x, c[j].y) > ep.caustic_tol * cmax) ++nsig;
+      v[0] += rec.mcaus[j];
+      v[1] += rec.mdead[j];
+      v[2] += f & 1;
+      if (f && hypot(c[j].x, c[j].y) > ep.caustic_tol * cmax) ++v[3];
+      v[4] += (unsigned)rec.mwork[3 * j];
+      v[5] += (unsigned)rec.mwork[3 * j + 1];
+      v[6] += (unsigned)rec.mwork[3 * j + 2];
     }
-    if (ncaus) atomicAdd(&cnt[0], ncaus);
-    if (ndead) atomicAdd(&cnt[1], ndead);
-    if (nfold) atomicAdd(&cnt[2], nfold);
-    if (nsig) atomicAdd(&cnt[3], nsig);
+    for (int k = 0; k < 7; ++k)
+      if (v[k]) atomicAdd(&cnt[k], v[k]);
     __syncthreads();
     if (threadIdx.x == 0) {
-      atomicAdd(&counters[0], cnt[0]);
-      atomicAdd(&counters[1], cnt[1]);
-      atomicAdd(&counters[2], cnt[2]);
-      atomicAdd(&counters[3], cnt[3]);
+      for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], cnt[k]);
       atomicAdd(&counters[4], 1ull);
+      for (int k = 4; k < 7; ++k) atomicAdd(&counters[k + 1], cnt[k]);
     }
   }
 }

@@ -45,7 +45,12 @@ struct DevRecords {
   int* mflag;     // per mode: bit0 folded, bit1 has caustic rays
   int* mcaus;     // per mode: caustic rays this march
   int* mdead;     // per mode: dead rays this march
+  int* mwork;     // per mode: RK4 evaluations, medium evaluations, medium terms (3 ints)
 };
+
+// Per-wavefront march counts: caustic, dead, RK4 evaluations, medium
+// evaluations, medium terms.
+constexpr int kWaveCounts = 5;
 
 struct Geometry {
   int N, M, P, R, T, S, rho, E, bc, P1, P2;
@@ -70,7 +75,14 @@ struct swkb_plan_s {
   std::vector<int> goff;  // host offsets into glist per screen (n_screens + 1)
   double2 *u, *Y, *c;
   swkb::DevRecords rec;
-  unsigned long long* counters;  // caustic, dead, folded, significant, screens
+  int* wcount;                   // per-wavefront march counts [M][waves][kWaveCounts]
+  unsigned long long* counters;  // caustic, dead, folded, significant, screens, rhs, med, terms
+  // event timing
+  int prof_on;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used;
+  struct Mark { int cls, a, b; };
+  std::vector<Mark> marks;
 };
 
 namespace swkb {

@@ -22,7 +22,7 @@ MEDIUM_LINEAR, MEDIUM_EXPGAUSS, MEDIUM_GAUSSSUM, MEDIUM_MPROFILE = 0, 1, 2, 3
 
 EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", "swkb_current_screen",
            "swkb_diagnostics", "swkb_destroy", "swkb_status_string", "swkb_last_error",
-           "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays"]
+           "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays", "swkb_profile", "swkb_profile_read"]
 
 
 class Params(C.Structure):
@@ -44,7 +44,14 @@ class Params(C.Structure):
 
 class Counters(C.Structure):
     _fields_ = [("caustic_rays", C.c_int64), ("dead_rays", C.c_int64), ("folded_modes", C.c_int64),
-                ("significant", C.c_int64), ("screens", C.c_int64)]
+                ("significant", C.c_int64), ("screens", C.c_int64), ("rhs_evals", C.c_int64),
+                ("medium_evals", C.c_int64), ("medium_terms", C.c_int64)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("march_ms", C.c_double), ("scan_ms", C.c_double), ("fft_ms", C.c_double),
+                ("superpose_ms", C.c_double), ("march_launches", C.c_int64), ("scan_launches", C.c_int64),
+                ("fft_launches", C.c_int64), ("superpose_launches", C.c_int64)]
 
 
 class SwkbError(RuntimeError):
@@ -82,8 +89,10 @@ def load(path: str = LIB_PATH):
     lib.swkb_stage_rays.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     lib.swkb_num_rays.argtypes = [vp]
     lib.swkb_num_rays.restype = i32
+    lib.swkb_profile.argtypes = [vp, i32]
+    lib.swkb_profile_read.argtypes = [vp, vp, C.POINTER(Timing)]
     for name in ("swkb_plan", "swkb_propagate", "swkb_field", "swkb_diagnostics", "swkb_stage_modes",
-                 "swkb_stage_rays"):
+                 "swkb_stage_rays", "swkb_profile", "swkb_profile_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -195,6 +204,16 @@ class Plan:
         if st not in (SWKB_OK, SWKB_ERR_CAUSTIC) or (raise_on_caustic and st != SWKB_OK):
             _check(st)
         return {f: int(getattr(cnt, f)) for f, _ in Counters._fields_}
+
+    def profile(self, enable=True):
+        """Record HIP events around every kernel launch of this plan."""
+        _check(_lib.swkb_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self, stream=None):
+        """Device milliseconds and launch counts per kernel class since the last read."""
+        t = Timing()
+        _check(_lib.swkb_profile_read(self._h, _stream_handle(stream), C.byref(t)))
+        return {f: (float(getattr(t, f)) if f.endswith("_ms") else int(getattr(t, f))) for f, _ in Timing._fields_}
 
     def stage_modes(self, u, stream=None):
         import torch
