@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/swkb.h: argument validation,
 // workspace layout, plan tables and the per-screen launch sequence.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -117,12 +118,19 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, tw, mprm, glist, u, Y, c, D, Pp, G, A, key, tstart, mflag, mcaus, mdead, mwork,
-      wcount, counters;
+  size_t xi, pbar, e1r, frac, tw, mprm, glist, gstage, gterm, gczl, u, Y, c, D, Pp, G, A, key, tstart, mflag,
+      mcaus, mdead, mwork, wcount, counters;
   size_t total;
 };
 
-Layout layout(const swkb_params* p, const Geometry& g, size_t nlist) {
+// The Gaussian-sum march without a mirror reads per-screen bump tables
+// (precomputed per RK4 stage position and per wavefront reference height).
+bool gauss_fast(const swkb_params* p, const std::vector<int>& off) {
+  (void)off;
+  return p->medium_kind == SWKB_MEDIUM_GAUSSSUM && p->bc == SWKB_BC_PERIODIC;
+}
+
+Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast) {
   Layout L;
   size_t o = 0;
   auto take = [&o](size_t bytes) {
@@ -139,6 +147,10 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist) {
   L.tw = take(sizeof(double2) * g.P);
   L.mprm = take(sizeof(double) * p->n_medium_params);
   L.glist = take(sizeof(int) * (nlist ? nlist : 1));
+  const size_t nl = gfast ? nlist : 0;
+  L.gstage = take(2 * ts * nl * (size_t)(2 * g.S + 1));
+  L.gterm = take(2 * ts * nl);
+  L.gczl = take(ts * nl * (size_t)waves_per_mode(g));
   L.u = take(sizeof(double2) * g.N);
   L.Y = take(sizeof(double2) * g.P);
   L.c = take(sizeof(double2) * g.M);
@@ -216,7 +228,7 @@ size_t swkb_workspace_bytes(const swkb_params* p) {
   const Geometry g = geometry(p);
   std::vector<int> off;
   const std::vector<int> list = gauss_lists(p, &off);
-  return layout(p, g, list.size()).total;
+  return layout(p, g, list.size(), gauss_fast(p, off)).total;
 }
 
 swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_bytes, void* hip_stream,
@@ -241,7 +253,8 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->cur_q = -1;
     const Geometry& g = pl->g;
     const std::vector<int> list = gauss_lists(p, &pl->goff);
-    const Layout L = layout(p, g, list.size());
+    pl->gfast = gauss_fast(p, pl->goff) ? 1 : 0;
+    const Layout L = layout(p, g, list.size(), pl->gfast != 0);
     if (workspace_bytes < L.total) {
       delete pl;
       return fail(SWKB_ERR_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
@@ -254,6 +267,9 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->tw = reinterpret_cast<double2*>(ws + L.tw);
     pl->mprm = reinterpret_cast<double*>(ws + L.mprm);
     pl->glist = reinterpret_cast<int*>(ws + L.glist);
+    pl->gstage = ws + L.gstage;
+    pl->gterm = ws + L.gterm;
+    pl->gczl = ws + L.gczl;
     pl->u = reinterpret_cast<double2*>(ws + L.u);
     pl->Y = reinterpret_cast<double2*>(ws + L.Y);
     pl->c = reinterpret_cast<double2*>(ws + L.c);
@@ -305,6 +321,53 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     put(pl->tw, tw.data(), sizeof(double2) * g.P);
     put(pl->mprm, pl->mparams.data(), sizeof(double) * p->n_medium_params);
     put(pl->glist, list.data(), sizeof(int) * list.size());
+    // Gaussian-sum bump tables per screen and RK4 stage position
+    std::vector<double> gst64, gtm64, gcz64;
+    std::vector<float> gst32, gtm32, gcz32;
+    if (pl->gfast) {
+      const int ns = 2 * g.S + 1;
+      const double* mp = pl->mparams.data();
+      const double hx2 = 0.5 * p->dx / p->rk4_steps;
+      const double log2e = 1.4426950408889634;
+      for (int q = 0; q < p->n_screens; ++q) {
+        const int o = pl->goff[q], nl = pl->goff[q + 1] - o;
+        const double x_q = p->x0 + q * p->dx;
+        for (int k = 0; k < ns; ++k) {
+          const double x = x_q + k * hx2;
+          for (int i = 0; i < nl; ++i) {
+            const double* b = mp + 1 + 4 * list[o + i];
+            const double ddx = x - b[2], s2 = b[1] * b[1];
+            const double ax = b[0] * std::exp(-ddx * ddx / (2.0 * s2)), cut = 64.0 * s2 - ddx * ddx;
+            if (p->precision == SWKB_FP64) { gst64.push_back(ax); gst64.push_back(cut); }
+            else { gst32.push_back((float)ax); gst32.push_back((float)cut); }
+          }
+        }
+        for (int i = 0; i < nl; ++i) {
+          const double* b = mp + 1 + 4 * list[o + i];
+          const double s2 = b[1] * b[1];
+          if (p->precision == SWKB_FP64) { gtm64.push_back(-0.5 / s2); gtm64.push_back(1.0 / s2); }
+          else { gtm32.push_back((float)(-0.5 * log2e / s2)); gtm32.push_back((float)(1.0 / s2)); }
+        }
+        const int wpm = waves_per_mode(g);
+        for (int w = 0; w < wpm; ++w) {
+          const double zw = g.z_a + (double)(w * 64 * g.rho - g.E) * g.h;
+          for (int i = 0; i < nl; ++i) {
+            const double czl = mp[1 + 4 * list[o + i] + 3] - zw;
+            if (p->precision == SWKB_FP64) gcz64.push_back(czl);
+            else gcz32.push_back((float)czl);
+          }
+        }
+      }
+      if (p->precision == SWKB_FP64) {
+        put(pl->gstage, gst64.data(), sizeof(double) * gst64.size());
+        put(pl->gterm, gtm64.data(), sizeof(double) * gtm64.size());
+      } else {
+        put(pl->gstage, gst32.data(), sizeof(float) * gst32.size());
+        put(pl->gterm, gtm32.data(), sizeof(float) * gtm32.size());
+      }
+      if (p->precision == SWKB_FP64) put(pl->gczl, gcz64.data(), sizeof(double) * gcz64.size());
+      else put(pl->gczl, gcz32.data(), sizeof(float) * gcz32.size());
+    }
     if (e == hipSuccess) e = hipMemsetAsync(pl->counters, 0, sizeof(unsigned long long) * 8, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host tables go out of scope
     if (e != hipSuccess) {

@@ -42,34 +42,199 @@ struct Deriv {
 
 enum { kLive = 0, kDeadLaunch = 1, kDead = 2, kCaustic = 3 };
 
-// Right-hand side at (x, state).  Returns kLive, kDead or kCaustic.
 template <typename T>
-__device__ inline int rhs(const DevMedium& md, const ModeC& mc, double x, double s, T dz, T dq, double Zs,
-                         double Qs, double p2_floor, Deriv<T>& d, int& nterms, int& nmed) {
+__device__ inline T fast_rsqrt(T x);
+template <>
+__device__ inline double fast_rsqrt<double>(double x) { return 1.0 / sqrt(x); }
+template <>
+__device__ inline float fast_rsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+
+template <typename T>
+__device__ inline T fast_rcp(T x);
+template <>
+__device__ inline double fast_rcp<double>(double x) { return 1.0 / x; }
+template <>
+__device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Medium evaluated through the generic device function (any kind, mirror).
+template <typename T>
+struct GenericMedium {
+  DevMedium md;
+  double x_q, hx2;  // stage k sits at x_q + k * hx2
+  double s;         // launch height of this lane's ray
+  __device__ Med<T> eval(int k, T dz, int& nterms) const {
+    return medium_eval<T>(md, x_q + k * hx2, s, dz, nterms);
+  }
+};
+
+// Gaussian-sum medium from the per-screen tables (wavefront-uniform, read
+// through scalar loads): for stage k and bump i,
+//   ax = a_i exp(-(x_k - cx_i)^2 / (2 s_i^2)),  cut = 64 s_i^2 - (x_k - cx_i)^2
+// (stage[k * nl + i]); nh = -1/(2 s_i^2) (times log2 e in FP32), is2 = 1/s_i^2
+// (term[i]); czl = cz_i - z_w relative to the wavefront's reference height.
+// A bump contributes when (z - cz)^2 <= cut, i.e. inside its 8-sigma disc.
+template <typename T>
+struct T2 { T x, y; };
+
+template <typename T>
+__device__ inline T bump_exp(T arg);
+template <>
+__device__ inline double bump_exp<double>(double arg) { return exp(arg); }
+template <>
+__device__ inline float bump_exp<float>(float arg) { return __builtin_amdgcn_exp2f(arg); }
+
+template <typename T>
+struct GaussMedium {
+  const T2<T>* __restrict__ stage;
+  const T2<T>* __restrict__ term;
+  const T* __restrict__ czl;
+  int nl;
+  T zl0;  // launch height of this lane's ray relative to the wavefront reference
+  __device__ inline void bump(T z, T c, T2<T> ac, T2<T> tk, T& dn, T& nz, T& nzz, int& nterms) const {
+    const T ddz = z - c;
+    const T d2 = ddz * ddz;
+    if (d2 > ac.y) return;
+    ++nterms;
+    const T gg = ac.x * bump_exp<T>(d2 * tk.x);
+    dn += gg;
+    const T t = tk.y * gg;
+    nz -= ddz * t;
+    nzz += (d2 * tk.y - T(1)) * t;
+  }
+  __device__ Med<T> eval(int k, T dz, int& nterms) const {
+    const T z = zl0 + dz;
+    const T2<T>* __restrict__ st = stage + k * nl;
+    T dn = T(0), nz = T(0), nzz = T(0);
+    int i = 0;
+    // four bumps per iteration: their table entries are fetched together
+    for (; i + 4 <= nl; i += 4) {
+      const T c0 = czl[i], c1 = czl[i + 1], c2 = czl[i + 2], c3 = czl[i + 3];
+      const T2<T> a0 = st[i], a1 = st[i + 1], a2 = st[i + 2], a3 = st[i + 3];
+      const T2<T> t0 = term[i], t1 = term[i + 1], t2 = term[i + 2], t3 = term[i + 3];
+      this->bump(z, c0, a0, t0, dn, nz, nzz, nterms);
+      this->bump(z, c1, a1, t1, dn, nz, nzz, nterms);
+      this->bump(z, c2, a2, t2, dn, nz, nzz, nterms);
+      this->bump(z, c3, a3, t3, dn, nz, nzz, nterms);
+    }
+    for (; i < nl; ++i) this->bump(z, czl[i], st[i], term[i], dn, nz, nzz, nterms);
+    return from_index<T>(dn, nz, nzz);
+  }
+};
+
+// Right-hand side at stage k.  Returns kLive, kDead or kCaustic.
+template <typename T, typename MED>
+__device__ inline int rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, double Zs, double Qs,
+                         double p2_floor, Deriv<T>& d, int& nterms, int& nmed) {
   if (!(Zs > 0.0)) return kCaustic;
-  const Med<T> m = medium_eval<T>(md, x, s, dz, nterms);
+  const Med<T> m = med.eval(k, dz, nterms);
   ++nmed;
   const T xi = (T)mc.xi;
   const T q = xi + dq;
   const T p2 = (T)mc.omx2 + m.e1 - dq * (T(2) * xi + dq);
   if (!(p2 > (T)p2_floor)) return kDead;
-  const T p = sqrt(p2);
-  const T ip = T(1) / p;
-  const T pbar = (T)mc.pbar;
+  const T ip = fast_rsqrt<T>(p2);
+  const T p = p2 * ip;
   d.dz = q * ip;
   d.dq = T(0.5) * m.ez * ip;
-  d.dps = ((m.e1 - (T)mc.e1r) - dq * (q + xi)) / (p + pbar) + q * dq * ip;
-  // ray-tube variations in FP64
-  const double pd = (double)p, ipd = 1.0 / pd;
-  const double ip3 = ipd * ipd * ipd;
-  const double eps = 1.0 + (double)m.e1;
-  const double qe = (double)q * (double)m.ez * 0.5 * ip3;  // q eps_z / (2 p^3)
-  const double ez = (double)m.ez;
-  d.Zs = eps * ip3 * Qs - qe * Zs;
-  d.Qs = (0.5 * (double)m.ezz * ipd - 0.25 * ez * ez * ip3) * Zs + qe * Qs;
+  d.dps = ((m.e1 - (T)mc.e1r) - dq * (q + xi)) * fast_rcp<T>(p + (T)mc.pbar) + q * dq * ip;
+  // ray-tube variations: coefficients in T, the update in FP64
+  const T ip3 = ip * ip * ip;
+  const T qe = T(0.5) * q * m.ez * ip3;                          // q eps_z / (2 p^3)
+  const T c12 = (T(1) + m.e1) * ip3;                              // eps / p^3
+  const T c21 = T(0.5) * m.ezz * ip - T(0.25) * m.ez * m.ez * ip3; // eps_zz/(2p) - eps_z^2/(4p^3)
+  d.Zs = (double)c12 * Qs - (double)qe * Zs;
+  d.Qs = (double)c21 * Zs + (double)qe * Qs;
   return kLive;
 }
 
+// One wavefront lane per ray: RK4 across the screen.  Writes the arrival
+// record and returns the lane's status and work counts.
+template <typename T, typename MED>
+__device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry& g, bool active, size_t o,
+                                 DevRecords& rec, int& st, int& nterms, int& nmed, int& nrhs) {
+  T dz = T(0), dq = T(0), dps = T(0);
+  double Zs = 1.0, Qs = 0.0;
+  double amp = 0.0;
+  st = kLive;
+  if (!active) return;
+  const Med<T> m0 = med.eval(0, T(0), nterms);
+  ++nmed;
+  const T p02 = (T)mc.omx2 + m0.e1;
+  if (!(p02 > (T)g.p2_floor)) {
+    st = kDeadLaunch;
+  } else {
+    const double p0 = (double)sqrt(p02);
+    const double hx = g.dx / g.S;
+    const T hh = (T)(0.5 * hx), hf = (T)hx, h6 = (T)(hx / 6.0);
+    const double hd2 = 0.5 * hx, hd6 = hx / 6.0;
+    Deriv<T> k1, k2, k3, k4;
+    for (int i = 0; i < g.S; ++i) {
+      if ((st = rhs<T>(med, mc, 2 * i, dz, dq, Zs, Qs, g.p2_floor, k1, nterms, nmed))) break;
+      if ((st = rhs<T>(med, mc, 2 * i + 1, dz + hh * k1.dz, dq + hh * k1.dq, Zs + hd2 * k1.Zs, Qs + hd2 * k1.Qs,
+                       g.p2_floor, k2, nterms, nmed)))
+        break;
+      if ((st = rhs<T>(med, mc, 2 * i + 1, dz + hh * k2.dz, dq + hh * k2.dq, Zs + hd2 * k2.Zs, Qs + hd2 * k2.Qs,
+                       g.p2_floor, k3, nterms, nmed)))
+        break;
+      if ((st = rhs<T>(med, mc, 2 * i + 2, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hx * k3.Zs, Qs + hx * k3.Qs,
+                       g.p2_floor, k4, nterms, nmed)))
+        break;
+      nrhs += 4;
+      dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
+      dq += h6 * (k1.dq + T(2) * k2.dq + T(2) * k3.dq + k4.dq);
+      dps += h6 * (k1.dps + T(2) * k2.dps + T(2) * k3.dps + k4.dps);
+      Zs += hd6 * (k1.Zs + 2.0 * k2.Zs + 2.0 * k3.Zs + k4.Zs);
+      Qs += hd6 * (k1.Qs + 2.0 * k2.Qs + 2.0 * k3.Qs + k4.Qs);
+    }
+    if (st == kLive) {
+      if (!(Zs > 0.0)) {
+        st = kCaustic;
+      } else {
+        const Med<T> m1 = med.eval(2 * g.S, dz, nterms);
+        ++nmed;
+        const T xi = (T)mc.xi;
+        const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
+        if (!(p2 > (T)g.p2_floor)) st = kDead;
+        else amp = sqrt(p0 / ((double)sqrt(p2) * Zs));
+      }
+    }
+  }
+  static_cast<T*>(rec.D)[o] = dz;
+  static_cast<T*>(rec.Pp)[o] = dps;
+  static_cast<T*>(rec.G)[o] = dq;
+  static_cast<T*>(rec.A)[o] = st == kLive ? (T)amp : (T)(-st);
+}
+
+__device__ inline void wave_counts(int* __restrict__ wcount, size_t slot, int lane, bool active, int st, int nrhs,
+                                   int nmed, int nterms) {
+  const unsigned long long bc = __ballot(active && st == kCaustic);
+  const unsigned long long bd = __ballot(active && (st == kDead || st == kDeadLaunch));
+  for (int off = 32; off > 0; off >>= 1) {
+    nrhs += __shfl_xor(nrhs, off);
+    nmed += __shfl_xor(nmed, off);
+    nterms += __shfl_xor(nterms, off);
+  }
+  if (lane == 0) {
+    int* wc = wcount + kWaveCounts * slot;
+    wc[0] = __popcll(bc);
+    wc[1] = __popcll(bd);
+    wc[2] = nrhs;
+    wc[3] = nmed;
+    wc[4] = nterms;
+  }
+}
+
+__device__ inline ModeC load_mode(const DevModes& modes, int j) {
+  ModeC mc;
+  mc.xi = modes.xi[j];
+  mc.omx2 = 1.0 - mc.xi * mc.xi;
+  mc.pbar = modes.pbar[j];
+  mc.e1r = modes.e1r[j];
+  return mc;
+}
+
+// Any medium kind, ground mirror allowed.  Wavefront w of the grid marches
+// rays w_in_mode * 64 + lane of mode j.
 template <typename T>
 __global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, DevModes modes, DevRecords rec,
                                                     int* __restrict__ wcount, double x_q, int waves_per_mode) {
@@ -80,87 +245,50 @@ __global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, De
   const int w = wave - j * waves_per_mode;
   const int r = w * 64 + lane;
   const bool active = r < g.R;
+  const ModeC mc = load_mode(modes, j);
+  GenericMedium<T> med;
+  med.md = md;
+  med.x_q = x_q;
+  med.hx2 = 0.5 * g.dx / g.S;
+  med.s = g.z_a + (double)(r * g.rho - g.E) * g.h;
+  int st, nterms = 0, nmed = 0, nrhs = 0;
+  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, rec, st, nterms, nmed, nrhs);
+  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, nrhs, nmed, nterms);
+}
 
-  ModeC mc;
-  mc.xi = modes.xi[j];
-  mc.omx2 = 1.0 - mc.xi * mc.xi;
-  mc.pbar = modes.pbar[j];
-  mc.e1r = modes.e1r[j];
+// Per-screen Gaussian tables in device memory.
+template <typename T>
+struct GaussTabs {
+  const T2<T>* stage;  // [(2S+1)][nl]
+  const T2<T>* term;   // [nl]
+  const T* czl;        // [waves_per_mode][nl]: cz_i - z_w per wavefront position w
+  int nl;
+};
 
-  const double s = g.z_a + (double)(r * g.rho - g.E) * g.h;
-  int st = kLive;
-  T dz = T(0), dq = T(0), dps = T(0);
-  double Zs = 1.0, Qs = 0.0;
-  double amp = 0.0;
-  int nterms = 0, nmed = 0, nrhs = 0;
-  if (active) {
-    const Med<T> m0 = medium_eval<T>(md, x_q, s, T(0), nterms);
-    ++nmed;
-    const T p02 = (T)mc.omx2 + m0.e1;
-    if (!(p02 > (T)g.p2_floor)) {
-      st = kDeadLaunch;
-    } else {
-      const double p0 = (double)sqrt(p02);
-      const double hx = g.dx / g.S;
-      Deriv<T> k1, k2, k3, k4;
-      for (int i = 0; i < g.S && st == kLive; ++i) {
-        const double x = x_q + i * hx;
-        const T hh = (T)(0.5 * hx);
-        if ((st = rhs<T>(md, mc, x, s, dz, dq, Zs, Qs, g.p2_floor, k1, nterms, nmed))) break;
-        if ((st = rhs<T>(md, mc, x + 0.5 * hx, s, dz + hh * k1.dz, dq + hh * k1.dq, Zs + 0.5 * hx * k1.Zs,
-                         Qs + 0.5 * hx * k1.Qs, g.p2_floor, k2, nterms, nmed)))
-          break;
-        if ((st = rhs<T>(md, mc, x + 0.5 * hx, s, dz + hh * k2.dz, dq + hh * k2.dq, Zs + 0.5 * hx * k2.Zs,
-                         Qs + 0.5 * hx * k2.Qs, g.p2_floor, k3, nterms, nmed)))
-          break;
-        const T hf = (T)hx;
-        if ((st = rhs<T>(md, mc, x + hx, s, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hx * k3.Zs, Qs + hx * k3.Qs,
-                         g.p2_floor, k4, nterms, nmed)))
-          break;
-        nrhs += 4;
-        const T h6 = (T)(hx / 6.0);
-        dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
-        dq += h6 * (k1.dq + T(2) * k2.dq + T(2) * k3.dq + k4.dq);
-        dps += h6 * (k1.dps + T(2) * k2.dps + T(2) * k3.dps + k4.dps);
-        const double hd6 = hx / 6.0;
-        Zs += hd6 * (k1.Zs + 2.0 * k2.Zs + 2.0 * k3.Zs + k4.Zs);
-        Qs += hd6 * (k1.Qs + 2.0 * k2.Qs + 2.0 * k3.Qs + k4.Qs);
-      }
-      if (st == kLive) {
-        if (!(Zs > 0.0)) {
-          st = kCaustic;
-        } else {
-          const Med<T> m1 = medium_eval<T>(md, x_q + g.dx, s, dz, nterms);
-          ++nmed;
-          const T xi = (T)mc.xi;
-          const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
-          if (!(p2 > (T)g.p2_floor)) st = kDead;
-          else amp = sqrt(p0 / ((double)sqrt(p2) * Zs));
-        }
-      }
-    }
-    const size_t o = (size_t)j * g.R + r;
-    static_cast<T*>(rec.D)[o] = dz;
-    static_cast<T*>(rec.Pp)[o] = dps;
-    static_cast<T*>(rec.G)[o] = dq;
-    static_cast<T*>(rec.A)[o] = st == kLive ? (T)amp : (T)(-st);
-  }
-  // per-wave counts (summed per mode by the scan kernel; no atomics)
-  const unsigned long long bc = __ballot(active && st == kCaustic);
-  const unsigned long long bd = __ballot(active && (st == kDead || st == kDeadLaunch));
-  for (int off = 32; off > 0; off >>= 1) {
-    nrhs += __shfl_xor(nrhs, off);
-    nmed += __shfl_xor(nmed, off);
-    nterms += __shfl_xor(nterms, off);
-  }
-  if (lane == 0) {
-    int* wc = wcount + kWaveCounts * ((size_t)j * waves_per_mode + w);
-    wc[0] = __popcll(bc);
-    wc[1] = __popcll(bd);
-    wc[2] = nrhs;
-    wc[3] = nmed;
-    wc[4] = nterms;
-  }
+// Gaussian-sum medium without a mirror.  Bump heights are relative to each
+// wavefront's first launch height z_w, so FP32 never carries an absolute
+// coordinate; all table reads are wavefront-uniform.
+template <typename T>
+__global__ void __launch_bounds__(256) march_gauss_kernel(Geometry g, GaussTabs<T> tabs, DevModes modes,
+                                                          DevRecords rec, int* __restrict__ wcount,
+                                                          int waves_per_mode) {
+  const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const int lane = threadIdx.x & 63;
+  const int j = wave / waves_per_mode;
+  if (j >= g.M) return;  // uniform per wavefront
+  const int w = wave - j * waves_per_mode;
+  const int r = w * 64 + lane;
+  const bool active = r < g.R;
+  const ModeC mc = load_mode(modes, j);
+  GaussMedium<T> med;
+  med.stage = tabs.stage;
+  med.term = tabs.term;
+  med.czl = tabs.czl + (size_t)w * tabs.nl;
+  med.nl = tabs.nl;
+  med.zl0 = (T)((double)(lane * g.rho) * g.h);
+  int st, nterms = 0, nmed = 0, nrhs = 0;
+  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, rec, st, nterms, nmed, nrhs);
+  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, nrhs, nmed, nterms);
 }
 
 // One workgroup per mode: running maximum of live arrivals (search keys),
@@ -292,6 +420,25 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
   const dim3 grid((unsigned)((waves + 3) / 4));
   const double x_q = pl.p.x0 + q * pl.p.dx;
   int* wcount = pl.wcount;
+  if (pl.gfast) {
+    const int nl = pl.goff[q + 1] - pl.goff[q];
+    const size_t off = (size_t)pl.goff[q];
+    const size_t nst = (size_t)(2 * g.S + 1);
+    if (pl.precision == SWKB_FP64) {
+      GaussTabs<double> t{reinterpret_cast<const T2<double>*>(pl.gstage) + off * nst,
+                          reinterpret_cast<const T2<double>*>(pl.gterm) + off,
+                          static_cast<const double*>(pl.gczl) + off * wpm, nl};
+      hipLaunchKernelGGL(march_gauss_kernel<double>, grid, dim3(256), 0, st, g, t, modes_of(pl), pl.rec, wcount,
+                         wpm);
+    } else {
+      GaussTabs<float> t{reinterpret_cast<const T2<float>*>(pl.gstage) + off * nst,
+                         reinterpret_cast<const T2<float>*>(pl.gterm) + off,
+                         static_cast<const float*>(pl.gczl) + off * wpm, nl};
+      hipLaunchKernelGGL(march_gauss_kernel<float>, grid, dim3(256), 0, st, g, t, modes_of(pl), pl.rec, wcount,
+                         wpm);
+    }
+    return hipGetLastError();
+  }
   if (pl.precision == SWKB_FP64)
     hipLaunchKernelGGL(march_kernel<double>, grid, dim3(256), 0, st, g, medium_for(pl, q), modes_of(pl), pl.rec,
                        wcount, x_q, wpm);

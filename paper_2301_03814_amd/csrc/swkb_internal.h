@@ -73,6 +73,10 @@ struct swkb_plan_s {
   double* mprm;
   int* glist;          // concatenated per-screen Gaussian lists
   std::vector<int> goff;  // host offsets into glist per screen (n_screens + 1)
+  int gfast;           // Gaussian-sum march from per-screen LDS tables
+  void* gstage;        // per screen [(2S+1)][nl] (a e^{-dx^2/2s^2}, 64 s^2 - dx^2) pairs of T
+  void* gterm;         // per screen [nl] (-1/(2 s^2) [x log2 e in FP32], 1/s^2) pairs of T
+  void* gczl;          // per screen [waves_per_mode][nl] bump heights minus each wavefront's z_w, T
   double2 *u, *Y, *c;
   swkb::DevRecords rec;
   int* wcount;                   // per-wavefront march counts [M][waves][kWaveCounts]
