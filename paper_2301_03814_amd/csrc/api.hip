@@ -118,7 +118,7 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, tw, mprm, glist, gstage, gterm, gczl, u, Y, c, D, Pp, G, A, key, tstart, mflag,
+  size_t xi, pbar, e1r, frac, tw, mprm, glist, gstage, gterm, gczl, u, Y, c, part, D, Pp, G, A, key, tstart, mflag,
       mcaus, mdead, mwork, wcount, counters;
   size_t total;
 };
@@ -154,6 +154,7 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.u = take(sizeof(double2) * g.N);
   L.Y = take(sizeof(double2) * g.P);
   L.c = take(sizeof(double2) * g.M);
+  L.part = take(sizeof(double2) * (size_t)g.N * superpose_groups(g));
   L.D = take(ts * MR);
   L.Pp = take(ts * MR);
   L.G = take(ts * MR);
@@ -273,6 +274,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->u = reinterpret_cast<double2*>(ws + L.u);
     pl->Y = reinterpret_cast<double2*>(ws + L.Y);
     pl->c = reinterpret_cast<double2*>(ws + L.c);
+    pl->part = reinterpret_cast<double2*>(ws + L.part);
     pl->rec.D = ws + L.D;
     pl->rec.Pp = ws + L.Pp;
     pl->rec.G = ws + L.G;

@@ -42,114 +42,185 @@ __device__ inline double taper(const Geometry& g, const Epi& e, double z) {
   return w;
 }
 
+// Interval record of rays (r, r+1) in power form around Z_r:
+//   dpsi(tau) = c0 + c1 tau + c2 tau^2 + c3 tau^3   (cubic Hermite, slopes q - xi)
+//   a(tau)    = a0 + a1 tau + a2 tau^2 + a3 tau^3   (Lagrange over r-1..r+2, or linear)
+// zr = Z_r relative to the tile's first grid point; H = Z_{r+1} - Z_r, or -1
+// when ray r or r+1 is not live (no contribution).
 template <typename T>
-__global__ void __launch_bounds__(1024) superpose_kernel(Geometry g, DevModes modes, DevRecords rec,
-                                                         const double2* __restrict__ c, double2* __restrict__ out,
-                                                         double2* __restrict__ hist,
-                                                         unsigned long long* __restrict__ counters, Epi ep, int ms) {
-  extern __shared__ double2 red[];  // ms * 64
+struct alignas(16) IvRec {
+  T zr, H, c0, c1, c2, c3, a0, a1, a2, a3, pad0, pad1;
+};
+
+template <typename T>
+__device__ inline T wave_shfl(T v, int src) { return __shfl(v, src, 64); }
+
+// Grid (tiles, mode groups); block = kWaves wavefronts.  Wavefront w of
+// group gi takes modes j = gi * kWaves + w + k * (groups * kWaves).  Each block
+// writes its fixed-order partial sum for the tile to part[gi][m].
+constexpr int kWaves = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevModes modes, DevRecords rec,
+                                                                const double2* __restrict__ c,
+                                                                double2* __restrict__ part, Epi ep) {
+  extern __shared__ double2 red[];  // kWaves * 64 partial sums, then per wavefront: br[64], IvRec<T>[64]
+  const int ms = kWaves;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int t = blockIdx.x;
-  const int m = t * kTile + lane;
+  const int gi = blockIdx.y;
+  const int jstep = (int)gridDim.y * kWaves;
+  const int m0 = t * kTile;
+  const int m = m0 + lane;
   const double zm = g.z_a + (double)m * g.h;
-  const long long mp = (long long)m + ep.mprime_off;
+  char* wbase = reinterpret_cast<char*>(red + (size_t)ms * 64) + (size_t)w * (64 * sizeof(int) + 64 * sizeof(IvRec<T>));
+  int* br = reinterpret_cast<int*>(wbase);
+  IvRec<T>* iv = reinterpret_cast<IvRec<T>*>(wbase + 64 * sizeof(int));
   const double inv_lam = 1.0 / g.lam;
   const T* __restrict__ D = static_cast<const T*>(rec.D);
   const T* __restrict__ Pp = static_cast<const T*>(rec.Pp);
   const T* __restrict__ G = static_cast<const T*>(rec.G);
   const T* __restrict__ A = static_cast<const T*>(rec.A);
+  const int pmask = g.P - 1;  // P is a power of two
+  const int mp0 = m0 + ep.mprime_off;
+  const T tau_lane = (T)((double)lane * g.h);  // z_m - z_{m0}
 
-  double re = 0.0, im = 0.0;  // FP64 path accumulators
-  float ref = 0.f, imf = 0.f; // mixed path accumulators (per wavefront)
-  for (int j = w; j < g.M; j += ms) {
+  T acc_re = T(0), acc_im = T(0);
+  for (int j = gi * kWaves + w; j < g.M; j += jstep) {
     if (rec.mflag[j] & 1) continue;  // folded mode
     const int* ts = rec.tstart + (size_t)j * (g.T + 1);
-    int lo = ts[t], hi = ts[t + 1];
+    const int lo = ts[t], hi = ts[t + 1];
+    // intervals [ia, ib]; the last ray R-1 takes part as an interval that
+    // never contributes, so points above its arrival find it as their bracket
+    const int ia = lo > 0 ? lo : 0;
+    const int ib = hi < g.R - 1 ? hi : g.R - 1;
+    if (ia > ib) continue;
     const size_t base = (size_t)j * g.R;
     const double* __restrict__ key = rec.key + base;
-    while (hi > lo) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (key[mid] <= zm) lo = mid;
-      else hi = mid - 1;
-    }
-    const int r = lo;
-    if (r < 0 || r >= g.R - 1) continue;
-    const T a0 = A[base + r], a1 = A[base + r + 1];
-    if (!(a0 > T(0) && a1 > T(0))) continue;
-    const bool cubic = r >= 1 && r + 2 < g.R && A[base + r - 1] > T(0) && A[base + r + 2] > T(0);
-    const long long n = (long long)j - (g.M >> 1);
-    long long nm = (n * mp) % g.P;
-    if (nm < 0) nm += g.P;
-    if constexpr (std::is_same<T, double>::value) {
-      const double sr = g.z_a + (double)(r * g.rho - g.E) * g.h;
-      const double Z0 = sr + D[base + r];
-      const double Z1 = (g.z_a + (double)((r + 1) * g.rho - g.E) * g.h) + D[base + r + 1];
-      const double H = Z1 - Z0;
-      const double tt = (zm - Z0) / H;
-      const double t2 = tt * tt, t3 = t2 * tt;
-      const double dps = (2 * t3 - 3 * t2 + 1) * Pp[base + r] + (t3 - 2 * t2 + tt) * H * G[base + r] +
-                         (-2 * t3 + 3 * t2) * Pp[base + r + 1] + (t3 - t2) * H * G[base + r + 1];
-      double a;
-      if (cubic) {
-        const double x0 = (g.z_a + (double)((r - 1) * g.rho - g.E) * g.h) + D[base + r - 1];
-        const double x3 = (g.z_a + (double)((r + 2) * g.rho - g.E) * g.h) + D[base + r + 2];
-        const double x1 = Z0, x2 = Z1;
-        const double l0 = (zm - x1) * (zm - x2) * (zm - x3) / ((x0 - x1) * (x0 - x2) * (x0 - x3));
-        const double l1 = (zm - x0) * (zm - x2) * (zm - x3) / ((x1 - x0) * (x1 - x2) * (x1 - x3));
-        const double l2 = (zm - x0) * (zm - x1) * (zm - x3) / ((x2 - x0) * (x2 - x1) * (x2 - x3));
-        const double l3 = (zm - x0) * (zm - x1) * (zm - x2) / ((x3 - x0) * (x3 - x1) * (x3 - x2));
-        a = l0 * A[base + r - 1] + l1 * a0 + l2 * a1 + l3 * A[base + r + 2];
-      } else {
-        a = (1.0 - tt) * a0 + tt * a1;
+    const int n = j - (g.M >> 1);
+    const int nm0 = (n * mp0) & pmask;
+    const double2 cj = c[j];
+    const T fj = (T)modes.frac[j];
+    for (int a0 = ia; a0 <= ib; a0 += 61) {
+      const int b0 = a0 + 60 < ib ? a0 + 60 : ib;  // intervals [a0, b0] in this pass
+      const int rb = a0 - 1;                        // ray held by lane 0
+      const int rl = rb + lane;
+      const bool in = rl >= 0 && rl < g.R;
+      const double kl = in ? key[rl] : INFINITY;
+      const T dl = in ? D[base + rl] : T(0);
+      const T al = in ? A[base + rl] : T(-1);
+      const T pl = in ? Pp[base + rl] : T(0);
+      const T gl = in ? G[base + rl] : T(0);
+      const T dm1 = wave_shfl(dl, lane - 1), dp1 = wave_shfl(dl, lane + 1), dp2 = wave_shfl(dl, lane + 2);
+      const T am1 = wave_shfl(al, lane - 1), ap1 = wave_shfl(al, lane + 1), ap2 = wave_shfl(al, lane + 2);
+      const T pp1 = wave_shfl(pl, lane + 1), gp1 = wave_shfl(gl, lane + 1);
+      br[lane] = -1;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      if (rl >= a0 && rl <= b0) {
+        // first grid point of the tile at or above key_rl: points m >= m0 + ci have key_rl <= z_m
+        int ci;
+        if (kl == -INFINITY) {
+          ci = 0;
+        } else {
+          const double x = (kl - g.z_a) / g.h - (double)m0;
+          ci = x <= 0.0 ? 0 : (x >= 64.0 ? 64 : (int)ceil(x));
+          while (ci > 0 && g.z_a + (double)(m0 + ci - 1) * g.h >= kl) --ci;
+          while (ci < 64 && g.z_a + (double)(m0 + ci) * g.h < kl) ++ci;
+        }
+        if (ci < 64) atomicMax(&br[ci], lane);
+        IvRec<T> r;
+        const bool live = al > T(0) && ap1 > T(0);
+        if constexpr (std::is_same<T, double>::value) {
+          const double Zl = (g.z_a + (double)(rl * g.rho - g.E) * g.h) + dl;
+          const double Zn = (g.z_a + (double)((rl + 1) * g.rho - g.E) * g.h) + dp1;
+          r.zr = Zl - (g.z_a + (double)m0 * g.h);
+          r.H = Zn - Zl;
+        } else {
+          const float hf = (float)g.h;
+          r.zr = (float)(rl * g.rho - g.E - m0) * hf + dl;
+          r.H = (float)g.rho * hf + (dp1 - dl);
+        }
+        const T H = r.H;
+        const T iH = T(1) / H;
+        const T dlt = (pp1 - pl) * iH;
+        r.c0 = pl;
+        r.c1 = gl;
+        r.c2 = (T(3) * dlt - T(2) * gl - gp1) * iH;
+        r.c3 = (gl + gp1 - T(2) * dlt) * iH * iH;
+        const bool cubic = rl >= 1 && rl + 2 < g.R && am1 > T(0) && ap2 > T(0);
+        const T f01 = (ap1 - al) * iH;
+        if (cubic) {
+          // Newton form on nodes 0, H, xm (ray r-1), x3 (ray r+2), then powers of tau
+          T xm, x3;
+          if constexpr (std::is_same<T, double>::value) {
+            const double Zl = (g.z_a + (double)(rl * g.rho - g.E) * g.h) + dl;
+            xm = ((g.z_a + (double)((rl - 1) * g.rho - g.E) * g.h) + dm1) - Zl;
+            x3 = ((g.z_a + (double)((rl + 2) * g.rho - g.E) * g.h) + dp2) - Zl;
+          } else {
+            const float rh = (float)g.rho * (float)g.h;
+            xm = -rh + (dm1 - dl);
+            x3 = T(2) * rh + (dp2 - dl);
+          }
+          const T f12 = (am1 - ap1) / (xm - H);
+          const T f23 = (ap2 - am1) / (x3 - xm);
+          const T f012 = (f12 - f01) / xm;
+          const T f123 = (f23 - f12) / (x3 - H);
+          const T f0123 = (f123 - f012) / x3;
+          r.a0 = al;
+          r.a1 = f01 - H * f012 + H * xm * f0123;
+          r.a2 = f012 - (H + xm) * f0123;
+          r.a3 = f0123;
+        } else {
+          r.a0 = al;
+          r.a1 = f01;
+          r.a2 = T(0);
+          r.a3 = T(0);
+        }
+        if (!live) r.H = T(-1);
+        iv[lane] = r;
       }
-      double turns = (double)nm / (double)g.P + modes.frac[j] + dps * inv_lam;
-      turns -= floor(turns);
-      double sn, cs;
-      sincospi(2.0 * turns, &sn, &cs);
-      const double2 cj = c[j];
-      const double er = a * cs, ei = a * sn;
-      re += cj.x * er - cj.y * ei;
-      im += cj.x * ei + cj.y * er;
-    } else {
-      // heights relative to Z_r: (m - r rho + E) h - D_r, small numbers in FP32
-      const float hf = (float)g.h;
-      const float rh = (float)g.rho * hf;
-      const float d0 = D[base + r], d1 = D[base + r + 1];
-      const float zr = (float)(m - r * g.rho + g.E) * hf - d0;  // z_m - Z_r
-      const float H = rh + (d1 - d0);
-      const float tt = zr / H;
-      const float t2 = tt * tt, t3 = t2 * tt;
-      const float dps = (2.f * t3 - 3.f * t2 + 1.f) * Pp[base + r] + (t3 - 2.f * t2 + tt) * H * G[base + r] +
-                        (-2.f * t3 + 3.f * t2) * Pp[base + r + 1] + (t3 - t2) * H * G[base + r + 1];
-      float a;
-      if (cubic) {
-        const float x0 = -rh + (D[base + r - 1] - d0);
-        const float x1 = 0.f, x2 = H;
-        const float x3 = 2.f * rh + (D[base + r + 2] - d0);
-        const float l0 = (zr - x1) * (zr - x2) * (zr - x3) / ((x0 - x1) * (x0 - x2) * (x0 - x3));
-        const float l1 = (zr - x0) * (zr - x2) * (zr - x3) / ((x1 - x0) * (x1 - x2) * (x1 - x3));
-        const float l2 = (zr - x0) * (zr - x1) * (zr - x3) / ((x2 - x0) * (x2 - x1) * (x2 - x3));
-        const float l3 = (zr - x0) * (zr - x1) * (zr - x2) / ((x3 - x0) * (x3 - x1) * (x3 - x2));
-        a = l0 * (float)A[base + r - 1] + l1 * (float)a0 + l2 * (float)a1 + l3 * (float)A[base + r + 2];
-      } else {
-        a = (1.f - tt) * (float)a0 + tt * (float)a1;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // bracket of this lane's point: largest interval lane whose key <= z_m
+      int lb = br[lane];
+      for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(lb, off, 64);
+        if (lane >= off && u > lb) lb = u;
       }
-      float turns = (float)nm / (float)g.P + (float)modes.frac[j] + dps * (float)inv_lam;
-      turns -= floorf(turns);
-      const float sn = __builtin_amdgcn_sinf(turns);  // argument in revolutions
-      const float cs = __builtin_amdgcn_cosf(turns);
-      const double2 cjd = c[j];
-      const float cr = (float)cjd.x, ci = (float)cjd.y;
-      const float er = a * cs, ei = a * sn;
-      ref += cr * er - ci * ei;
-      imf += cr * ei + ci * er;
+      bool ok = lb >= 0;
+      if (ok && b0 < ib && lb == b0 - rb) ok = zm < key[b0 + 1];  // point belongs to a later pass
+      if (ok) {
+        const IvRec<T> r = iv[lb];
+        if (r.H > T(0)) {
+          const T tau = tau_lane - r.zr;
+          const T dps = ((r.c3 * tau + r.c2) * tau + r.c1) * tau + r.c0;
+          const T a = ((r.a3 * tau + r.a2) * tau + r.a1) * tau + r.a0;
+          const int nm = (nm0 + __mul24(n, lane)) & pmask;
+          if constexpr (std::is_same<T, double>::value) {
+            double turns = (double)nm / (double)g.P + modes.frac[j] + dps * inv_lam;
+            turns -= floor(turns);
+            double sn, cs;
+            sincospi(2.0 * turns, &sn, &cs);
+            const double er = a * cs, ei = a * sn;
+            acc_re += cj.x * er - cj.y * ei;
+            acc_im += cj.x * ei + cj.y * er;
+          } else {
+            float turns = (float)nm * (1.0f / (float)g.P) + fj + dps * (float)inv_lam;
+            turns -= floorf(turns);
+            const float sn = __builtin_amdgcn_sinf(turns);  // argument in revolutions
+            const float cs = __builtin_amdgcn_cosf(turns);
+            const float cr = (float)cj.x * a, ci = (float)cj.y * a;
+            acc_re += cr * cs - ci * sn;
+            acc_im += cr * sn + ci * cs;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
   }
-  if constexpr (!std::is_same<T, double>::value) {
-    re = ref;
-    im = imf;
-  }
+  const double re = (double)acc_re, im = (double)acc_im;
   red[w * 64 + lane] = make_double2(re, im);
   __syncthreads();
   if (w == 0) {
@@ -159,17 +230,32 @@ __global__ void __launch_bounds__(1024) superpose_kernel(Geometry g, DevModes mo
       sr += v.x;
       si += v.y;
     }
-    const double wz = taper(g, ep, zm);
+    part[(size_t)gi * g.N + m] = make_double2(sr, si);
+  }
+}
+
+// Sum of the mode-group partials in a fixed order, exit taper, field and
+// history writes; block 0 also accumulates the screen's diagnostics.
+__global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords rec, const double2* __restrict__ c,
+                                                       const double2* __restrict__ part, int groups,
+                                                       double2* __restrict__ out, double2* __restrict__ hist,
+                                                       unsigned long long* __restrict__ counters, Epi ep) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < g.N) {
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < groups; ++k) {
+      const double2 v = part[(size_t)k * g.N + m];
+      sr += v.x;
+      si += v.y;
+    }
+    const double wz = taper(g, ep, g.z_a + (double)m * g.h);
     const double2 val = make_double2(wz * sr, wz * si);
     out[m] = val;
     if (hist) hist[m] = val;
   }
-  // screen diagnostics, once per screen (block 0): ray counts of the march,
-  // folded modes, and caustic/folded modes whose weight exceeds the tolerance
-  if (t == 0) {
+  if (blockIdx.x == 0) {
+    __shared__ double sm[256];
     __shared__ unsigned long long cnt[7];
-    double* sm = reinterpret_cast<double*>(red);
-    __syncthreads();
     double cmax = 0.0;
     for (int j = threadIdx.x; j < g.M; j += blockDim.x) cmax = fmax(cmax, hypot(c[j].x, c[j].y));
     sm[threadIdx.x] = cmax;
@@ -204,14 +290,15 @@ __global__ void __launch_bounds__(1024) superpose_kernel(Geometry g, DevModes mo
 
 }  // namespace
 
-// Wavefronts per workgroup (a power of two): enough workgroups x
-// wavefronts to fill 256 CUs several times over.
-int superpose_waves(const Geometry& g) {
-  int ms = 2048 / g.T;
-  if (ms < 1) ms = 1;
-  if (ms > 16) ms = 16;
-  while (ms > g.M) ms >>= 1;
-  return ms;
+// Mode groups (second grid dimension): enough workgroups to give every CU
+// several wavefronts per SIMD.
+int superpose_groups(const Geometry& g) {
+  int groups = (256 * 4 * 6) / (g.T * kWaves);
+  if (groups < 1) groups = 1;
+  const int maxg = (g.M + kWaves - 1) / kWaves;
+  if (groups > maxg) groups = maxg;
+  if (groups > 64) groups = 64;
+  return groups;
 }
 
 hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, hipStream_t st) {
@@ -221,15 +308,22 @@ hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, 
   ep.absorber_top = pl.p.absorber_top;
   ep.caustic_tol = pl.p.caustic_tol;
   ep.mprime_off = g.bc == SWKB_BC_PERIODIC ? 0 : g.N;
-  const int ms = superpose_waves(g);
+  const int groups = superpose_groups(g);
   DevModes md{pl.xi, pl.pbar, pl.e1r, pl.frac};
-  const size_t shmem = sizeof(double2) * 64 * (ms < 16 ? 16 : ms);
+  const size_t red = sizeof(double2) * 64 * kWaves;
+  const dim3 grid(g.T, groups);
   if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL(superpose_kernel<double>, dim3(g.T), dim3(64 * ms), shmem, st, g, md, pl.rec, pl.c, out,
-                       hist, pl.counters, ep, ms);
+    hipLaunchKernelGGL(superpose_kernel<double>, grid, dim3(64 * kWaves),
+                       red + kWaves * (64 * sizeof(int) + 64 * sizeof(IvRec<double>)), st, g, md, pl.rec, pl.c,
+                       pl.part, ep);
   else
-    hipLaunchKernelGGL(superpose_kernel<float>, dim3(g.T), dim3(64 * ms), shmem, st, g, md, pl.rec, pl.c, out,
-                       hist, pl.counters, ep, ms);
+    hipLaunchKernelGGL(superpose_kernel<float>, grid, dim3(64 * kWaves),
+                       red + kWaves * (64 * sizeof(int) + 64 * sizeof(IvRec<float>)), st, g, md, pl.rec, pl.c,
+                       pl.part, ep);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finalize_kernel, dim3((g.N + 255) / 256), dim3(256), 0, st, g, pl.rec, pl.c, pl.part, groups,
+                     out, hist, pl.counters, ep);
   return hipGetLastError();
 }
 

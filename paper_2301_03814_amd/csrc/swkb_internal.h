@@ -78,6 +78,7 @@ struct swkb_plan_s {
   void* gterm;         // per screen [nl] (-1/(2 s^2) [x log2 e in FP32], 1/s^2) pairs of T
   void* gczl;          // per screen [waves_per_mode][nl] bump heights minus each wavefront's z_w, T
   double2 *u, *Y, *c;
+  double2* part;                 // superposition partials [mode groups][N]
   swkb::DevRecords rec;
   int* wcount;                   // per-wavefront march counts [M][waves][kWaveCounts]
   unsigned long long* counters;  // caustic, dead, folded, significant, screens, rhs, med, terms
@@ -98,6 +99,7 @@ hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, hipStream_t
 hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st);
 hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st);
 hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, hipStream_t st);
+int superpose_groups(const Geometry& g);
 hipError_t launch_export_rays(const swkb_plan_s& pl, int q, double* Z, double* psi, double* qz,
                               double* amp, int* flag, hipStream_t st);
 
