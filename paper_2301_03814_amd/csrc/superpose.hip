@@ -55,28 +55,40 @@ struct alignas(16) IvRec {
 template <typename T>
 __device__ inline T wave_shfl(T v, int src) { return __shfl(v, src, 64); }
 
-// Grid (tiles, mode groups); block = kWaves wavefronts.  Wavefront w of
-// group gi takes modes j = gi * kWaves + w + k * (groups * kWaves).  Each block
-// writes its fixed-order partial sum for the tile to part[gi][m].
+// Grid (super-tiles, mode groups); block = kWaves wavefronts.  A super-tile
+// is kSub consecutive 64-point tiles; wavefront w of group gi takes modes
+// j = gi * kWaves + w + k * (groups * kWaves) and, per mode, builds the
+// interval records of the super-tile's rays once and evaluates them at all
+// kSub * 64 points (lane = point within each 64-point tile).  Each block
+// writes its fixed-order partial sums to part[gi][m].
 constexpr int kWaves = 4;
+constexpr int kSub = 4;
+
+template <typename T>
+__device__ inline T rcp_t(T x);
+template <>
+__device__ inline double rcp_t<double>(double x) { return 1.0 / x; }
+template <>
+__device__ inline float rcp_t<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 template <typename T>
 __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevModes modes, DevRecords rec,
                                                                 const double2* __restrict__ c,
-                                                                double2* __restrict__ part, Epi ep) {
-  extern __shared__ double2 red[];  // kWaves * 64 partial sums, then per wavefront: br[64], IvRec<T>[64]
-  const int ms = kWaves;
+                                                                double2* __restrict__ part, Epi ep, int sub) {
+  // LDS: kWaves * kSub * 64 partial sums, then per wavefront br[kSub * 64], IvRec<T>[64]
+  extern __shared__ double2 red[];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int t = blockIdx.x;
+  const int sb = blockIdx.x;
   const int gi = blockIdx.y;
   const int jstep = (int)gridDim.y * kWaves;
-  const int m0 = t * kTile;
-  const int m = m0 + lane;
-  const double zm = g.z_a + (double)m * g.h;
-  char* wbase = reinterpret_cast<char*>(red + (size_t)ms * 64) + (size_t)w * (64 * sizeof(int) + 64 * sizeof(IvRec<T>));
+  const int npts = sub * 64;
+  const int m0 = sb * npts;  // first grid point of the super-tile
+  const int t0 = sb * sub;   // its first 64-point tile
+  char* wbase = reinterpret_cast<char*>(red + (size_t)kWaves * kSub * 64) +
+                (size_t)w * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<T>));
   int* br = reinterpret_cast<int*>(wbase);
-  IvRec<T>* iv = reinterpret_cast<IvRec<T>*>(wbase + 64 * sizeof(int));
+  IvRec<T>* iv = reinterpret_cast<IvRec<T>*>(wbase + kSub * 64 * sizeof(int));
   const double inv_lam = 1.0 / g.lam;
   const T* __restrict__ D = static_cast<const T*>(rec.D);
   const T* __restrict__ Pp = static_cast<const T*>(rec.Pp);
@@ -84,13 +96,14 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
   const T* __restrict__ A = static_cast<const T*>(rec.A);
   const int pmask = g.P - 1;  // P is a power of two
   const int mp0 = m0 + ep.mprime_off;
-  const T tau_lane = (T)((double)lane * g.h);  // z_m - z_{m0}
+  const double zs0 = g.z_a + (double)m0 * g.h;
 
-  T acc_re = T(0), acc_im = T(0);
+  T acc_re[kSub], acc_im[kSub];
+  for (int u = 0; u < kSub; ++u) acc_re[u] = acc_im[u] = T(0);
   for (int j = gi * kWaves + w; j < g.M; j += jstep) {
     if (rec.mflag[j] & 1) continue;  // folded mode
     const int* ts = rec.tstart + (size_t)j * (g.T + 1);
-    const int lo = ts[t], hi = ts[t + 1];
+    const int lo = ts[t0], hi = ts[t0 + sub];
     // intervals [ia, ib]; the last ray R-1 takes part as an interval that
     // never contributes, so points above its arrival find it as their bracket
     const int ia = lo > 0 ? lo : 0;
@@ -115,34 +128,40 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
       const T dm1 = wave_shfl(dl, lane - 1), dp1 = wave_shfl(dl, lane + 1), dp2 = wave_shfl(dl, lane + 2);
       const T am1 = wave_shfl(al, lane - 1), ap1 = wave_shfl(al, lane + 1), ap2 = wave_shfl(al, lane + 2);
       const T pp1 = wave_shfl(pl, lane + 1), gp1 = wave_shfl(gl, lane + 1);
-      br[lane] = -1;
+      for (int u = 0; u < sub; ++u) br[u * 64 + lane] = -1;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       if (rl >= a0 && rl <= b0) {
-        // first grid point of the tile at or above key_rl: points m >= m0 + ci have key_rl <= z_m
+        // first point of the super-tile at or above key_rl: points m >= m0 + ci have key_rl <= z_m
         int ci;
         if (kl == -INFINITY) {
           ci = 0;
         } else {
           const double x = (kl - g.z_a) / g.h - (double)m0;
-          ci = x <= 0.0 ? 0 : (x >= 64.0 ? 64 : (int)ceil(x));
+          ci = x <= 0.0 ? 0 : (x >= (double)npts ? npts : (int)ceil(x));
           while (ci > 0 && g.z_a + (double)(m0 + ci - 1) * g.h >= kl) --ci;
-          while (ci < 64 && g.z_a + (double)(m0 + ci) * g.h < kl) ++ci;
+          while (ci < npts && g.z_a + (double)(m0 + ci) * g.h < kl) ++ci;
         }
-        if (ci < 64) atomicMax(&br[ci], lane);
+        if (ci < npts) atomicMax(&br[ci], lane);
         IvRec<T> r;
         const bool live = al > T(0) && ap1 > T(0);
+        T xm, x3;
         if constexpr (std::is_same<T, double>::value) {
           const double Zl = (g.z_a + (double)(rl * g.rho - g.E) * g.h) + dl;
           const double Zn = (g.z_a + (double)((rl + 1) * g.rho - g.E) * g.h) + dp1;
-          r.zr = Zl - (g.z_a + (double)m0 * g.h);
+          r.zr = Zl - zs0;
           r.H = Zn - Zl;
+          xm = ((g.z_a + (double)((rl - 1) * g.rho - g.E) * g.h) + dm1) - Zl;
+          x3 = ((g.z_a + (double)((rl + 2) * g.rho - g.E) * g.h) + dp2) - Zl;
         } else {
           const float hf = (float)g.h;
+          const float rh = (float)g.rho * hf;
           r.zr = (float)(rl * g.rho - g.E - m0) * hf + dl;
-          r.H = (float)g.rho * hf + (dp1 - dl);
+          r.H = rh + (dp1 - dl);
+          xm = -rh + (dm1 - dl);
+          x3 = T(2) * rh + (dp2 - dl);
         }
         const T H = r.H;
-        const T iH = T(1) / H;
+        const T iH = rcp_t<T>(H);
         const T dlt = (pp1 - pl) * iH;
         r.c0 = pl;
         r.c1 = gl;
@@ -150,29 +169,18 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
         r.c3 = (gl + gp1 - T(2) * dlt) * iH * iH;
         const bool cubic = rl >= 1 && rl + 2 < g.R && am1 > T(0) && ap2 > T(0);
         const T f01 = (ap1 - al) * iH;
+        r.a0 = al;
         if (cubic) {
           // Newton form on nodes 0, H, xm (ray r-1), x3 (ray r+2), then powers of tau
-          T xm, x3;
-          if constexpr (std::is_same<T, double>::value) {
-            const double Zl = (g.z_a + (double)(rl * g.rho - g.E) * g.h) + dl;
-            xm = ((g.z_a + (double)((rl - 1) * g.rho - g.E) * g.h) + dm1) - Zl;
-            x3 = ((g.z_a + (double)((rl + 2) * g.rho - g.E) * g.h) + dp2) - Zl;
-          } else {
-            const float rh = (float)g.rho * (float)g.h;
-            xm = -rh + (dm1 - dl);
-            x3 = T(2) * rh + (dp2 - dl);
-          }
-          const T f12 = (am1 - ap1) / (xm - H);
-          const T f23 = (ap2 - am1) / (x3 - xm);
-          const T f012 = (f12 - f01) / xm;
-          const T f123 = (f23 - f12) / (x3 - H);
-          const T f0123 = (f123 - f012) / x3;
-          r.a0 = al;
+          const T f12 = (am1 - ap1) * rcp_t<T>(xm - H);
+          const T f23 = (ap2 - am1) * rcp_t<T>(x3 - xm);
+          const T f012 = (f12 - f01) * rcp_t<T>(xm);
+          const T f123 = (f23 - f12) * rcp_t<T>(x3 - H);
+          const T f0123 = (f123 - f012) * rcp_t<T>(x3);
           r.a1 = f01 - H * f012 + H * xm * f0123;
           r.a2 = f012 - (H + xm) * f0123;
           r.a3 = f0123;
         } else {
-          r.a0 = al;
           r.a1 = f01;
           r.a2 = T(0);
           r.a3 = T(0);
@@ -182,37 +190,47 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      // bracket of this lane's point: largest interval lane whose key <= z_m
-      int lb = br[lane];
-      for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(lb, off, 64);
-        if (lane >= off && u > lb) lb = u;
-      }
-      bool ok = lb >= 0;
-      if (ok && b0 < ib && lb == b0 - rb) ok = zm < key[b0 + 1];  // point belongs to a later pass
-      if (ok) {
-        const IvRec<T> r = iv[lb];
-        if (r.H > T(0)) {
-          const T tau = tau_lane - r.zr;
-          const T dps = ((r.c3 * tau + r.c2) * tau + r.c1) * tau + r.c0;
-          const T a = ((r.a3 * tau + r.a2) * tau + r.a1) * tau + r.a0;
-          const int nm = (nm0 + __mul24(n, lane)) & pmask;
-          if constexpr (std::is_same<T, double>::value) {
-            double turns = (double)nm / (double)g.P + modes.frac[j] + dps * inv_lam;
-            turns -= floor(turns);
-            double sn, cs;
-            sincospi(2.0 * turns, &sn, &cs);
-            const double er = a * cs, ei = a * sn;
-            acc_re += cj.x * er - cj.y * ei;
-            acc_im += cj.x * ei + cj.y * er;
-          } else {
-            float turns = (float)nm * (1.0f / (float)g.P) + fj + dps * (float)inv_lam;
-            turns -= floorf(turns);
-            const float sn = __builtin_amdgcn_sinf(turns);  // argument in revolutions
-            const float cs = __builtin_amdgcn_cosf(turns);
-            const float cr = (float)cj.x * a, ci = (float)cj.y * a;
-            acc_re += cr * cs - ci * sn;
-            acc_im += cr * sn + ci * cs;
+      const bool last_pass = b0 >= ib;
+      const double knext = last_pass ? INFINITY : key[b0 + 1];
+      int carry = -1;
+      for (int u = 0; u < sub; ++u) {
+        // bracket of point m0 + 64u + lane: largest interval lane whose key <= z_m
+        int lb = br[u * 64 + lane];
+        for (int off = 1; off < 64; off <<= 1) {
+          const int v = __shfl_up(lb, off, 64);
+          if (lane >= off && v > lb) lb = v;
+        }
+        if (carry > lb) lb = carry;
+        carry = __shfl(lb, 63, 64);
+        const int pu = u * 64 + lane;
+        bool ok = lb >= 0;
+        if (ok && !last_pass && lb == b0 - rb) ok = g.z_a + (double)(m0 + pu) * g.h < knext;  // later pass
+        if (ok) {
+          const IvRec<T> r = iv[lb];
+          if (r.H > T(0)) {
+            T tau;
+            if constexpr (std::is_same<T, double>::value) tau = (double)pu * g.h - r.zr;
+            else tau = (float)pu * (float)g.h - r.zr;
+            const T dps = ((r.c3 * tau + r.c2) * tau + r.c1) * tau + r.c0;
+            const T a = ((r.a3 * tau + r.a2) * tau + r.a1) * tau + r.a0;
+            const int nm = (nm0 + __mul24(n, pu)) & pmask;
+            if constexpr (std::is_same<T, double>::value) {
+              double turns = (double)nm / (double)g.P + modes.frac[j] + dps * inv_lam;
+              turns -= floor(turns);
+              double sn, cs;
+              sincospi(2.0 * turns, &sn, &cs);
+              const double er = a * cs, ei = a * sn;
+              acc_re[u] += cj.x * er - cj.y * ei;
+              acc_im[u] += cj.x * ei + cj.y * er;
+            } else {
+              float turns = (float)nm * (1.0f / (float)g.P) + fj + dps * (float)inv_lam;
+              turns -= floorf(turns);
+              const float sn = __builtin_amdgcn_sinf(turns);  // argument in revolutions
+              const float cs = __builtin_amdgcn_cosf(turns);
+              const float cr = (float)cj.x * a, ci = (float)cj.y * a;
+              acc_re[u] += cr * cs - ci * sn;
+              acc_im[u] += cr * sn + ci * cs;
+            }
           }
         }
       }
@@ -220,17 +238,18 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
       __builtin_amdgcn_wave_barrier();
     }
   }
-  const double re = (double)acc_re, im = (double)acc_im;
-  red[w * 64 + lane] = make_double2(re, im);
+  for (int u = 0; u < kSub; ++u) red[(w * kSub + u) * 64 + lane] = make_double2((double)acc_re[u], (double)acc_im[u]);
   __syncthreads();
   if (w == 0) {
-    double sr = 0.0, si = 0.0;
-    for (int k = 0; k < ms; ++k) {
-      const double2 v = red[k * 64 + lane];
-      sr += v.x;
-      si += v.y;
+    for (int u = 0; u < sub; ++u) {
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k < kWaves; ++k) {
+        const double2 v = red[(k * kSub + u) * 64 + lane];
+        sr += v.x;
+        si += v.y;
+      }
+      part[(size_t)gi * g.N + m0 + u * 64 + lane] = make_double2(sr, si);
     }
-    part[(size_t)gi * g.N + m] = make_double2(sr, si);
   }
 }
 
@@ -292,12 +311,15 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
 
 // Mode groups (second grid dimension): enough workgroups to give every CU
 // several wavefronts per SIMD.
+int superpose_sub(const Geometry& g) { return g.T < kSub ? g.T : kSub; }
+
 int superpose_groups(const Geometry& g) {
-  int groups = (256 * 4 * 6) / (g.T * kWaves);
+  const int tiles = g.T / superpose_sub(g);
+  int groups = (256 * 4 * 6) / (tiles * kWaves);
   if (groups < 1) groups = 1;
   const int maxg = (g.M + kWaves - 1) / kWaves;
   if (groups > maxg) groups = maxg;
-  if (groups > 64) groups = 64;
+  if (groups > 128) groups = 128;
   return groups;
 }
 
@@ -308,18 +330,19 @@ hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, 
   ep.absorber_top = pl.p.absorber_top;
   ep.caustic_tol = pl.p.caustic_tol;
   ep.mprime_off = g.bc == SWKB_BC_PERIODIC ? 0 : g.N;
+  const int sub = superpose_sub(g);
   const int groups = superpose_groups(g);
   DevModes md{pl.xi, pl.pbar, pl.e1r, pl.frac};
-  const size_t red = sizeof(double2) * 64 * kWaves;
-  const dim3 grid(g.T, groups);
+  const size_t red = sizeof(double2) * 64 * kWaves * kSub;
+  const dim3 grid(g.T / sub, groups);
   if (pl.precision == SWKB_FP64)
     hipLaunchKernelGGL(superpose_kernel<double>, grid, dim3(64 * kWaves),
-                       red + kWaves * (64 * sizeof(int) + 64 * sizeof(IvRec<double>)), st, g, md, pl.rec, pl.c,
-                       pl.part, ep);
+                       red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<double>)), st, g, md, pl.rec,
+                       pl.c, pl.part, ep, sub);
   else
     hipLaunchKernelGGL(superpose_kernel<float>, grid, dim3(64 * kWaves),
-                       red + kWaves * (64 * sizeof(int) + 64 * sizeof(IvRec<float>)), st, g, md, pl.rec, pl.c,
-                       pl.part, ep);
+                       red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<float>)), st, g, md, pl.rec,
+                       pl.c, pl.part, ep, sub);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(finalize_kernel, dim3((g.N + 255) / 256), dim3(256), 0, st, g, pl.rec, pl.c, pl.part, groups,
