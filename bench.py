@@ -60,12 +60,49 @@ def traffic_from_profiles(precision):
     return None if rec is None else rec.get("hbm_bytes_per_launch")
 
 
+def bench_duct(args, torch, np, W, Plan, FP64, MIXED):
+    """Surface duct at 6 GHz (N = 16384, M = 4096, 1000 screens of 100 m,
+    Dirichlet ground mirror): an x-invariant medium, so the plan tabulates
+    the mode functions once and every screen is FFT + matrix product."""
+    cfg = W.surface_duct()
+    N, M, Q = cfg["n_z"], cfg["n_modes"], cfg["n_screens"]
+    dev = torch.device("cuda:0")
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    out = {"workload": "surface duct: lambda=0.05 m, M-profile -0.3/+0.118 M/m (corner 40 m), 0-300 m, "
+                       "N_z=16384, 4096 modes, 1000 screens of 100 m (100 km), Dirichlet ground"}
+    hist = {}
+    for name, prec in (("mixed", MIXED), ("fp64", FP64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = Plan(cfg, precision=prec, device=dev)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        h = torch.empty((Q, N), dtype=torch.complex128, device=dev)
+        plan.propagate(u0, 0, Q, out=h)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.propagate(u0, 0, Q, out=h)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        hist[name] = h[::50].cpu().numpy()
+        out[name] = {"mode_point_evals_per_s": M * N * Q / dt, "ms_per_run": 1e3 * dt,
+                     "range_km_per_s": 100.0 / dt, "plan_build_ms": 1e3 * t_plan,
+                     "uses_matrix": plan.uses_matrix}
+        plan.close()
+        del h
+    out["rel_err_mixed_vs_fp64_every_50th_screen"] = float(
+        np.linalg.norm(hist["mixed"] - hist["fp64"]) / np.linalg.norm(hist["fp64"]))
+    print(f"[bench] duct: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-duct", action="store_true", help="skip the surface-duct measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy kernel over BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -150,7 +187,7 @@ def main():
         t = traffic_from_profiles(prec)
         return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
                 "frac": round(achieved * 1e12 / peak, 4), "traffic": t,
-                "kernel": f"march_kernel<{'float' if prec == 'mixed' else 'double'}>",
+                "kernel": f"march_gauss_kernel<{'float' if prec == 'mixed' else 'double'}>",
                 "flops_per_launch": per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
 
     roof_m = roof(rm, PEAK_FP32_VECTOR, "mixed")
@@ -174,6 +211,10 @@ def main():
                "sample": f"screens {list(samples)} of the same workload (FP64 oracle, OpenMP over modes, "
                          f"{threads} threads), each started from the GPU FP64 field on that screen",
                "seconds": round(tc, 2), "fp64_gpu_vs_oracle_rel_l2_max": max(errs)}
+
+    duct = None
+    if not args.no_duct:
+        duct = bench_duct(args, torch, np, W, Plan, FP64, MIXED)
 
     p50 = float(np.percentile(rm["lat_ms"], 50))
     p99 = float(np.percentile(rm["lat_ms"], 99))
@@ -204,6 +245,7 @@ def main():
         "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in rm["prof"].items() if k.endswith("_ms")},
         "roofline": roof_m,
         "cpu_baseline": cpu,
+        "surface_duct": duct,
     }
     print(json.dumps(line))
     for p in plans.values():

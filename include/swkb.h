@@ -48,6 +48,16 @@ typedef enum swkb_status {
 } swkb_status;
 
 enum { SWKB_FP64 = 0, SWKB_MIXED = 1 };
+/* How a screen's mode functions are obtained for media that do not depend
+ * on x (LINEAR, EXPGAUSS, MPROFILE): every screen then sees the same rays,
+ * so the interpolated mode functions T[n][m] = a_n(z_m) exp(i k psi_n(z_m))
+ * (eq. ray_bundle_q_plus_1 without the amplitudes c_n) are the same on every
+ * screen and can be built once per plan. */
+enum {
+  SWKB_PROP_AUTO = 0,      /* matrix when the medium is x-invariant and T fits in 16 GiB */
+  SWKB_PROP_MATRIX = 1,    /* always build T once (SWKB_ERR_ARG for GAUSSSUM)            */
+  SWKB_PROP_RECOMPUTE = 2  /* interpolate and sum every screen                          */
+};
 enum { SWKB_BC_PERIODIC = 0, SWKB_BC_DIRICHLET = 1, SWKB_BC_NEUMANN = 2 };
 enum {
   SWKB_MEDIUM_LINEAR = 0,   /* params [eps0, g]:          eps = eps0 + g z                       */
@@ -85,6 +95,9 @@ typedef struct swkb_params {
   double eps_ref;           /* reference permittivity of the phase split (bookkeeping only) */
   double caustic_tol;       /* SWKB_ERR_CAUSTIC when a mode with |c_n| > caustic_tol max|c|
                                has a caustic (Z_s <= 0) or crossing rays in a screen          */
+  int32_t propagator;       /* SWKB_PROP_*; the matrix costs N*M*16 bytes (FP64) or N*M*8
+                               bytes (mixed) of workspace                                     */
+  int32_t reserved;         /* must be 0                                                     */
 } swkb_params;
 
 /* Device-side health counters, summed over all screens propagated so far. */
@@ -174,6 +187,9 @@ swkb_status swkb_stage_rays(swkb_plan_t plan, int32_t q, void* Z, void* psi, voi
 
 /* Rays per mode R of the plan. */
 int32_t swkb_num_rays(swkb_plan_t plan);
+
+/* 1 if the plan holds the mode-function matrix T (SWKB_PROP_*), else 0. */
+int32_t swkb_uses_matrix(swkb_plan_t plan);
 
 #ifdef __cplusplus
 }

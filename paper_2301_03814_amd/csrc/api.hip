@@ -67,7 +67,23 @@ std::string validate(const swkb_params* p) {
       if (!(p->medium_params[2 + 4 * j] > 0.0)) return "GAUSSSUM widths must be positive";
   }
   if (p->medium_kind == SWKB_MEDIUM_MPROFILE && !(p->medium_params[4] > 0.0)) return "MPROFILE w must be > 0";
+  if (p->propagator < SWKB_PROP_AUTO || p->propagator > SWKB_PROP_RECOMPUTE) return "propagator must be SWKB_PROP_*";
+  if (p->propagator == SWKB_PROP_MATRIX && p->medium_kind == SWKB_MEDIUM_GAUSSSUM)
+    return "SWKB_PROP_MATRIX needs a medium that does not depend on x";
+  if (p->reserved != 0) return "reserved must be 0";
   return "";
+}
+
+// The mode-function matrix is used for x-invariant media unless the caller
+// asks to recompute; AUTO also requires it to fit in 16 GiB.
+size_t matrix_bytes(const swkb_params* p) {
+  return (size_t)p->n_z * (size_t)p->n_modes * (p->precision == SWKB_FP64 ? sizeof(double2) : sizeof(float2));
+}
+
+bool use_matrix(const swkb_params* p) {
+  if (p->medium_kind == SWKB_MEDIUM_GAUSSSUM || p->propagator == SWKB_PROP_RECOMPUTE) return false;
+  if (p->propagator == SWKB_PROP_MATRIX) return true;
+  return matrix_bytes(p) <= ((size_t)16 << 30);
 }
 
 Geometry geometry(const swkb_params* p) {
@@ -118,7 +134,7 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, tw, mprm, glist, gstage, gterm, gczl, u, Y, c, part, D, Pp, G, A, key, tstart, mflag,
+  size_t xi, pbar, e1r, frac, tw, mprm, glist, gstage, gterm, gczl, u, Y, c, part, tmat, D, Pp, G, A, key, tstart, mflag,
       mcaus, mdead, mwork, wcount, counters;
   size_t total;
 };
@@ -155,6 +171,7 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.Y = take(sizeof(double2) * g.P);
   L.c = take(sizeof(double2) * g.M);
   L.part = take(sizeof(double2) * (size_t)g.N * superpose_groups(g));
+  L.tmat = take(use_matrix(p) ? matrix_bytes(p) : 0);
   L.D = take(ts * MR);
   L.Pp = take(ts * MR);
   L.G = take(ts * MR);
@@ -275,6 +292,8 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->Y = reinterpret_cast<double2*>(ws + L.Y);
     pl->c = reinterpret_cast<double2*>(ws + L.c);
     pl->part = reinterpret_cast<double2*>(ws + L.part);
+    pl->use_matrix = use_matrix(p) ? 1 : 0;
+    pl->tmat = ws + L.tmat;
     pl->rec.D = ws + L.D;
     pl->rec.Pp = ws + L.Pp;
     pl->rec.G = ws + L.G;
@@ -371,6 +390,13 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
       else put(pl->gczl, gcz32.data(), sizeof(float) * gcz32.size());
     }
     if (e == hipSuccess) e = hipMemsetAsync(pl->counters, 0, sizeof(unsigned long long) * 8, st);
+    if (e == hipSuccess && pl->use_matrix) {
+      // x-invariant medium: march once and tabulate the mode functions
+      e = launch_march(*pl, 0, st);
+      if (e == hipSuccess) e = launch_scan(*pl, st);
+      if (e == hipSuccess) e = launch_build_matrix(*pl, st);
+      if (e == hipSuccess) pl->march_valid_q = -2;
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host tables go out of scope
     if (e != hipSuccess) {
       delete pl;
@@ -403,12 +429,17 @@ swkb_status swkb_propagate(swkb_plan_t pl, const void* u_in, int32_t q_begin, in
     return SWKB_OK;
   }
   for (int q = q_begin; q < q_end; ++q) {
-    swkb_status s = ensure_rays(pl, q, st);
-    if (s != SWKB_OK) return s;
+    if (!pl->use_matrix) {
+      swkb_status s = ensure_rays(pl, q, st);
+      if (s != SWKB_OK) return s;
+    }
     hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, st); });
     if (e != hipSuccess) return hip_fail(e, "fft launch");
     double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * g.N : nullptr;
-    e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->u, hist, st); });
+    if (pl->use_matrix)
+      e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->u, hist, st); });
+    else
+      e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->u, hist, st); });
     if (e != hipSuccess) return hip_fail(e, "superposition launch");
     src = pl->u;
     pl->cur_q = q + 1;
@@ -521,5 +552,7 @@ swkb_status swkb_stage_rays(swkb_plan_t pl, int32_t q, void* Z, void* psi, void*
 }
 
 int32_t swkb_num_rays(swkb_plan_t pl) { return pl ? pl->g.R : 0; }
+
+int32_t swkb_uses_matrix(swkb_plan_t pl) { return pl ? pl->use_matrix : 0; }
 
 }  // extern "C"

@@ -71,10 +71,23 @@ __device__ inline double rcp_t<double>(double x) { return 1.0 / x; }
 template <>
 __device__ inline float rcp_t<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// TABLE = false: sum over modes into part[][] (one screen).
+// TABLE = true : write the mode functions T[j][m] = a e^{2 pi i turns} (zero
+//                where mode j has no bracket) for a medium that does not
+//                depend on x; c and part are not used.
 template <typename T>
+struct CplxOf;
+template <>
+struct CplxOf<double> { using type = double2; };
+template <>
+struct CplxOf<float> { using type = float2; };
+
+template <typename T, bool TABLE>
 __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevModes modes, DevRecords rec,
                                                                 const double2* __restrict__ c,
-                                                                double2* __restrict__ part, Epi ep, int sub) {
+                                                                double2* __restrict__ part,
+                                                                typename CplxOf<T>::type* __restrict__ tab, Epi ep,
+                                                                int sub) {
   // LDS: kWaves * kSub * 64 partial sums, then per wavefront br[kSub * 64], IvRec<T>[64]
   extern __shared__ double2 red[];
   const int lane = threadIdx.x & 63;
@@ -101,6 +114,14 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
   T acc_re[kSub], acc_im[kSub];
   for (int u = 0; u < kSub; ++u) acc_re[u] = acc_im[u] = T(0);
   for (int j = gi * kWaves + w; j < g.M; j += jstep) {
+    if constexpr (TABLE) {
+      for (int u = 0; u < sub; ++u) {
+        typename CplxOf<T>::type z0;
+        z0.x = T(0);
+        z0.y = T(0);
+        tab[(size_t)j * g.N + m0 + u * 64 + lane] = z0;
+      }
+    }
     if (rec.mflag[j] & 1) continue;  // folded mode
     const int* ts = rec.tstart + (size_t)j * (g.T + 1);
     const int lo = ts[t0], hi = ts[t0 + sub];
@@ -214,20 +235,24 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
             const T dps = ((r.c3 * tau + r.c2) * tau + r.c1) * tau + r.c0;
             const T a = ((r.a3 * tau + r.a2) * tau + r.a1) * tau + r.a0;
             const int nm = (nm0 + __mul24(n, pu)) & pmask;
+            T sn, cs;
             if constexpr (std::is_same<T, double>::value) {
               double turns = (double)nm / (double)g.P + modes.frac[j] + dps * inv_lam;
               turns -= floor(turns);
-              double sn, cs;
               sincospi(2.0 * turns, &sn, &cs);
-              const double er = a * cs, ei = a * sn;
-              acc_re[u] += cj.x * er - cj.y * ei;
-              acc_im[u] += cj.x * ei + cj.y * er;
             } else {
               float turns = (float)nm * (1.0f / (float)g.P) + fj + dps * (float)inv_lam;
               turns -= floorf(turns);
-              const float sn = __builtin_amdgcn_sinf(turns);  // argument in revolutions
-              const float cs = __builtin_amdgcn_cosf(turns);
-              const float cr = (float)cj.x * a, ci = (float)cj.y * a;
+              sn = __builtin_amdgcn_sinf(turns);  // argument in revolutions
+              cs = __builtin_amdgcn_cosf(turns);
+            }
+            if constexpr (TABLE) {
+              typename CplxOf<T>::type v;
+              v.x = a * cs;
+              v.y = a * sn;
+              tab[(size_t)j * g.N + m0 + pu] = v;
+            } else {
+              const T cr = (T)cj.x * a, ci = (T)cj.y * a;
               acc_re[u] += cr * cs - ci * sn;
               acc_im[u] += cr * sn + ci * cs;
             }
@@ -236,6 +261,52 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
+    }
+  }
+  if constexpr (TABLE) return;
+  for (int u = 0; u < kSub; ++u) red[(w * kSub + u) * 64 + lane] = make_double2((double)acc_re[u], (double)acc_im[u]);
+  __syncthreads();
+  if (w == 0) {
+    for (int u = 0; u < sub; ++u) {
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k < kWaves; ++k) {
+        const double2 v = red[(k * kSub + u) * 64 + lane];
+        sr += v.x;
+        si += v.y;
+      }
+      part[(size_t)gi * g.N + m0 + u * 64 + lane] = make_double2(sr, si);
+    }
+  }
+}
+
+// One screen from the mode-function matrix: part[gi][m] = sum over the
+// group's modes of c_j T[j][m], in the same grid/partial layout as the
+// superposition (a streaming read of T, coalesced along m).
+template <typename T>
+__global__ void __launch_bounds__(64 * kWaves) apply_matrix_kernel(Geometry g,
+                                                                   const typename CplxOf<T>::type* __restrict__ tab,
+                                                                   const double2* __restrict__ c,
+                                                                   double2* __restrict__ part, int sub) {
+  extern __shared__ double2 red[];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int sb = blockIdx.x;
+  const int gi = blockIdx.y;
+  const int jstep = (int)gridDim.y * kWaves;
+  const int m0 = sb * sub * 64;
+  T acc_re[kSub], acc_im[kSub];
+  for (int u = 0; u < kSub; ++u) acc_re[u] = acc_im[u] = T(0);
+#pragma unroll 2
+  for (int j = gi * kWaves + w; j < g.M; j += jstep) {
+    const double2 cj = c[j];
+    const T cr = (T)cj.x, ci = (T)cj.y;
+    const typename CplxOf<T>::type* col = tab + (size_t)j * g.N + m0 + lane;
+    for (int u = 0; u < kSub; ++u) {
+      if (u < sub) {
+        const typename CplxOf<T>::type v = col[u * 64];
+        acc_re[u] += cr * v.x - ci * v.y;
+        acc_im[u] += cr * v.y + ci * v.x;
+      }
     }
   }
   for (int u = 0; u < kSub; ++u) red[(w * kSub + u) * 64 + lane] = make_double2((double)acc_re[u], (double)acc_im[u]);
@@ -253,57 +324,68 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
   }
 }
 
-// Sum of the mode-group partials in a fixed order, exit taper, field and
-// history writes; block 0 also accumulates the screen's diagnostics.
+// Sum of the mode-group partials in a fixed order (four threads per point,
+// each over every fourth group, then combined in order), exit taper, field
+// and history writes.  The last block accumulates the screen's diagnostics.
 __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords rec, const double2* __restrict__ c,
                                                        const double2* __restrict__ part, int groups,
                                                        double2* __restrict__ out, double2* __restrict__ hist,
                                                        unsigned long long* __restrict__ counters, Epi ep) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m < g.N) {
+  if (blockIdx.x + 1 < gridDim.x) {
+    const int sub = threadIdx.x & 3;
+    const int m = blockIdx.x * 64 + (threadIdx.x >> 2);
     double sr = 0.0, si = 0.0;
-    for (int k = 0; k < groups; ++k) {
-      const double2 v = part[(size_t)k * g.N + m];
-      sr += v.x;
-      si += v.y;
+    if (m < g.N) {
+#pragma unroll 4
+      for (int k = sub; k < groups; k += 4) {
+        const double2 v = part[(size_t)k * g.N + m];
+        sr += v.x;
+        si += v.y;
+      }
     }
-    const double wz = taper(g, ep, g.z_a + (double)m * g.h);
-    const double2 val = make_double2(wz * sr, wz * si);
-    out[m] = val;
-    if (hist) hist[m] = val;
+    // combine the four partial sums in the order 0, 1, 2, 3
+    const double r1 = __shfl_down(sr, 1, 4), i1 = __shfl_down(si, 1, 4);
+    const double r2 = __shfl_down(sr, 2, 4), i2 = __shfl_down(si, 2, 4);
+    const double r3 = __shfl_down(sr, 3, 4), i3 = __shfl_down(si, 3, 4);
+    if (sub == 0 && m < g.N) {
+      const double tr = ((sr + r1) + r2) + r3, ti = ((si + i1) + i2) + i3;
+      const double wz = taper(g, ep, g.z_a + (double)m * g.h);
+      const double2 val = make_double2(wz * tr, wz * ti);
+      out[m] = val;
+      if (hist) hist[m] = val;
+    }
+    return;
   }
-  if (blockIdx.x == 0) {
-    __shared__ double sm[256];
-    __shared__ unsigned long long cnt[7];
-    double cmax = 0.0;
-    for (int j = threadIdx.x; j < g.M; j += blockDim.x) cmax = fmax(cmax, hypot(c[j].x, c[j].y));
-    sm[threadIdx.x] = cmax;
-    if (threadIdx.x < 7) cnt[threadIdx.x] = 0;
+  __shared__ double sm[256];
+  __shared__ unsigned long long cnt[7];
+  double cmax = 0.0;
+  for (int j = threadIdx.x; j < g.M; j += blockDim.x) cmax = fmax(cmax, hypot(c[j].x, c[j].y));
+  sm[threadIdx.x] = cmax;
+  if (threadIdx.x < 7) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
     __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-      __syncthreads();
-    }
-    cmax = sm[0];
-    unsigned long long v[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
-      const int f = rec.mflag[j];
-      v[0] += rec.mcaus[j];
-      v[1] += rec.mdead[j];
-      v[2] += f & 1;
-      if (f && hypot(c[j].x, c[j].y) > ep.caustic_tol * cmax) ++v[3];
-      v[4] += (unsigned)rec.mwork[3 * j];
-      v[5] += (unsigned)rec.mwork[3 * j + 1];
-      v[6] += (unsigned)rec.mwork[3 * j + 2];
-    }
-    for (int k = 0; k < 7; ++k)
-      if (v[k]) atomicAdd(&cnt[k], v[k]);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], cnt[k]);
-      atomicAdd(&counters[4], 1ull);
-      for (int k = 4; k < 7; ++k) atomicAdd(&counters[k + 1], cnt[k]);
-    }
+  }
+  cmax = sm[0];
+  unsigned long long v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
+    const int f = rec.mflag[j];
+    v[0] += rec.mcaus[j];
+    v[1] += rec.mdead[j];
+    v[2] += f & 1;
+    if (f && hypot(c[j].x, c[j].y) > ep.caustic_tol * cmax) ++v[3];
+    v[4] += (unsigned)rec.mwork[3 * j];
+    v[5] += (unsigned)rec.mwork[3 * j + 1];
+    v[6] += (unsigned)rec.mwork[3 * j + 2];
+  }
+  for (int k = 0; k < 7; ++k)
+    if (v[k]) atomicAdd(&cnt[k], v[k]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], cnt[k]);
+    atomicAdd(&counters[4], 1ull);
+    for (int k = 4; k < 7; ++k) atomicAdd(&counters[k + 1], cnt[k]);
   }
 }
 
@@ -336,16 +418,64 @@ hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, 
   const size_t red = sizeof(double2) * 64 * kWaves * kSub;
   const dim3 grid(g.T / sub, groups);
   if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL(superpose_kernel<double>, grid, dim3(64 * kWaves),
+    hipLaunchKernelGGL((superpose_kernel<double, false>), grid, dim3(64 * kWaves),
                        red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<double>)), st, g, md, pl.rec,
-                       pl.c, pl.part, ep, sub);
+                       pl.c, pl.part, nullptr, ep, sub);
   else
-    hipLaunchKernelGGL(superpose_kernel<float>, grid, dim3(64 * kWaves),
+    hipLaunchKernelGGL((superpose_kernel<float, false>), grid, dim3(64 * kWaves),
                        red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<float>)), st, g, md, pl.rec,
-                       pl.c, pl.part, ep, sub);
+                       pl.c, pl.part, nullptr, ep, sub);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(finalize_kernel, dim3((g.N + 255) / 256), dim3(256), 0, st, g, pl.rec, pl.c, pl.part, groups,
+  hipLaunchKernelGGL(finalize_kernel, dim3((g.N + 63) / 64 + 1), dim3(256), 0, st, g, pl.rec, pl.c, pl.part, groups,
+                     out, hist, pl.counters, ep);
+  return hipGetLastError();
+}
+
+static Epi epi_of(const swkb_plan_s& pl) {
+  Epi ep;
+  ep.absorber_bot = pl.p.absorber_bot;
+  ep.absorber_top = pl.p.absorber_top;
+  ep.caustic_tol = pl.p.caustic_tol;
+  ep.mprime_off = pl.g.bc == SWKB_BC_PERIODIC ? 0 : pl.g.N;
+  return ep;
+}
+
+hipError_t launch_build_matrix(const swkb_plan_s& pl, hipStream_t st) {
+  const Geometry& g = pl.g;
+  const Epi ep = epi_of(pl);
+  const int sub = superpose_sub(g);
+  const int groups = superpose_groups(g);
+  DevModes md{pl.xi, pl.pbar, pl.e1r, pl.frac};
+  const size_t red = sizeof(double2) * 64 * kWaves * kSub;
+  const dim3 grid(g.T / sub, groups);
+  if (pl.precision == SWKB_FP64)
+    hipLaunchKernelGGL((superpose_kernel<double, true>), grid, dim3(64 * kWaves),
+                       red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<double>)), st, g, md, pl.rec,
+                       pl.c, pl.part, static_cast<double2*>(pl.tmat), ep, sub);
+  else
+    hipLaunchKernelGGL((superpose_kernel<float, true>), grid, dim3(64 * kWaves),
+                       red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<float>)), st, g, md, pl.rec,
+                       pl.c, pl.part, static_cast<float2*>(pl.tmat), ep, sub);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* hist, hipStream_t st) {
+  const Geometry& g = pl.g;
+  const Epi ep = epi_of(pl);
+  const int sub = superpose_sub(g);
+  const int groups = superpose_groups(g);
+  const size_t red = sizeof(double2) * 64 * kWaves * kSub;
+  const dim3 grid(g.T / sub, groups);
+  if (pl.precision == SWKB_FP64)
+    hipLaunchKernelGGL(apply_matrix_kernel<double>, grid, dim3(64 * kWaves), red, st, g,
+                       static_cast<const double2*>(pl.tmat), pl.c, pl.part, sub);
+  else
+    hipLaunchKernelGGL(apply_matrix_kernel<float>, grid, dim3(64 * kWaves), red, st, g,
+                       static_cast<const float2*>(pl.tmat), pl.c, pl.part, sub);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finalize_kernel, dim3((g.N + 63) / 64 + 1), dim3(256), 0, st, g, pl.rec, pl.c, pl.part, groups,
                      out, hist, pl.counters, ep);
   return hipGetLastError();
 }

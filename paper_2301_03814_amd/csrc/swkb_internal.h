@@ -79,6 +79,8 @@ struct swkb_plan_s {
   void* gczl;          // per screen [waves_per_mode][nl] bump heights minus each wavefront's z_w, T
   double2 *u, *Y, *c;
   double2* part;                 // superposition partials [mode groups][N]
+  int use_matrix;                // mode functions tabulated once (x-invariant medium)
+  void* tmat;                    // T[mode][point], complex T (double2 or float2)
   swkb::DevRecords rec;
   int* wcount;                   // per-wavefront march counts [M][waves][kWaveCounts]
   unsigned long long* counters;  // caustic, dead, folded, significant, screens, rhs, med, terms
@@ -100,6 +102,8 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st);
 hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st);
 hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, hipStream_t st);
 int superpose_groups(const Geometry& g);
+hipError_t launch_build_matrix(const swkb_plan_s& pl, hipStream_t st);
+hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* hist, hipStream_t st);
 hipError_t launch_export_rays(const swkb_plan_s& pl, int q, double* Z, double* psi, double* qz,
                               double* amp, int* flag, hipStream_t st);
 

@@ -19,10 +19,12 @@ SWKB_OK, SWKB_ERR_ARG, SWKB_ERR_NOMEM, SWKB_ERR_DEVICE, SWKB_ERR_CAUSTIC, SWKB_E
 FP64, MIXED = 0, 1
 BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
 MEDIUM_LINEAR, MEDIUM_EXPGAUSS, MEDIUM_GAUSSSUM, MEDIUM_MPROFILE = 0, 1, 2, 3
+PROP_AUTO, PROP_MATRIX, PROP_RECOMPUTE = 0, 1, 2
 
 EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", "swkb_current_screen",
            "swkb_diagnostics", "swkb_destroy", "swkb_status_string", "swkb_last_error",
-           "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays", "swkb_profile", "swkb_profile_read"]
+           "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays", "swkb_profile", "swkb_profile_read",
+           "swkb_uses_matrix"]
 
 
 class Params(C.Structure):
@@ -39,6 +41,7 @@ class Params(C.Structure):
         ("medium_params", C.POINTER(C.c_double)),
         ("n_medium_params", C.c_int32), ("precision", C.c_int32),
         ("eps_ref", C.c_double), ("caustic_tol", C.c_double),
+        ("propagator", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -90,6 +93,8 @@ def load(path: str = LIB_PATH):
     lib.swkb_num_rays.argtypes = [vp]
     lib.swkb_num_rays.restype = i32
     lib.swkb_profile.argtypes = [vp, i32]
+    lib.swkb_uses_matrix.argtypes = [vp]
+    lib.swkb_uses_matrix.restype = i32
     lib.swkb_profile_read.argtypes = [vp, vp, C.POINTER(Timing)]
     for name in ("swkb_plan", "swkb_propagate", "swkb_field", "swkb_diagnostics", "swkb_stage_modes",
                  "swkb_stage_rays", "swkb_profile", "swkb_profile_read"):
@@ -113,7 +118,7 @@ def make_params(cfg, precision=FP64):
         bc=cfg["bc"], medium_kind=cfg["medium_kind"], absorber_bot=cfg["absorber_bot"],
         absorber_top=cfg["absorber_top"], medium_params=mp.ctypes.data_as(C.POINTER(C.c_double)),
         n_medium_params=mp.size, precision=int(precision), eps_ref=cfg["eps_ref"],
-        caustic_tol=cfg["caustic_tol"])
+        caustic_tol=cfg["caustic_tol"], propagator=int(cfg.get("propagator", PROP_AUTO)), reserved=0)
     p._keep = mp
     return p
 
@@ -158,6 +163,7 @@ class Plan:
         self.n_z = cfg["n_z"]
         self.n_modes = cfg["n_modes"]
         self.num_rays = int(lib.swkb_num_rays(h))
+        self.uses_matrix = bool(lib.swkb_uses_matrix(h))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -77,6 +77,14 @@ def test_workspace_bytes_validates_arguments(lib):
     assert swkb.workspace_bytes(W.with_overrides(good, medium_kind=W.MEDIUM_GAUSSSUM, medium_params=gp)) > 0
     assert swkb.workspace_bytes(W.with_overrides(good, medium_kind=W.MEDIUM_GAUSSSUM,
                                                  medium_params=gp[:-1])) == 0
+    # the mode-function matrix (N*M complex) is part of the workspace for
+    # x-invariant media unless recomputation is requested; never for GAUSSSUM
+    n_mat = swkb.workspace_bytes(W.with_overrides(good, propagator=swkb.PROP_MATRIX))
+    n_rec = swkb.workspace_bytes(W.with_overrides(good, propagator=swkb.PROP_RECOMPUTE))
+    assert n_mat - n_rec >= good["n_z"] * good["n_modes"] * 16
+    assert swkb.workspace_bytes(W.with_overrides(good, propagator=3)) == 0
+    assert swkb.workspace_bytes(W.with_overrides(good, medium_kind=W.MEDIUM_GAUSSSUM, medium_params=gp,
+                                                 propagator=swkb.PROP_MATRIX)) == 0
 
 
 def test_status_strings_and_missing_library(lib):

@@ -86,11 +86,18 @@ def oracle_runs():
 
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_propagation_matches_oracle(torch_dev, swkb, oracle_runs, name, prec):
+@pytest.mark.parametrize("prop", ["auto", "recompute"])
+def test_propagation_matches_oracle(torch_dev, swkb, oracle_runs, name, prec, prop):
+    """auto = mode-function matrix for media that do not depend on x."""
     torch, dev = torch_dev
     cfg, u0, ref, cnt = oracle_runs(name)
-    say(f"[parity] {name} {prec} N={cfg['n_z']} M={cfg['n_modes']} Q={cfg['n_screens']}")
+    if prop == "recompute":
+        if cfg["medium_kind"] == W.MEDIUM_GAUSSSUM:
+            pytest.skip("x-varying medium: always recomputed")
+        cfg = W.with_overrides(cfg, propagator=2)
+    say(f"[parity] {name} {prec} {prop} N={cfg['n_z']} M={cfg['n_modes']} Q={cfg['n_screens']}")
     plan = swkb.Plan(cfg, precision=swkb.FP64 if prec == "fp64" else swkb.MIXED, device=dev)
+    assert plan.uses_matrix == (prop == "auto" and cfg["medium_kind"] != W.MEDIUM_GAUSSSUM)
     hist = plan.propagate(torch.from_numpy(u0).to(dev), 0, cfg["n_screens"])
     got = hist.cpu().numpy()
     diag = plan.diagnostics()
@@ -239,4 +246,35 @@ def test_random_medium_full_size_sampled_screens(torch_dev, swkb):
     assert err <= MIXED_TOL
     assert d64["significant"] == 0
     p64.close()
+    p32.close()
+
+
+@pytest.mark.slow
+def test_surface_duct_full_size_sampled_screen(torch_dev, swkb):
+    """Full surface duct (N = 16384, M = 4096, 1000 screens, Dirichlet ground)
+    through the mode-function matrix: screen 500 recomputed by the oracle
+    from the GPU's field on screen 499; the mixed run held against FP64."""
+    import oracle
+    torch, dev = torch_dev
+    cfg = W.surface_duct()
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    Q = cfg["n_screens"]
+    p64 = swkb.Plan(cfg, precision=swkb.FP64, device=dev)
+    assert p64.uses_matrix
+    h64 = p64.propagate(u0, 0, Q)
+    sel = h64[::25].cpu().numpy()
+    q = 500
+    uin = h64[q - 1].cpu().numpy()
+    got = h64[q].cpu().numpy()
+    del h64
+    p64.close()
+    ref, _ = oracle.screen(cfg, q, uin)
+    err = rel(got, ref)
+    say(f"[duct] screen {q} fp64 vs oracle rel={err:.3e}")
+    assert err <= FP64_TOL
+    p32 = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
+    h32 = p32.propagate(u0, 0, Q)[::25].cpu().numpy()
+    err = rel(h32, sel)
+    say(f"[duct] mixed vs fp64 every 25th screen rel={err:.3e}")
+    assert err <= MIXED_TOL
     p32.close()

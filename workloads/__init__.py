@@ -22,6 +22,7 @@ Every workload is a plain ``dict`` whose keys mirror the fields of the
     absorber_bot/top  thickness of the cos^2 taper layers (0 = none)
     caustic_tol       a mode with caustic or crossing rays is reported as an
                       error when |c_n| > caustic_tol * max |c|
+    propagator        GPU library only: 0 auto, 1 mode-function matrix, 2 recompute
     medium_kind       MEDIUM_* below;  medium_params: float64 array
     eps_ref           reference permittivity for the phase split
     source            dict(z0, width, xi0) of the incident Gaussian beam
@@ -60,7 +61,7 @@ PRECISION_MIXED = 1
 
 def _base(lam, z_a, z_b, n_z, n_modes, x0, dx, n_screens, rk4_steps, ray_stride,
           launch_ext_cells, bc, absorber_bot, absorber_top, medium_kind,
-          medium_params, eps_ref, source, p2_floor=1e-2, caustic_tol=1e-3, name=""):
+          medium_params, eps_ref, source, p2_floor=1e-2, caustic_tol=1e-3, propagator=0, name=""):
     return dict(
         name=name,
         lam=float(lam), k=2.0 * math.pi / float(lam),
@@ -71,7 +72,8 @@ def _base(lam, z_a, z_b, n_z, n_modes, x0, dx, n_screens, rk4_steps, ray_stride,
         bc=int(bc), absorber_bot=float(absorber_bot), absorber_top=float(absorber_top),
         medium_kind=int(medium_kind),
         medium_params=np.ascontiguousarray(np.asarray(medium_params, dtype=np.float64)),
-        eps_ref=float(eps_ref), caustic_tol=float(caustic_tol), source=dict(source),
+        eps_ref=float(eps_ref), caustic_tol=float(caustic_tol), propagator=int(propagator),
+        source=dict(source),
     )
 
 
