@@ -97,7 +97,8 @@ typedef struct swkb_params {
                                has a caustic (Z_s <= 0) or crossing rays in a screen          */
   int32_t propagator;       /* SWKB_PROP_*; the matrix costs N*M*16 bytes (FP64) or N*M*8
                                bytes (mixed) of workspace                                     */
-  int32_t reserved;         /* must be 0                                                     */
+  int32_t max_batch;        /* largest number of fields swkb_propagate_batch carries at once
+                               (>= 1); workspace for the fields grows with it               */
 } swkb_params;
 
 /* Device-side health counters, summed over all screens propagated so far. */
@@ -145,6 +146,23 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
  * Asynchronous on hip_stream; caustics are reported by swkb_diagnostics. */
 swkb_status swkb_propagate(swkb_plan_t plan, const void* u_in, int32_t q_begin, int32_t q_end,
                            void* history, void* hip_stream);
+
+/* Propagate `batch` fields (several sources in the same medium) across
+ * screens q_begin .. q_end-1 together: the rays, and for an x-invariant
+ * medium the mode-function matrix, are shared, so each screen costs one
+ * march (x-varying media) plus per-field FFTs and sums; with the matrix the
+ * sums over modes of all fields form one complex matrix product (rocBLAS
+ * GEMM on the matrix cores).  Results equal `batch` separate swkb_propagate
+ * runs up to rounding.
+ *   u_in:    device complex128[batch][N], fields on screen q_begin;
+ *   history: device complex128[q_end - q_begin][batch][N] or NULL;
+ *   u_out:   device complex128[batch][N], fields on screen q_end, or NULL.
+ * 1 <= batch <= max_batch, 0 <= q_begin < q_end <= n_screens.  With
+ * max_batch > 1 the plan's single-field state (swkb_field,
+ * swkb_current_screen) is not changed; with max_batch == 1 the call uses the
+ * single-field buffer and leaves the plan without a current field. */
+swkb_status swkb_propagate_batch(swkb_plan_t plan, const void* u_in, int32_t batch, int32_t q_begin,
+                                 int32_t q_end, void* history, void* u_out, void* hip_stream);
 
 /* Copy the plan's current field (device complex128[N]) into out (device).
  * Returns SWKB_ERR_STATE before the first swkb_propagate. */

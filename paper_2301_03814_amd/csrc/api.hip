@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "swkb_internal.h"
 
 namespace swkb {
@@ -70,7 +72,7 @@ std::string validate(const swkb_params* p) {
   if (p->propagator < SWKB_PROP_AUTO || p->propagator > SWKB_PROP_RECOMPUTE) return "propagator must be SWKB_PROP_*";
   if (p->propagator == SWKB_PROP_MATRIX && p->medium_kind == SWKB_MEDIUM_GAUSSSUM)
     return "SWKB_PROP_MATRIX needs a medium that does not depend on x";
-  if (p->reserved != 0) return "reserved must be 0";
+  if (p->max_batch < 1 || p->max_batch > 4096) return "max_batch must be in [1, 4096]";
   return "";
 }
 
@@ -134,7 +136,7 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, tw, mprm, glist, gstage, gterm, gczl, u, Y, c, part, tmat, D, Pp, G, A, key, tstart, mflag,
+  size_t xi, pbar, e1r, frac, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, part, tmat, D, Pp, G, A, key, tstart, mflag,
       mcaus, mdead, mwork, wcount, counters;
   size_t total;
 };
@@ -167,10 +169,13 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.gstage = take(2 * ts * nl * (size_t)(2 * g.S + 1));
   L.gterm = take(2 * ts * nl);
   L.gczl = take(ts * nl * (size_t)waves_per_mode(g));
+  const size_t B = (size_t)p->max_batch;
   L.u = take(sizeof(double2) * g.N);
-  L.Y = take(sizeof(double2) * g.P);
-  L.c = take(sizeof(double2) * g.M);
-  L.part = take(sizeof(double2) * (size_t)g.N * superpose_groups(g));
+  L.ub = take(B > 1 ? sizeof(double2) * g.N * B : 0);
+  L.Y = take(sizeof(double2) * g.P * B);
+  L.c = take(sizeof(double2) * g.M * B);
+  L.cf = take(B > 1 && use_matrix(p) && p->precision == SWKB_MIXED ? sizeof(float2) * g.M * B : 0);
+  L.part = take(sizeof(double2) * (size_t)g.N * superpose_groups(g) * B);
   L.tmat = take(use_matrix(p) ? matrix_bytes(p) : 0);
   L.D = take(ts * MR);
   L.Pp = take(ts * MR);
@@ -289,6 +294,10 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->gterm = ws + L.gterm;
     pl->gczl = ws + L.gczl;
     pl->u = reinterpret_cast<double2*>(ws + L.u);
+    pl->ub = reinterpret_cast<double2*>(ws + L.ub);
+    pl->cf = reinterpret_cast<float2*>(ws + L.cf);
+    pl->max_batch = p->max_batch;
+    pl->blas = nullptr;
     pl->Y = reinterpret_cast<double2*>(ws + L.Y);
     pl->c = reinterpret_cast<double2*>(ws + L.c);
     pl->part = reinterpret_cast<double2*>(ws + L.part);
@@ -433,16 +442,77 @@ swkb_status swkb_propagate(swkb_plan_t pl, const void* u_in, int32_t q_begin, in
       swkb_status s = ensure_rays(pl, q, st);
       if (s != SWKB_OK) return s;
     }
-    hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, st); });
+    hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, 1, st); });
     if (e != hipSuccess) return hip_fail(e, "fft launch");
     double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * g.N : nullptr;
     if (pl->use_matrix)
-      e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->u, hist, st); });
+      e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->u, hist, 1, st); });
     else
-      e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->u, hist, st); });
+      e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->u, hist, 1, st); });
     if (e != hipSuccess) return hip_fail(e, "superposition launch");
     src = pl->u;
     pl->cur_q = q + 1;
+  }
+  return SWKB_OK;
+}
+
+swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch, int32_t q_begin, int32_t q_end,
+                                 void* history, void* u_out, void* hip_stream) {
+  if (!pl || !u_in) return fail(SWKB_ERR_ARG, "plan or u_in is NULL");
+  if (batch < 1 || batch > pl->max_batch) return fail(SWKB_ERR_ARG, "need 1 <= batch <= max_batch");
+  if (q_begin < 0 || q_end <= q_begin || q_end > pl->p.n_screens)
+    return fail(SWKB_ERR_ARG, "need 0 <= q_begin < q_end <= n_screens");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const Geometry& g = pl->g;
+  if (batch == 1) {
+    // one field: the single-field kernels, without touching the plan's field
+    double2* keep = pl->u;
+    pl->u = pl->ub ? pl->ub : pl->u;
+    const int keep_q = pl->cur_q;
+    swkb_status s = SWKB_OK;
+    if (pl->u == keep) {
+      // no separate batch buffer (max_batch == 1): the single-field state is consumed
+      s = swkb_propagate(pl, u_in, q_begin, q_end, history, hip_stream);
+      if (s == SWKB_OK && u_out) {
+        hipError_t e = hipMemcpyAsync(u_out, pl->u, sizeof(double2) * g.N, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) s = hip_fail(e, "field copy");
+      }
+      pl->cur_q = -1;
+      return s;
+    }
+    s = swkb_propagate(pl, u_in, q_begin, q_end, history, hip_stream);
+    if (s == SWKB_OK && u_out) {
+      hipError_t e = hipMemcpyAsync(u_out, pl->u, sizeof(double2) * g.N, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) s = hip_fail(e, "field copy");
+    }
+    pl->u = keep;
+    pl->cur_q = keep_q;
+    return s;
+  }
+  if (pl->use_matrix && !pl->blas) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return fail(SWKB_ERR_DEVICE, "rocblas_create_handle failed");
+    pl->blas = h;
+  }
+  const double2* src = static_cast<const double2*>(u_in);
+  for (int q = q_begin; q < q_end; ++q) {
+    if (!pl->use_matrix) {
+      swkb_status s = ensure_rays(pl, q, st);
+      if (s != SWKB_OK) return s;
+    }
+    hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, batch, st); });
+    if (e != hipSuccess) return hip_fail(e, "fft launch");
+    double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * batch * g.N : nullptr;
+    if (pl->use_matrix)
+      e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->ub, hist, batch, st); });
+    else
+      e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->ub, hist, batch, st); });
+    if (e != hipSuccess) return hip_fail(e, "batched screen launch");
+    src = pl->ub;
+  }
+  if (u_out) {
+    hipError_t e = hipMemcpyAsync(u_out, pl->ub, sizeof(double2) * g.N * batch, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "field copy");
   }
   return SWKB_OK;
 }
@@ -511,6 +581,7 @@ swkb_status swkb_profile_read(swkb_plan_t pl, void* hip_stream, swkb_timing* out
 
 void swkb_destroy(swkb_plan_t pl) {
   if (!pl) return;
+  if (pl->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(pl->blas));
   for (hipEvent_t ev : pl->ev_pool) (void)hipEventDestroy(ev);
   delete pl;
 }
@@ -532,7 +603,7 @@ const char* swkb_last_error(void) { return g_err.c_str(); }
 swkb_status swkb_stage_modes(swkb_plan_t pl, const void* u, void* c, void* hip_stream) {
   if (!pl || !u || !c) return fail(SWKB_ERR_ARG, "NULL argument");
   hipStream_t st = (hipStream_t)hip_stream;
-  hipError_t e = launch_fft_modes(*pl, static_cast<const double2*>(u), st);
+  hipError_t e = launch_fft_modes(*pl, static_cast<const double2*>(u), 1, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c, pl->c, sizeof(double2) * pl->g.M, hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "stage modes");
   return SWKB_OK;

@@ -62,6 +62,8 @@ __global__ void __launch_bounds__(256) fft_cols(const double2* __restrict__ u, d
                                                 int P2, int logP1, int CA) {
   extern __shared__ double2 L[];  // CA sequences of length P1
   const int c0 = blockIdx.x * CA;
+  u += (size_t)blockIdx.y * N;  // field of this batch member
+  Y += (size_t)blockIdx.y * P;
   for (int idx = threadIdx.x; idx < CA * P1; idx += blockDim.x) {
     const int cc = idx % CA, m1 = idx / CA;
     L[cc * P1 + bitrev(m1, logP1)] = extended(u, P2 * m1 + c0 + cc, N, bc);
@@ -79,6 +81,8 @@ __global__ void __launch_bounds__(256) fft_rows(const double2* __restrict__ Y, d
                                                 int logP2, int RB, int M) {
   extern __shared__ double2 L[];  // RB sequences of length P2
   const int r0 = blockIdx.x * RB;
+  Y += (size_t)blockIdx.y * P;  // batch member
+  c += (size_t)blockIdx.y * M;
   for (int idx = threadIdx.x; idx < RB * P2; idx += blockDim.x) {
     const int rr = idx / P2, m2 = idx - rr * P2;
     L[rr * P2 + bitrev(m2, logP2)] = Y[(r0 + rr) * P2 + m2];
@@ -108,17 +112,17 @@ int ilog2(int x) {
 
 }  // namespace
 
-hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, hipStream_t st) {
+hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, int batch, hipStream_t st) {
   const Geometry& g = pl.g;
   const int CA = g.P2 < 16 ? g.P2 : 16;
   int RB = 2048 / g.P2;
   if (RB < 1) RB = 1;
   if (RB > g.P1) RB = g.P1;
-  hipLaunchKernelGGL(fft_cols, dim3(g.P2 / CA), dim3(256), sizeof(double2) * CA * g.P1, st, u, pl.Y, pl.tw,
+  hipLaunchKernelGGL(fft_cols, dim3(g.P2 / CA, batch), dim3(256), sizeof(double2) * CA * g.P1, st, u, pl.Y, pl.tw,
                      g.N, g.bc, g.P, g.P1, g.P2, ilog2(g.P1), CA);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fft_rows, dim3(g.P1 / RB), dim3(256), sizeof(double2) * RB * g.P2, st, pl.Y, pl.c, pl.tw,
+  hipLaunchKernelGGL(fft_rows, dim3(g.P1 / RB, batch), dim3(256), sizeof(double2) * RB * g.P2, st, pl.Y, pl.c, pl.tw,
                      g.P, g.P1, g.P2, ilog2(g.P2), RB, g.M);
   return hipGetLastError();
 }

@@ -82,12 +82,17 @@ struct CplxOf<double> { using type = double2; };
 template <>
 struct CplxOf<float> { using type = float2; };
 
-template <typename T, bool TABLE>
+//
+// NB fields of a batch share each record evaluation (interpolation and
+// sin/cos once, NB complex multiply-adds); blockIdx.z selects the fields
+// b0 = NB * blockIdx.z .. b0 + nb - 1.  c is [batch][M]; part is
+// [batch][groups][N].
+template <typename T, bool TABLE, int NB>
 __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevModes modes, DevRecords rec,
                                                                 const double2* __restrict__ c,
                                                                 double2* __restrict__ part,
                                                                 typename CplxOf<T>::type* __restrict__ tab, Epi ep,
-                                                                int sub) {
+                                                                int sub, int batch) {
   // LDS: kWaves * kSub * 64 partial sums, then per wavefront br[kSub * 64], IvRec<T>[64]
   extern __shared__ double2 red[];
   const int lane = threadIdx.x & 63;
@@ -95,6 +100,8 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
   const int sb = blockIdx.x;
   const int gi = blockIdx.y;
   const int jstep = (int)gridDim.y * kWaves;
+  const int b0 = (int)blockIdx.z * NB;
+  const int nb = batch - b0 < NB ? batch - b0 : NB;
   const int npts = sub * 64;
   const int m0 = sb * npts;  // first grid point of the super-tile
   const int t0 = sb * sub;   // its first 64-point tile
@@ -111,8 +118,9 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
   const int mp0 = m0 + ep.mprime_off;
   const double zs0 = g.z_a + (double)m0 * g.h;
 
-  T acc_re[kSub], acc_im[kSub];
-  for (int u = 0; u < kSub; ++u) acc_re[u] = acc_im[u] = T(0);
+  T acc_re[NB][kSub], acc_im[NB][kSub];
+  for (int bb = 0; bb < NB; ++bb)
+    for (int u = 0; u < kSub; ++u) acc_re[bb][u] = acc_im[bb][u] = T(0);
   for (int j = gi * kWaves + w; j < g.M; j += jstep) {
     if constexpr (TABLE) {
       for (int u = 0; u < sub; ++u) {
@@ -134,7 +142,12 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
     const double* __restrict__ key = rec.key + base;
     const int n = j - (g.M >> 1);
     const int nm0 = (n * mp0) & pmask;
-    const double2 cj = c[j];
+    T cjr[NB], cji[NB];
+    for (int bb = 0; bb < NB; ++bb) {
+      const double2 v = bb < nb ? c[(size_t)(b0 + bb) * g.M + j] : make_double2(0.0, 0.0);
+      cjr[bb] = (T)v.x;
+      cji[bb] = (T)v.y;
+    }
     const T fj = (T)modes.frac[j];
     for (int a0 = ia; a0 <= ib; a0 += 61) {
       const int b0 = a0 + 60 < ib ? a0 + 60 : ib;  // intervals [a0, b0] in this pass
@@ -252,9 +265,11 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
               v.y = a * sn;
               tab[(size_t)j * g.N + m0 + pu] = v;
             } else {
-              const T cr = (T)cj.x * a, ci = (T)cj.y * a;
-              acc_re[u] += cr * cs - ci * sn;
-              acc_im[u] += cr * sn + ci * cs;
+              const T ea = a * cs, eb = a * sn;  // a e^{i phase}
+              for (int bb = 0; bb < NB; ++bb) {
+                acc_re[bb][u] += cjr[bb] * ea - cji[bb] * eb;
+                acc_im[bb][u] += cjr[bb] * eb + cji[bb] * ea;
+              }
             }
           }
         }
@@ -264,18 +279,23 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
     }
   }
   if constexpr (TABLE) return;
-  for (int u = 0; u < kSub; ++u) red[(w * kSub + u) * 64 + lane] = make_double2((double)acc_re[u], (double)acc_im[u]);
-  __syncthreads();
-  if (w == 0) {
-    for (int u = 0; u < sub; ++u) {
-      double sr = 0.0, si = 0.0;
-      for (int k = 0; k < kWaves; ++k) {
-        const double2 v = red[(k * kSub + u) * 64 + lane];
-        sr += v.x;
-        si += v.y;
+  for (int bb = 0; bb < NB; ++bb) {
+    if (bb >= nb) break;  // uniform over the block
+    for (int u = 0; u < kSub; ++u)
+      red[(w * kSub + u) * 64 + lane] = make_double2((double)acc_re[bb][u], (double)acc_im[bb][u]);
+    __syncthreads();
+    if (w == 0) {
+      for (int u = 0; u < sub; ++u) {
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < kWaves; ++k) {
+          const double2 v = red[(k * kSub + u) * 64 + lane];
+          sr += v.x;
+          si += v.y;
+        }
+        part[((size_t)(b0 + bb) * gridDim.y + gi) * g.N + m0 + u * 64 + lane] = make_double2(sr, si);
       }
-      part[(size_t)gi * g.N + m0 + u * 64 + lane] = make_double2(sr, si);
     }
+    __syncthreads();
   }
 }
 
@@ -326,21 +346,27 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_kernel(Geometry g,
 
 // Sum of the mode-group partials in a fixed order (four threads per point,
 // each over every fourth group, then combined in order), exit taper, field
-// and history writes.  The last block accumulates the screen's diagnostics.
+// and history writes, for field blockIdx.y of the batch (part is
+// [batch][groups][N] of PT = double2 or float2).  The last block of field 0
+// accumulates the screen's diagnostics; a mode is significant when its
+// energy summed over the batch exceeds caustic_tol^2 times the largest.
+template <typename PT>
 __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords rec, const double2* __restrict__ c,
-                                                       const double2* __restrict__ part, int groups,
+                                                       const PT* __restrict__ part, int groups, int batch,
                                                        double2* __restrict__ out, double2* __restrict__ hist,
                                                        unsigned long long* __restrict__ counters, Epi ep) {
+  const int b = blockIdx.y;
   if (blockIdx.x + 1 < gridDim.x) {
     const int sub = threadIdx.x & 3;
     const int m = blockIdx.x * 64 + (threadIdx.x >> 2);
+    const PT* pb = part + (size_t)b * groups * g.N;
     double sr = 0.0, si = 0.0;
     if (m < g.N) {
 #pragma unroll 4
       for (int k = sub; k < groups; k += 4) {
-        const double2 v = part[(size_t)k * g.N + m];
-        sr += v.x;
-        si += v.y;
+        const PT v = pb[(size_t)k * g.N + m];
+        sr += (double)v.x;
+        si += (double)v.y;
       }
     }
     // combine the four partial sums in the order 0, 1, 2, 3
@@ -351,30 +377,46 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
       const double tr = ((sr + r1) + r2) + r3, ti = ((si + i1) + i2) + i3;
       const double wz = taper(g, ep, g.z_a + (double)m * g.h);
       const double2 val = make_double2(wz * tr, wz * ti);
-      out[m] = val;
-      if (hist) hist[m] = val;
+      out[(size_t)b * g.N + m] = val;
+      if (hist) hist[(size_t)b * g.N + m] = val;
     }
     return;
   }
+  if (b != 0) return;
   __shared__ double sm[256];
   __shared__ unsigned long long cnt[7];
-  double cmax = 0.0;
-  for (int j = threadIdx.x; j < g.M; j += blockDim.x) cmax = fmax(cmax, hypot(c[j].x, c[j].y));
-  sm[threadIdx.x] = cmax;
+  double emax = 0.0;
+  for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
+    double e = 0.0;
+    for (int bb = 0; bb < batch; ++bb) {
+      const double2 v = c[(size_t)bb * g.M + j];
+      e += v.x * v.x + v.y * v.y;
+    }
+    emax = fmax(emax, e);
+  }
+  sm[threadIdx.x] = emax;
   if (threadIdx.x < 7) cnt[threadIdx.x] = 0;
   __syncthreads();
   for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
     __syncthreads();
   }
-  cmax = sm[0];
+  emax = sm[0];
+  const double thr = ep.caustic_tol * ep.caustic_tol * emax;
   unsigned long long v[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
     const int f = rec.mflag[j];
     v[0] += rec.mcaus[j];
     v[1] += rec.mdead[j];
     v[2] += f & 1;
-    if (f && hypot(c[j].x, c[j].y) > ep.caustic_tol * cmax) ++v[3];
+    if (f) {
+      double e = 0.0;
+      for (int bb = 0; bb < batch; ++bb) {
+        const double2 cv = c[(size_t)bb * g.M + j];
+        e += cv.x * cv.x + cv.y * cv.y;
+      }
+      if (e > thr) ++v[3];
+    }
     v[4] += (unsigned)rec.mwork[3 * j];
     v[5] += (unsigned)rec.mwork[3 * j + 1];
     v[6] += (unsigned)rec.mwork[3 * j + 2];
@@ -387,6 +429,12 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
     atomicAdd(&counters[4], 1ull);
     for (int k = 4; k < 7; ++k) atomicAdd(&counters[k + 1], cnt[k]);
   }
+}
+
+// c [batch][M] complex128 -> complex64 for the FP32 matrix product.
+__global__ void to_c64_kernel(const double2* __restrict__ c, float2* __restrict__ cf, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cf[i] = make_float2((float)c[i].x, (float)c[i].y);
 }
 
 }  // namespace
@@ -405,31 +453,14 @@ int superpose_groups(const Geometry& g) {
   return groups;
 }
 
-hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, hipStream_t st) {
-  const Geometry& g = pl.g;
-  Epi ep;
-  ep.absorber_bot = pl.p.absorber_bot;
-  ep.absorber_top = pl.p.absorber_top;
-  ep.caustic_tol = pl.p.caustic_tol;
-  ep.mprime_off = g.bc == SWKB_BC_PERIODIC ? 0 : g.N;
-  const int sub = superpose_sub(g);
-  const int groups = superpose_groups(g);
-  DevModes md{pl.xi, pl.pbar, pl.e1r, pl.frac};
+template <typename T, int NB>
+static void launch_sum(const swkb_plan_s& pl, const dim3& grid, const DevModes& md, const Epi& ep, int sub, int batch,
+                       hipStream_t st) {
   const size_t red = sizeof(double2) * 64 * kWaves * kSub;
-  const dim3 grid(g.T / sub, groups);
-  if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL((superpose_kernel<double, false>), grid, dim3(64 * kWaves),
-                       red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<double>)), st, g, md, pl.rec,
-                       pl.c, pl.part, nullptr, ep, sub);
-  else
-    hipLaunchKernelGGL((superpose_kernel<float, false>), grid, dim3(64 * kWaves),
-                       red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<float>)), st, g, md, pl.rec,
-                       pl.c, pl.part, nullptr, ep, sub);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(finalize_kernel, dim3((g.N + 63) / 64 + 1), dim3(256), 0, st, g, pl.rec, pl.c, pl.part, groups,
-                     out, hist, pl.counters, ep);
-  return hipGetLastError();
+  const size_t shmem = red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<T>));
+  const dim3 g3(grid.x, grid.y, (batch + NB - 1) / NB);
+  hipLaunchKernelGGL((superpose_kernel<T, false, NB>), g3, dim3(64 * kWaves), shmem, st, pl.g, md, pl.rec, pl.c,
+                     pl.part, static_cast<typename CplxOf<T>::type*>(nullptr), ep, sub, batch);
 }
 
 static Epi epi_of(const swkb_plan_s& pl) {
@@ -441,6 +472,27 @@ static Epi epi_of(const swkb_plan_s& pl) {
   return ep;
 }
 
+hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st) {
+  const Geometry& g = pl.g;
+  const Epi ep = epi_of(pl);
+  const int sub = superpose_sub(g);
+  const int groups = superpose_groups(g);
+  DevModes md{pl.xi, pl.pbar, pl.e1r, pl.frac};
+  const dim3 grid(g.T / sub, groups);
+  if (pl.precision == SWKB_FP64) {
+    if (batch == 1) launch_sum<double, 1>(pl, grid, md, ep, sub, batch, st);
+    else launch_sum<double, 2>(pl, grid, md, ep, sub, batch, st);
+  } else {
+    if (batch == 1) launch_sum<float, 1>(pl, grid, md, ep, sub, batch, st);
+    else launch_sum<float, 4>(pl, grid, md, ep, sub, batch, st);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + 63) / 64 + 1, batch), dim3(256), 0, st, g, pl.rec, pl.c,
+                     pl.part, groups, batch, out, hist, pl.counters, ep);
+  return hipGetLastError();
+}
+
 hipError_t launch_build_matrix(const swkb_plan_s& pl, hipStream_t st) {
   const Geometry& g = pl.g;
   const Epi ep = epi_of(pl);
@@ -450,33 +502,51 @@ hipError_t launch_build_matrix(const swkb_plan_s& pl, hipStream_t st) {
   const size_t red = sizeof(double2) * 64 * kWaves * kSub;
   const dim3 grid(g.T / sub, groups);
   if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL((superpose_kernel<double, true>), grid, dim3(64 * kWaves),
+    hipLaunchKernelGGL((superpose_kernel<double, true, 1>), grid, dim3(64 * kWaves),
                        red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<double>)), st, g, md, pl.rec,
-                       pl.c, pl.part, static_cast<double2*>(pl.tmat), ep, sub);
+                       pl.c, pl.part, static_cast<double2*>(pl.tmat), ep, sub, 1);
   else
-    hipLaunchKernelGGL((superpose_kernel<float, true>), grid, dim3(64 * kWaves),
+    hipLaunchKernelGGL((superpose_kernel<float, true, 1>), grid, dim3(64 * kWaves),
                        red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<float>)), st, g, md, pl.rec,
-                       pl.c, pl.part, static_cast<float2*>(pl.tmat), ep, sub);
+                       pl.c, pl.part, static_cast<float2*>(pl.tmat), ep, sub, 1);
   return hipGetLastError();
 }
 
-hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* hist, hipStream_t st) {
+hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st) {
   const Geometry& g = pl.g;
   const Epi ep = epi_of(pl);
   const int sub = superpose_sub(g);
-  const int groups = superpose_groups(g);
-  const size_t red = sizeof(double2) * 64 * kWaves * kSub;
-  const dim3 grid(g.T / sub, groups);
-  if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL(apply_matrix_kernel<double>, grid, dim3(64 * kWaves), red, st, g,
-                       static_cast<const double2*>(pl.tmat), pl.c, pl.part, sub);
-  else
-    hipLaunchKernelGGL(apply_matrix_kernel<float>, grid, dim3(64 * kWaves), red, st, g,
-                       static_cast<const float2*>(pl.tmat), pl.c, pl.part, sub);
-  hipError_t e = hipGetLastError();
+  if (batch == 1) {
+    const int groups = superpose_groups(g);
+    const size_t red = sizeof(double2) * 64 * kWaves * kSub;
+    const dim3 grid(g.T / sub, groups);
+    if (pl.precision == SWKB_FP64)
+      hipLaunchKernelGGL(apply_matrix_kernel<double>, grid, dim3(64 * kWaves), red, st, g,
+                         static_cast<const double2*>(pl.tmat), pl.c, pl.part, sub);
+    else
+      hipLaunchKernelGGL(apply_matrix_kernel<float>, grid, dim3(64 * kWaves), red, st, g,
+                         static_cast<const float2*>(pl.tmat), pl.c, pl.part, sub);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + 63) / 64 + 1, 1), dim3(256), 0, st, g, pl.rec, pl.c,
+                       pl.part, groups, 1, out, hist, pl.counters, ep);
+    return hipGetLastError();
+  }
+  // several fields: one complex matrix product U[b][m] = sum_j C[b][j] T[j][m]
+  hipError_t e = gemm_fields(pl, batch, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(finalize_kernel, dim3((g.N + 63) / 64 + 1), dim3(256), 0, st, g, pl.rec, pl.c, pl.part, groups,
-                     out, hist, pl.counters, ep);
+  if (pl.precision == SWKB_FP64)
+    hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + 63) / 64 + 1, batch), dim3(256), 0, st, g, pl.rec,
+                       pl.c, pl.part, 1, batch, out, hist, pl.counters, ep);
+  else
+    hipLaunchKernelGGL(finalize_kernel<float2>, dim3((g.N + 63) / 64 + 1, batch), dim3(256), 0, st, g, pl.rec,
+                       pl.c, reinterpret_cast<const float2*>(pl.part), 1, batch, out, hist, pl.counters, ep);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_c64(const swkb_plan_s& pl, int batch, hipStream_t st) {
+  const int n = batch * pl.g.M;
+  hipLaunchKernelGGL(to_c64_kernel, dim3((n + 255) / 256), dim3(256), 0, st, pl.c, pl.cf, n);
   return hipGetLastError();
 }
 

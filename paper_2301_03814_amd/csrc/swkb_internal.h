@@ -77,8 +77,12 @@ struct swkb_plan_s {
   void* gstage;        // per screen [(2S+1)][nl] (a e^{-dx^2/2s^2}, 64 s^2 - dx^2) pairs of T
   void* gterm;         // per screen [nl] (-1/(2 s^2) [x log2 e in FP32], 1/s^2) pairs of T
   void* gczl;          // per screen [waves_per_mode][nl] bump heights minus each wavefront's z_w, T
-  double2 *u, *Y, *c;
-  double2* part;                 // superposition partials [mode groups][N]
+  double2 *u, *ub;               // single field [N]; batch fields [B][N] (max_batch > 1)
+  double2 *Y, *c;                // FFT scratch [B][P], modes [B][M]
+  double2* part;                 // superposition partials [B][mode groups][N]
+  float2* cf;                    // modes as complex64 [B][M] (FP32 matrix product)
+  int max_batch;
+  void* blas;                    // rocBLAS handle for batched matrix products (created on first use)
   int use_matrix;                // mode functions tabulated once (x-invariant medium)
   void* tmat;                    // T[mode][point], complex T (double2 or float2)
   swkb::DevRecords rec;
@@ -97,13 +101,17 @@ namespace swkb {
 void set_error(const std::string& msg);
 
 // Launchers (return hipSuccess or the launch error).
-hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, hipStream_t st);
+hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, int batch, hipStream_t st);
 hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st);
 hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st);
-hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, hipStream_t st);
+// out [batch][N]; hist [batch][N] for this screen (or NULL).
+hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st);
 int superpose_groups(const Geometry& g);
 hipError_t launch_build_matrix(const swkb_plan_s& pl, hipStream_t st);
-hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* hist, hipStream_t st);
+hipError_t launch_to_c64(const swkb_plan_s& pl, int batch, hipStream_t st);
+// U[b][m] = sum_j C[b][j] T[j][m] for batch > 1 into pl.part (rocBLAS GEMM)
+hipError_t gemm_fields(const swkb_plan_s& pl, int batch, hipStream_t st);
+hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st);
 hipError_t launch_export_rays(const swkb_plan_s& pl, int q, double* Z, double* psi, double* qz,
                               double* amp, int* flag, hipStream_t st);
 

@@ -24,7 +24,7 @@ PROP_AUTO, PROP_MATRIX, PROP_RECOMPUTE = 0, 1, 2
 EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", "swkb_current_screen",
            "swkb_diagnostics", "swkb_destroy", "swkb_status_string", "swkb_last_error",
            "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays", "swkb_profile", "swkb_profile_read",
-           "swkb_uses_matrix"]
+           "swkb_uses_matrix", "swkb_propagate_batch"]
 
 
 class Params(C.Structure):
@@ -41,7 +41,7 @@ class Params(C.Structure):
         ("medium_params", C.POINTER(C.c_double)),
         ("n_medium_params", C.c_int32), ("precision", C.c_int32),
         ("eps_ref", C.c_double), ("caustic_tol", C.c_double),
-        ("propagator", C.c_int32), ("reserved", C.c_int32),
+        ("propagator", C.c_int32), ("max_batch", C.c_int32),
     ]
 
 
@@ -80,6 +80,8 @@ def load(path: str = LIB_PATH):
     lib.swkb_plan.argtypes = [pp, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.swkb_propagate.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.swkb_field.argtypes = [vp, vp, vp]
+    lib.swkb_propagate_batch.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
+    lib.swkb_propagate_batch.restype = C.c_int
     lib.swkb_current_screen.argtypes = [vp]
     lib.swkb_current_screen.restype = i32
     lib.swkb_diagnostics.argtypes = [vp, vp, C.POINTER(Counters)]
@@ -118,7 +120,8 @@ def make_params(cfg, precision=FP64):
         bc=cfg["bc"], medium_kind=cfg["medium_kind"], absorber_bot=cfg["absorber_bot"],
         absorber_top=cfg["absorber_top"], medium_params=mp.ctypes.data_as(C.POINTER(C.c_double)),
         n_medium_params=mp.size, precision=int(precision), eps_ref=cfg["eps_ref"],
-        caustic_tol=cfg["caustic_tol"], propagator=int(cfg.get("propagator", PROP_AUTO)), reserved=0)
+        caustic_tol=cfg["caustic_tol"], propagator=int(cfg.get("propagator", PROP_AUTO)),
+        max_batch=int(cfg.get("max_batch", 1)))
     p._keep = mp
     return p
 
@@ -197,6 +200,27 @@ class Plan:
             hp = C.c_void_p(hist.data_ptr())
         _check(_lib.swkb_propagate(self._h, up, int(q_begin), int(q_end), hp, _stream_handle(stream)))
         return hist
+
+    def propagate_batch(self, u0, q_begin=0, q_end=None, history=True, stream=None):
+        """Carry B fields (u0: complex128 [B, N] on the device) across screens
+        q_begin..q_end-1 together.  Returns (history [q_end-q_begin, B, N] or
+        None, fields on screen q_end [B, N])."""
+        import torch
+        if q_end is None:
+            q_end = self.cfg["n_screens"]
+        if u0.dim() != 2:
+            raise ValueError("u0 must be [B, N]")
+        B = int(u0.shape[0])
+        up = _dev_ptr(u0, torch.complex128, B * self.n_z, "u0")
+        hist = None
+        hp = C.c_void_p(0)
+        if history:
+            hist = torch.empty((q_end - q_begin, B, self.n_z), dtype=torch.complex128, device=self.device)
+            hp = C.c_void_p(hist.data_ptr())
+        out = torch.empty((B, self.n_z), dtype=torch.complex128, device=self.device)
+        _check(_lib.swkb_propagate_batch(self._h, up, B, int(q_begin), int(q_end), hp, C.c_void_p(out.data_ptr()),
+                                         _stream_handle(stream)))
+        return hist, out
 
     def field(self, stream=None):
         import torch

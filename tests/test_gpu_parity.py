@@ -278,3 +278,50 @@ def test_surface_duct_full_size_sampled_screen(torch_dev, swkb):
     say(f"[duct] mixed vs fp64 every 25th screen rel={err:.3e}")
     assert err <= MIXED_TOL
     p32.close()
+
+
+def _sources(cfg, B):
+    """B different incident beams on the same screen grid (heights, tilts)."""
+    out = []
+    L = cfg["z_b"] - cfg["z_a"]
+    for b in range(B):
+        c = W.with_overrides(cfg)
+        c["source"] = dict(z0=cfg["z_a"] + L * (0.3 + 0.4 * b / max(1, B - 1)),
+                           width=cfg["source"]["width"] * (1.0 + 0.25 * b),
+                           xi0=cfg["source"]["xi0"] + 0.01 * b)
+        out.append(W.incident_field(c))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("name,prop", [("random_medium_N1024", "auto"), ("linear_caustic_N512", "auto"),
+                                       ("linear_caustic_N512", "recompute"), ("duct_dirichlet_N2048", "auto")])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_equals_separate_runs(torch_dev, swkb, name, prop, prec):
+    """Several sources through one plan at once (shared rays; for x-invariant
+    media one complex GEMM per screen) equal separate single-field runs."""
+    torch, dev = torch_dev
+    B = 3
+    cfg = W.with_overrides(CASES[name](), max_batch=4, propagator=2 if prop == "recompute" else 0)
+    P = swkb.FP64 if prec == "fp64" else swkb.MIXED
+    U0 = _sources(cfg, B)
+    plan = swkb.Plan(cfg, precision=P, device=dev)
+    u_keep = torch.from_numpy(U0[0]).to(dev)
+    plan.propagate(u_keep, 0, 2)
+    f_before = plan.field()
+    Q = cfg["n_screens"]
+    hist, last = plan.propagate_batch(torch.from_numpy(U0).to(dev), 0, Q)
+    assert torch.equal(plan.field(), f_before) and plan.current_screen == 2  # single-field state untouched
+    hist = hist.cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    for b in range(B):
+        single = swkb.Plan(cfg, precision=P, device=dev)
+        ref = single.propagate(torch.from_numpy(U0[b]).to(dev), 0, Q).cpu().numpy()
+        err = rel(hist[:, b, :], ref)
+        say(f"[batch] {name} {prop} {prec} field {b} rel={err:.2e} matrix={plan.uses_matrix}")
+        assert err <= tol
+        single.close()
+    assert torch.equal(last, torch.from_numpy(hist[-1]).to(dev))
+    # one field through the batch entry point
+    h1, _ = plan.propagate_batch(torch.from_numpy(U0[1:2]).to(dev), 0, Q)
+    assert rel(h1.cpu().numpy()[:, 0, :], hist[:, 1, :]) <= tol
+    plan.close()

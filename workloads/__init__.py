@@ -23,6 +23,7 @@ Every workload is a plain ``dict`` whose keys mirror the fields of the
     caustic_tol       a mode with caustic or crossing rays is reported as an
                       error when |c_n| > caustic_tol * max |c|
     propagator        GPU library only: 0 auto, 1 mode-function matrix, 2 recompute
+    max_batch         GPU library only: most fields one batched propagation carries
     medium_kind       MEDIUM_* below;  medium_params: float64 array
     eps_ref           reference permittivity for the phase split
     source            dict(z0, width, xi0) of the incident Gaussian beam
@@ -61,7 +62,8 @@ PRECISION_MIXED = 1
 
 def _base(lam, z_a, z_b, n_z, n_modes, x0, dx, n_screens, rk4_steps, ray_stride,
           launch_ext_cells, bc, absorber_bot, absorber_top, medium_kind,
-          medium_params, eps_ref, source, p2_floor=1e-2, caustic_tol=1e-3, propagator=0, name=""):
+          medium_params, eps_ref, source, p2_floor=1e-2, caustic_tol=1e-3, propagator=0, max_batch=1,
+          name=""):
     return dict(
         name=name,
         lam=float(lam), k=2.0 * math.pi / float(lam),
@@ -73,6 +75,7 @@ def _base(lam, z_a, z_b, n_z, n_modes, x0, dx, n_screens, rk4_steps, ray_stride,
         medium_kind=int(medium_kind),
         medium_params=np.ascontiguousarray(np.asarray(medium_params, dtype=np.float64)),
         eps_ref=float(eps_ref), caustic_tol=float(caustic_tol), propagator=int(propagator),
+        max_batch=int(max_batch),
         source=dict(source),
     )
 
