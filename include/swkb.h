@@ -164,6 +164,16 @@ swkb_status swkb_propagate(swkb_plan_t plan, const void* u_in, int32_t q_begin, 
 swkb_status swkb_propagate_batch(swkb_plan_t plan, const void* u_in, int32_t batch, int32_t q_begin,
                                  int32_t q_end, void* history, void* u_out, void* hip_stream);
 
+/* Fields between screens q and q+1 (the paper's "additional interpolation
+ * points", end of Sec. 2.1.2): for each station i in stations (host int32
+ * array of n values, 1 <= i <= rk4_steps) the field at x_q + i*dx/S obtained
+ * from the modes of the field u (device complex128[N] on screen q) by the
+ * same step as a screen of width i*dx/S marched with i RK4 steps of the
+ * screen's step size (taper included).  out: device complex128[n][N].
+ * Synchronises hip_stream.  Does not change the plan's field or counters. */
+swkb_status swkb_propagate_stations(swkb_plan_t plan, const void* u, int32_t q, const int32_t* stations, int32_t n,
+                                    void* out, void* hip_stream);
+
 /* Copy the plan's current field (device complex128[N]) into out (device).
  * Returns SWKB_ERR_STATE before the first swkb_propagate. */
 swkb_status swkb_field(swkb_plan_t plan, void* out, void* hip_stream);

@@ -136,7 +136,7 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, part, tmat, D, Pp, G, A, key, tstart, mflag,
+  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, part, tmat, D, Pp, G, A, key, tstart, mflag,
       mcaus, mdead, mwork, wcount, counters;
   size_t total;
 };
@@ -162,6 +162,7 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.pbar = take(sizeof(double) * g.M);
   L.e1r = take(sizeof(double) * g.M);
   L.frac = take(sizeof(double) * g.M);
+  L.frac_st = take(sizeof(double) * g.M * (size_t)g.S);
   L.tw = take(sizeof(double2) * g.P);
   L.mprm = take(sizeof(double) * p->n_medium_params);
   L.glist = take(sizeof(int) * (nlist ? nlist : 1));
@@ -188,7 +189,7 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.mdead = take(sizeof(int) * g.M);
   L.mwork = take(sizeof(int) * 3 * (size_t)g.M);
   L.wcount = take(sizeof(int) * kWaveCounts * (size_t)g.M * waves_per_mode(g));
-  L.counters = take(sizeof(unsigned long long) * 8);
+  L.counters = take(sizeof(unsigned long long) * 16);
   L.total = o;
   return L;
 }
@@ -277,6 +278,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     const Geometry& g = pl->g;
     const std::vector<int> list = gauss_lists(p, &pl->goff);
     pl->gfast = gauss_fast(p, pl->goff) ? 1 : 0;
+    pl->tab_S = p->rk4_steps;
     const Layout L = layout(p, g, list.size(), pl->gfast != 0);
     if (workspace_bytes < L.total) {
       delete pl;
@@ -287,6 +289,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->pbar = reinterpret_cast<double*>(ws + L.pbar);
     pl->e1r = reinterpret_cast<double*>(ws + L.e1r);
     pl->frac = reinterpret_cast<double*>(ws + L.frac);
+    pl->frac_st = reinterpret_cast<double*>(ws + L.frac_st);
     pl->tw = reinterpret_cast<double2*>(ws + L.tw);
     pl->mprm = reinterpret_cast<double*>(ws + L.mprm);
     pl->glist = reinterpret_cast<int*>(ws + L.glist);
@@ -317,6 +320,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->prof_on = 0;
     pl->ev_used = 0;
     pl->counters = reinterpret_cast<unsigned long long*>(ws + L.counters);
+    pl->counters_scratch = pl->counters + 8;
 
     // mode tables: xi_n = 2 pi n / (k P h); reference pbar and range phase
     std::vector<double> xi(g.M), pbar(g.M), e1r(g.M), frac(g.M);
@@ -398,7 +402,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
       if (p->precision == SWKB_FP64) put(pl->gczl, gcz64.data(), sizeof(double) * gcz64.size());
       else put(pl->gczl, gcz32.data(), sizeof(float) * gcz32.size());
     }
-    if (e == hipSuccess) e = hipMemsetAsync(pl->counters, 0, sizeof(unsigned long long) * 8, st);
+    if (e == hipSuccess) e = hipMemsetAsync(pl->counters, 0, sizeof(unsigned long long) * 16, st);
     if (e == hipSuccess && pl->use_matrix) {
       // x-invariant medium: march once and tabulate the mode functions
       e = launch_march(*pl, 0, st);
@@ -513,6 +517,61 @@ swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch
   if (u_out) {
     hipError_t e = hipMemcpyAsync(u_out, pl->ub, sizeof(double2) * g.N * batch, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "field copy");
+  }
+  return SWKB_OK;
+}
+
+swkb_status swkb_propagate_stations(swkb_plan_t pl, const void* u, int32_t q, const int32_t* stations, int32_t n,
+                                    void* out, void* hip_stream) {
+  if (!pl || !u || !stations || !out || n < 1) return fail(SWKB_ERR_ARG, "NULL argument or n < 1");
+  if (q < 0 || q >= pl->p.n_screens) return fail(SWKB_ERR_ARG, "q out of range");
+  const Geometry& g = pl->g;
+  for (int s = 0; s < n; ++s)
+    if (stations[s] < 1 || stations[s] > g.S) return fail(SWKB_ERR_ARG, "stations must be in [1, rk4_steps]");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const double hx = pl->p.dx / pl->p.rk4_steps;
+  try {
+    // range phase frac(pbar * i hx / lambda) of every mode at every station
+    std::vector<double> pbar(g.M), fr((size_t)n * g.M);
+    hipError_t e = hipMemcpy(pbar.data(), pl->pbar, sizeof(double) * g.M, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "stations");
+    for (int s = 0; s < n; ++s) {
+      const double dxs = stations[s] * hx;
+      for (int j = 0; j < g.M; ++j) {
+        const long double turns = (long double)pbar[j] * (long double)dxs * (long double)g.k / (2.0L * M_PIl);
+        fr[(size_t)s * g.M + j] = (double)(turns - floorl(turns));
+      }
+    }
+    e = launch_fft_modes(*pl, static_cast<const double2*>(u), 1, st);
+    for (int s0 = 0; s0 < n && e == hipSuccess; s0 += g.S) {
+      const int cnt = n - s0 < g.S ? n - s0 : g.S;
+      e = hipMemcpyAsync(pl->frac_st, fr.data() + (size_t)s0 * g.M, sizeof(double) * g.M * cnt,
+                         hipMemcpyHostToDevice, st);
+      for (int s = s0; s < s0 + cnt && e == hipSuccess; ++s) {
+        swkb_plan_s tmp = *pl;  // same plan, a screen of width i hx marched with i steps
+        tmp.g.S = stations[s];
+        tmp.g.dx = stations[s] * hx;
+        tmp.frac = pl->frac_st + (size_t)(s - s0) * g.M;
+        tmp.counters = pl->counters_scratch;
+        tmp.use_matrix = 0;
+        e = launch_march(tmp, q, st);
+        if (e == hipSuccess) e = launch_scan(tmp, st);
+        if (e == hipSuccess)
+          e = launch_superpose(tmp, static_cast<double2*>(out) + (size_t)s * g.N, nullptr, 1, st);
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(st);  // host phase tables go out of scope
+    }
+    if (e != hipSuccess) return hip_fail(e, "stations");
+    // the records now hold station rays: re-establish the plan's own march
+    pl->march_valid_q = -1;
+    if (pl->use_matrix) {
+      e = launch_march(*pl, 0, st);
+      if (e == hipSuccess) e = launch_scan(*pl, st);
+      if (e != hipSuccess) return hip_fail(e, "stations");
+      pl->march_valid_q = -2;
+    }
+  } catch (const std::exception& ex) {
+    return fail(SWKB_ERR_NOMEM, std::string("stations: ") + ex.what());
   }
   return SWKB_OK;
 }

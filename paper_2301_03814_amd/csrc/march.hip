@@ -423,7 +423,7 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
   if (pl.gfast) {
     const int nl = pl.goff[q + 1] - pl.goff[q];
     const size_t off = (size_t)pl.goff[q];
-    const size_t nst = (size_t)(2 * g.S + 1);
+    const size_t nst = (size_t)(2 * pl.tab_S + 1);  // table stride per screen
     if (pl.precision == SWKB_FP64) {
       GaussTabs<double> t{reinterpret_cast<const T2<double>*>(pl.gstage) + off * nst,
                           reinterpret_cast<const T2<double>*>(pl.gterm) + off,

@@ -73,7 +73,8 @@ struct swkb_plan_s {
   double* mprm;
   int* glist;          // concatenated per-screen Gaussian lists
   std::vector<int> goff;  // host offsets into glist per screen (n_screens + 1)
-  int gfast;           // Gaussian-sum march from per-screen LDS tables
+  int gfast;           // Gaussian-sum march from per-screen bump tables
+  int tab_S;           // RK4 steps the bump tables were built for (stage stride 2*tab_S+1)
   void* gstage;        // per screen [(2S+1)][nl] (a e^{-dx^2/2s^2}, 64 s^2 - dx^2) pairs of T
   void* gterm;         // per screen [nl] (-1/(2 s^2) [x log2 e in FP32], 1/s^2) pairs of T
   void* gczl;          // per screen [waves_per_mode][nl] bump heights minus each wavefront's z_w, T
@@ -88,6 +89,8 @@ struct swkb_plan_s {
   swkb::DevRecords rec;
   int* wcount;                   // per-wavefront march counts [M][waves][kWaveCounts]
   unsigned long long* counters;  // caustic, dead, folded, significant, screens, rhs, med, terms
+  unsigned long long* counters_scratch;  // diagnostics of station evaluations (discarded)
+  double* frac_st;               // per-station range phases [rk4_steps][M]
   // event timing
   int prof_on;
   std::vector<hipEvent_t> ev_pool;

@@ -24,7 +24,7 @@ PROP_AUTO, PROP_MATRIX, PROP_RECOMPUTE = 0, 1, 2
 EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", "swkb_current_screen",
            "swkb_diagnostics", "swkb_destroy", "swkb_status_string", "swkb_last_error",
            "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays", "swkb_profile", "swkb_profile_read",
-           "swkb_uses_matrix", "swkb_propagate_batch"]
+           "swkb_uses_matrix", "swkb_propagate_batch", "swkb_propagate_stations"]
 
 
 class Params(C.Structure):
@@ -82,6 +82,8 @@ def load(path: str = LIB_PATH):
     lib.swkb_field.argtypes = [vp, vp, vp]
     lib.swkb_propagate_batch.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
     lib.swkb_propagate_batch.restype = C.c_int
+    lib.swkb_propagate_stations.argtypes = [vp, vp, i32, C.POINTER(C.c_int32), i32, vp, vp]
+    lib.swkb_propagate_stations.restype = C.c_int
     lib.swkb_current_screen.argtypes = [vp]
     lib.swkb_current_screen.restype = i32
     lib.swkb_diagnostics.argtypes = [vp, vp, C.POINTER(Counters)]
@@ -221,6 +223,17 @@ class Plan:
         _check(_lib.swkb_propagate_batch(self._h, up, B, int(q_begin), int(q_end), hp, C.c_void_p(out.data_ptr()),
                                          _stream_handle(stream)))
         return hist, out
+
+    def stations(self, u, q, stations, stream=None):
+        """Fields at x_q + i dx/S for i in stations, from the field u on screen q.
+        Returns complex128 [len(stations), N] on the device."""
+        import torch
+        st = np.ascontiguousarray(np.asarray(stations, dtype=np.int32))
+        out = torch.empty((st.size, self.n_z), dtype=torch.complex128, device=self.device)
+        _check(_lib.swkb_propagate_stations(self._h, _dev_ptr(u, torch.complex128, self.n_z, "u"), int(q),
+                                            st.ctypes.data_as(C.POINTER(C.c_int32)), int(st.size),
+                                            C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
 
     def field(self, stream=None):
         import torch

@@ -325,3 +325,33 @@ def test_batch_equals_separate_runs(torch_dev, swkb, name, prop, prec):
     h1, _ = plan.propagate_batch(torch.from_numpy(U0[1:2]).to(dev), 0, Q)
     assert rel(h1.cpu().numpy()[:, 0, :], hist[:, 1, :]) <= tol
     plan.close()
+
+
+@pytest.mark.parametrize("name", ["random_medium_N1024", "linear_caustic_N512", "duct_dirichlet_N2048"])
+def test_fields_between_screens_match_oracle(torch_dev, swkb, name):
+    """Stations x_q + i dx/S: the oracle runs the screen step with width
+    i dx/S and i RK4 steps from the same field."""
+    import oracle
+    torch, dev = torch_dev
+    cfg = CASES[name]()
+    S = cfg["rk4_steps"]
+    q = 2
+    plan = swkb.Plan(cfg, device=dev)
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    hist = plan.propagate(u0, 0, q + 1)
+    uq = hist[q - 1].contiguous()
+    st = [1, S // 2, S]
+    got = plan.stations(uq, q, st).cpu().numpy()
+    for k, i in enumerate(st):
+        c_i = W.with_overrides(cfg, dx=i * (cfg["dx"] / S), rk4_steps=i)
+        c_i["x0"] = cfg["x0"] + q * cfg["dx"] - q * c_i["dx"]  # screen q of c_i sits at x_q
+        ref, _ = oracle.screen(c_i, q, uq.cpu().numpy())
+        err = rel(got[k], ref)
+        say(f"[stations] {name} i={i} rel={err:.2e}")
+        assert err <= FP64_TOL
+    # the last station is the next screen
+    assert rel(got[-1], hist[q].cpu().numpy()) <= 1e-12
+    # the plan's own propagation is unaffected afterwards
+    again = plan.propagate(u0, 0, q + 1)
+    assert torch.equal(again, hist)
+    plan.close()
