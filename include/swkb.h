@@ -174,6 +174,21 @@ swkb_status swkb_propagate_batch(swkb_plan_t plan, const void* u_in, int32_t bat
 swkb_status swkb_propagate_stations(swkb_plan_t plan, const void* u, int32_t q, const int32_t* stations, int32_t n,
                                     void* out, void* hip_stream);
 
+/* Reference solution by separation of variables (the paper's reference
+ * method, Sec. 3.1, eqs. series_sol, phi_equation, series_init,
+ * sl_expansion) for a medium that does not depend on x: the Sturm-Liouville
+ * operator d^2/dz^2 + k^2 eps is discretised Fourier-spectrally on the screen
+ * grid (on the doubled grid with eps reflected about z_a for a ground
+ * mirror, the field extended oddly/evenly) and diagonalised in FP64 with
+ * rocSOLVER; u(x) = Phi e^{i alpha x} Phi^T u0 with alpha = sqrt(lambda)
+ * (decaying for lambda < 0).  Uses p (no plan); u0: device complex128[N];
+ * xs: host double[nx] ranges from the screen of u0; out: device
+ * complex128[nx][N].  P = N (periodic) or 2N must be <= 16384.  Allocates
+ * and frees its own device memory (P^2 doubles); synchronises hip_stream.
+ * SWKB_ERR_ARG for an x-varying medium. */
+swkb_status swkb_modal_reference(const swkb_params* p, const void* u0, const double* xs, int32_t nx, void* out,
+                                 void* hip_stream);
+
 /* Copy the plan's current field (device complex128[N]) into out (device).
  * Returns SWKB_ERR_STATE before the first swkb_propagate. */
 swkb_status swkb_field(swkb_plan_t plan, void* out, void* hip_stream);

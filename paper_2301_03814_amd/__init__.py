@@ -5,4 +5,4 @@ HIP sources in csrc/ by ``paper_2301_03814_amd.build``; ``swkb`` is its thin
 Python binding.
 """
 from .swkb import (BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC, FP64, MIXED, Plan, SwkbError, load,  # noqa: F401
-                   make_params, workspace_bytes)
+                   make_params, modal_reference, workspace_bytes)

@@ -24,7 +24,7 @@ PROP_AUTO, PROP_MATRIX, PROP_RECOMPUTE = 0, 1, 2
 EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", "swkb_current_screen",
            "swkb_diagnostics", "swkb_destroy", "swkb_status_string", "swkb_last_error",
            "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays", "swkb_profile", "swkb_profile_read",
-           "swkb_uses_matrix", "swkb_propagate_batch", "swkb_propagate_stations"]
+           "swkb_uses_matrix", "swkb_propagate_batch", "swkb_propagate_stations", "swkb_modal_reference"]
 
 
 class Params(C.Structure):
@@ -84,6 +84,8 @@ def load(path: str = LIB_PATH):
     lib.swkb_propagate_batch.restype = C.c_int
     lib.swkb_propagate_stations.argtypes = [vp, vp, i32, C.POINTER(C.c_int32), i32, vp, vp]
     lib.swkb_propagate_stations.restype = C.c_int
+    lib.swkb_modal_reference.argtypes = [pp, vp, C.POINTER(C.c_double), i32, vp, vp]
+    lib.swkb_modal_reference.restype = C.c_int
     lib.swkb_current_screen.argtypes = [vp]
     lib.swkb_current_screen.restype = i32
     lib.swkb_diagnostics.argtypes = [vp, vp, C.POINTER(Counters)]
@@ -145,6 +147,20 @@ def _dev_ptr(t, dtype, numel, name):
     if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
         raise ValueError(f"{name} must be a contiguous {dtype} tensor with {numel} elements")
     return C.c_void_p(t.data_ptr())
+
+
+def modal_reference(cfg, u0, xs, stream=None):
+    """Separation-of-variables reference (x-invariant media) on the GPU:
+    fields at ranges xs (from the screen of u0), complex128 [len(xs), N]."""
+    import torch
+    lib = load()
+    p = make_params(cfg)
+    xs = np.ascontiguousarray(np.asarray(xs, dtype=np.float64))
+    out = torch.empty((xs.size, cfg["n_z"]), dtype=torch.complex128, device=u0.device)
+    _check(lib.swkb_modal_reference(C.byref(p), _dev_ptr(u0, torch.complex128, cfg["n_z"], "u0"),
+                                    xs.ctypes.data_as(C.POINTER(C.c_double)), int(xs.size),
+                                    C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
 
 
 class Plan:
