@@ -30,9 +30,12 @@ METRIC = "mode×point evals/s; range km/s at 1e-3 rel err vs FP64 plain; p50/p99
 #     (39 in the right-hand side, 16 in the stage/step combinations)
 #   per evaluation of eps, eps_z, eps_zz from the index deviation     9
 #   per Gaussian term inside its cutoff (distance, exp, 3 sums)      22
+#   per medium value read from the per-screen table (node index 6,
+#     Hermite basis 15, three interpolants 21)                        42
 FLOPS_PER_RHS = 55
 FLOPS_PER_MEDIUM = 9
 FLOPS_PER_TERM = 22
+FLOPS_PER_TABLE = 42
 PEAK_FP32_VECTOR = 157.3e12   # MI355X published dense FP32 vector FLOP/s
 PEAK_FP64_VECTOR = 78.6e12
 
@@ -177,7 +180,8 @@ def main():
         prof = plan.profile_read()
         plan.profile(False)
         diag = plan.diagnostics()
-        work = {k: diag[k] - base[k] for k in ("rhs_evals", "medium_evals", "medium_terms", "screens")}
+        work = {k: diag[k] - base[k] for k in ("rhs_evals", "medium_evals", "medium_terms", "table_evals",
+                                                "screens")}
         res[name] = dict(seconds=t1 - t0, prof=prof, work=work, diag=diag,
                          lat_ms=sorted(a.elapsed_time(b) for a, b in lat))
         print(f"[bench] {name}: {1e3 * (t1 - t0) / args.steps:.1f} ms/step {prof}", file=sys.stderr, flush=True)
@@ -216,7 +220,7 @@ def main():
     def roof(r, peak, prec):
         w, p = r["work"], r["prof"]
         flops = FLOPS_PER_RHS * w["rhs_evals"] + FLOPS_PER_MEDIUM * w["medium_evals"] + \
-            FLOPS_PER_TERM * w["medium_terms"]
+            FLOPS_PER_TERM * w["medium_terms"] + FLOPS_PER_TABLE * w["table_evals"]
         launches = max(1, p["march_launches"])
         avg_s = p["march_ms"] * 1e-3 / launches
         per_launch = flops / launches
@@ -224,7 +228,9 @@ def main():
         t = traffic_from_profiles(prec)
         return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
                 "frac": round(achieved * 1e12 / peak, 4), "traffic": t,
-                "kernel": f"march_gauss_kernel<{'float' if prec == 'mixed' else 'double'}>",
+                "kernel": "march_table_kernel" if w["table_evals"] else
+                          f"march_gauss_kernel<{'float' if prec == 'mixed' else 'double'}>",
+                "table_share": round(w["table_evals"] / max(1, w["table_evals"] + w["medium_evals"]), 4),
                 "flops_per_launch": per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
 
     roof_m = roof(rm, PEAK_FP32_VECTOR, "mixed")

@@ -110,8 +110,11 @@ typedef struct swkb_counters {
   int64_t screens;      /* screen steps executed                                         */
   /* work of the method, per screen step summed (for throughput accounting):          */
   int64_t rhs_evals;    /* RK4 stage evaluations of the ray system by live rays          */
-  int64_t medium_evals; /* evaluations of eps, eps_z, eps_zz (stages, launch, arrival)   */
+  int64_t medium_evals; /* direct evaluations of eps, eps_z, eps_zz (stages, launch,
+                           arrival)                                                      */
   int64_t medium_terms; /* Gaussian terms inside their cutoff evaluated (GAUSSSUM)        */
+  int64_t table_evals;  /* evaluations read from the per-screen medium table (mixed
+                           precision, GAUSSSUM, periodic)                                */
 } swkb_counters;
 
 /* Device time per kernel class, from HIP events recorded on the launch
@@ -119,6 +122,8 @@ typedef struct swkb_counters {
 typedef struct swkb_timing {
   double march_ms, scan_ms, fft_ms, superpose_ms;
   int64_t march_launches, scan_launches, fft_launches, superpose_launches;
+  double table_ms;        /* per-screen medium table builds (mixed GAUSSSUM march)  */
+  int64_t table_launches;
 } swkb_timing;
 
 typedef struct swkb_plan_s* swkb_plan_t;

@@ -136,7 +136,7 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, part, tmat, D, Pp, G, A, key, tstart, mflag,
+  size_t xi, pbar, e1r, frac, frac_st, tw, mtab, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, part, tmat, D, Pp, G, A, key, tstart, mflag,
       mcaus, mdead, mwork, wcount, counters;
   size_t total;
 };
@@ -146,6 +146,32 @@ struct Layout {
 bool gauss_fast(const swkb_params* p, const std::vector<int>& off) {
   (void)off;
   return p->medium_kind == SWKB_MEDIUM_GAUSSSUM && p->bc == SWKB_BC_PERIODIC;
+}
+
+// Medium table of the mixed Gaussian-sum march: node spacing s_min / 40 over
+// the launch span, widened on both sides by the launch extension plus the
+// farthest a ray can travel in z across one screen (|q| / p with
+// p^2 > p2_floor and eps <= 1 + max(0, sum of bump amplitudes)^2 terms).
+// Returns n = 0 where the direct evaluation is used.
+MedTab med_table(const swkb_params* p, const Geometry& g) {
+  MedTab t{nullptr, 0, 0.0, 0.0};
+  if (p->medium_kind != SWKB_MEDIUM_GAUSSSUM || p->bc != SWKB_BC_PERIODIC || p->precision != SWKB_MIXED) return t;
+  const int ng = (int)p->medium_params[0];
+  if (ng < 1) return t;
+  double smin = p->medium_params[2], amax = 0.0;
+  for (int j = 0; j < ng; ++j) {
+    smin = std::min(smin, p->medium_params[2 + 4 * j]);
+    amax += std::max(0.0, p->medium_params[1 + 4 * j]);
+  }
+  const double eps_max = (1.0 + amax) * (1.0 + amax);
+  const double reach = p->dx * std::sqrt(eps_max / std::max(p->p2_floor, 1e-6));
+  const double margin = g.E * g.h + std::min(reach, 0.5 * (g.z_b - g.z_a));
+  t.dz = smin / 40.0;
+  t.z_lo = g.z_a - margin;
+  const double n = std::ceil(((g.z_b - g.z_a) + 2.0 * margin) / t.dz) + 2.0;
+  if (n > (double)(1 << 22)) return MedTab{nullptr, 0, 0.0, 0.0};  // too fine: evaluate directly
+  t.n = (int)n;
+  return t;
 }
 
 Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast) {
@@ -163,6 +189,7 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.e1r = take(sizeof(double) * g.M);
   L.frac = take(sizeof(double) * g.M);
   L.frac_st = take(sizeof(double) * g.M * (size_t)g.S);
+  L.mtab = take(sizeof(float4) * (size_t)med_table(p, g).n * (2 * g.S + 1));
   L.tw = take(sizeof(double2) * g.P);
   L.mprm = take(sizeof(double) * p->n_medium_params);
   L.glist = take(sizeof(int) * (nlist ? nlist : 1));
@@ -187,9 +214,9 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.mflag = take(sizeof(int) * g.M);
   L.mcaus = take(sizeof(int) * g.M);
   L.mdead = take(sizeof(int) * g.M);
-  L.mwork = take(sizeof(int) * 3 * (size_t)g.M);
+  L.mwork = take(sizeof(int) * 4 * (size_t)g.M);
   L.wcount = take(sizeof(int) * kWaveCounts * (size_t)g.M * waves_per_mode(g));
-  L.counters = take(sizeof(unsigned long long) * 16);
+  L.counters = take(sizeof(unsigned long long) * 32);
   L.total = o;
   return L;
 }
@@ -209,8 +236,8 @@ swkb_status hip_fail(hipError_t e, const char* what) {
 using namespace swkb;
 
 // Event timing: an event is recorded on the launch stream before and after
-// each kernel (class 0 march, 1 scan, 2 fft, 3 superposition).
-enum { kProfMarch = 0, kProfScan = 1, kProfFft = 2, kProfSuper = 3 };
+// each kernel (class 0 march, 1 scan, 2 fft, 3 superposition, 4 medium table).
+enum { kProfMarch = 0, kProfScan = 1, kProfFft = 2, kProfSuper = 3, kProfTable = 4, kProfClasses = 5 };
 
 static int prof_mark(swkb_plan_s* pl, hipStream_t st) {
   if (pl->ev_used == pl->ev_pool.size()) {
@@ -235,7 +262,9 @@ static hipError_t timed(swkb_plan_s* pl, int cls, hipStream_t st, F&& launch) {
 
 static swkb_status ensure_rays(swkb_plan_s* pl, int q, hipStream_t st) {
   if (pl->x_invariant ? pl->march_valid_q == -2 : pl->march_valid_q == q) return SWKB_OK;
-  hipError_t e = timed(pl, kProfMarch, st, [&] { return launch_march(*pl, q, st); });
+  hipError_t e = hipSuccess;
+  if (pl->mtab.tab) e = timed(pl, kProfTable, st, [&] { return launch_medium_table(*pl, q, st); });
+  if (e == hipSuccess) e = timed(pl, kProfMarch, st, [&] { return launch_march(*pl, q, st); });
   if (e == hipSuccess) e = timed(pl, kProfScan, st, [&] { return launch_scan(*pl, st); });
   if (e != hipSuccess) {
     pl->march_valid_q = -1;
@@ -290,6 +319,8 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->e1r = reinterpret_cast<double*>(ws + L.e1r);
     pl->frac = reinterpret_cast<double*>(ws + L.frac);
     pl->frac_st = reinterpret_cast<double*>(ws + L.frac_st);
+    pl->mtab = med_table(p, g);
+    if (pl->mtab.n > 0) pl->mtab.tab = reinterpret_cast<const float4*>(ws + L.mtab);
     pl->tw = reinterpret_cast<double2*>(ws + L.tw);
     pl->mprm = reinterpret_cast<double*>(ws + L.mprm);
     pl->glist = reinterpret_cast<int*>(ws + L.glist);
@@ -320,7 +351,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->prof_on = 0;
     pl->ev_used = 0;
     pl->counters = reinterpret_cast<unsigned long long*>(ws + L.counters);
-    pl->counters_scratch = pl->counters + 8;
+    pl->counters_scratch = pl->counters + 16;
 
     // mode tables: xi_n = 2 pi n / (k P h); reference pbar and range phase
     std::vector<double> xi(g.M), pbar(g.M), e1r(g.M), frac(g.M);
@@ -402,7 +433,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
       if (p->precision == SWKB_FP64) put(pl->gczl, gcz64.data(), sizeof(double) * gcz64.size());
       else put(pl->gczl, gcz32.data(), sizeof(float) * gcz32.size());
     }
-    if (e == hipSuccess) e = hipMemsetAsync(pl->counters, 0, sizeof(unsigned long long) * 16, st);
+    if (e == hipSuccess) e = hipMemsetAsync(pl->counters, 0, sizeof(unsigned long long) * 32, st);
     if (e == hipSuccess && pl->use_matrix) {
       // x-invariant medium: march once and tabulate the mode functions
       e = launch_march(*pl, 0, st);
@@ -554,7 +585,8 @@ swkb_status swkb_propagate_stations(swkb_plan_t pl, const void* u, int32_t q, co
         tmp.frac = pl->frac_st + (size_t)(s - s0) * g.M;
         tmp.counters = pl->counters_scratch;
         tmp.use_matrix = 0;
-        e = launch_march(tmp, q, st);
+        e = launch_medium_table(tmp, q, st);
+        if (e == hipSuccess) e = launch_march(tmp, q, st);
         if (e == hipSuccess) e = launch_scan(tmp, st);
         if (e == hipSuccess)
           e = launch_superpose(tmp, static_cast<double2*>(out) + (size_t)s * g.N, nullptr, 1, st);
@@ -589,7 +621,7 @@ int32_t swkb_current_screen(swkb_plan_t pl) { return pl ? pl->cur_q : -1; }
 
 swkb_status swkb_diagnostics(swkb_plan_t pl, void* hip_stream, swkb_counters* out) {
   if (!pl || !out) return fail(SWKB_ERR_ARG, "plan or out is NULL");
-  unsigned long long h[8];
+  unsigned long long h[9];
   hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
   if (e == hipSuccess) e = hipMemcpy(h, pl->counters, sizeof(h), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "diagnostics");
@@ -601,6 +633,7 @@ swkb_status swkb_diagnostics(swkb_plan_t pl, void* hip_stream, swkb_counters* ou
   out->rhs_evals = (int64_t)h[5];
   out->medium_evals = (int64_t)h[6];
   out->medium_terms = (int64_t)h[7];
+  out->table_evals = (int64_t)h[8];
   if (out->significant > 0) return fail(SWKB_ERR_CAUSTIC, "a significant mode met a caustic inside a screen");
   return SWKB_OK;
 }
@@ -615,8 +648,8 @@ swkb_status swkb_profile_read(swkb_plan_t pl, void* hip_stream, swkb_timing* out
   if (!pl || !out) return fail(SWKB_ERR_ARG, "plan or out is NULL");
   hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "profile read");
-  double ms[4] = {0, 0, 0, 0};
-  int64_t n[4] = {0, 0, 0, 0};
+  double ms[kProfClasses] = {0, 0, 0, 0, 0};
+  int64_t n[kProfClasses] = {0, 0, 0, 0, 0};
   for (const auto& mk : pl->marks) {
     float t = 0.f;
     e = hipEventSynchronize(pl->ev_pool[mk.b]);
@@ -635,6 +668,8 @@ swkb_status swkb_profile_read(swkb_plan_t pl, void* hip_stream, swkb_timing* out
   out->scan_launches = n[kProfScan];
   out->fft_launches = n[kProfFft];
   out->superpose_launches = n[kProfSuper];
+  out->table_ms = ms[kProfTable];
+  out->table_launches = n[kProfTable];
   return SWKB_OK;
 }
 

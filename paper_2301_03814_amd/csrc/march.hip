@@ -42,6 +42,12 @@ struct Deriv {
 
 enum { kLive = 0, kDeadLaunch = 1, kDead = 2, kCaustic = 3 };
 
+// Work of one ray: RK4 stage evaluations, direct medium evaluations,
+// Gaussian terms inside their cutoff, medium values read from a table.
+struct Work {
+  int rhs = 0, med = 0, terms = 0, tab = 0;
+};
+
 template <typename T>
 __device__ inline T fast_rsqrt(T x);
 template <>
@@ -62,8 +68,9 @@ struct GenericMedium {
   DevMedium md;
   double x_q, hx2;  // stage k sits at x_q + k * hx2
   double s;         // launch height of this lane's ray
-  __device__ Med<T> eval(int k, T dz, int& nterms) const {
-    return medium_eval<T>(md, x_q + k * hx2, s, dz, nterms);
+  __device__ Med<T> eval(int k, T dz, Work& c) const {
+    ++c.med;
+    return medium_eval<T>(md, x_q + k * hx2, s, dz, c.terms);
   }
 };
 
@@ -101,7 +108,9 @@ struct GaussMedium {
     nz -= ddz * t;
     nzz += (d2 * tk.y - T(1)) * t;
   }
-  __device__ Med<T> eval(int k, T dz, int& nterms) const {
+  __device__ Med<T> eval(int k, T dz, Work& c) const {
+    ++c.med;
+    int& nterms = c.terms;
     const T z = zl0 + dz;
     const T2<T>* __restrict__ st = stage + k * nl;
     T dn = T(0), nz = T(0), nzz = T(0);
@@ -121,13 +130,49 @@ struct GaussMedium {
   }
 };
 
+// Gaussian-sum medium read from a per-screen table (mixed path).  At each
+// RK4 stage position x_k of the screen the table holds eps - 1, eps_z,
+// eps_zz and eps_zzz, computed in FP64 and stored as FP32, on z-nodes
+// z_lo + i dz_t; a value at z is the cubic Hermite interpolant between the
+// two enclosing nodes, each quantity taking the next derivative as its
+// slope.  The interpolation error of a quantity f is at most
+// dz_t^4 max|f^(4)| / 384; with dz_t = s_min / 40 it stays below 1e-9 of
+// the bump amplitude for eps and eps_z and below 1e-8 for eps_zz (times
+// 1/s^2), under the FP32 rounding of a direct evaluation.  Heights outside
+// the table fall back to the direct evaluation.
+struct TableMedium {
+  const float4* __restrict__ tab;  // [(2S+1)][nt]
+  int nt;
+  float inv_dz, dzt;
+  int j0;          // node at or below the wavefront's reference height z_w
+  float f0;        // z_w minus the height of node j0, in [0, dz_t)
+  float tlo, thi;  // node offsets from j0 that keep nodes j0 + t and j0 + t + 1 inside
+  GaussMedium<float> direct;
+  __device__ Med<float> eval(int k, float dz, Work& c) const {
+    const float t = (f0 + direct.zl0 + dz) * inv_dz;
+    const float tf = floorf(t);
+    // a NaN height fails both comparisons and takes the direct path too
+    if (!(tf >= tlo && tf <= thi)) return direct.eval(k, dz, c);
+    const int node = j0 + (int)tf;
+    ++c.tab;
+    const float u = t - tf, v = 1.0f - u;
+    const float4 a = tab[k * nt + node], b = tab[k * nt + node + 1];
+    const float h00 = (1.0f + 2.0f * u) * v * v, h10 = u * v * v * dzt;
+    const float h01 = u * u * (3.0f - 2.0f * u), h11 = u * u * (u - 1.0f) * dzt;
+    Med<float> m;
+    m.e1 = h00 * a.x + h10 * a.y + h01 * b.x + h11 * b.y;
+    m.ez = h00 * a.y + h10 * a.z + h01 * b.y + h11 * b.z;
+    m.ezz = h00 * a.z + h10 * a.w + h01 * b.z + h11 * b.w;
+    return m;
+  }
+};
+
 // Right-hand side at stage k.  Returns kLive, kDead or kCaustic.
 template <typename T, typename MED>
 __device__ inline int rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, double Zs, double Qs,
-                         double p2_floor, Deriv<T>& d, int& nterms, int& nmed) {
+                         double p2_floor, Deriv<T>& d, Work& c) {
   if (!(Zs > 0.0)) return kCaustic;
-  const Med<T> m = med.eval(k, dz, nterms);
-  ++nmed;
+  const Med<T> m = med.eval(k, dz, c);
   const T xi = (T)mc.xi;
   const T q = xi + dq;
   const T p2 = (T)mc.omx2 + m.e1 - dq * (T(2) * xi + dq);
@@ -151,14 +196,13 @@ __device__ inline int rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, do
 // record and returns the lane's status and work counts.
 template <typename T, typename MED>
 __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry& g, bool active, size_t o,
-                                 DevRecords& rec, int& st, int& nterms, int& nmed, int& nrhs) {
+                                 DevRecords& rec, int& st, Work& c) {
   T dz = T(0), dq = T(0), dps = T(0);
   double Zs = 1.0, Qs = 0.0;
   double amp = 0.0;
   st = kLive;
   if (!active) return;
-  const Med<T> m0 = med.eval(0, T(0), nterms);
-  ++nmed;
+  const Med<T> m0 = med.eval(0, T(0), c);
   const T p02 = (T)mc.omx2 + m0.e1;
   if (!(p02 > (T)g.p2_floor)) {
     st = kDeadLaunch;
@@ -169,17 +213,17 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
     const double hd2 = 0.5 * hx, hd6 = hx / 6.0;
     Deriv<T> k1, k2, k3, k4;
     for (int i = 0; i < g.S; ++i) {
-      if ((st = rhs<T>(med, mc, 2 * i, dz, dq, Zs, Qs, g.p2_floor, k1, nterms, nmed))) break;
+      if ((st = rhs<T>(med, mc, 2 * i, dz, dq, Zs, Qs, g.p2_floor, k1, c))) break;
       if ((st = rhs<T>(med, mc, 2 * i + 1, dz + hh * k1.dz, dq + hh * k1.dq, Zs + hd2 * k1.Zs, Qs + hd2 * k1.Qs,
-                       g.p2_floor, k2, nterms, nmed)))
+                       g.p2_floor, k2, c)))
         break;
       if ((st = rhs<T>(med, mc, 2 * i + 1, dz + hh * k2.dz, dq + hh * k2.dq, Zs + hd2 * k2.Zs, Qs + hd2 * k2.Qs,
-                       g.p2_floor, k3, nterms, nmed)))
+                       g.p2_floor, k3, c)))
         break;
       if ((st = rhs<T>(med, mc, 2 * i + 2, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hx * k3.Zs, Qs + hx * k3.Qs,
-                       g.p2_floor, k4, nterms, nmed)))
+                       g.p2_floor, k4, c)))
         break;
-      nrhs += 4;
+      c.rhs += 4;
       dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
       dq += h6 * (k1.dq + T(2) * k2.dq + T(2) * k3.dq + k4.dq);
       dps += h6 * (k1.dps + T(2) * k2.dps + T(2) * k3.dps + k4.dps);
@@ -190,8 +234,7 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
       if (!(Zs > 0.0)) {
         st = kCaustic;
       } else {
-        const Med<T> m1 = med.eval(2 * g.S, dz, nterms);
-        ++nmed;
+        const Med<T> m1 = med.eval(2 * g.S, dz, c);
         const T xi = (T)mc.xi;
         const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
         if (!(p2 > (T)g.p2_floor)) st = kDead;
@@ -205,22 +248,23 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
   static_cast<T*>(rec.A)[o] = st == kLive ? (T)amp : (T)(-st);
 }
 
-__device__ inline void wave_counts(int* __restrict__ wcount, size_t slot, int lane, bool active, int st, int nrhs,
-                                   int nmed, int nterms) {
+__device__ inline void wave_counts(int* __restrict__ wcount, size_t slot, int lane, bool active, int st, Work c) {
   const unsigned long long bc = __ballot(active && st == kCaustic);
   const unsigned long long bd = __ballot(active && (st == kDead || st == kDeadLaunch));
   for (int off = 32; off > 0; off >>= 1) {
-    nrhs += __shfl_xor(nrhs, off);
-    nmed += __shfl_xor(nmed, off);
-    nterms += __shfl_xor(nterms, off);
+    c.rhs += __shfl_xor(c.rhs, off);
+    c.med += __shfl_xor(c.med, off);
+    c.terms += __shfl_xor(c.terms, off);
+    c.tab += __shfl_xor(c.tab, off);
   }
   if (lane == 0) {
     int* wc = wcount + kWaveCounts * slot;
     wc[0] = __popcll(bc);
     wc[1] = __popcll(bd);
-    wc[2] = nrhs;
-    wc[3] = nmed;
-    wc[4] = nterms;
+    wc[2] = c.rhs;
+    wc[3] = c.med;
+    wc[4] = c.terms;
+    wc[5] = c.tab;
   }
 }
 
@@ -251,9 +295,10 @@ __global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, De
   med.x_q = x_q;
   med.hx2 = 0.5 * g.dx / g.S;
   med.s = g.z_a + (double)(r * g.rho - g.E) * g.h;
-  int st, nterms = 0, nmed = 0, nrhs = 0;
-  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, rec, st, nterms, nmed, nrhs);
-  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, nrhs, nmed, nterms);
+  int st;
+  Work c;
+  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, rec, st, c);
+  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
 }
 
 // Per-screen Gaussian tables in device memory.
@@ -286,9 +331,77 @@ __global__ void __launch_bounds__(256) march_gauss_kernel(Geometry g, GaussTabs<
   med.czl = tabs.czl + (size_t)w * tabs.nl;
   med.nl = tabs.nl;
   med.zl0 = (T)((double)(lane * g.rho) * g.h);
-  int st, nterms = 0, nmed = 0, nrhs = 0;
-  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, rec, st, nterms, nmed, nrhs);
-  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, nrhs, nmed, nterms);
+  int st;
+  Work c;
+  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, rec, st, c);
+  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
+}
+
+// Per-screen medium table of the mixed Gaussian-sum march: node i at height
+// z_lo + i dz_t and stage k at x_q + k hx/2 hold eps - 1 and its first three
+// z-derivatives.  Same candidate bumps and 8-sigma cutoff as the direct
+// evaluation, in FP64.  With g_i the bump value and d = z - cz_i:
+//   n - 1 = sum g_i,  n_z = -sum d g_i / s_i^2,
+//   n_zz = sum (d^2/s_i^2 - 1) g_i / s_i^2,  n_zzz = sum (3 - d^2/s_i^2) d g_i / s_i^4,
+//   eps - 1 = (n-1)(n+1), eps_z = 2 n n_z, eps_zz = 2 (n_z^2 + n n_zz),
+//   eps_zzz = 2 (3 n_z n_zz + n n_zzz).
+__global__ void __launch_bounds__(256) medium_table_kernel(const double* __restrict__ prm,
+                                                           const int* __restrict__ list, int nl, double x_q,
+                                                           double hx2, double z_lo, double dzt, int nt,
+                                                           float4* __restrict__ tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= nt) return;
+  const double x = x_q + k * hx2, z = z_lo + i * dzt;
+  double dn = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
+  for (int t = 0; t < nl; ++t) {
+    const double* b = prm + 1 + 4 * list[t];
+    const double ddx = x - b[2], ddz = z - b[3], s2 = b[1] * b[1];
+    if (ddx * ddx + ddz * ddz > 64.0 * s2) continue;
+    const double is2 = 1.0 / s2, d2 = ddz * ddz * is2;
+    const double gg = b[0] * exp(-0.5 * (ddx * ddx + ddz * ddz) * is2);
+    dn += gg;
+    n1 -= ddz * is2 * gg;
+    n2 += (d2 - 1.0) * is2 * gg;
+    n3 += (3.0 - d2) * ddz * is2 * is2 * gg;
+  }
+  const double n = 1.0 + dn;
+  tab[(size_t)k * nt + i] = make_float4((float)(dn * (2.0 + dn)), (float)(2.0 * n * n1),
+                                        (float)(2.0 * (n1 * n1 + n * n2)),
+                                        (float)(2.0 * (3.0 * n1 * n2 + n * n3)));
+}
+
+// Mixed-path Gaussian-sum march through the screen's medium table.
+__global__ void __launch_bounds__(256) march_table_kernel(Geometry g, GaussTabs<float> tabs, MedTab mt,
+                                                          DevModes modes, DevRecords rec, int* __restrict__ wcount,
+                                                          int waves_per_mode) {
+  const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const int lane = threadIdx.x & 63;
+  const int j = wave / waves_per_mode;
+  if (j >= g.M) return;  // uniform per wavefront
+  const int w = wave - j * waves_per_mode;
+  const int r = w * 64 + lane;
+  const bool active = r < g.R;
+  const ModeC mc = load_mode(modes, j);
+  TableMedium med;
+  med.direct.stage = tabs.stage;
+  med.direct.term = tabs.term;
+  med.direct.czl = tabs.czl + (size_t)w * tabs.nl;
+  med.direct.nl = tabs.nl;
+  med.direct.zl0 = (float)((double)(lane * g.rho) * g.h);
+  med.tab = mt.tab;
+  med.nt = mt.n;
+  med.dzt = (float)mt.dz;
+  med.inv_dz = (float)(1.0 / mt.dz);
+  const double rel = (g.z_a + (double)(w * 64 * g.rho - g.E) * g.h) - mt.z_lo;  // z_w above the table's base
+  med.j0 = (int)floor(rel / mt.dz);
+  med.f0 = (float)(rel - (double)med.j0 * mt.dz);
+  med.tlo = (float)(-med.j0);
+  med.thi = (float)(mt.n - 2 - med.j0);
+  int st;
+  Work c;
+  march_ray<float>(med, mc, g, active, (size_t)j * g.R + r, rec, st, c);
+  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
 }
 
 // One workgroup per mode: running maximum of live arrivals (search keys),
@@ -349,7 +462,7 @@ __global__ void __launch_bounds__(256) scan_kernel(Geometry g, DevRecords rec, c
   }
   // counts
   if (tid < 64) {
-    int v[kWaveCounts] = {0, 0, 0, 0, 0};
+    int v[kWaveCounts] = {0, 0, 0, 0, 0, 0};
     for (int w = tid; w < waves_per_mode; w += 64)
       for (int k = 0; k < kWaveCounts; ++k) v[k] += wcount[kWaveCounts * ((size_t)j * waves_per_mode + w) + k];
     for (int off = 32; off > 0; off >>= 1)
@@ -357,9 +470,10 @@ __global__ void __launch_bounds__(256) scan_kernel(Geometry g, DevRecords rec, c
     if (tid == 0) {
       rec.mcaus[j] = v[0];
       rec.mdead[j] = v[1];
-      rec.mwork[3 * j] = v[2];
-      rec.mwork[3 * j + 1] = v[3];
-      rec.mwork[3 * j + 2] = v[4];
+      rec.mwork[4 * j] = v[2];
+      rec.mwork[4 * j + 1] = v[3];
+      rec.mwork[4 * j + 2] = v[4];
+      rec.mwork[4 * j + 3] = v[5];
     }
   }
   __syncthreads();
@@ -430,6 +544,13 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
                           static_cast<const double*>(pl.gczl) + off * wpm, nl};
       hipLaunchKernelGGL(march_gauss_kernel<double>, grid, dim3(256), 0, st, g, t, modes_of(pl), pl.rec, wcount,
                          wpm);
+    } else if (pl.mtab.tab) {
+      GaussTabs<float> t{reinterpret_cast<const T2<float>*>(pl.gstage) + off * nst,
+                         reinterpret_cast<const T2<float>*>(pl.gterm) + off,
+                         static_cast<const float*>(pl.gczl) + off * wpm, nl};
+      // reads the table launch_medium_table built for screen q
+      hipLaunchKernelGGL(march_table_kernel, grid, dim3(256), 0, st, g, t, pl.mtab, modes_of(pl), pl.rec, wcount,
+                         wpm);
     } else {
       GaussTabs<float> t{reinterpret_cast<const T2<float>*>(pl.gstage) + off * nst,
                          reinterpret_cast<const T2<float>*>(pl.gterm) + off,
@@ -445,6 +566,16 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
   else
     hipLaunchKernelGGL(march_kernel<float>, grid, dim3(256), 0, st, g, medium_for(pl, q), modes_of(pl), pl.rec,
                        wcount, x_q, wpm);
+  return hipGetLastError();
+}
+
+hipError_t launch_medium_table(const swkb_plan_s& pl, int q, hipStream_t st) {
+  const MedTab& mt = pl.mtab;
+  if (!mt.tab || !pl.gfast || pl.precision == SWKB_FP64) return hipSuccess;
+  const int nl = pl.goff[q + 1] - pl.goff[q];
+  const double x_q = pl.p.x0 + q * pl.p.dx, hx2 = 0.5 * pl.p.dx / pl.tab_S;
+  hipLaunchKernelGGL(medium_table_kernel, dim3((mt.n + 255) / 256, 2 * pl.tab_S + 1), dim3(256), 0, st, pl.mprm,
+                     pl.glist + pl.goff[q], nl, x_q, hx2, mt.z_lo, mt.dz, mt.n, const_cast<float4*>(mt.tab));
   return hipGetLastError();
 }
 

@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
   }
   if (b != 0) return;
   __shared__ double sm[256];
-  __shared__ unsigned long long cnt[7];
+  __shared__ unsigned long long cnt[8];
   double emax = 0.0;
   for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
     double e = 0.0;
@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
     emax = fmax(emax, e);
   }
   sm[threadIdx.x] = emax;
-  if (threadIdx.x < 7) cnt[threadIdx.x] = 0;
+  if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
   __syncthreads();
   for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
   }
   emax = sm[0];
   const double thr = ep.caustic_tol * ep.caustic_tol * emax;
-  unsigned long long v[7] = {0, 0, 0, 0, 0, 0, 0};
+  unsigned long long v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
     const int f = rec.mflag[j];
     v[0] += rec.mcaus[j];
@@ -417,17 +417,18 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
       }
       if (e > thr) ++v[3];
     }
-    v[4] += (unsigned)rec.mwork[3 * j];
-    v[5] += (unsigned)rec.mwork[3 * j + 1];
-    v[6] += (unsigned)rec.mwork[3 * j + 2];
+    v[4] += (unsigned)rec.mwork[4 * j];
+    v[5] += (unsigned)rec.mwork[4 * j + 1];
+    v[6] += (unsigned)rec.mwork[4 * j + 2];
+    v[7] += (unsigned)rec.mwork[4 * j + 3];
   }
-  for (int k = 0; k < 7; ++k)
+  for (int k = 0; k < 8; ++k)
     if (v[k]) atomicAdd(&cnt[k], v[k]);
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], cnt[k]);
     atomicAdd(&counters[4], 1ull);
-    for (int k = 4; k < 7; ++k) atomicAdd(&counters[k + 1], cnt[k]);
+    for (int k = 4; k < 8; ++k) atomicAdd(&counters[k + 1], cnt[k]);
   }
 }
 

@@ -45,12 +45,19 @@ struct DevRecords {
   int* mflag;     // per mode: bit0 folded, bit1 has caustic rays
   int* mcaus;     // per mode: caustic rays this march
   int* mdead;     // per mode: dead rays this march
-  int* mwork;     // per mode: RK4 evaluations, medium evaluations, medium terms (3 ints)
+  int* mwork;     // per mode: RK4 evaluations, direct medium evaluations, medium terms, table reads (4 ints)
 };
 
-// Per-wavefront march counts: caustic, dead, RK4 evaluations, medium
-// evaluations, medium terms.
-constexpr int kWaveCounts = 5;
+// Per-wavefront march counts: caustic, dead, RK4 evaluations, direct medium
+// evaluations, medium terms, table reads.
+constexpr int kWaveCounts = 6;
+
+// Per-screen medium table of the mixed Gaussian-sum march (tab == NULL: none).
+struct MedTab {
+  const float4* tab;  // [(2S+1)][n] {eps - 1, eps_z, eps_zz, eps_zzz}
+  int n;              // z-nodes
+  double z_lo, dz;    // node i at z_lo + i dz
+};
 
 struct Geometry {
   int N, M, P, R, T, S, rho, E, bc, P1, P2;
@@ -78,6 +85,7 @@ struct swkb_plan_s {
   void* gstage;        // per screen [(2S+1)][nl] (a e^{-dx^2/2s^2}, 64 s^2 - dx^2) pairs of T
   void* gterm;         // per screen [nl] (-1/(2 s^2) [x log2 e in FP32], 1/s^2) pairs of T
   void* gczl;          // per screen [waves_per_mode][nl] bump heights minus each wavefront's z_w, T
+  swkb::MedTab mtab;   // mixed Gaussian-sum path: the current screen's medium table
   double2 *u, *ub;               // single field [N]; batch fields [B][N] (max_batch > 1)
   double2 *Y, *c;                // FFT scratch [B][P], modes [B][M]
   double2* part;                 // superposition partials [B][mode groups][N]
@@ -88,7 +96,7 @@ struct swkb_plan_s {
   void* tmat;                    // T[mode][point], complex T (double2 or float2)
   swkb::DevRecords rec;
   int* wcount;                   // per-wavefront march counts [M][waves][kWaveCounts]
-  unsigned long long* counters;  // caustic, dead, folded, significant, screens, rhs, med, terms
+  unsigned long long* counters;  // caustic, dead, folded, significant, screens, rhs, med, terms, table reads
   unsigned long long* counters_scratch;  // diagnostics of station evaluations (discarded)
   double* frac_st;               // per-station range phases [rk4_steps][M]
   // event timing
@@ -105,6 +113,10 @@ void set_error(const std::string& msg);
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, int batch, hipStream_t st);
+// Builds screen q's medium table where the plan marches through one (mixed
+// precision, Gaussian sum, periodic); no-op otherwise.  Call before
+// launch_march for the same screen.
+hipError_t launch_medium_table(const swkb_plan_s& pl, int q, hipStream_t st);
 hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st);
 hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st);
 // out [batch][N]; hist [batch][N] for this screen (or NULL).

@@ -48,13 +48,15 @@ class Params(C.Structure):
 class Counters(C.Structure):
     _fields_ = [("caustic_rays", C.c_int64), ("dead_rays", C.c_int64), ("folded_modes", C.c_int64),
                 ("significant", C.c_int64), ("screens", C.c_int64), ("rhs_evals", C.c_int64),
-                ("medium_evals", C.c_int64), ("medium_terms", C.c_int64)]
+                ("medium_evals", C.c_int64), ("medium_terms", C.c_int64),
+                ("table_evals", C.c_int64)]
 
 
 class Timing(C.Structure):
     _fields_ = [("march_ms", C.c_double), ("scan_ms", C.c_double), ("fft_ms", C.c_double),
                 ("superpose_ms", C.c_double), ("march_launches", C.c_int64), ("scan_launches", C.c_int64),
-                ("fft_launches", C.c_int64), ("superpose_launches", C.c_int64)]
+                ("fft_launches", C.c_int64), ("superpose_launches", C.c_int64),
+                ("table_ms", C.c_double), ("table_launches", C.c_int64)]
 
 
 class SwkbError(RuntimeError):

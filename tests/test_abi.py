@@ -38,20 +38,23 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, n), n
 
 
-def test_params_struct_layout_matches_header(tmp_path):
-    from paper_2301_03814_amd.swkb import Counters, Params
-    fields = [f for f, _ in Params._fields_]
+@pytest.mark.parametrize("cname,pyname", [("swkb_params", "Params"), ("swkb_counters", "Counters"),
+                                           ("swkb_timing", "Timing")])
+def test_struct_layout_matches_header(tmp_path, cname, pyname):
+    from paper_2301_03814_amd import swkb
+    S = getattr(swkb, pyname)
+    fields = [f for f, _ in S._fields_]
     src = ['#include <stddef.h>', '#include <stdio.h>', f'#include "{HEADER}"', 'int main(void){',
-           'printf("%zu\\n", sizeof(swkb_params));', 'printf("%zu\\n", sizeof(swkb_counters));']
-    src += [f'printf("%zu\\n", offsetof(swkb_params, {f}));' for f in fields]
+           f'printf("%zu\\n", sizeof({cname}));']
+    src += [f'printf("%zu\\n", offsetof({cname}, {f}));' for f in fields]
     src += ['return 0;}']
     c = tmp_path / "layout.c"
     c.write_text("\n".join(src))
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-std=c99", "-o", str(exe), str(c)])
     out = [int(x) for x in subprocess.check_output([str(exe)]).split()]
-    assert out[0] == C.sizeof(Params) and out[1] == C.sizeof(Counters)
-    assert out[2:] == [getattr(Params, f).offset for f in fields]
+    assert out[0] == C.sizeof(S)
+    assert out[1:] == [getattr(S, f).offset for f in fields]
 
 
 def test_workspace_bytes_validates_arguments(lib):

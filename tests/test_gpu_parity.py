@@ -216,6 +216,52 @@ def test_caustic_is_reported(torch_dev, swkb):
     plan.close()
 
 
+def test_mixed_medium_table_and_fallback(torch_dev, swkb, oracle_runs):
+    """The mixed Gaussian-sum march reads eps and its z-derivatives from a
+    per-screen FP64-built table (cubic Hermite in z) and evaluates the bump
+    sum directly for heights outside it.  In this case steep rays leave the
+    table, so both paths run; the result stays within the FP32 rounding
+    level of the FP64 run and within the mixed bar of the oracle."""
+    torch, dev = torch_dev
+    cfg, u0, ref, _ = oracle_runs("random_medium_N1024")
+    u0_d = torch.from_numpy(u0).to(dev)
+    res = {}
+    for prec in (swkb.FP64, swkb.MIXED):
+        plan = swkb.Plan(cfg, precision=prec, device=dev)
+        res[prec] = (plan.propagate(u0_d, 0, cfg["n_screens"]).cpu().numpy(), plan.diagnostics())
+        plan.close()
+    (h64, d64), (h32, d32) = res[swkb.FP64], res[swkb.MIXED]
+    say(f"[table] fp64 diag={d64}")
+    say(f"[table] mixed diag={d32}")
+    assert d64["table_evals"] == 0
+    assert d32["table_evals"] > 0 and d32["medium_evals"] > 0
+    err = rel(h32, h64)
+    say(f"[table] mixed vs fp64 rel_l2={err:.3e}, mixed vs oracle {rel(h32, ref):.3e}")
+    assert err <= 1e-4
+    assert rel(h32, ref) <= MIXED_TOL
+
+
+def test_mixed_direct_evaluation_when_table_too_fine(torch_dev, swkb, oracle_runs):
+    """A bump much narrower than the others would make the table too fine;
+    the mixed march then evaluates the bump sum directly at every stage."""
+    torch, dev = torch_dev
+    cfg, u0, _, _ = oracle_runs("random_medium_N1024")
+    mp = np.concatenate([cfg["medium_params"], [0.0, 1e-4, 60.0, 60.0]])  # zero amplitude, width 1e-4
+    mp[0] += 1
+    cfg = W.with_overrides(cfg, medium_params=mp)
+    u0_d = torch.from_numpy(u0).to(dev)
+    res = {}
+    for prec in (swkb.FP64, swkb.MIXED):
+        plan = swkb.Plan(cfg, precision=prec, device=dev)
+        res[prec] = (plan.propagate(u0_d, 0, cfg["n_screens"]).cpu().numpy(), plan.diagnostics())
+        plan.close()
+    (h64, _), (h32, d32) = res[swkb.FP64], res[swkb.MIXED]
+    err = rel(h32, h64)
+    say(f"[table] direct mixed diag={d32} vs fp64 rel_l2={err:.3e}")
+    assert d32["table_evals"] == 0 and d32["medium_evals"] > 0
+    assert err <= 1e-4
+
+
 @pytest.mark.slow
 def test_random_medium_full_size_sampled_screens(torch_dev, swkb):
     """Full random-medium workload (N = 8192, M = 2048, 400 screens) in the
@@ -241,8 +287,10 @@ def test_random_medium_full_size_sampled_screens(torch_dev, swkb):
         assert err <= FP64_TOL
     p32 = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
     h32 = p32.propagate(u0_d, 0, Q).cpu().numpy()
+    d32 = p32.diagnostics()
     err = rel(h32, hist)
-    say(f"[full] mixed vs fp64 over {Q} screens rel={err:.3e}")
+    say(f"[full] mixed vs fp64 over {Q} screens rel={err:.3e} diag={d32}")
+    assert d32["table_evals"] > 0
     assert err <= MIXED_TOL
     assert d64["significant"] == 0
     p64.close()
