@@ -154,7 +154,7 @@ bool gauss_fast(const swkb_params* p, const std::vector<int>& off) {
 // p^2 > p2_floor and eps <= 1 + max(0, sum of bump amplitudes)^2 terms).
 // Returns n = 0 where the direct evaluation is used.
 MedTab med_table(const swkb_params* p, const Geometry& g) {
-  MedTab t{nullptr, 0, 0.0, 0.0};
+  MedTab t{nullptr, nullptr, 0, 0.0, 0.0};
   if (p->medium_kind != SWKB_MEDIUM_GAUSSSUM || p->bc != SWKB_BC_PERIODIC || p->precision != SWKB_MIXED) return t;
   const int ng = (int)p->medium_params[0];
   if (ng < 1) return t;
@@ -169,7 +169,7 @@ MedTab med_table(const swkb_params* p, const Geometry& g) {
   t.dz = smin / 40.0;
   t.z_lo = g.z_a - margin;
   const double n = std::ceil(((g.z_b - g.z_a) + 2.0 * margin) / t.dz) + 2.0;
-  if (n > (double)(1 << 22)) return MedTab{nullptr, 0, 0.0, 0.0};  // too fine: evaluate directly
+  if (n > (double)(1 << 22)) return MedTab{nullptr, nullptr, 0, 0.0, 0.0};  // too fine: evaluate directly
   t.n = (int)n;
   return t;
 }
@@ -189,7 +189,7 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.e1r = take(sizeof(double) * g.M);
   L.frac = take(sizeof(double) * g.M);
   L.frac_st = take(sizeof(double) * g.M * (size_t)g.S);
-  L.mtab = take(sizeof(float4) * (size_t)med_table(p, g).n * (2 * g.S + 1));
+  L.mtab = take((sizeof(float4) + sizeof(float2)) * (size_t)med_table(p, g).n * (2 * g.S + 1));
   L.tw = take(sizeof(double2) * g.P);
   L.mprm = take(sizeof(double) * p->n_medium_params);
   L.glist = take(sizeof(int) * (nlist ? nlist : 1));
@@ -320,7 +320,10 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->frac = reinterpret_cast<double*>(ws + L.frac);
     pl->frac_st = reinterpret_cast<double*>(ws + L.frac_st);
     pl->mtab = med_table(p, g);
-    if (pl->mtab.n > 0) pl->mtab.tab = reinterpret_cast<const float4*>(ws + L.mtab);
+    if (pl->mtab.n > 0) {
+      pl->mtab.tab = reinterpret_cast<const float4*>(ws + L.mtab);
+      pl->mtab.tb = reinterpret_cast<const float2*>(pl->mtab.tab + (size_t)(2 * g.S + 1) * (pl->mtab.n - 1));
+    }
     pl->tw = reinterpret_cast<double2*>(ws + L.tw);
     pl->mprm = reinterpret_cast<double*>(ws + L.mprm);
     pl->glist = reinterpret_cast<int*>(ws + L.glist);

@@ -131,38 +131,52 @@ struct GaussMedium {
 };
 
 // Gaussian-sum medium read from a per-screen table (mixed path).  At each
-// RK4 stage position x_k of the screen the table holds eps - 1, eps_z,
-// eps_zz and eps_zzz, computed in FP64 and stored as FP32, on z-nodes
-// z_lo + i dz_t; a value at z is the cubic Hermite interpolant between the
-// two enclosing nodes, each quantity taking the next derivative as its
-// slope.  The interpolation error of a quantity f is at most
-// dz_t^4 max|f^(4)| / 384; with dz_t = s_min / 40 it stays below 1e-9 of
-// the bump amplitude for eps and eps_z and below 1e-8 for eps_zz (times
-// 1/s^2), under the FP32 rounding of a direct evaluation.  Heights outside
-// the table fall back to the direct evaluation.
+// RK4 stage position x_k of the screen, eps - 1 is the quintic Hermite
+// interpolant in z between nodes z_lo + i dz_t of its FP64 values and first
+// two z-derivatives; eps_z and eps_zz are the interpolant's derivatives.
+// Per interval the table holds power-form coefficients in u = (z - z_i)/dz_t,
+//   p(u) = c0 + c1 u + ... + c5 u^5:  ta[k][i] = (c0, c1, c2, c3), tb[k][i] = (c4, c5).
+// The interpolation error of eps - 1 is of order dz_t^6 max|eps^(6)|, of
+// eps_zz of order dz_t^4 max|eps^(6)|; with dz_t = s_min / 40 both stay
+// below 1e-7 relative, the FP32 rounding level of a direct evaluation.
+// Heights outside the table fall back to the direct evaluation.
 struct TableMedium {
-  const float4* __restrict__ tab;  // [(2S+1)][nt]
-  int nt;
-  float inv_dz, dzt;
-  int j0;          // node at or below the wavefront's reference height z_w
-  float f0;        // z_w minus the height of node j0, in [0, dz_t)
-  float tlo, thi;  // node offsets from j0 that keep nodes j0 + t and j0 + t + 1 inside
+  const float4* __restrict__ ta;  // [(2S+1)][ni]
+  const float2* __restrict__ tb;  // [(2S+1)][ni]
+  unsigned ni;                    // intervals
+  float inv_dz, inv_dz2x2;        // 1/dz_t, 2/dz_t^2
+  int j0;    // node at or below the wavefront's reference height z_w
+  float f0;  // z_w minus the height of node j0, in [0, dz_t)
   GaussMedium<float> direct;
   __device__ Med<float> eval(int k, float dz, Work& c) const {
     const float t = (f0 + direct.zl0 + dz) * inv_dz;
     const float tf = floorf(t);
-    // a NaN height fails both comparisons and takes the direct path too
-    if (!(tf >= tlo && tf <= thi)) return direct.eval(k, dz, c);
-    const int node = j0 + (int)tf;
+    // unsigned wrap sends heights below the table (and saturated conversions) out of range too
+    const unsigned iv = (unsigned)j0 + (unsigned)(int)tf;
+    if (!(iv < ni)) return direct.eval(k, dz, c);
     ++c.tab;
-    const float u = t - tf, v = 1.0f - u;
-    const float4 a = tab[k * nt + node], b = tab[k * nt + node + 1];
-    const float h00 = (1.0f + 2.0f * u) * v * v, h10 = u * v * v * dzt;
-    const float h01 = u * u * (3.0f - 2.0f * u), h11 = u * u * (u - 1.0f) * dzt;
+    const float u = t - tf;
+    const size_t o = (size_t)k * ni + iv;
+    const float4 a = ta[o];
+    const float2 b = tb[o];
+    // Horner for p, p' and p''/2 together
+    float p = b.y * u + b.x, d1 = b.y;
+    float d2 = d1;
+    d1 = d1 * u + p;
+    p = p * u + a.w;
+    d2 = d2 * u + d1;
+    d1 = d1 * u + p;
+    p = p * u + a.z;
+    d2 = d2 * u + d1;
+    d1 = d1 * u + p;
+    p = p * u + a.y;
+    d2 = d2 * u + d1;
+    d1 = d1 * u + p;
+    p = p * u + a.x;
     Med<float> m;
-    m.e1 = h00 * a.x + h10 * a.y + h01 * b.x + h11 * b.y;
-    m.ez = h00 * a.y + h10 * a.z + h01 * b.y + h11 * b.z;
-    m.ezz = h00 * a.z + h10 * a.w + h01 * b.z + h11 * b.w;
+    m.e1 = p;
+    m.ez = d1 * inv_dz;
+    m.ezz = d2 * inv_dz2x2;
     return m;
   }
 };
@@ -337,38 +351,62 @@ __global__ void __launch_bounds__(256) march_gauss_kernel(Geometry g, GaussTabs<
   wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
 }
 
-// Per-screen medium table of the mixed Gaussian-sum march: node i at height
-// z_lo + i dz_t and stage k at x_q + k hx/2 hold eps - 1 and its first three
-// z-derivatives.  Same candidate bumps and 8-sigma cutoff as the direct
-// evaluation, in FP64.  With g_i the bump value and d = z - cz_i:
-//   n - 1 = sum g_i,  n_z = -sum d g_i / s_i^2,
-//   n_zz = sum (d^2/s_i^2 - 1) g_i / s_i^2,  n_zzz = sum (3 - d^2/s_i^2) d g_i / s_i^4,
-//   eps - 1 = (n-1)(n+1), eps_z = 2 n n_z, eps_zz = 2 (n_z^2 + n n_zz),
-//   eps_zzz = 2 (3 n_z n_zz + n n_zzz).
-__global__ void __launch_bounds__(256) medium_table_kernel(const double* __restrict__ prm,
-                                                           const int* __restrict__ list, int nl, double x_q,
-                                                           double hx2, double z_lo, double dzt, int nt,
-                                                           float4* __restrict__ tab) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (i >= nt) return;
-  const double x = x_q + k * hx2, z = z_lo + i * dzt;
-  double dn = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
-  for (int t = 0; t < nl; ++t) {
-    const double* b = prm + 1 + 4 * list[t];
-    const double ddx = x - b[2], ddz = z - b[3], s2 = b[1] * b[1];
-    if (ddx * ddx + ddz * ddz > 64.0 * s2) continue;
-    const double is2 = 1.0 / s2, d2 = ddz * ddz * is2;
-    const double gg = b[0] * exp(-0.5 * (ddx * ddx + ddz * ddz) * is2);
-    dn += gg;
-    n1 -= ddz * is2 * gg;
-    n2 += (d2 - 1.0) * is2 * gg;
-    n3 += (3.0 - d2) * ddz * is2 * is2 * gg;
+// Per-screen medium table of the mixed Gaussian-sum march.  Node values at
+// height z_lo + i dz_t and stage x_q + k hx/2: eps - 1 and its first two
+// z-derivatives, from the same candidate bumps and 8-sigma cutoff as the
+// direct evaluation, in FP64.  With g_i the bump value and d = z - cz_i:
+//   n - 1 = sum g_i,  n_z = -sum d g_i / s_i^2,  n_zz = sum (d^2/s_i^2 - 1) g_i / s_i^2,
+//   eps - 1 = (n-1)(n+1), eps_z = 2 n n_z, eps_zz = 2 (n_z^2 + n n_zz).
+// Each block computes 256 consecutive nodes and writes the 255 intervals
+// between them (blocks overlap by one node).  Quintic Hermite coefficients
+// from node values f, slopes d = dz_t f' and curvatures s = dz_t^2 f'' at
+// both ends (D = f1 - f0):
+//   c0 = f0, c1 = d0, c2 = s0/2, c3 = 10 D - 6 d0 - 4 d1 - (3 s0 - s1)/2,
+//   c4 = -15 D + 8 d0 + 7 d1 + (3 s0 - 2 s1)/2, c5 = 6 D - 3 (d0 + d1) - (s0 - s1)/2.
+constexpr int kTabBumps = 256;  // bumps staged in LDS per pass
+constexpr int kTabNodes = 256;  // nodes per block
+
+__global__ void __launch_bounds__(kTabNodes) medium_table_kernel(const double* __restrict__ prm,
+                                                                 const int* __restrict__ list, int nl, double x_q,
+                                                                 double hx2, double z_lo, double dzt, int ni,
+                                                                 float4* __restrict__ ta, float2* __restrict__ tb) {
+  // per bump at this stage: a e^{-(x - cx)^2 / (2 s^2)}, 64 s^2 - (x - cx)^2, cz, 1/s^2
+  __shared__ double4 sb[kTabBumps];
+  __shared__ double4 nv[kTabNodes];  // eps - 1, dz_t eps_z, dz_t^2 eps_zz at this block's nodes
+  const int i = blockIdx.x * (kTabNodes - 1) + threadIdx.x;  // node
+  const double x = x_q + blockIdx.y * hx2, z = z_lo + i * dzt;
+  double dn = 0.0, n1 = 0.0, n2 = 0.0;
+  for (int t0 = 0; t0 < nl; t0 += kTabBumps) {
+    const int cnt = nl - t0 < kTabBumps ? nl - t0 : kTabBumps;
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const double* b = prm + 1 + 4 * list[t0 + t];
+      const double ddx = x - b[2], s2 = b[1] * b[1];
+      sb[t] = make_double4(b[0] * exp(-0.5 * ddx * ddx / s2), 64.0 * s2 - ddx * ddx, b[3], 1.0 / s2);
+    }
+    __syncthreads();
+    for (int t = 0; t < cnt; ++t) {
+      const double4 b = sb[t];
+      const double ddz = z - b.z, dz2 = ddz * ddz;
+      if (dz2 > b.y) continue;  // outside the 8-sigma disc
+      const double d2 = dz2 * b.w;
+      const double gg = b.x * exp(-0.5 * d2);
+      dn += gg;
+      n1 -= ddz * b.w * gg;
+      n2 += (d2 - 1.0) * b.w * gg;
+    }
   }
   const double n = 1.0 + dn;
-  tab[(size_t)k * nt + i] = make_float4((float)(dn * (2.0 + dn)), (float)(2.0 * n * n1),
-                                        (float)(2.0 * (n1 * n1 + n * n2)),
-                                        (float)(2.0 * (3.0 * n1 * n2 + n * n3)));
+  nv[threadIdx.x] = make_double4(dn * (2.0 + dn), dzt * 2.0 * n * n1, dzt * dzt * 2.0 * (n1 * n1 + n * n2), 0.0);
+  __syncthreads();
+  if (threadIdx.x >= kTabNodes - 1 || i >= ni) return;
+  const double4 p = nv[threadIdx.x], q = nv[threadIdx.x + 1];
+  const double D = q.x - p.x;
+  const size_t o = (size_t)blockIdx.y * ni + i;
+  ta[o] = make_float4((float)p.x, (float)p.y, (float)(0.5 * p.z),
+                      (float)(10.0 * D - 6.0 * p.y - 4.0 * q.y - 0.5 * (3.0 * p.z - q.z)));
+  tb[o] = make_float2((float)(-15.0 * D + 8.0 * p.y + 7.0 * q.y + 0.5 * (3.0 * p.z - 2.0 * q.z)),
+                      (float)(6.0 * D - 3.0 * (p.y + q.y) - 0.5 * (p.z - q.z)));
 }
 
 // Mixed-path Gaussian-sum march through the screen's medium table.
@@ -389,15 +427,14 @@ __global__ void __launch_bounds__(256) march_table_kernel(Geometry g, GaussTabs<
   med.direct.czl = tabs.czl + (size_t)w * tabs.nl;
   med.direct.nl = tabs.nl;
   med.direct.zl0 = (float)((double)(lane * g.rho) * g.h);
-  med.tab = mt.tab;
-  med.nt = mt.n;
-  med.dzt = (float)mt.dz;
+  med.ni = (unsigned)(mt.n - 1);
+  med.ta = mt.tab;
+  med.tb = mt.tb;
   med.inv_dz = (float)(1.0 / mt.dz);
+  med.inv_dz2x2 = (float)(2.0 / (mt.dz * mt.dz));
   const double rel = (g.z_a + (double)(w * 64 * g.rho - g.E) * g.h) - mt.z_lo;  // z_w above the table's base
   med.j0 = (int)floor(rel / mt.dz);
   med.f0 = (float)(rel - (double)med.j0 * mt.dz);
-  med.tlo = (float)(-med.j0);
-  med.thi = (float)(mt.n - 2 - med.j0);
   int st;
   Work c;
   march_ray<float>(med, mc, g, active, (size_t)j * g.R + r, rec, st, c);
@@ -574,8 +611,10 @@ hipError_t launch_medium_table(const swkb_plan_s& pl, int q, hipStream_t st) {
   if (!mt.tab || !pl.gfast || pl.precision == SWKB_FP64) return hipSuccess;
   const int nl = pl.goff[q + 1] - pl.goff[q];
   const double x_q = pl.p.x0 + q * pl.p.dx, hx2 = 0.5 * pl.p.dx / pl.tab_S;
-  hipLaunchKernelGGL(medium_table_kernel, dim3((mt.n + 255) / 256, 2 * pl.tab_S + 1), dim3(256), 0, st, pl.mprm,
-                     pl.glist + pl.goff[q], nl, x_q, hx2, mt.z_lo, mt.dz, mt.n, const_cast<float4*>(mt.tab));
+  const int ni = mt.n - 1;  // intervals; a block writes kTabNodes - 1 of them
+  hipLaunchKernelGGL(medium_table_kernel, dim3((ni + kTabNodes - 2) / (kTabNodes - 1), 2 * pl.tab_S + 1),
+                     dim3(kTabNodes), 0, st, pl.mprm, pl.glist + pl.goff[q], nl, x_q, hx2, mt.z_lo, mt.dz, ni,
+                     const_cast<float4*>(mt.tab), const_cast<float2*>(mt.tb));
   return hipGetLastError();
 }
 
