@@ -136,8 +136,11 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, frac_st, tw, mtab, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, part, tmat, D, Pp, G, A, key, tstart, mflag,
-      mcaus, mdead, mwork, wcount, counters;
+  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, part, tmat, counters;
+  // one ray-record slot (offsets from its start); nslots of them from slot0
+  size_t mtab, D, Pp, G, A, key, cidx, tstart, mflag, mcaus, mdead, mwork, wcount;
+  size_t slot0, slot_bytes;
+  int nslots;
   size_t total;
 };
 
@@ -189,7 +192,6 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.e1r = take(sizeof(double) * g.M);
   L.frac = take(sizeof(double) * g.M);
   L.frac_st = take(sizeof(double) * g.M * (size_t)g.S);
-  L.mtab = take((sizeof(float4) + sizeof(float2)) * (size_t)med_table(p, g).n * (2 * g.S + 1));
   L.tw = take(sizeof(double2) * g.P);
   L.mprm = take(sizeof(double) * p->n_medium_params);
   L.glist = take(sizeof(int) * (nlist ? nlist : 1));
@@ -203,21 +205,28 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.Y = take(sizeof(double2) * g.P * B);
   L.c = take(sizeof(double2) * g.M * B);
   L.cf = take(B > 1 && use_matrix(p) && p->precision == SWKB_MIXED ? sizeof(float2) * g.M * B : 0);
-  L.part = take(sizeof(double2) * (size_t)g.N * superpose_groups(g) * B);
+  L.part = take(sizeof(double2) * (size_t)g.N * partial_groups(g) * B);
   L.tmat = take(use_matrix(p) ? matrix_bytes(p) : 0);
+  L.counters = take(sizeof(unsigned long long) * 32);
+  // ray-record slots: two for media that change with x (march and sum overlap)
+  L.slot0 = o;
+  o = 0;
+  L.mtab = take((sizeof(float4) + sizeof(float2)) * (size_t)med_table(p, g).n * (2 * g.S + 1));
   L.D = take(ts * MR);
   L.Pp = take(ts * MR);
   L.G = take(ts * MR);
   L.A = take(ts * MR);
   L.key = take(sizeof(double) * MR);
+  L.cidx = take(sizeof(int) * MR);
   L.tstart = take(sizeof(int) * (size_t)g.M * (g.T + 1));
   L.mflag = take(sizeof(int) * g.M);
   L.mcaus = take(sizeof(int) * g.M);
   L.mdead = take(sizeof(int) * g.M);
   L.mwork = take(sizeof(int) * 4 * (size_t)g.M);
   L.wcount = take(sizeof(int) * kWaveCounts * (size_t)g.M * waves_per_mode(g));
-  L.counters = take(sizeof(unsigned long long) * 32);
-  L.total = o;
+  L.slot_bytes = o;
+  L.nslots = p->medium_kind == SWKB_MEDIUM_GAUSSSUM ? 2 : 1;
+  L.total = L.slot0 + L.slot_bytes * L.nslots;
   return L;
 }
 
@@ -260,17 +269,88 @@ static hipError_t timed(swkb_plan_s* pl, int cls, hipStream_t st, F&& launch) {
   return e;
 }
 
-static swkb_status ensure_rays(swkb_plan_s* pl, int q, hipStream_t st) {
-  if (pl->x_invariant ? pl->march_valid_q == -2 : pl->march_valid_q == q) return SWKB_OK;
+// The launchers read the active slot's records through pl->rec, pl->wcount
+// and pl->mtab (captured by value at each launch).
+static void select_slot(swkb_plan_s* pl, int k) {
+  const swkb_plan_s::Slot& sl = pl->slots[k];
+  pl->rec = sl.rec;
+  pl->wcount = sl.wcount;
+  pl->mtab = sl.mtab;
+  pl->march_valid_q = sl.q;
+}
+
+static void set_slot_q(swkb_plan_s* pl, int k, int q) {
+  pl->slots[k].q = q;
+  if (pl->rec.D == pl->slots[k].rec.D) pl->march_valid_q = q;
+}
+
+static void destroy_streams(swkb_plan_s* pl) {
+  if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+  for (int k = 0; k < 2; ++k) {
+    if (pl->ev_ready[k]) (void)hipEventDestroy(pl->ev_ready[k]);
+    if (pl->ev_free[k]) (void)hipEventDestroy(pl->ev_free[k]);
+  }
+  if (pl->ms) (void)hipStreamDestroy(pl->ms);
+  pl->ms = nullptr;
+  pl->ev_fork = nullptr;
+  for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = nullptr;
+}
+
+static int slot_of(const swkb_plan_s* pl, int q) { return pl->nslots == 2 ? (q & 1) : 0; }
+
+// Table, march and scan of screen q into slot k on stream st.
+static hipError_t march_chain(swkb_plan_s* pl, int q, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (pl->mtab.tab) e = timed(pl, kProfTable, st, [&] { return launch_medium_table(*pl, q, st); });
   if (e == hipSuccess) e = timed(pl, kProfMarch, st, [&] { return launch_march(*pl, q, st); });
   if (e == hipSuccess) e = timed(pl, kProfScan, st, [&] { return launch_scan(*pl, st); });
+  return e;
+}
+
+// Rays of screen q in the active slot, marched on st if the slot lacks them.
+static swkb_status ensure_rays(swkb_plan_s* pl, int q, hipStream_t st) {
+  const int k = pl->x_invariant ? 0 : slot_of(pl, q);
+  select_slot(pl, k);
+  if (pl->x_invariant ? pl->slots[k].q == -2 : pl->slots[k].q == q) return SWKB_OK;
+  const hipError_t e = march_chain(pl, q, st);
   if (e != hipSuccess) {
-    pl->march_valid_q = -1;
+    set_slot_q(pl, k, -1);
     return hip_fail(e, "ray march launch");
   }
-  pl->march_valid_q = pl->x_invariant ? -2 : q;
+  set_slot_q(pl, k, pl->x_invariant ? -2 : q);
+  return SWKB_OK;
+}
+
+// Overlap march and sum on two streams: x-varying medium without profiling
+// (per-kernel event times need the kernels one after another).
+static bool overlap(const swkb_plan_s* pl) {
+  return pl->nslots == 2 && pl->ms && !pl->use_matrix && !pl->x_invariant && !pl->prof_on;
+}
+
+// Screens [q_begin, q_end) of an x-varying medium with the march of the next
+// screen overlapping the sum of the current one: slot k = q & 1 is filled on
+// the march stream (after the sum that last read it) and summed on st.
+// field(q, st) launches the screen's FFT and sum.
+template <typename F>
+static swkb_status pipelined(swkb_plan_s* pl, int q_begin, int q_end, hipStream_t st, F&& field) {
+  hipError_t e = hipEventRecord(pl->ev_fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(pl->ms, pl->ev_fork, 0);
+  bool pending_free[2] = {false, false};
+  for (int q = q_begin; q < q_end && e == hipSuccess; ++q) {
+    const int k = q & 1;
+    select_slot(pl, k);
+    if (pl->slots[k].q != q) {
+      if (pending_free[k]) e = hipStreamWaitEvent(pl->ms, pl->ev_free[k], 0);
+      if (e == hipSuccess) e = march_chain(pl, q, pl->ms);
+      if (e == hipSuccess) e = hipEventRecord(pl->ev_ready[k], pl->ms);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, pl->ev_ready[k], 0);
+      set_slot_q(pl, k, e == hipSuccess ? q : -1);
+    }
+    if (e == hipSuccess) e = field(q);
+    if (e == hipSuccess) e = hipEventRecord(pl->ev_free[k], st);
+    pending_free[k] = true;
+  }
+  if (e != hipSuccess) return hip_fail(e, "screen launch");
   return SWKB_OK;
 }
 
@@ -319,11 +399,6 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->e1r = reinterpret_cast<double*>(ws + L.e1r);
     pl->frac = reinterpret_cast<double*>(ws + L.frac);
     pl->frac_st = reinterpret_cast<double*>(ws + L.frac_st);
-    pl->mtab = med_table(p, g);
-    if (pl->mtab.n > 0) {
-      pl->mtab.tab = reinterpret_cast<const float4*>(ws + L.mtab);
-      pl->mtab.tb = reinterpret_cast<const float2*>(pl->mtab.tab + (size_t)(2 * g.S + 1) * (pl->mtab.n - 1));
-    }
     pl->tw = reinterpret_cast<double2*>(ws + L.tw);
     pl->mprm = reinterpret_cast<double*>(ws + L.mprm);
     pl->glist = reinterpret_cast<int*>(ws + L.glist);
@@ -340,17 +415,45 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->part = reinterpret_cast<double2*>(ws + L.part);
     pl->use_matrix = use_matrix(p) ? 1 : 0;
     pl->tmat = ws + L.tmat;
-    pl->rec.D = ws + L.D;
-    pl->rec.Pp = ws + L.Pp;
-    pl->rec.G = ws + L.G;
-    pl->rec.A = ws + L.A;
-    pl->rec.key = reinterpret_cast<double*>(ws + L.key);
-    pl->rec.tstart = reinterpret_cast<int*>(ws + L.tstart);
-    pl->rec.mflag = reinterpret_cast<int*>(ws + L.mflag);
-    pl->rec.mcaus = reinterpret_cast<int*>(ws + L.mcaus);
-    pl->rec.mdead = reinterpret_cast<int*>(ws + L.mdead);
-    pl->rec.mwork = reinterpret_cast<int*>(ws + L.mwork);
-    pl->wcount = reinterpret_cast<int*>(ws + L.wcount);
+    pl->nslots = L.nslots;
+    for (int k = 0; k < 2; ++k) {
+      char* sb = ws + L.slot0 + L.slot_bytes * (k < L.nslots ? k : 0);
+      swkb_plan_s::Slot& sl = pl->slots[k];
+      sl.rec.D = sb + L.D;
+      sl.rec.Pp = sb + L.Pp;
+      sl.rec.G = sb + L.G;
+      sl.rec.A = sb + L.A;
+      sl.rec.key = reinterpret_cast<double*>(sb + L.key);
+      sl.rec.cidx = reinterpret_cast<int*>(sb + L.cidx);
+      sl.rec.tstart = reinterpret_cast<int*>(sb + L.tstart);
+      sl.rec.mflag = reinterpret_cast<int*>(sb + L.mflag);
+      sl.rec.mcaus = reinterpret_cast<int*>(sb + L.mcaus);
+      sl.rec.mdead = reinterpret_cast<int*>(sb + L.mdead);
+      sl.rec.mwork = reinterpret_cast<int*>(sb + L.mwork);
+      sl.wcount = reinterpret_cast<int*>(sb + L.wcount);
+      sl.mtab = med_table(p, g);
+      if (sl.mtab.n > 0) {
+        sl.mtab.tab = reinterpret_cast<const float4*>(sb + L.mtab);
+        sl.mtab.tb = reinterpret_cast<const float2*>(sl.mtab.tab + (size_t)(2 * g.S + 1) * (sl.mtab.n - 1));
+      }
+      sl.q = -1;
+    }
+    select_slot(pl, 0);
+    pl->ms = nullptr;
+    pl->ev_fork = nullptr;
+    for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = nullptr;
+    if (pl->nslots == 2) {
+      bool ok = hipStreamCreateWithFlags(&pl->ms, hipStreamNonBlocking) == hipSuccess &&
+                hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess;
+      for (int k = 0; k < 2 && ok; ++k)
+        ok = hipEventCreateWithFlags(&pl->ev_ready[k], hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&pl->ev_free[k], hipEventDisableTiming) == hipSuccess;
+      if (!ok) {
+        destroy_streams(pl);
+        delete pl;
+        return fail(SWKB_ERR_DEVICE, "swkb_plan: stream or event creation failed");
+      }
+    }
     pl->prof_on = 0;
     pl->ev_used = 0;
     pl->counters = reinterpret_cast<unsigned long long*>(ws + L.counters);
@@ -442,10 +545,11 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
       e = launch_march(*pl, 0, st);
       if (e == hipSuccess) e = launch_scan(*pl, st);
       if (e == hipSuccess) e = launch_build_matrix(*pl, st);
-      if (e == hipSuccess) pl->march_valid_q = -2;
+      if (e == hipSuccess) set_slot_q(pl, 0, -2);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host tables go out of scope
     if (e != hipSuccess) {
+      destroy_streams(pl);
       delete pl;
       return hip_fail(e, "swkb_plan upload");
     }
@@ -475,21 +579,26 @@ swkb_status swkb_propagate(swkb_plan_t pl, const void* u_in, int32_t q_begin, in
     pl->cur_q = q_begin;
     return SWKB_OK;
   }
-  for (int q = q_begin; q < q_end; ++q) {
-    if (!pl->use_matrix) {
-      swkb_status s = ensure_rays(pl, q, st);
-      if (s != SWKB_OK) return s;
-    }
+  auto field = [&](int q) {
     hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, 1, st); });
-    if (e != hipSuccess) return hip_fail(e, "fft launch");
+    if (e != hipSuccess) return e;
     double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * g.N : nullptr;
     if (pl->use_matrix)
       e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->u, hist, 1, st); });
     else
       e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->u, hist, 1, st); });
-    if (e != hipSuccess) return hip_fail(e, "superposition launch");
     src = pl->u;
     pl->cur_q = q + 1;
+    return e;
+  };
+  if (overlap(pl)) return pipelined(pl, q_begin, q_end, st, field);
+  for (int q = q_begin; q < q_end; ++q) {
+    if (!pl->use_matrix) {
+      swkb_status s = ensure_rays(pl, q, st);
+      if (s != SWKB_OK) return s;
+    }
+    const hipError_t e = field(q);
+    if (e != hipSuccess) return hip_fail(e, "screen launch");
   }
   return SWKB_OK;
 }
@@ -533,20 +642,29 @@ swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch
     pl->blas = h;
   }
   const double2* src = static_cast<const double2*>(u_in);
-  for (int q = q_begin; q < q_end; ++q) {
-    if (!pl->use_matrix) {
-      swkb_status s = ensure_rays(pl, q, st);
-      if (s != SWKB_OK) return s;
-    }
+  auto field = [&](int q) {
     hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, batch, st); });
-    if (e != hipSuccess) return hip_fail(e, "fft launch");
+    if (e != hipSuccess) return e;
     double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * batch * g.N : nullptr;
     if (pl->use_matrix)
       e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->ub, hist, batch, st); });
     else
       e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->ub, hist, batch, st); });
-    if (e != hipSuccess) return hip_fail(e, "batched screen launch");
     src = pl->ub;
+    return e;
+  };
+  if (overlap(pl)) {
+    swkb_status s = pipelined(pl, q_begin, q_end, st, field);
+    if (s != SWKB_OK) return s;
+  } else {
+    for (int q = q_begin; q < q_end; ++q) {
+      if (!pl->use_matrix) {
+        swkb_status s = ensure_rays(pl, q, st);
+        if (s != SWKB_OK) return s;
+      }
+      const hipError_t e = field(q);
+      if (e != hipSuccess) return hip_fail(e, "batched screen launch");
+    }
   }
   if (u_out) {
     hipError_t e = hipMemcpyAsync(u_out, pl->ub, sizeof(double2) * g.N * batch, hipMemcpyDeviceToDevice, st);
@@ -564,6 +682,8 @@ swkb_status swkb_propagate_stations(swkb_plan_t pl, const void* u, int32_t q, co
     if (stations[s] < 1 || stations[s] > g.S) return fail(SWKB_ERR_ARG, "stations must be in [1, rk4_steps]");
   hipStream_t st = (hipStream_t)hip_stream;
   const double hx = pl->p.dx / pl->p.rk4_steps;
+  const int k = pl->x_invariant ? 0 : slot_of(pl, q);  // slot the station rays go through
+  select_slot(pl, k);
   try {
     // range phase frac(pbar * i hx / lambda) of every mode at every station
     std::vector<double> pbar(g.M), fr((size_t)n * g.M);
@@ -598,12 +718,12 @@ swkb_status swkb_propagate_stations(swkb_plan_t pl, const void* u, int32_t q, co
     }
     if (e != hipSuccess) return hip_fail(e, "stations");
     // the records now hold station rays: re-establish the plan's own march
-    pl->march_valid_q = -1;
+    set_slot_q(pl, k, -1);
     if (pl->use_matrix) {
       e = launch_march(*pl, 0, st);
       if (e == hipSuccess) e = launch_scan(*pl, st);
       if (e != hipSuccess) return hip_fail(e, "stations");
-      pl->march_valid_q = -2;
+      set_slot_q(pl, k, -2);
     }
   } catch (const std::exception& ex) {
     return fail(SWKB_ERR_NOMEM, std::string("stations: ") + ex.what());
@@ -680,6 +800,7 @@ void swkb_destroy(swkb_plan_t pl) {
   if (!pl) return;
   if (pl->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(pl->blas));
   for (hipEvent_t ev : pl->ev_pool) (void)hipEventDestroy(ev);
+  destroy_streams(pl);
   delete pl;
 }
 

@@ -37,17 +37,18 @@ __device__ inline double2 extended(const double2* __restrict__ u, int i, int N, 
 
 // nb sequences of length len (power of two) stored at L[b * len + i] in
 // bit-reversed order; in-place radix-2 decimation in time.  The twiddle of
-// butterfly k at half-size hs is e^{-2 pi i k / (2 hs)} = tw[k * P / (2 hs)].
-__device__ void lds_fft(double2* L, int nb, int len, const double2* __restrict__ tw, int P) {
+// butterfly k at half-size hs is e^{-2 pi i k / (2 hs)} = wl[k * len / (2 hs)],
+// wl[k] = e^{-2 pi i k / len} (k < len / 2) staged in LDS.
+__device__ void lds_fft(double2* L, int nb, int len, const double2* wl) {
   const int half = len >> 1;
   const int nbf = nb * half;
   for (int hs = 1; hs < len; hs <<= 1) {
-    const int tstride = P / (2 * hs);
+    const int tstride = len / (2 * hs);
     for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
       const int seq = b / half, bb = b - seq * half;
       const int grp = bb / hs, kk = bb - grp * hs;
       const int i0 = seq * len + grp * 2 * hs + kk, i1 = i0 + hs;
-      const double2 w = tw[kk * tstride];
+      const double2 w = wl[kk * tstride];
       const double2 x0 = L[i0];
       const double2 x1 = cmul(L[i1], w);
       L[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
@@ -60,16 +61,18 @@ __device__ void lds_fft(double2* L, int nb, int len, const double2* __restrict__
 __global__ void __launch_bounds__(256) fft_cols(const double2* __restrict__ u, double2* __restrict__ Y,
                                                 const double2* __restrict__ tw, int N, int bc, int P, int P1,
                                                 int P2, int logP1, int CA) {
-  extern __shared__ double2 L[];  // CA sequences of length P1
+  extern __shared__ double2 L[];  // CA sequences of length P1, then P1 / 2 twiddles
+  double2* wl = L + CA * P1;
   const int c0 = blockIdx.x * CA;
   u += (size_t)blockIdx.y * N;  // field of this batch member
   Y += (size_t)blockIdx.y * P;
+  for (int k = threadIdx.x; k < P1 / 2; k += blockDim.x) wl[k] = tw[k * (P / P1)];
   for (int idx = threadIdx.x; idx < CA * P1; idx += blockDim.x) {
     const int cc = idx % CA, m1 = idx / CA;
     L[cc * P1 + bitrev(m1, logP1)] = extended(u, P2 * m1 + c0 + cc, N, bc);
   }
   __syncthreads();
-  lds_fft(L, CA, P1, tw, P);
+  lds_fft(L, CA, P1, wl);
   for (int idx = threadIdx.x; idx < CA * P1; idx += blockDim.x) {
     const int cc = idx % CA, n1 = idx / CA, m2 = c0 + cc;
     Y[n1 * P2 + m2] = cmul(L[cc * P1 + n1], tw[n1 * m2]);  // n1 m2 < P
@@ -79,16 +82,18 @@ __global__ void __launch_bounds__(256) fft_cols(const double2* __restrict__ u, d
 __global__ void __launch_bounds__(256) fft_rows(const double2* __restrict__ Y, double2* __restrict__ c,
                                                 const double2* __restrict__ tw, int P, int P1, int P2,
                                                 int logP2, int RB, int M) {
-  extern __shared__ double2 L[];  // RB sequences of length P2
+  extern __shared__ double2 L[];  // RB sequences of length P2, then P2 / 2 twiddles
+  double2* wl = L + RB * P2;
   const int r0 = blockIdx.x * RB;
   Y += (size_t)blockIdx.y * P;  // batch member
   c += (size_t)blockIdx.y * M;
+  for (int k = threadIdx.x; k < P2 / 2; k += blockDim.x) wl[k] = tw[k * (P / P2)];
   for (int idx = threadIdx.x; idx < RB * P2; idx += blockDim.x) {
     const int rr = idx / P2, m2 = idx - rr * P2;
     L[rr * P2 + bitrev(m2, logP2)] = Y[(r0 + rr) * P2 + m2];
   }
   __syncthreads();
-  lds_fft(L, RB, P2, tw, P);
+  lds_fft(L, RB, P2, wl);
   const double inv = 1.0 / (double)P;  // exact: P is a power of two
   const int halfM = M >> 1;
   for (int idx = threadIdx.x; idx < RB * P2; idx += blockDim.x) {
@@ -118,11 +123,13 @@ hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, int batch, 
   int RB = 2048 / g.P2;
   if (RB < 1) RB = 1;
   if (RB > g.P1) RB = g.P1;
-  hipLaunchKernelGGL(fft_cols, dim3(g.P2 / CA, batch), dim3(256), sizeof(double2) * CA * g.P1, st, u, pl.Y, pl.tw,
+  hipLaunchKernelGGL(fft_cols, dim3(g.P2 / CA, batch), dim3(256), sizeof(double2) * (CA * g.P1 + g.P1 / 2), st, u,
+                     pl.Y, pl.tw,
                      g.N, g.bc, g.P, g.P1, g.P2, ilog2(g.P1), CA);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fft_rows, dim3(g.P1 / RB, batch), dim3(256), sizeof(double2) * RB * g.P2, st, pl.Y, pl.c, pl.tw,
+  hipLaunchKernelGGL(fft_rows, dim3(g.P1 / RB, batch), dim3(256), sizeof(double2) * (RB * g.P2 + g.P2 / 2), st,
+                     pl.Y, pl.c, pl.tw,
                      g.P, g.P1, g.P2, ilog2(g.P2), RB, g.M);
   return hipGetLastError();
 }

@@ -18,7 +18,8 @@
 // FP64 number per mode, and only the small deviation dpsi is marched:
 //   d dpsi/dx = ((eps - eps_ref_n) - (q - xi)(q + xi)) / (p + pbar) + q (q - xi) / p
 // (= eps/p - xi q/p - pbar, written in small quantities).  State per ray:
-// dz = z - s, dq = q - xi, dpsi in T; Zs, Qs always in FP64.
+// dz = z - s, dq = q - xi, dpsi, Zs, Qs in T (FP32 in the mixed path); the
+// amplitude on arrival in FP64.
 //
 // Ray r of mode n starts at s_r = z_a + (r rho - E) h with q = xi_n
 // (Sec. 2.1.2 initial conditions), Zs = 1, Qs = 0.  A ray is dead when
@@ -37,7 +38,7 @@ struct ModeC {
 template <typename T>
 struct Deriv {
   T dz, dq, dps;
-  double Zs, Qs;
+  T Zs, Qs;
 };
 
 enum { kLive = 0, kDeadLaunch = 1, kDead = 2, kCaustic = 3 };
@@ -183,7 +184,7 @@ struct TableMedium {
 
 // Right-hand side at stage k.  Returns kLive, kDead or kCaustic.
 template <typename T, typename MED>
-__device__ inline int rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, double Zs, double Qs,
+__device__ inline int rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, T Zs, T Qs,
                          double p2_floor, Deriv<T>& d, Work& c) {
   if (!(Zs > 0.0)) return kCaustic;
   const Med<T> m = med.eval(k, dz, c);
@@ -196,13 +197,13 @@ __device__ inline int rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, do
   d.dz = q * ip;
   d.dq = T(0.5) * m.ez * ip;
   d.dps = ((m.e1 - (T)mc.e1r) - dq * (q + xi)) * fast_rcp<T>(p + (T)mc.pbar) + q * dq * ip;
-  // ray-tube variations: coefficients in T, the update in FP64
+  // ray-tube variations
   const T ip3 = ip * ip * ip;
   const T qe = T(0.5) * q * m.ez * ip3;                          // q eps_z / (2 p^3)
   const T c12 = (T(1) + m.e1) * ip3;                              // eps / p^3
   const T c21 = T(0.5) * m.ezz * ip - T(0.25) * m.ez * m.ez * ip3; // eps_zz/(2p) - eps_z^2/(4p^3)
-  d.Zs = (double)c12 * Qs - (double)qe * Zs;
-  d.Qs = (double)c21 * Zs + (double)qe * Qs;
+  d.Zs = c12 * Qs - qe * Zs;
+  d.Qs = c21 * Zs + qe * Qs;
   return kLive;
 }
 
@@ -212,7 +213,7 @@ template <typename T, typename MED>
 __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry& g, bool active, size_t o,
                                  DevRecords& rec, int& st, Work& c) {
   T dz = T(0), dq = T(0), dps = T(0);
-  double Zs = 1.0, Qs = 0.0;
+  T Zs = T(1), Qs = T(0);
   double amp = 0.0;
   st = kLive;
   if (!active) return;
@@ -224,7 +225,7 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
     const double p0 = (double)sqrt(p02);
     const double hx = g.dx / g.S;
     const T hh = (T)(0.5 * hx), hf = (T)hx, h6 = (T)(hx / 6.0);
-    const double hd2 = 0.5 * hx, hd6 = hx / 6.0;
+    const T hd2 = (T)(0.5 * hx), hd6 = (T)(hx / 6.0);
     Deriv<T> k1, k2, k3, k4;
     for (int i = 0; i < g.S; ++i) {
       if ((st = rhs<T>(med, mc, 2 * i, dz, dq, Zs, Qs, g.p2_floor, k1, c))) break;
@@ -234,15 +235,15 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
       if ((st = rhs<T>(med, mc, 2 * i + 1, dz + hh * k2.dz, dq + hh * k2.dq, Zs + hd2 * k2.Zs, Qs + hd2 * k2.Qs,
                        g.p2_floor, k3, c)))
         break;
-      if ((st = rhs<T>(med, mc, 2 * i + 2, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hx * k3.Zs, Qs + hx * k3.Qs,
+      if ((st = rhs<T>(med, mc, 2 * i + 2, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hf * k3.Zs, Qs + hf * k3.Qs,
                        g.p2_floor, k4, c)))
         break;
       c.rhs += 4;
       dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
       dq += h6 * (k1.dq + T(2) * k2.dq + T(2) * k3.dq + k4.dq);
       dps += h6 * (k1.dps + T(2) * k2.dps + T(2) * k3.dps + k4.dps);
-      Zs += hd6 * (k1.Zs + 2.0 * k2.Zs + 2.0 * k3.Zs + k4.Zs);
-      Qs += hd6 * (k1.Qs + 2.0 * k2.Qs + 2.0 * k3.Qs + k4.Qs);
+      Zs += hd6 * (k1.Zs + T(2) * k2.Zs + T(2) * k3.Zs + k4.Zs);
+      Qs += hd6 * (k1.Qs + T(2) * k2.Qs + T(2) * k3.Qs + k4.Qs);
     }
     if (st == kLive) {
       if (!(Zs > 0.0)) {
@@ -252,7 +253,7 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
         const T xi = (T)mc.xi;
         const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
         if (!(p2 > (T)g.p2_floor)) st = kDead;
-        else amp = sqrt(p0 / ((double)sqrt(p2) * Zs));
+        else amp = sqrt(p0 / ((double)sqrt(p2) * (double)Zs));
       }
     }
   }
@@ -441,69 +442,103 @@ __global__ void __launch_bounds__(256) march_table_kernel(Geometry g, GaussTabs<
   wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
 }
 
-// One workgroup per mode: running maximum of live arrivals (search keys),
-// the fold test (live arrivals must increase strictly), the per-tile search
-// windows and the mode's ray counts.
+// One workgroup per mode: running maximum of live arrival heights (search
+// keys), the first grid point at or above each key, the fold test (live
+// arrivals must increase strictly), the per-tile search windows and the
+// mode's ray counts.  Each thread takes `run` consecutive rays (run =
+// ceil(R / 256), at most 8; longer ray sets are taken in several chunks):
+// the thread's maximum, a workgroup exclusive prefix maximum over threads
+// plus the carry of the previous chunk, then the thread's keys in order.
+//
+// Ray r owns the grid points [ci_r, ci_{r+1}), ci_r = smallest m in [0, N]
+// with z_m >= key_r (N + 1 if none; 0 for an empty key): those are the
+// points whose largest r' with key_{r'} <= z_m is r.  Tile t (first point
+// 64 t) therefore starts in the interval of ray r - 1 for
+// ceil(ci_{r-1} / 64) <= t < ceil(ci_r / 64) (ci_{-1} = 0), and tiles at or
+// above ceil(ci_{R-1} / 64) in that of ray R - 1.
+constexpr int kScanThreads = 256;
+constexpr int kScanRun = 8;  // most consecutive rays per thread
+
+__device__ inline int first_point_at_or_above(const Geometry& g, double key, double inv_h) {
+  if (key == -INFINITY) return 0;
+  const double x = (key - g.z_a) * inv_h;
+  int ci = x <= 0.0 ? 0 : (x >= (double)(g.N + 1) ? g.N + 1 : (int)ceil(x));
+  // exact decisions with the same arithmetic as z_m = z_a + m h
+  while (ci > 0 && g.z_a + (double)(ci - 1) * g.h >= key) --ci;
+  while (ci <= g.N && g.z_a + (double)ci * g.h < key) ++ci;
+  return ci;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) scan_kernel(Geometry g, DevRecords rec, const int* __restrict__ wcount,
-                                                   int waves_per_mode) {
-  __shared__ double sh[256];
+__global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecords rec,
+                                                            const int* __restrict__ wcount, int waves_per_mode) {
+  __shared__ double wtot[kScanThreads / 64];
   __shared__ int sfold;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int j = blockIdx.x;
-  const int tid = threadIdx.x;
   const size_t base = (size_t)j * g.R;
   int* __restrict__ ts = rec.tstart + (size_t)j * (g.T + 1);
-  const double tileh = (double)kTile * g.h;
+  const T* __restrict__ A = static_cast<const T*>(rec.A) + base;
+  const T* __restrict__ D = static_cast<const T*>(rec.D) + base;
+  const double inv_h = 1.0 / g.h;
+  int run = (g.R + kScanThreads - 1) / kScanThreads;
+  if (run > kScanRun) run = kScanRun;
   if (tid == 0) sfold = 0;
-  double carry = -INFINITY;
-  for (int c0 = 0; c0 < g.R; c0 += 256) {
-    const int r = c0 + tid;
-    double Z = -INFINITY;
-    bool live = false;
-    if (r < g.R) {
-      const T a = static_cast<const T*>(rec.A)[base + r];
-      live = a > T(0);
-      if (live) Z = (g.z_a + (double)(r * g.rho - g.E) * g.h) + (double)static_cast<const T*>(rec.D)[base + r];
+  double carry = -INFINITY;  // key of the last ray before this chunk
+  int carry_ci = 0;          // its first point
+  bool fold = false;
+  for (int c0 = 0; c0 < g.R; c0 += kScanThreads * run) {
+    const int r0 = c0 + tid * run;  // this thread's first ray
+    double Z[kScanRun];
+    double lmax = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < kScanRun; ++i) {
+      const int r = r0 + i;
+      Z[i] = -INFINITY;
+      if (i < run && r < g.R && A[r] > T(0)) Z[i] = (g.z_a + (double)(r * g.rho - g.E) * g.h) + (double)D[r];
+      lmax = fmax(lmax, Z[i]);
     }
-    sh[tid] = Z;
+    double incl = lmax;  // wavefront inclusive prefix maximum
+    for (int off = 1; off < 64; off <<= 1) {
+      const double v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl = fmax(incl, v);
+    }
+    if (lane == 63) wtot[wv] = incl;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const double v = tid >= off ? sh[tid - off] : -INFINITY;
-      __syncthreads();
-      sh[tid] = fmax(sh[tid], v);
-      __syncthreads();
-    }
-    const double incl = fmax(carry, sh[tid]);
-    const double prev = fmax(carry, tid > 0 ? sh[tid - 1] : -INFINITY);  // key of ray r-1
-    if (live && !(Z > prev)) sfold = 1;
-    if (r < g.R) {
-      rec.key[base + r] = incl;
-      // tiles whose first point z_t satisfies key_{r-1} <= z_t < key_r get window start r-1
-      if (incl > prev) {
-        int t = prev == -INFINITY ? 0 : (int)floor((prev - g.z_a) / tileh) - 1;
-        if (t < 0) t = 0;
-        for (; t <= g.T; ++t) {
-          const double zt = g.z_a + (double)(t * kTile) * g.h;
-          if (!(zt < incl)) break;
-          if (prev <= zt) ts[t] = r - 1;
-        }
+    double key = __shfl_up(incl, 1, 64);
+    if (lane == 0) key = -INFINITY;
+    for (int k = 0; k < wv; ++k) key = fmax(key, wtot[k]);
+    key = fmax(carry, key);  // key of ray r0 - 1
+    int ci_prev = first_point_at_or_above(g, key, inv_h);
+#pragma unroll
+    for (int i = 0; i < kScanRun; ++i) {
+      const int r = r0 + i;
+      if (i < run && r < g.R) {
+        if (Z[i] != -INFINITY && !(Z[i] > key)) fold = true;
+        key = fmax(key, Z[i]);
+        const int ci = first_point_at_or_above(g, key, inv_h);
+        rec.key[base + r] = key;
+        rec.cidx[base + r] = ci;
+        for (int t = (ci_prev + 63) >> 6; t < ((ci + 63) >> 6) && t <= g.T; ++t) ts[t] = r - 1;
+        ci_prev = ci;
       }
     }
-    carry = fmax(carry, sh[255]);
-    __syncthreads();
+    double tot = carry;
+    for (int k = 0; k < kScanThreads / 64; ++k) tot = fmax(tot, wtot[k]);
+    __syncthreads();  // wtot is rewritten by the next chunk
+    carry = tot;
+    carry_ci = first_point_at_or_above(g, carry, inv_h);
   }
-  // tiles at or above the last key start at the last ray
-  for (int t = tid; t <= g.T; t += 256) {
-    const double zt = g.z_a + (double)(t * kTile) * g.h;
-    if (carry <= zt) ts[t] = g.R - 1;
-  }
+  // the last ray of the mode is R - 1: carry holds its key, carry_ci its first point
+  for (int t = ((carry_ci + 63) >> 6) + tid; t <= g.T; t += kScanThreads) ts[t] = g.R - 1;
+  if (fold) sfold = 1;
   // counts
   if (tid < 64) {
     int v[kWaveCounts] = {0, 0, 0, 0, 0, 0};
     for (int w = tid; w < waves_per_mode; w += 64)
       for (int k = 0; k < kWaveCounts; ++k) v[k] += wcount[kWaveCounts * ((size_t)j * waves_per_mode + w) + k];
     for (int off = 32; off > 0; off >>= 1)
-      for (int k = 0; k < kWaveCounts; ++k) v[k] += __shfl_down(v[k], off);
+      for (int k = 0; k < kWaveCounts; ++k) v[k] += __shfl_down(v[k], off, 64);
     if (tid == 0) {
       rec.mcaus[j] = v[0];
       rec.mdead[j] = v[1];
@@ -623,9 +658,9 @@ hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st) {
   const int wpm = waves_per_mode(g);
   const int* wcount = pl.wcount;
   if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL(scan_kernel<double>, dim3(g.M), dim3(256), 0, st, g, pl.rec, wcount, wpm);
+    hipLaunchKernelGGL(scan_kernel<double>, dim3(g.M), dim3(kScanThreads), 0, st, g, pl.rec, wcount, wpm);
   else
-    hipLaunchKernelGGL(scan_kernel<float>, dim3(g.M), dim3(256), 0, st, g, pl.rec, wcount, wpm);
+    hipLaunchKernelGGL(scan_kernel<float>, dim3(g.M), dim3(kScanThreads), 0, st, g, pl.rec, wcount, wpm);
   return hipGetLastError();
 }
 

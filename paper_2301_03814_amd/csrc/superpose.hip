@@ -299,6 +299,175 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
   }
 }
 
+// Sum over modes for one screen, organised by interval owner.  For a mode,
+// grid point m belongs to the interval of the largest ray r with
+// key_r <= z_m, i.e. to the points [ci_r, ci_{r+1}) where ci_r is the first
+// grid index at or above key_r (computed by the scan).  So every point has
+// exactly one interval per mode and the intervals of one mode cover
+// disjoint point ranges: the lane that owns interval (r, r+1) builds its
+// record in registers and adds its contribution to each of its points in
+// the wavefront's LDS accumulator, with no search and no write conflict.
+//
+// Grid (super-tiles, mode groups, field chunks); block = kWaves wavefronts.
+// Wavefront w of group gi takes modes j = gi * kWaves + w + k * (groups *
+// kWaves).  Per mode it walks the super-tile's intervals [tstart of its
+// first tile, tstart of the next super-tile], 61 per pass (the lane holds
+// ray a0 - 1 + lane; interval lanes 1..61 read rays r - 1 .. r + 2 through
+// shuffles).  At the end the kWaves accumulators are summed in a fixed order
+// into part[b][gi][m]; the contributions to one accumulator entry arrive in
+// program order, so the result does not depend on scheduling.
+//
+// LDS accumulator row of a wavefront: point m at m + m / 8 (intervals are
+// about rho points long, so the lanes of one step fall into different banks).
+template <typename T, int NB>
+__global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, DevModes modes, DevRecords rec,
+                                                                   const double2* __restrict__ c,
+                                                                   double2* __restrict__ part, Epi ep, int sub,
+                                                                   int batch) {
+  extern __shared__ double2 lds_raw[];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int gi = blockIdx.y;
+  const int jstep = (int)gridDim.y * kWaves;
+  const int b0 = (int)blockIdx.z * NB;
+  const int nb = batch - b0 < NB ? batch - b0 : NB;
+  const int t0 = (int)blockIdx.x * sub;                 // first 64-point tile of the super-tile
+  const int t1 = t0 + sub < g.T ? t0 + sub : g.T;       // (the last super-tile may be shorter)
+  const int npts = (t1 - t0) * 64;
+  const int m0 = t0 * 64;                                // its first grid point
+  const int row = sub * 64 + sub * 8;
+  T* acc = reinterpret_cast<T*>(lds_raw) + (size_t)w * 2 * NB * row;  // [NB][re | im][row]
+  for (int i = lane; i < 2 * NB * row; i += 64) acc[i] = T(0);
+  const double inv_lam = 1.0 / g.lam;
+  const T* __restrict__ D = static_cast<const T*>(rec.D);
+  const T* __restrict__ Pp = static_cast<const T*>(rec.Pp);
+  const T* __restrict__ G = static_cast<const T*>(rec.G);
+  const T* __restrict__ A = static_cast<const T*>(rec.A);
+  const int pmask = g.P - 1;  // P is a power of two
+  const int mp0 = m0 + ep.mprime_off;
+  const double zs0 = g.z_a + (double)m0 * g.h;
+  for (int j = gi * kWaves + w; j < g.M; j += jstep) {
+    if (rec.mflag[j] & 1) continue;  // folded mode
+    const int* ts = rec.tstart + (size_t)j * (g.T + 1);
+    const int lo = ts[t0], hi = ts[t1];
+    // intervals (r, r + 1) for r in [ia, ib]
+    const int ia = lo > 0 ? lo : 0;
+    const int ib = hi < g.R - 2 ? hi : g.R - 2;
+    if (ia > ib) continue;
+    const size_t base = (size_t)j * g.R;
+    const int n = j - (g.M >> 1);
+    const int nm0 = (n * mp0) & pmask;
+    T cjr[NB], cji[NB];
+    for (int bb = 0; bb < NB; ++bb) {
+      const double2 v = bb < nb ? c[(size_t)(b0 + bb) * g.M + j] : make_double2(0.0, 0.0);
+      cjr[bb] = (T)v.x;
+      cji[bb] = (T)v.y;
+    }
+    const T fj = (T)modes.frac[j];
+    const double fjd = modes.frac[j];
+    for (int a0 = ia; a0 <= ib; a0 += 61) {
+      const int a1 = a0 + 60 < ib ? a0 + 60 : ib;  // intervals [a0, a1] in this pass
+      const int rl = a0 - 1 + lane;                 // ray held by this lane
+      const bool in = rl >= 0 && rl < g.R;
+      const T dl = in ? D[base + rl] : T(0);
+      const T al = in ? A[base + rl] : T(-1);
+      const T pl = in ? Pp[base + rl] : T(0);
+      const T gl = in ? G[base + rl] : T(0);
+      const int cl = in ? rec.cidx[base + rl] : 0;
+      const T dm1 = wave_shfl(dl, lane - 1), dp1 = wave_shfl(dl, lane + 1), dp2 = wave_shfl(dl, lane + 2);
+      const T am1 = wave_shfl(al, lane - 1), ap1 = wave_shfl(al, lane + 1), ap2 = wave_shfl(al, lane + 2);
+      const T pp1 = wave_shfl(pl, lane + 1), gp1 = wave_shfl(gl, lane + 1);
+      const int cp1 = __shfl(cl, lane + 1, 64);
+      int mlo = 0, mhi = 0;  // owned points [m0 + mlo, m0 + mhi)
+      T zr = T(0), H = T(1), c0 = T(0), c1 = T(0), c2 = T(0), c3 = T(0), q0 = T(0), q1 = T(0), q2 = T(0), q3 = T(0);
+      if (rl >= a0 && rl <= a1 && al > T(0) && ap1 > T(0)) {
+        T xm, x3;
+        if constexpr (std::is_same<T, double>::value) {
+          const double Zl = (g.z_a + (double)(rl * g.rho - g.E) * g.h) + dl;
+          const double Zn = (g.z_a + (double)((rl + 1) * g.rho - g.E) * g.h) + dp1;
+          zr = Zl - zs0;
+          H = Zn - Zl;
+          xm = ((g.z_a + (double)((rl - 1) * g.rho - g.E) * g.h) + dm1) - Zl;
+          x3 = ((g.z_a + (double)((rl + 2) * g.rho - g.E) * g.h) + dp2) - Zl;
+        } else {
+          const float hf = (float)g.h;
+          const float rh = (float)g.rho * hf;
+          zr = (float)(rl * g.rho - g.E - m0) * hf + dl;
+          H = rh + (dp1 - dl);
+          xm = -rh + (dm1 - dl);
+          x3 = T(2) * rh + (dp2 - dl);
+        }
+        if (H > T(0)) {
+          const T iH = rcp_t<T>(H);
+          const T dlt = (pp1 - pl) * iH;
+          c0 = pl;
+          c1 = gl;
+          c2 = (T(3) * dlt - T(2) * gl - gp1) * iH;
+          c3 = (gl + gp1 - T(2) * dlt) * iH * iH;
+          const bool cubic = rl >= 1 && rl + 2 < g.R && am1 > T(0) && ap2 > T(0);
+          const T f01 = (ap1 - al) * iH;
+          q0 = al;
+          if (cubic) {
+            // Newton form on nodes 0, H, xm (ray r-1), x3 (ray r+2), then powers of tau
+            const T f12 = (am1 - ap1) * rcp_t<T>(xm - H);
+            const T f23 = (ap2 - am1) * rcp_t<T>(x3 - xm);
+            const T f012 = (f12 - f01) * rcp_t<T>(xm);
+            const T f123 = (f23 - f12) * rcp_t<T>(x3 - H);
+            const T f0123 = (f123 - f012) * rcp_t<T>(x3);
+            q1 = f01 - H * f012 + H * xm * f0123;
+            q2 = f012 - (H + xm) * f0123;
+            q3 = f0123;
+          } else {
+            q1 = f01;
+          }
+          mlo = cl - m0 > 0 ? cl - m0 : 0;
+          mhi = cp1 - m0 < npts ? cp1 - m0 : npts;
+        }
+      }
+      int nm = (nm0 + n * mlo) & pmask;
+      for (int m = mlo; m < mhi; ++m) {
+        T tau;
+        if constexpr (std::is_same<T, double>::value) tau = (double)m * g.h - zr;
+        else tau = (float)m * (float)g.h - zr;
+        const T dps = ((c3 * tau + c2) * tau + c1) * tau + c0;
+        const T a = ((q3 * tau + q2) * tau + q1) * tau + q0;
+        T sn, cs;
+        if constexpr (std::is_same<T, double>::value) {
+          double turns = (double)nm / (double)g.P + fjd + dps * inv_lam;
+          turns -= floor(turns);
+          sincospi(2.0 * turns, &sn, &cs);
+        } else {
+          float turns = (float)nm * (1.0f / (float)g.P) + fj + dps * (float)inv_lam;
+          turns -= floorf(turns);
+          sn = __builtin_amdgcn_sinf(turns);  // argument in revolutions
+          cs = __builtin_amdgcn_cosf(turns);
+        }
+        const T ea = a * cs, eb = a * sn;  // a e^{i phase}
+        const int pm = m + (m >> 3);
+        for (int bb = 0; bb < NB; ++bb) {
+          // lanes of one step own different points; LDS keeps the wavefront's accesses in order
+          acc[(2 * bb) * row + pm] += cjr[bb] * ea - cji[bb] * eb;
+          acc[(2 * bb + 1) * row + pm] += cjr[bb] * eb + cji[bb] * ea;
+        }
+        nm = (nm + n) & pmask;
+      }
+    }
+  }
+  __syncthreads();
+  T* acc0 = reinterpret_cast<T*>(lds_raw);
+  for (int bb = 0; bb < nb; ++bb) {
+    for (int m = threadIdx.x; m < npts; m += blockDim.x) {
+      const int pm = m + (m >> 3);
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k < kWaves; ++k) {
+        sr += (double)acc0[((size_t)k * 2 * NB + 2 * bb) * row + pm];
+        si += (double)acc0[((size_t)k * 2 * NB + 2 * bb + 1) * row + pm];
+      }
+      part[((size_t)(b0 + bb) * gridDim.y + gi) * g.N + m0 + m] = make_double2(sr, si);
+    }
+  }
+}
+
 // One screen from the mode-function matrix: part[gi][m] = sum over the
 // group's modes of c_j T[j][m], in the same grid/partial layout as the
 // superposition (a streaming read of T, coalesced along m).
@@ -383,8 +552,10 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
     return;
   }
   if (b != 0) return;
-  __shared__ double sm[256];
-  __shared__ unsigned long long cnt[8];
+  // diagnostics: wavefront reductions, then the four wavefronts in order
+  __shared__ double sm[4];
+  __shared__ unsigned long long cnt[4][8];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double emax = 0.0;
   for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
     double e = 0.0;
@@ -394,14 +565,10 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
     }
     emax = fmax(emax, e);
   }
-  sm[threadIdx.x] = emax;
-  if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
+  for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off, 64));
+  if (lane == 0) sm[wv] = emax;
   __syncthreads();
-  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-    __syncthreads();
-  }
-  emax = sm[0];
+  emax = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
   const double thr = ep.caustic_tol * ep.caustic_tol * emax;
   unsigned long long v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
@@ -423,12 +590,16 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
     v[7] += (unsigned)rec.mwork[4 * j + 3];
   }
   for (int k = 0; k < 8; ++k)
-    if (v[k]) atomicAdd(&cnt[k], v[k]);
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  if (lane == 0)
+    for (int k = 0; k < 8; ++k) cnt[wv][k] = v[k];
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], cnt[k]);
+    unsigned long long t[8];
+    for (int k = 0; k < 8; ++k) t[k] = ((cnt[0][k] + cnt[1][k]) + cnt[2][k]) + cnt[3][k];
+    for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], t[k]);
     atomicAdd(&counters[4], 1ull);
-    for (int k = 4; k < 8; ++k) atomicAdd(&counters[k + 1], cnt[k]);
+    for (int k = 4; k < 8; ++k) atomicAdd(&counters[k + 1], t[k]);
   }
 }
 
@@ -444,8 +615,8 @@ __global__ void to_c64_kernel(const double2* __restrict__ c, float2* __restrict_
 // several wavefronts per SIMD.
 int superpose_sub(const Geometry& g) { return g.T < kSub ? g.T : kSub; }
 
-int superpose_groups(const Geometry& g) {
-  const int tiles = g.T / superpose_sub(g);
+static int groups_for(const Geometry& g, int sub) {
+  const int tiles = (g.T + sub - 1) / sub;
   int groups = (256 * 4 * 6) / (tiles * kWaves);
   if (groups < 1) groups = 1;
   const int maxg = (g.M + kWaves - 1) / kWaves;
@@ -454,14 +625,33 @@ int superpose_groups(const Geometry& g) {
   return groups;
 }
 
+int superpose_groups(const Geometry& g) { return groups_for(g, superpose_sub(g)); }
+
+// Interval-owner sum: a pass handles 61 intervals, so a super-tile spans
+// about 48 ray spacings (rho points each) and fits one pass unless rays
+// crowd; at most 512 points (FP32) or 256 (FP64) for the LDS accumulators.
+static int iv_sub(const Geometry& g, int precision) {
+  int s = (48 * g.rho) / 64;
+  const int smax = precision == SWKB_FP64 ? 4 : 8;
+  if (s > smax) s = smax;
+  if (s < 1) s = 1;
+  return g.T < s ? g.T : s;
+}
+
+int partial_groups(const Geometry& g) {
+  int m = superpose_groups(g);
+  for (int s = 1; s <= 8; ++s) m = groups_for(g, s) > m ? groups_for(g, s) : m;
+  return m;
+}
+
 template <typename T, int NB>
 static void launch_sum(const swkb_plan_s& pl, const dim3& grid, const DevModes& md, const Epi& ep, int sub, int batch,
                        hipStream_t st) {
-  const size_t red = sizeof(double2) * 64 * kWaves * kSub;
-  const size_t shmem = red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<T>));
+  const int row = sub * 64 + sub * 8;
+  const size_t shmem = sizeof(T) * (size_t)kWaves * 2 * NB * row;
   const dim3 g3(grid.x, grid.y, (batch + NB - 1) / NB);
-  hipLaunchKernelGGL((superpose_kernel<T, false, NB>), g3, dim3(64 * kWaves), shmem, st, pl.g, md, pl.rec, pl.c,
-                     pl.part, static_cast<typename CplxOf<T>::type*>(nullptr), ep, sub, batch);
+  hipLaunchKernelGGL((superpose_iv_kernel<T, NB>), g3, dim3(64 * kWaves), shmem, st, pl.g, md, pl.rec, pl.c, pl.part,
+                     ep, sub, batch);
 }
 
 static Epi epi_of(const swkb_plan_s& pl) {
@@ -476,10 +666,12 @@ static Epi epi_of(const swkb_plan_s& pl) {
 hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st) {
   const Geometry& g = pl.g;
   const Epi ep = epi_of(pl);
-  const int sub = superpose_sub(g);
-  const int groups = superpose_groups(g);
+  // batches keep the accumulators of NB fields in LDS: 256-point super-tiles
+  int sub = iv_sub(g, pl.precision);
+  if (batch > 1 && sub > 4) sub = 4;
+  const int groups = groups_for(g, sub);
   DevModes md{pl.xi, pl.pbar, pl.e1r, pl.frac};
-  const dim3 grid(g.T / sub, groups);
+  const dim3 grid((g.T + sub - 1) / sub, groups);
   if (pl.precision == SWKB_FP64) {
     if (batch == 1) launch_sum<double, 1>(pl, grid, md, ep, sub, batch, st);
     else launch_sum<double, 2>(pl, grid, md, ep, sub, batch, st);

@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/swkb.h"
+#include "swkb.h"
 
 namespace swkb {
 
@@ -41,6 +41,7 @@ struct DevRecords {
   void* G;        // q - xi at arrival, T
   void* A;        // transport factor a (> 0 live); -flag otherwise, T
   double* key;    // running maximum of live arrival heights (search keys)
+  int* cidx;      // first grid index m in [0, N] with z_m >= key, N + 1 if none (ray r owns [cidx_r, cidx_{r+1}))
   int* tstart;    // [mode][tile 0..T]: largest r with key_r <= z of the tile's first point
   int* mflag;     // per mode: bit0 folded, bit1 has caustic rays
   int* mcaus;     // per mode: caustic rays this march
@@ -73,7 +74,7 @@ struct swkb_plan_s {
   swkb::Geometry g;
   int precision;
   int x_invariant;
-  int march_valid_q;   // screen whose rays the records hold (-1 none; -2 any, x-invariant)
+  int march_valid_q;   // screen whose rays the active slot holds (-1 none; -2 any, x-invariant)
   int cur_q;
   // device pointers inside the caller's workspace
   double *xi, *pbar, *e1r, *frac;
@@ -100,6 +101,19 @@ struct swkb_plan_s {
   unsigned long long* counters;  // caustic, dead, folded, significant, screens, rhs, med, terms, table reads
   unsigned long long* counters_scratch;  // diagnostics of station evaluations (discarded)
   double* frac_st;               // per-station range phases [rk4_steps][M]
+  // Ray records of two screens (x-varying media): the march of screen q + 1
+  // fills one slot on stream `ms` while screen q is summed from the other on
+  // the caller's stream.  rec, wcount and mtab above are the active slot.
+  struct Slot {
+    swkb::DevRecords rec;
+    int* wcount;
+    swkb::MedTab mtab;
+    int q;  // screen whose rays the slot holds (-1 none, -2 x-invariant)
+  };
+  Slot slots[2];
+  int nslots;
+  hipStream_t ms;                // march stream (default priority), or NULL
+  hipEvent_t ev_fork, ev_ready[2], ev_free[2];
   // event timing
   int prof_on;
   std::vector<hipEvent_t> ev_pool;
@@ -123,6 +137,8 @@ hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st);
 // out [batch][N]; hist [batch][N] for this screen (or NULL).
 hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st);
 int superpose_groups(const Geometry& g);
+// Largest number of mode groups any superposition writes partial sums for.
+int partial_groups(const Geometry& g);
 hipError_t launch_build_matrix(const swkb_plan_s& pl, hipStream_t st);
 hipError_t launch_to_c64(const swkb_plan_s& pl, int batch, hipStream_t st);
 // U[b][m] = sum_j C[b][j] T[j][m] for batch > 1 into pl.part (rocBLAS GEMM)

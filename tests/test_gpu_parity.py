@@ -183,6 +183,33 @@ def test_resume_and_determinism(torch_dev, swkb):
         p.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_overlapped_march_equals_serial(torch_dev, swkb, prec):
+    """For a medium that changes with x the march of screen q + 1 runs on a
+    second stream while screen q is summed (two record slots).  With
+    profiling on, every kernel runs on the caller's stream one after
+    another; both orders give the same field bit for bit, also when single
+    screens are stepped one call at a time and the same screen is
+    propagated twice."""
+    torch, dev = torch_dev
+    cfg = small_random()
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    Q = cfg["n_screens"]
+    p = swkb.Plan(cfg, precision=swkb.FP64 if prec == "fp64" else swkb.MIXED, device=dev)
+    fast = p.propagate(u0, 0, Q)
+    p.profile(True)
+    slow = p.propagate(u0, 0, Q)
+    t = p.profile_read()
+    p.profile(False)
+    assert t["march_launches"] == Q and t["superpose_launches"] == Q
+    assert torch.equal(fast, slow)
+    steps = [p.propagate(u0 if q == 0 else None, q, q + 1) for q in range(Q)]
+    assert torch.equal(torch.cat(steps), fast)
+    again = p.propagate(fast[2].contiguous(), 3, 4)  # screen 3 again: its rays are reused
+    assert torch.equal(again[0], fast[3])
+    p.close()
+
+
 def test_zero_screens_and_state_errors(torch_dev, swkb):
     torch, dev = torch_dev
     cfg = W.linear_caustic()
