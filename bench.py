@@ -26,16 +26,16 @@ METRIC = "mode×point evals/s; range km/s at 1e-3 rel err vs FP64 plain; p50/p99
 
 # Algorithmic flops of the ray march (transcendentals, divisions and square
 # roots count as one flop each; a fused multiply-add as two):
-#   per RK4 stage evaluation of the ray system                      55
-#     (39 in the right-hand side, 16 in the stage/step combinations)
-#   per evaluation of eps, eps_z, eps_zz from the index deviation     9
+#   per RK4 stage evaluation of the ray system                      51
+#     (35 in the right-hand side, 16 in the stage/step combinations)
+#   per evaluation of eps, eps_z/2, eps_zz/2 from the index deviation 7
 #   per Gaussian term inside its cutoff (distance, exp, 3 sums)      22
 #   per medium value read from the per-screen table (node index and
-#     offset 5, three cubics in Horner form 18)                       23
-FLOPS_PER_RHS = 55
-FLOPS_PER_MEDIUM = 9
+#     offset 4, quintic and its two derivatives by Horner 24, scaling 2)  30
+FLOPS_PER_RHS = 51
+FLOPS_PER_MEDIUM = 7
 FLOPS_PER_TERM = 22
-FLOPS_PER_TABLE = 23
+FLOPS_PER_TABLE = 30
 PEAK_FP32_VECTOR = 157.3e12   # MI355X published dense FP32 vector FLOP/s
 PEAK_FP64_VECTOR = 78.6e12
 
@@ -121,9 +121,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-duct", action="store_true", help="skip the surface-duct measurement")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the step with per-kernel events (kernels one after another), for rocprofv3")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy kernel over BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
+    if args.profile_only:
+        args.steps = 0
     if args.copy_probe:
         import torch
         n = args.copy_probe // 4
@@ -160,6 +164,22 @@ def main():
             step(name)
     torch.cuda.synchronize()
 
+    def roof(r, peak, prec):
+        w, p = r["work"], r["prof"]
+        flops = FLOPS_PER_RHS * w["rhs_evals"] + FLOPS_PER_MEDIUM * w["medium_evals"] + \
+            FLOPS_PER_TERM * w["medium_terms"] + FLOPS_PER_TABLE * w["table_evals"]
+        launches = max(1, p["march_launches"])
+        avg_s = p["march_ms"] * 1e-3 / launches
+        per_launch = flops / launches
+        achieved = per_launch / avg_s / 1e12
+        t = traffic_from_profiles(prec)
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
+                "frac": round(achieved * 1e12 / peak, 4), "traffic": t,
+                "kernel": "march_table_kernel" if w["table_evals"] else
+                          f"march_gauss_kernel<{'float' if prec == 'mixed' else 'double'}>",
+                "table_share": round(w["table_evals"] / max(1, w["table_evals"] + w["medium_evals"]), 4),
+                "flops_per_launch": per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
+
     res = {}
     for name, plan in plans.items():
         # timed steps: no per-kernel events
@@ -186,7 +206,13 @@ def main():
                                                 "screens")}
         res[name] = dict(seconds=t1 - t0, prof=prof, work=work, diag=diag,
                          lat_ms=sorted(a.elapsed_time(b) for a, b in lat))
-        print(f"[bench] {name}: {1e3 * (t1 - t0) / args.steps:.1f} ms/step {prof}", file=sys.stderr, flush=True)
+        print(f"[bench] {name}: {1e3 * (t1 - t0) / max(1, args.steps):.1f} ms/step {prof}", file=sys.stderr,
+              flush=True)
+    if args.profile_only:
+        print(json.dumps({"profile_only": True, "kernel_ms_per_step": {n: r["prof"] for n, r in res.items()},
+                          "roofline": roof(res["mixed"], PEAK_FP32_VECTOR, "mixed"),
+                          "fp64_roofline": roof(res["fp64"], PEAK_FP64_VECTOR, "fp64")}))
+        return
 
     # four sources through the same random medium: rays marched once per screen
     Bm = 4
@@ -219,22 +245,6 @@ def main():
     value = mp_per_step * args.steps / rm["seconds"]
     fp64_ms = 1e3 * res["fp64"]["seconds"] / args.steps
 
-    def roof(r, peak, prec):
-        w, p = r["work"], r["prof"]
-        flops = FLOPS_PER_RHS * w["rhs_evals"] + FLOPS_PER_MEDIUM * w["medium_evals"] + \
-            FLOPS_PER_TERM * w["medium_terms"] + FLOPS_PER_TABLE * w["table_evals"]
-        launches = max(1, p["march_launches"])
-        avg_s = p["march_ms"] * 1e-3 / launches
-        per_launch = flops / launches
-        achieved = per_launch / avg_s / 1e12
-        t = traffic_from_profiles(prec)
-        return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
-                "frac": round(achieved * 1e12 / peak, 4), "traffic": t,
-                "kernel": "march_table_kernel" if w["table_evals"] else
-                          f"march_gauss_kernel<{'float' if prec == 'mixed' else 'double'}>",
-                "table_share": round(w["table_evals"] / max(1, w["table_evals"] + w["medium_evals"]), 4),
-                "flops_per_launch": per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
-
     roof_m = roof(rm, PEAK_FP32_VECTOR, "mixed")
     roof_d = roof(res["fp64"], PEAK_FP64_VECTOR, "fp64")
 
@@ -243,7 +253,7 @@ def main():
         import oracle
         oracle.build()
         threads = oracle.max_threads()
-        samples = (0, Q // 2)
+        samples = tuple(range(0, Q, Q // 8))  # 8 screens, about 10 s of oracle work
         t0 = time.perf_counter()
         errs = []
         for q in samples:

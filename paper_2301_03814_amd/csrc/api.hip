@@ -285,14 +285,12 @@ static void set_slot_q(swkb_plan_s* pl, int k, int q) {
 }
 
 static void destroy_streams(swkb_plan_s* pl) {
-  if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
   for (int k = 0; k < 2; ++k) {
     if (pl->ev_ready[k]) (void)hipEventDestroy(pl->ev_ready[k]);
     if (pl->ev_free[k]) (void)hipEventDestroy(pl->ev_free[k]);
   }
   if (pl->ms) (void)hipStreamDestroy(pl->ms);
   pl->ms = nullptr;
-  pl->ev_fork = nullptr;
   for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = nullptr;
 }
 
@@ -327,28 +325,38 @@ static bool overlap(const swkb_plan_s* pl) {
   return pl->nslots == 2 && pl->ms && !pl->use_matrix && !pl->x_invariant && !pl->prof_on;
 }
 
-// Screens [q_begin, q_end) of an x-varying medium with the march of the next
-// screen overlapping the sum of the current one: slot k = q & 1 is filled on
-// the march stream (after the sum that last read it) and summed on st.
-// field(q, st) launches the screen's FFT and sum.
+// Screens [q_begin, q_end) of an x-varying medium with march and scan on
+// their own stream.  Slot k = q & 1 holds screen q's rays.  The caller's
+// stream st builds the medium table of screen q (into slot k, once the sum
+// of screen q - 2 has released it); after the march and scan of screen q on
+// the march stream it runs the FFT and the sum of screen q.  field(q)
+// launches the screen's FFT and sum.
 template <typename F>
 static swkb_status pipelined(swkb_plan_s* pl, int q_begin, int q_end, hipStream_t st, F&& field) {
-  hipError_t e = hipEventRecord(pl->ev_fork, st);
-  if (e == hipSuccess) e = hipStreamWaitEvent(pl->ms, pl->ev_fork, 0);
-  bool pending_free[2] = {false, false};
+  hipError_t e = hipSuccess;
+  // table of screen q into its slot on st, then the slot is open for the march
+  auto prepare = [&](int q) {
+    const int k = q & 1;
+    select_slot(pl, k);
+    hipError_t r = launch_medium_table(*pl, q, st);
+    if (r == hipSuccess) r = hipEventRecord(pl->ev_free[k], st);
+    return r;
+  };
+  for (int q = q_begin; q < q_end && q < q_begin + 2 && e == hipSuccess; ++q)
+    if (pl->slots[q & 1].q != q) e = prepare(q);
   for (int q = q_begin; q < q_end && e == hipSuccess; ++q) {
     const int k = q & 1;
     select_slot(pl, k);
     if (pl->slots[k].q != q) {
-      if (pending_free[k]) e = hipStreamWaitEvent(pl->ms, pl->ev_free[k], 0);
-      if (e == hipSuccess) e = march_chain(pl, q, pl->ms);
+      e = hipStreamWaitEvent(pl->ms, pl->ev_free[k], 0);
+      if (e == hipSuccess) e = launch_march(*pl, q, pl->ms);
+      if (e == hipSuccess) e = launch_scan(*pl, pl->ms);
       if (e == hipSuccess) e = hipEventRecord(pl->ev_ready[k], pl->ms);
       if (e == hipSuccess) e = hipStreamWaitEvent(st, pl->ev_ready[k], 0);
       set_slot_q(pl, k, e == hipSuccess ? q : -1);
     }
     if (e == hipSuccess) e = field(q);
-    if (e == hipSuccess) e = hipEventRecord(pl->ev_free[k], st);
-    pending_free[k] = true;
+    if (e == hipSuccess && q + 2 < q_end) e = prepare(q + 2);
   }
   if (e != hipSuccess) return hip_fail(e, "screen launch");
   return SWKB_OK;
@@ -440,11 +448,9 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     }
     select_slot(pl, 0);
     pl->ms = nullptr;
-    pl->ev_fork = nullptr;
     for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = nullptr;
     if (pl->nslots == 2) {
-      bool ok = hipStreamCreateWithFlags(&pl->ms, hipStreamNonBlocking) == hipSuccess &&
-                hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess;
+      bool ok = hipStreamCreateWithFlags(&pl->ms, hipStreamNonBlocking) == hipSuccess;
       for (int k = 0; k < 2 && ok; ++k)
         ok = hipEventCreateWithFlags(&pl->ev_ready[k], hipEventDisableTiming) == hipSuccess &&
              hipEventCreateWithFlags(&pl->ev_free[k], hipEventDisableTiming) == hipSuccess;

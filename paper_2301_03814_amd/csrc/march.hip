@@ -134,7 +134,8 @@ struct GaussMedium {
 // Gaussian-sum medium read from a per-screen table (mixed path).  At each
 // RK4 stage position x_k of the screen, eps - 1 is the quintic Hermite
 // interpolant in z between nodes z_lo + i dz_t of its FP64 values and first
-// two z-derivatives; eps_z and eps_zz are the interpolant's derivatives.
+// two z-derivatives; eps_z / 2 and eps_zz / 2 come from the interpolant's
+// derivatives.
 // Per interval the table holds power-form coefficients in u = (z - z_i)/dz_t,
 //   p(u) = c0 + c1 u + ... + c5 u^5:  ta[k][i] = (c0, c1, c2, c3), tb[k][i] = (c4, c5).
 // The interpolation error of eps - 1 is of order dz_t^6 max|eps^(6)|, of
@@ -145,12 +146,13 @@ struct TableMedium {
   const float4* __restrict__ ta;  // [(2S+1)][ni]
   const float2* __restrict__ tb;  // [(2S+1)][ni]
   unsigned ni;                    // intervals
-  float inv_dz, inv_dz2x2;        // 1/dz_t, 2/dz_t^2
-  int j0;    // node at or below the wavefront's reference height z_w
-  float f0;  // z_w minus the height of node j0, in [0, dz_t)
+  float inv_dz, half_inv_dz;      // 1/dz_t, 1/(2 dz_t)
+  float inv_dz2;                  // 1/dz_t^2
+  int j0;      // node at or below the wavefront's reference height z_w
+  float tl;    // this lane's launch height above node j0, in node spacings
   GaussMedium<float> direct;
   __device__ Med<float> eval(int k, float dz, Work& c) const {
-    const float t = (f0 + direct.zl0 + dz) * inv_dz;
+    const float t = dz * inv_dz + tl;
     const float tf = floorf(t);
     // unsigned wrap sends heights below the table (and saturated conversions) out of range too
     const unsigned iv = (unsigned)j0 + (unsigned)(int)tf;
@@ -176,8 +178,8 @@ struct TableMedium {
     p = p * u + a.x;
     Med<float> m;
     m.e1 = p;
-    m.ez = d1 * inv_dz;
-    m.ezz = d2 * inv_dz2x2;
+    m.hz = d1 * half_inv_dz;
+    m.hzz = d2 * inv_dz2;
     return m;
   }
 };
@@ -195,13 +197,13 @@ __device__ inline int rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, T 
   const T ip = fast_rsqrt<T>(p2);
   const T p = p2 * ip;
   d.dz = q * ip;
-  d.dq = T(0.5) * m.ez * ip;
+  d.dq = m.hz * ip;
   d.dps = ((m.e1 - (T)mc.e1r) - dq * (q + xi)) * fast_rcp<T>(p + (T)mc.pbar) + q * dq * ip;
   // ray-tube variations
   const T ip3 = ip * ip * ip;
-  const T qe = T(0.5) * q * m.ez * ip3;                          // q eps_z / (2 p^3)
+  const T qe = q * m.hz * ip3;                                    // q eps_z / (2 p^3)
   const T c12 = (T(1) + m.e1) * ip3;                              // eps / p^3
-  const T c21 = T(0.5) * m.ezz * ip - T(0.25) * m.ez * m.ez * ip3; // eps_zz/(2p) - eps_z^2/(4p^3)
+  const T c21 = m.hzz * ip - m.hz * m.hz * ip3;                   // eps_zz/(2p) - eps_z^2/(4p^3)
   d.Zs = c12 * Qs - qe * Zs;
   d.Qs = c21 * Zs + qe * Qs;
   return kLive;
@@ -432,10 +434,11 @@ __global__ void __launch_bounds__(256) march_table_kernel(Geometry g, GaussTabs<
   med.ta = mt.tab;
   med.tb = mt.tb;
   med.inv_dz = (float)(1.0 / mt.dz);
-  med.inv_dz2x2 = (float)(2.0 / (mt.dz * mt.dz));
+  med.half_inv_dz = (float)(0.5 / mt.dz);
+  med.inv_dz2 = (float)(1.0 / (mt.dz * mt.dz));
   const double rel = (g.z_a + (double)(w * 64 * g.rho - g.E) * g.h) - mt.z_lo;  // z_w above the table's base
   med.j0 = (int)floor(rel / mt.dz);
-  med.f0 = (float)(rel - (double)med.j0 * mt.dz);
+  med.tl = (float)((rel - (double)med.j0 * mt.dz + (double)(lane * g.rho) * g.h) / mt.dz);
   int st;
   Work c;
   march_ray<float>(med, mc, g, active, (size_t)j * g.R + r, rec, st, c);

@@ -1,5 +1,6 @@
-// Device evaluation of the medium seen by the rays: eps - 1, eps_z and
-// eps_zz at (x, z), z = s + dz with s the ray's launch height.
+// Device evaluation of the medium seen by the rays: eps - 1, eps_z / 2 and
+// eps_zz / 2 at (x, z), z = s + dz with s the ray's launch height (the ray
+// system uses the derivatives only halved).
 //
 // T = double: everything in FP64.
 // T = float : the small deviation dz and the medium are evaluated in FP32,
@@ -16,7 +17,7 @@ namespace swkb {
 
 template <typename T>
 struct Med {
-  T e1, ez, ezz;  // eps - 1, d eps / dz, d^2 eps / dz^2
+  T e1, hz, hzz;  // eps - 1, (d eps / dz) / 2, (d^2 eps / dz^2) / 2
 };
 
 template <typename T>
@@ -39,8 +40,8 @@ __device__ inline Med<T> from_index(T dn, T nz, T nzz) {
   const T n = T(1) + dn;
   Med<T> m;
   m.e1 = dn * (T(2) + dn);
-  m.ez = T(2) * n * nz;
-  m.ezz = T(2) * (nz * nz + n * nzz);
+  m.hz = n * nz;
+  m.hzz = nz * nz + n * nzz;
   return m;
 }
 
@@ -73,8 +74,8 @@ __device__ inline Med<T> medium_eval(const DevMedium& md, double x, double s, T 
       // eps - 1 = (eps0 - 1) + g z
       const T g = (T)p[1];
       m.e1 = (T)((p[0] - 1.0) + p[1] * s) + g * dz;
-      m.ez = g;
-      m.ezz = T(0);
+      m.hz = T(0.5) * g;
+      m.hzz = T(0);
       break;
     }
     case SWKB_MEDIUM_EXPGAUSS: {
@@ -82,8 +83,8 @@ __device__ inline Med<T> medium_eval(const DevMedium& md, double x, double s, T 
       const T d = rel<T>(s, p[3], dz);
       const T gg = a * dev_exp<T>(-b * d * d);
       m.e1 = (T)(p[0] - 1.0) + gg;
-      m.ez = T(-2) * b * d * gg;
-      m.ezz = (T(4) * b * b * d * d - T(2) * b) * gg;
+      m.hz = -b * d * gg;
+      m.hzz = (T(2) * b * b * d * d - b) * gg;
       break;
     }
     case SWKB_MEDIUM_GAUSSSUM: {
@@ -123,7 +124,7 @@ __device__ inline Med<T> medium_eval(const DevMedium& md, double x, double s, T 
       break;
     }
   }
-  if (flip) m.ez = -m.ez;
+  if (flip) m.hz = -m.hz;
   return m;
 }
 

@@ -104,6 +104,8 @@ struct swkb_plan_s {
   // Ray records of two screens (x-varying media): the march of screen q + 1
   // fills one slot on stream `ms` while screen q is summed from the other on
   // the caller's stream.  rec, wcount and mtab above are the active slot.
+  // ev_free[k]: slot k's table is built and its last sum done (march may
+  // start); ev_ready[k]: its march is done.
   struct Slot {
     swkb::DevRecords rec;
     int* wcount;
@@ -113,7 +115,7 @@ struct swkb_plan_s {
   Slot slots[2];
   int nslots;
   hipStream_t ms;                // march stream (default priority), or NULL
-  hipEvent_t ev_fork, ev_ready[2], ev_free[2];
+  hipEvent_t ev_ready[2], ev_free[2];
   // event timing
   int prof_on;
   std::vector<hipEvent_t> ev_pool;
