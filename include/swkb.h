@@ -239,6 +239,66 @@ int32_t swkb_num_rays(swkb_plan_t plan);
 /* 1 if the plan holds the mode-function matrix T (SWKB_PROP_*), else 0. */
 int32_t swkb_uses_matrix(swkb_plan_t plan);
 
+/* ---- serving loop ----------------------------------------------------- */
+
+/* Continuous batching of independent propagation requests on the current
+ * device (one problem = one swkb_params and incident field; Algorithm 1 over
+ * all its screens).  Requests are admitted in arrival order while their
+ * device footprint (workspace + field) fits hbm_budget_bytes and fewer than
+ * max_active are admitted; each admitted request gets its own plan,
+ * workspace (hipMalloc) and stream, and every swkb_server_step advances each
+ * admitted request whose previous chunk has finished by screens_per_round
+ * screens, so the requests' work overlaps on the device.  The result of a
+ * request does not depend on what else is being served.  Not thread-safe:
+ * one host thread drives a server. */
+typedef struct swkb_server_config {
+  size_t hbm_budget_bytes;   /* device bytes the admitted requests may hold (> 0) */
+  int32_t max_active;        /* most requests admitted at once (>= 1)            */
+  int32_t screens_per_round; /* screens enqueued per request and step (>= 1)     */
+} swkb_server_config;
+
+typedef struct swkb_request_info {
+  int32_t state;     /* 0 pending, 1 admitted, 2 done, 3 failed                    */
+  int32_t n_z;
+  double queue_us;   /* submit -> admission (host clock), -1 while pending          */
+  double latency_us; /* submit -> completion seen by swkb_server_step, -1 before    */
+} swkb_request_info;
+
+typedef struct swkb_server_stats_t {
+  int64_t completed, screens, mode_points; /* finished requests and their work (M N Q summed) */
+  size_t device_bytes_in_use;
+  int32_t active, pending;
+  double seconds;                          /* since swkb_server_create                        */
+} swkb_server_stats_t;
+
+typedef struct swkb_server_s* swkb_server_t;
+
+/* Host only.  SWKB_ERR_ARG for a config outside the ranges above. */
+swkb_status swkb_server_create(const swkb_server_config* cfg, swkb_server_t* out);
+
+/* Queue a request: *p is copied (medium parameters included), u0 (host
+ * complex128[n_z], the field on screen 0) is copied into pinned host
+ * memory.  *id receives the request's handle.  SWKB_ERR_ARG for invalid
+ * parameters, SWKB_ERR_NOMEM if the request alone exceeds the budget. */
+swkb_status swkb_server_submit(swkb_server_t s, const swkb_params* p, const void* u0, int64_t* id);
+
+/* One scheduling round (host, non-blocking except for plan builds of newly
+ * admitted requests): retire finished requests, advance the others by a
+ * chunk, admit pending requests.  *n_active / *n_pending (may be NULL)
+ * receive the counts afterwards. */
+swkb_status swkb_server_step(swkb_server_t s, int32_t* n_active, int32_t* n_pending);
+
+/* State of request id in *info (may be NULL).  When done and out != NULL,
+ * copies the field on the last screen into out (host complex128[n_z]) and
+ * forgets the request.  SWKB_ERR_STATE while not done, SWKB_ERR_DEVICE
+ * (message in swkb_last_error) if it failed, SWKB_ERR_ARG for an unknown id. */
+swkb_status swkb_server_poll(swkb_server_t s, int64_t id, void* out, swkb_request_info* info);
+
+swkb_status swkb_server_stats(swkb_server_t s, swkb_server_stats_t* out);
+
+/* Waits for admitted requests, frees everything the server holds. */
+void swkb_server_destroy(swkb_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

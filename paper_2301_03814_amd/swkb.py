@@ -24,7 +24,9 @@ PROP_AUTO, PROP_MATRIX, PROP_RECOMPUTE = 0, 1, 2
 EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", "swkb_current_screen",
            "swkb_diagnostics", "swkb_destroy", "swkb_status_string", "swkb_last_error",
            "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays", "swkb_profile", "swkb_profile_read",
-           "swkb_uses_matrix", "swkb_propagate_batch", "swkb_propagate_stations", "swkb_modal_reference"]
+           "swkb_uses_matrix", "swkb_propagate_batch", "swkb_propagate_stations", "swkb_modal_reference",
+           "swkb_server_create", "swkb_server_submit", "swkb_server_step", "swkb_server_poll",
+           "swkb_server_stats", "swkb_server_destroy"]
 
 
 class Params(C.Structure):
@@ -57,6 +59,23 @@ class Timing(C.Structure):
                 ("superpose_ms", C.c_double), ("march_launches", C.c_int64), ("scan_launches", C.c_int64),
                 ("fft_launches", C.c_int64), ("superpose_launches", C.c_int64),
                 ("table_ms", C.c_double), ("table_launches", C.c_int64)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_active", C.c_int32), ("screens_per_round", C.c_int32)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("n_z", C.c_int32), ("queue_us", C.c_double), ("latency_us", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("screens", C.c_int64), ("mode_points", C.c_int64),
+                ("device_bytes_in_use", C.c_size_t), ("active", C.c_int32), ("pending", C.c_int32),
+                ("seconds", C.c_double)]
+
+
+REQ_PENDING, REQ_ACTIVE, REQ_DONE, REQ_FAILED = range(4)
 
 
 class SwkbError(RuntimeError):
@@ -104,8 +123,16 @@ def load(path: str = LIB_PATH):
     lib.swkb_uses_matrix.argtypes = [vp]
     lib.swkb_uses_matrix.restype = i32
     lib.swkb_profile_read.argtypes = [vp, vp, C.POINTER(Timing)]
+    lib.swkb_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(vp)]
+    lib.swkb_server_submit.argtypes = [vp, pp, vp, C.POINTER(C.c_int64)]
+    lib.swkb_server_step.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    lib.swkb_server_poll.argtypes = [vp, C.c_int64, vp, C.POINTER(RequestInfo)]
+    lib.swkb_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    lib.swkb_server_destroy.argtypes = [vp]
+    lib.swkb_server_destroy.restype = None
     for name in ("swkb_plan", "swkb_propagate", "swkb_field", "swkb_diagnostics", "swkb_stage_modes",
-                 "swkb_stage_rays", "swkb_profile", "swkb_profile_read"):
+                 "swkb_stage_rays", "swkb_profile", "swkb_profile_read", "swkb_server_create",
+                 "swkb_server_submit", "swkb_server_step", "swkb_server_poll", "swkb_server_stats"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -294,3 +321,63 @@ class Plan:
                                     _stream_handle(stream)))
         del n
         return arrs
+
+
+class Server:
+    """Serving loop of the library (swkb_server_*): requests are independent
+    problems, admitted by device footprint and advanced together in chunks
+    of screens on their own streams.  Fields are host numpy complex128."""
+
+    def __init__(self, hbm_budget_bytes, max_active=16, screens_per_round=8):
+        lib = load()
+        cfg = ServerConfig(hbm_budget_bytes=int(hbm_budget_bytes), max_active=int(max_active),
+                           screens_per_round=int(screens_per_round))
+        h = C.c_void_p()
+        _check(lib.swkb_server_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._n_z = {}
+
+    def submit(self, cfg, u0, precision=MIXED) -> int:
+        p = make_params(cfg, precision)
+        u0 = np.ascontiguousarray(np.asarray(u0, dtype=np.complex128))
+        if u0.shape != (cfg["n_z"],):
+            raise ValueError("u0 must be complex128[n_z]")
+        rid = C.c_int64()
+        _check(_lib.swkb_server_submit(self._h, C.byref(p), C.c_void_p(u0.ctypes.data), C.byref(rid)))
+        self._n_z[rid.value] = cfg["n_z"]
+        return rid.value
+
+    def step(self):
+        """One scheduling round; returns (admitted, pending)."""
+        a, b = C.c_int32(), C.c_int32()
+        _check(_lib.swkb_server_step(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def poll(self, rid):
+        """(state, info dict, field or None); the field is returned once, when done."""
+        info = RequestInfo()
+        st = _lib.swkb_server_poll(self._h, int(rid), None, C.byref(info))
+        d = {"state": info.state, "queue_us": info.queue_us, "latency_us": info.latency_us}
+        if st == SWKB_ERR_STATE:
+            return info.state, d, None
+        if st != SWKB_OK:
+            _check(st)
+        out = np.empty(self._n_z.pop(rid), dtype=np.complex128)
+        _check(_lib.swkb_server_poll(self._h, int(rid), C.c_void_p(out.ctypes.data), None))
+        return REQ_DONE, d, out
+
+    def stats(self):
+        s = ServerStats()
+        _check(_lib.swkb_server_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.swkb_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import workloads as W
@@ -39,7 +40,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 @pytest.mark.parametrize("cname,pyname", [("swkb_params", "Params"), ("swkb_counters", "Counters"),
-                                           ("swkb_timing", "Timing")])
+                                           ("swkb_timing", "Timing"), ("swkb_server_config", "ServerConfig"),
+                                           ("swkb_request_info", "RequestInfo"),
+                                           ("swkb_server_stats_t", "ServerStats")])
 def test_struct_layout_matches_header(tmp_path, cname, pyname):
     from paper_2301_03814_amd import swkb
     S = getattr(swkb, pyname)
@@ -116,3 +119,26 @@ def test_plan_rejects_bad_arguments_on_host(lib):
     assert st == swkb.SWKB_ERR_NOMEM
     st = lib.swkb_plan(C.byref(p), C.c_void_p(257), 1 << 30, None, C.byref(h))
     assert st == swkb.SWKB_ERR_ARG
+
+
+def test_server_host_side_errors(lib):
+    """Server creation and submission reject bad arguments on the host."""
+    from paper_2301_03814_amd import swkb
+    h = C.c_void_p()
+    bad = swkb.ServerConfig(hbm_budget_bytes=0, max_active=1, screens_per_round=1)
+    assert lib.swkb_server_create(C.byref(bad), C.byref(h)) == swkb.SWKB_ERR_ARG
+    good = swkb.ServerConfig(hbm_budget_bytes=1 << 20, max_active=2, screens_per_round=4)
+    assert lib.swkb_server_create(C.byref(good), C.byref(h)) == swkb.SWKB_OK
+    cfg = W.linear_caustic()
+    u0 = np.zeros(cfg["n_z"], dtype=np.complex128)
+    rid = C.c_int64()
+    p_bad = swkb.make_params(W.with_overrides(cfg, n_modes=0))
+    assert lib.swkb_server_submit(h, C.byref(p_bad), C.c_void_p(u0.ctypes.data), C.byref(rid)) == swkb.SWKB_ERR_ARG
+    # larger than the 1 MiB budget
+    p_big = swkb.make_params(cfg)
+    assert lib.swkb_server_submit(h, C.byref(p_big), C.c_void_p(u0.ctypes.data), C.byref(rid)) == swkb.SWKB_ERR_NOMEM
+    assert b"budget" in lib.swkb_last_error()
+    st = swkb.ServerStats()
+    assert lib.swkb_server_stats(h, C.byref(st)) == swkb.SWKB_OK and st.pending == 0
+    assert lib.swkb_server_poll(h, 12345, None, None) == swkb.SWKB_ERR_ARG
+    lib.swkb_server_destroy(h)
