@@ -63,6 +63,72 @@ def traffic_from_profiles(precision):
     return None if rec is None else rec.get("hbm_bytes_per_launch")
 
 
+def bench_serving(torch, np, W, Plan, Server, FP64, MIXED, n_req=24):
+    """Serving loop on the first n_req requests of the seeded Poisson stream
+    (20 req/s; ducts and random media, N_z 1024..32768, M = N_z/4, ranges as
+    in the stream): requests are submitted at their arrival times (wall
+    clock) to the library's server (mixed precision, continuous batching),
+    latency = completion seen by the host minus arrival.  Baseline: the same
+    requests served one after another in arrival order with plain FP64
+    plans (FIFO; its latencies follow from the measured service times)."""
+    reqs = W.serving_stream(seed=5, rate=20.0, duration=60.0)[:n_req]
+    dev = torch.device("cuda:0")
+    u0s = [W.incident_field(c) for _, c in reqs]
+    work = sum(c["n_modes"] * c["n_z"] * c["n_screens"] for _, c in reqs)
+    srv = Server(200 << 30, max_active=8, screens_per_round=16)
+    ids, done, nxt = {}, {}, 0
+    t0 = time.perf_counter()
+    while len(done) < n_req:
+        now = time.perf_counter() - t0
+        while nxt < n_req and reqs[nxt][0] <= now:
+            ids[nxt] = srv.submit(reqs[nxt][1], u0s[nxt], precision=MIXED)
+            nxt += 1
+        srv.step()
+        for i, rid in ids.items():
+            if i not in done:
+                _, _, field = srv.poll(rid)
+                if field is not None:
+                    done[i] = (time.perf_counter() - t0 - reqs[i][0], field)
+        time.sleep(0.0002)
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([done[i][0] for i in range(n_req)])
+    # FP64 plain, one request at a time, FIFO over the same arrivals
+    service, errs, t_free = [], [], 0.0
+    lat64 = []
+    for i, (t_arr, c) in enumerate(reqs):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        p = Plan(c, precision=FP64, device=dev)
+        h = p.propagate(torch.from_numpy(u0s[i]).to(dev), 0, c["n_screens"])
+        ref = h[-1].cpu().numpy()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - s0
+        p.close()
+        del p, h
+        service.append(dt)
+        t_free = max(t_free, t_arr) + dt
+        lat64.append(t_free - t_arr)
+        errs.append(float(np.linalg.norm(done[i][1] - ref) / np.linalg.norm(ref)))
+    lat64 = np.array(lat64)
+    end64 = t_free
+    return {
+        "workload": f"first {n_req} requests of the Poisson stream (seed 5, 20 req/s): ducts (1-10 GHz, 200-500 m, "
+                    "10-100 km) and random media (1000-4000 wavelengths), N_z 1024-32768, M = N_z/4",
+        "requests": n_req, "mode_points": work,
+        "mixed_served": {"wall_s": wall, "requests_per_s": n_req / wall, "mode_points_per_s": work / wall,
+                         "latency_ms_p50": float(np.percentile(lat, 50)) * 1e3,
+                         "latency_ms_p99": float(np.percentile(lat, 99)) * 1e3,
+                         "max_active": 8, "screens_per_round": 16},
+        "fp64_serial": {"wall_s": end64, "service_s_sum": float(sum(service)),
+                        "requests_per_s": n_req / end64, "mode_points_per_s": work / float(sum(service)),
+                        "latency_ms_p50": float(np.percentile(lat64, 50)) * 1e3,
+                        "latency_ms_p99": float(np.percentile(lat64, 99)) * 1e3},
+        "speedup_throughput": float(sum(service)) / wall,
+        "rel_err_mixed_vs_fp64_max": max(errs),
+    }
+
+
 def bench_duct(args, torch, np, W, Plan, FP64, MIXED):
     """Surface duct at 6 GHz (N = 16384, M = 4096, 1000 screens of 100 m,
     Dirichlet ground mirror): an x-invariant medium, so the plan tabulates
@@ -121,6 +187,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-duct", action="store_true", help="skip the surface-duct measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the step with per-kernel events (kernels one after another), for rocprofv3")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -270,6 +337,11 @@ def main():
     duct = None
     if not args.no_duct:
         duct = bench_duct(args, torch, np, W, Plan, FP64, MIXED)
+    serving = None
+    if not args.no_serving:
+        from paper_2301_03814_amd import Server
+        serving = bench_serving(torch, np, W, Plan, Server, FP64, MIXED)
+        print(f"[bench] serving: {serving}", file=sys.stderr, flush=True)
 
     p50 = float(np.percentile(rm["lat_ms"], 50))
     p99 = float(np.percentile(rm["lat_ms"], 99))
@@ -302,6 +374,7 @@ def main():
         "roofline": roof_m,
         "cpu_baseline": cpu,
         "surface_duct": duct,
+        "serving": serving,
     }
     print(json.dumps(line))
     for p in plans.values():
