@@ -209,11 +209,23 @@ __device__ inline int rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, T 
   return kLive;
 }
 
+// First grid index m in [0, N] with z_m = z_a + m h >= key (N + 1 if none,
+// 0 for an empty key), with the FP64 comparisons of the bracket search.
+__device__ inline int first_point_at_or_above(const Geometry& g, double key, double inv_h) {
+  if (key == -INFINITY) return 0;
+  const double x = (key - g.z_a) * inv_h;
+  int ci = x <= 0.0 ? 0 : (x >= (double)(g.N + 1) ? g.N + 1 : (int)ceil(x));
+  // exact decisions with the same arithmetic as z_m = z_a + m h
+  while (ci > 0 && g.z_a + (double)(ci - 1) * g.h >= key) --ci;
+  while (ci <= g.N && g.z_a + (double)ci * g.h < key) ++ci;
+  return ci;
+}
+
 // One wavefront lane per ray: RK4 across the screen.  Writes the arrival
 // record and returns the lane's status and work counts.
 template <typename T, typename MED>
 __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry& g, bool active, size_t o,
-                                 DevRecords& rec, int& st, Work& c) {
+                                 double s_launch, DevRecords& rec, int& st, Work& c) {
   T dz = T(0), dq = T(0), dps = T(0);
   T Zs = T(1), Qs = T(0);
   double amp = 0.0;
@@ -263,6 +275,8 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
   static_cast<T*>(rec.Pp)[o] = dps;
   static_cast<T*>(rec.G)[o] = dq;
   static_cast<T*>(rec.A)[o] = st == kLive ? (T)amp : (T)(-st);
+  // first grid point at or above the arrival (the scan's running maximum of these gives the brackets)
+  rec.cz[o] = st == kLive ? first_point_at_or_above(g, s_launch + (double)dz, 1.0 / g.h) : 0;
 }
 
 __device__ inline void wave_counts(int* __restrict__ wcount, size_t slot, int lane, bool active, int st, Work c) {
@@ -314,7 +328,7 @@ __global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, De
   med.s = g.z_a + (double)(r * g.rho - g.E) * g.h;
   int st;
   Work c;
-  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, rec, st, c);
+  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec, st, c);
   wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
 }
 
@@ -350,7 +364,7 @@ __global__ void __launch_bounds__(256) march_gauss_kernel(Geometry g, GaussTabs<
   med.zl0 = (T)((double)(lane * g.rho) * g.h);
   int st;
   Work c;
-  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, rec, st, c);
+  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec, st, c);
   wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
 }
 
@@ -441,7 +455,8 @@ __global__ void __launch_bounds__(256) march_table_kernel(Geometry g, GaussTabs<
   med.tl = (float)((rel - (double)med.j0 * mt.dz + (double)(lane * g.rho) * g.h) / mt.dz);
   int st;
   Work c;
-  march_ray<float>(med, mc, g, active, (size_t)j * g.R + r, rec, st, c);
+  march_ray<float>(med, mc, g, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec, st,
+                   c);
   wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
 }
 
@@ -460,22 +475,18 @@ __global__ void __launch_bounds__(256) march_table_kernel(Geometry g, GaussTabs<
 // ceil(ci_{r-1} / 64) <= t < ceil(ci_r / 64) (ci_{-1} = 0), and tiles at or
 // above ceil(ci_{R-1} / 64) in that of ray R - 1.
 constexpr int kScanThreads = 256;
-constexpr int kScanRun = 8;  // most consecutive rays per thread
-
-__device__ inline int first_point_at_or_above(const Geometry& g, double key, double inv_h) {
-  if (key == -INFINITY) return 0;
-  const double x = (key - g.z_a) * inv_h;
-  int ci = x <= 0.0 ? 0 : (x >= (double)(g.N + 1) ? g.N + 1 : (int)ceil(x));
-  // exact decisions with the same arithmetic as z_m = z_a + m h
-  while (ci > 0 && g.z_a + (double)(ci - 1) * g.h >= key) --ci;
-  while (ci <= g.N && g.z_a + (double)ci * g.h < key) ++ci;
-  return ci;
-}
+constexpr int kScanRun = 6;  // most consecutive rays per thread
 
 template <typename T>
 __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecords rec,
                                                             const int* __restrict__ wcount, int waves_per_mode) {
+  constexpr int kChunk = kScanThreads * kScanRun;
+  // the chunk's rays staged in LDS so that global loads and stores stay coalesced
+  __shared__ T sA[kChunk], sD[kChunk];
+  __shared__ int sC[kChunk], sI[kChunk];
+  __shared__ double sK[kChunk];
   __shared__ double wtot[kScanThreads / 64];
+  __shared__ int wci[kScanThreads / 64];
   __shared__ int sfold;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int j = blockIdx.x;
@@ -483,7 +494,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecor
   int* __restrict__ ts = rec.tstart + (size_t)j * (g.T + 1);
   const T* __restrict__ A = static_cast<const T*>(rec.A) + base;
   const T* __restrict__ D = static_cast<const T*>(rec.D) + base;
-  const double inv_h = 1.0 / g.h;
+  const int* __restrict__ CZ = rec.cz + base;
   int run = (g.R + kScanThreads - 1) / kScanThreads;
   if (run > kScanRun) run = kScanRun;
   if (tid == 0) sfold = 0;
@@ -491,46 +502,84 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecor
   int carry_ci = 0;          // its first point
   bool fold = false;
   for (int c0 = 0; c0 < g.R; c0 += kScanThreads * run) {
-    const int r0 = c0 + tid * run;  // this thread's first ray
+    const int n = g.R - c0 < kScanThreads * run ? g.R - c0 : kScanThreads * run;
+    for (int i = tid; i < n; i += kScanThreads) {
+      sA[i] = A[c0 + i];
+      sD[i] = D[c0 + i];
+      sC[i] = CZ[c0 + i];
+    }
+    __syncthreads();
+    const int l0 = tid * run;  // this thread's first ray in the chunk
+    // the thread's rays: arrival height of live rays (-inf otherwise) and the
+    // first grid point at or above it (computed by the march)
     double Z[kScanRun];
+    int cz[kScanRun];
     double lmax = -INFINITY;
+    int lci = 0;
 #pragma unroll
     for (int i = 0; i < kScanRun; ++i) {
-      const int r = r0 + i;
-      Z[i] = -INFINITY;
-      if (i < run && r < g.R && A[r] > T(0)) Z[i] = (g.z_a + (double)(r * g.rho - g.E) * g.h) + (double)D[r];
+      const int l = l0 + i;
+      const bool live = i < run && l < n && sA[l < n ? l : 0] > T(0);
+      Z[i] = live ? (g.z_a + (double)((c0 + l) * g.rho - g.E) * g.h) + (double)sD[l] : -INFINITY;
+      cz[i] = live ? sC[l] : 0;
       lmax = fmax(lmax, Z[i]);
+      lci = cz[i] > lci ? cz[i] : lci;
     }
-    double incl = lmax;  // wavefront inclusive prefix maximum
+    // workgroup exclusive prefix maxima of (height, first point)
+    double incl = lmax;
+    int icl = lci;
     for (int off = 1; off < 64; off <<= 1) {
       const double v = __shfl_up(incl, off, 64);
-      if (lane >= off) incl = fmax(incl, v);
+      const int vi = __shfl_up(icl, off, 64);
+      if (lane >= off) {
+        incl = fmax(incl, v);
+        icl = vi > icl ? vi : icl;
+      }
     }
-    if (lane == 63) wtot[wv] = incl;
+    if (lane == 63) {
+      wtot[wv] = incl;
+      wci[wv] = icl;
+    }
     __syncthreads();
     double key = __shfl_up(incl, 1, 64);
-    if (lane == 0) key = -INFINITY;
-    for (int k = 0; k < wv; ++k) key = fmax(key, wtot[k]);
-    key = fmax(carry, key);  // key of ray r0 - 1
-    int ci_prev = first_point_at_or_above(g, key, inv_h);
+    int ci = __shfl_up(icl, 1, 64);
+    if (lane == 0) {
+      key = -INFINITY;
+      ci = 0;
+    }
+    for (int k = 0; k < wv; ++k) {
+      key = fmax(key, wtot[k]);
+      ci = wci[k] > ci ? wci[k] : ci;
+    }
+    key = fmax(carry, key);  // key of ray c0 + l0 - 1 and its first point
+    ci = carry_ci > ci ? carry_ci : ci;
 #pragma unroll
     for (int i = 0; i < kScanRun; ++i) {
-      const int r = r0 + i;
-      if (i < run && r < g.R) {
+      const int l = l0 + i;
+      if (i < run && l < n) {
         if (Z[i] != -INFINITY && !(Z[i] > key)) fold = true;
         key = fmax(key, Z[i]);
-        const int ci = first_point_at_or_above(g, key, inv_h);
-        rec.key[base + r] = key;
-        rec.cidx[base + r] = ci;
-        for (int t = (ci_prev + 63) >> 6; t < ((ci + 63) >> 6) && t <= g.T; ++t) ts[t] = r - 1;
-        ci_prev = ci;
+        const int ci_prev = ci;
+        ci = cz[i] > ci ? cz[i] : ci;
+        sK[l] = key;
+        sI[l] = ci;
+        for (int t = (ci_prev + 63) >> 6; t < ((ci + 63) >> 6) && t <= g.T; ++t) ts[t] = c0 + l - 1;
       }
     }
     double tot = carry;
-    for (int k = 0; k < kScanThreads / 64; ++k) tot = fmax(tot, wtot[k]);
-    __syncthreads();  // wtot is rewritten by the next chunk
+    int tci = carry_ci;
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+      tot = fmax(tot, wtot[k]);
+      tci = wci[k] > tci ? wci[k] : tci;
+    }
+    __syncthreads();  // sK, sI complete; wtot, wci are rewritten by the next chunk
+    for (int i = tid; i < n; i += kScanThreads) {
+      rec.key[base + c0 + i] = sK[i];
+      rec.cidx[base + c0 + i] = sI[i];
+    }
     carry = tot;
-    carry_ci = first_point_at_or_above(g, carry, inv_h);
+    carry_ci = tci;
+    __syncthreads();  // the staging arrays are refilled by the next chunk
   }
   // the last ray of the mode is R - 1: carry holds its key, carry_ci its first point
   for (int t = ((carry_ci + 63) >> 6) + tid; t <= g.T; t += kScanThreads) ts[t] = g.R - 1;
