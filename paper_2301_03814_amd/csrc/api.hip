@@ -138,7 +138,7 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 struct Layout {
   size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, part, tmat, counters;
   // one ray-record slot (offsets from its start); nslots of them from slot0
-  size_t mtab, D, Pp, G, A, cz, key, cidx, tstart, mflag, mcaus, mdead, mwork, wcount;
+  size_t mtab, D, Pp, G, A, cz, cidx, tstart, mflag, mcaus, mdead, mwork, wcount;
   size_t slot0, slot_bytes;
   int nslots;
   size_t total;
@@ -217,7 +217,6 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.G = take(ts * MR);
   L.A = take(ts * MR);
   L.cz = take(sizeof(int) * MR);
-  L.key = take(sizeof(double) * MR);
   L.cidx = take(sizeof(int) * MR);
   L.tstart = take(sizeof(int) * (size_t)g.M * (g.T + 1));
   L.mflag = take(sizeof(int) * g.M);
@@ -433,7 +432,6 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
       sl.rec.G = sb + L.G;
       sl.rec.A = sb + L.A;
       sl.rec.cz = reinterpret_cast<int*>(sb + L.cz);
-      sl.rec.key = reinterpret_cast<double*>(sb + L.key);
       sl.rec.cidx = reinterpret_cast<int*>(sb + L.cidx);
       sl.rec.tstart = reinterpret_cast<int*>(sb + L.tstart);
       sl.rec.mflag = reinterpret_cast<int*>(sb + L.mflag);

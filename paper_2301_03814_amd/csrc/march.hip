@@ -484,7 +484,6 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecor
   // the chunk's rays staged in LDS so that global loads and stores stay coalesced
   __shared__ T sA[kChunk], sD[kChunk];
   __shared__ int sC[kChunk], sI[kChunk];
-  __shared__ double sK[kChunk];
   __shared__ double wtot[kScanThreads / 64];
   __shared__ int wci[kScanThreads / 64];
   __shared__ int sfold;
@@ -561,7 +560,6 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecor
         key = fmax(key, Z[i]);
         const int ci_prev = ci;
         ci = cz[i] > ci ? cz[i] : ci;
-        sK[l] = key;
         sI[l] = ci;
         for (int t = (ci_prev + 63) >> 6; t < ((ci + 63) >> 6) && t <= g.T; ++t) ts[t] = c0 + l - 1;
       }
@@ -572,11 +570,8 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecor
       tot = fmax(tot, wtot[k]);
       tci = wci[k] > tci ? wci[k] : tci;
     }
-    __syncthreads();  // sK, sI complete; wtot, wci are rewritten by the next chunk
-    for (int i = tid; i < n; i += kScanThreads) {
-      rec.key[base + c0 + i] = sK[i];
-      rec.cidx[base + c0 + i] = sI[i];
-    }
+    __syncthreads();  // sI complete; wtot, wci are rewritten by the next chunk
+    for (int i = tid; i < n; i += kScanThreads) rec.cidx[base + c0 + i] = sI[i];
     carry = tot;
     carry_ci = tci;
     __syncthreads();  // the staging arrays are refilled by the next chunk

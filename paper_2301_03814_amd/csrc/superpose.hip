@@ -3,19 +3,15 @@
 // modes (eq. ray_bundle_q_plus_1), followed by the exit epilogue (cos^2
 // taper at open ends) and the writes of the new screen field.
 //
-// Layout: one workgroup per tile of 64 consecutive grid points (lane =
-// point), `ms` wavefronts per workgroup splitting the modes round-robin;
-// the per-wavefront partial sums are reduced in LDS in a fixed order, so the
-// result does not depend on scheduling.  No [mode][point] intermediate is
-// ever written to memory.
-//
-// Per (mode, point): the bracket is the largest ray r with key_r <= z_m,
-// searched inside the tile's window [tstart[t], tstart[t+1]]; it
-// contributes when rays r and r+1 are both live.  dpsi: cubic Hermite with
-// end slopes q - xi (dpsi_z at fixed x); amplitude: 4-point Lagrange over
-// r-1..r+2 when all four are live, else linear.  The phase in turns is
+// Per (mode, point): the bracket is the largest ray r whose key (running
+// maximum of live arrival heights) is <= z_m; it contributes when rays r and
+// r+1 are both live.  dpsi: cubic Hermite with end slopes q - xi (dpsi_z at
+// fixed x); amplitude: 4-point Lagrange over r-1..r+2 when all four are
+// live, else linear.  The phase in turns is
 //   (n m' mod P)/P + frac(pbar dx / lambda) + dpsi / lambda,
-// the first term exact in integers.
+// the first term exact in integers.  No [mode][point] intermediate is
+// written to memory (except the mode-function matrix of an x-invariant
+// medium, built once per plan).
 #include <type_traits>
 
 #include "swkb_internal.h"
@@ -42,27 +38,11 @@ __device__ inline double taper(const Geometry& g, const Epi& e, double z) {
   return w;
 }
 
-// Interval record of rays (r, r+1) in power form around Z_r:
-//   dpsi(tau) = c0 + c1 tau + c2 tau^2 + c3 tau^3   (cubic Hermite, slopes q - xi)
-//   a(tau)    = a0 + a1 tau + a2 tau^2 + a3 tau^3   (Lagrange over r-1..r+2, or linear)
-// zr = Z_r relative to the tile's first grid point; H = Z_{r+1} - Z_r, or -1
-// when ray r or r+1 is not live (no contribution).
-template <typename T>
-struct alignas(16) IvRec {
-  T zr, H, c0, c1, c2, c3, a0, a1, a2, a3, pad0, pad1;
-};
-
 template <typename T>
 __device__ inline T wave_shfl(T v, int src) { return __shfl(v, src, 64); }
 
-// Grid (super-tiles, mode groups); block = kWaves wavefronts.  A super-tile
-// is kSub consecutive 64-point tiles; wavefront w of group gi takes modes
-// j = gi * kWaves + w + k * (groups * kWaves) and, per mode, builds the
-// interval records of the super-tile's rays once and evaluates them at all
-// kSub * 64 points (lane = point within each 64-point tile).  Each block
-// writes its fixed-order partial sums to part[gi][m].
-constexpr int kWaves = 4;
-constexpr int kSub = 4;
+constexpr int kWaves = 4;  // wavefronts per workgroup
+constexpr int kSub = 4;    // 64-point tiles per super-tile of the matrix product
 
 template <typename T>
 __device__ inline T rcp_t(T x);
@@ -71,233 +51,12 @@ __device__ inline double rcp_t<double>(double x) { return 1.0 / x; }
 template <>
 __device__ inline float rcp_t<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// TABLE = false: sum over modes into part[][] (one screen).
-// TABLE = true : write the mode functions T[j][m] = a e^{2 pi i turns} (zero
-//                where mode j has no bracket) for a medium that does not
-//                depend on x; c and part are not used.
 template <typename T>
 struct CplxOf;
 template <>
 struct CplxOf<double> { using type = double2; };
 template <>
 struct CplxOf<float> { using type = float2; };
-
-//
-// NB fields of a batch share each record evaluation (interpolation and
-// sin/cos once, NB complex multiply-adds); blockIdx.z selects the fields
-// b0 = NB * blockIdx.z .. b0 + nb - 1.  c is [batch][M]; part is
-// [batch][groups][N].
-template <typename T, bool TABLE, int NB>
-__global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevModes modes, DevRecords rec,
-                                                                const double2* __restrict__ c,
-                                                                double2* __restrict__ part,
-                                                                typename CplxOf<T>::type* __restrict__ tab, Epi ep,
-                                                                int sub, int batch) {
-  // LDS: kWaves * kSub * 64 partial sums, then per wavefront br[kSub * 64], IvRec<T>[64]
-  extern __shared__ double2 red[];
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int sb = blockIdx.x;
-  const int gi = blockIdx.y;
-  const int jstep = (int)gridDim.y * kWaves;
-  const int b0 = (int)blockIdx.z * NB;
-  const int nb = batch - b0 < NB ? batch - b0 : NB;
-  const int npts = sub * 64;
-  const int m0 = sb * npts;  // first grid point of the super-tile
-  const int t0 = sb * sub;   // its first 64-point tile
-  char* wbase = reinterpret_cast<char*>(red + (size_t)kWaves * kSub * 64) +
-                (size_t)w * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<T>));
-  int* br = reinterpret_cast<int*>(wbase);
-  IvRec<T>* iv = reinterpret_cast<IvRec<T>*>(wbase + kSub * 64 * sizeof(int));
-  const double inv_lam = 1.0 / g.lam;
-  const T* __restrict__ D = static_cast<const T*>(rec.D);
-  const T* __restrict__ Pp = static_cast<const T*>(rec.Pp);
-  const T* __restrict__ G = static_cast<const T*>(rec.G);
-  const T* __restrict__ A = static_cast<const T*>(rec.A);
-  const int pmask = g.P - 1;  // P is a power of two
-  const int mp0 = m0 + ep.mprime_off;
-  const double zs0 = g.z_a + (double)m0 * g.h;
-
-  T acc_re[NB][kSub], acc_im[NB][kSub];
-  for (int bb = 0; bb < NB; ++bb)
-    for (int u = 0; u < kSub; ++u) acc_re[bb][u] = acc_im[bb][u] = T(0);
-  for (int j = gi * kWaves + w; j < g.M; j += jstep) {
-    if constexpr (TABLE) {
-      for (int u = 0; u < sub; ++u) {
-        typename CplxOf<T>::type z0;
-        z0.x = T(0);
-        z0.y = T(0);
-        tab[(size_t)j * g.N + m0 + u * 64 + lane] = z0;
-      }
-    }
-    if (rec.mflag[j] & 1) continue;  // folded mode
-    const int* ts = rec.tstart + (size_t)j * (g.T + 1);
-    const int lo = ts[t0], hi = ts[t0 + sub];
-    // intervals [ia, ib]; the last ray R-1 takes part as an interval that
-    // never contributes, so points above its arrival find it as their bracket
-    const int ia = lo > 0 ? lo : 0;
-    const int ib = hi < g.R - 1 ? hi : g.R - 1;
-    if (ia > ib) continue;
-    const size_t base = (size_t)j * g.R;
-    const double* __restrict__ key = rec.key + base;
-    const int n = j - (g.M >> 1);
-    const int nm0 = (n * mp0) & pmask;
-    T cjr[NB], cji[NB];
-    for (int bb = 0; bb < NB; ++bb) {
-      const double2 v = bb < nb ? c[(size_t)(b0 + bb) * g.M + j] : make_double2(0.0, 0.0);
-      cjr[bb] = (T)v.x;
-      cji[bb] = (T)v.y;
-    }
-    const T fj = (T)modes.frac[j];
-    for (int a0 = ia; a0 <= ib; a0 += 61) {
-      const int b0 = a0 + 60 < ib ? a0 + 60 : ib;  // intervals [a0, b0] in this pass
-      const int rb = a0 - 1;                        // ray held by lane 0
-      const int rl = rb + lane;
-      const bool in = rl >= 0 && rl < g.R;
-      const double kl = in ? key[rl] : INFINITY;
-      const T dl = in ? D[base + rl] : T(0);
-      const T al = in ? A[base + rl] : T(-1);
-      const T pl = in ? Pp[base + rl] : T(0);
-      const T gl = in ? G[base + rl] : T(0);
-      const T dm1 = wave_shfl(dl, lane - 1), dp1 = wave_shfl(dl, lane + 1), dp2 = wave_shfl(dl, lane + 2);
-      const T am1 = wave_shfl(al, lane - 1), ap1 = wave_shfl(al, lane + 1), ap2 = wave_shfl(al, lane + 2);
-      const T pp1 = wave_shfl(pl, lane + 1), gp1 = wave_shfl(gl, lane + 1);
-      for (int u = 0; u < sub; ++u) br[u * 64 + lane] = -1;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      if (rl >= a0 && rl <= b0) {
-        // first point of the super-tile at or above key_rl: points m >= m0 + ci have key_rl <= z_m
-        int ci;
-        if (kl == -INFINITY) {
-          ci = 0;
-        } else {
-          const double x = (kl - g.z_a) / g.h - (double)m0;
-          ci = x <= 0.0 ? 0 : (x >= (double)npts ? npts : (int)ceil(x));
-          while (ci > 0 && g.z_a + (double)(m0 + ci - 1) * g.h >= kl) --ci;
-          while (ci < npts && g.z_a + (double)(m0 + ci) * g.h < kl) ++ci;
-        }
-        if (ci < npts) atomicMax(&br[ci], lane);
-        IvRec<T> r;
-        const bool live = al > T(0) && ap1 > T(0);
-        T xm, x3;
-        if constexpr (std::is_same<T, double>::value) {
-          const double Zl = (g.z_a + (double)(rl * g.rho - g.E) * g.h) + dl;
-          const double Zn = (g.z_a + (double)((rl + 1) * g.rho - g.E) * g.h) + dp1;
-          r.zr = Zl - zs0;
-          r.H = Zn - Zl;
-          xm = ((g.z_a + (double)((rl - 1) * g.rho - g.E) * g.h) + dm1) - Zl;
-          x3 = ((g.z_a + (double)((rl + 2) * g.rho - g.E) * g.h) + dp2) - Zl;
-        } else {
-          const float hf = (float)g.h;
-          const float rh = (float)g.rho * hf;
-          r.zr = (float)(rl * g.rho - g.E - m0) * hf + dl;
-          r.H = rh + (dp1 - dl);
-          xm = -rh + (dm1 - dl);
-          x3 = T(2) * rh + (dp2 - dl);
-        }
-        const T H = r.H;
-        const T iH = rcp_t<T>(H);
-        const T dlt = (pp1 - pl) * iH;
-        r.c0 = pl;
-        r.c1 = gl;
-        r.c2 = (T(3) * dlt - T(2) * gl - gp1) * iH;
-        r.c3 = (gl + gp1 - T(2) * dlt) * iH * iH;
-        const bool cubic = rl >= 1 && rl + 2 < g.R && am1 > T(0) && ap2 > T(0);
-        const T f01 = (ap1 - al) * iH;
-        r.a0 = al;
-        if (cubic) {
-          // Newton form on nodes 0, H, xm (ray r-1), x3 (ray r+2), then powers of tau
-          const T f12 = (am1 - ap1) * rcp_t<T>(xm - H);
-          const T f23 = (ap2 - am1) * rcp_t<T>(x3 - xm);
-          const T f012 = (f12 - f01) * rcp_t<T>(xm);
-          const T f123 = (f23 - f12) * rcp_t<T>(x3 - H);
-          const T f0123 = (f123 - f012) * rcp_t<T>(x3);
-          r.a1 = f01 - H * f012 + H * xm * f0123;
-          r.a2 = f012 - (H + xm) * f0123;
-          r.a3 = f0123;
-        } else {
-          r.a1 = f01;
-          r.a2 = T(0);
-          r.a3 = T(0);
-        }
-        if (!live) r.H = T(-1);
-        iv[lane] = r;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      const bool last_pass = b0 >= ib;
-      const double knext = last_pass ? INFINITY : key[b0 + 1];
-      int carry = -1;
-      for (int u = 0; u < sub; ++u) {
-        // bracket of point m0 + 64u + lane: largest interval lane whose key <= z_m
-        int lb = br[u * 64 + lane];
-        for (int off = 1; off < 64; off <<= 1) {
-          const int v = __shfl_up(lb, off, 64);
-          if (lane >= off && v > lb) lb = v;
-        }
-        if (carry > lb) lb = carry;
-        carry = __shfl(lb, 63, 64);
-        const int pu = u * 64 + lane;
-        bool ok = lb >= 0;
-        if (ok && !last_pass && lb == b0 - rb) ok = g.z_a + (double)(m0 + pu) * g.h < knext;  // later pass
-        if (ok) {
-          const IvRec<T> r = iv[lb];
-          if (r.H > T(0)) {
-            T tau;
-            if constexpr (std::is_same<T, double>::value) tau = (double)pu * g.h - r.zr;
-            else tau = (float)pu * (float)g.h - r.zr;
-            const T dps = ((r.c3 * tau + r.c2) * tau + r.c1) * tau + r.c0;
-            const T a = ((r.a3 * tau + r.a2) * tau + r.a1) * tau + r.a0;
-            const int nm = (nm0 + __mul24(n, pu)) & pmask;
-            T sn, cs;
-            if constexpr (std::is_same<T, double>::value) {
-              double turns = (double)nm / (double)g.P + modes.frac[j] + dps * inv_lam;
-              turns -= floor(turns);
-              sincospi(2.0 * turns, &sn, &cs);
-            } else {
-              float turns = (float)nm * (1.0f / (float)g.P) + fj + dps * (float)inv_lam;
-              turns -= floorf(turns);
-              sn = __builtin_amdgcn_sinf(turns);  // argument in revolutions
-              cs = __builtin_amdgcn_cosf(turns);
-            }
-            if constexpr (TABLE) {
-              typename CplxOf<T>::type v;
-              v.x = a * cs;
-              v.y = a * sn;
-              tab[(size_t)j * g.N + m0 + pu] = v;
-            } else {
-              const T ea = a * cs, eb = a * sn;  // a e^{i phase}
-              for (int bb = 0; bb < NB; ++bb) {
-                acc_re[bb][u] += cjr[bb] * ea - cji[bb] * eb;
-                acc_im[bb][u] += cjr[bb] * eb + cji[bb] * ea;
-              }
-            }
-          }
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  if constexpr (TABLE) return;
-  for (int bb = 0; bb < NB; ++bb) {
-    if (bb >= nb) break;  // uniform over the block
-    for (int u = 0; u < kSub; ++u)
-      red[(w * kSub + u) * 64 + lane] = make_double2((double)acc_re[bb][u], (double)acc_im[bb][u]);
-    __syncthreads();
-    if (w == 0) {
-      for (int u = 0; u < sub; ++u) {
-        double sr = 0.0, si = 0.0;
-        for (int k = 0; k < kWaves; ++k) {
-          const double2 v = red[(k * kSub + u) * 64 + lane];
-          sr += v.x;
-          si += v.y;
-        }
-        part[((size_t)(b0 + bb) * gridDim.y + gi) * g.N + m0 + u * 64 + lane] = make_double2(sr, si);
-      }
-    }
-    __syncthreads();
-  }
-}
 
 // Sum over modes for one screen, organised by interval owner.  For a mode,
 // grid point m belongs to the interval of the largest ray r with
@@ -319,11 +78,15 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_kernel(Geometry g, DevM
 //
 // LDS accumulator row of a wavefront: point m at m + m / 8 (intervals are
 // about rho points long, so the lanes of one step fall into different banks).
-template <typename T, int NB>
+// TABLE = true: write the mode functions T[j][m] = a e^{2 pi i turns} of an
+// x-invariant medium instead (entries without an owning interval must be
+// zero beforehand); c, part and the accumulators are not used.
+template <typename T, int NB, bool TABLE>
 __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, DevModes modes, DevRecords rec,
                                                                    const double2* __restrict__ c,
-                                                                   double2* __restrict__ part, Epi ep, int sub,
-                                                                   int batch) {
+                                                                   double2* __restrict__ part,
+                                                                   typename CplxOf<T>::type* __restrict__ tab, Epi ep,
+                                                                   int sub, int batch) {
   extern __shared__ double2 lds_raw[];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -337,7 +100,8 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
   const int m0 = t0 * 64;                                // its first grid point
   const int row = sub * 64 + sub * 8;
   T* acc = reinterpret_cast<T*>(lds_raw) + (size_t)w * 2 * NB * row;  // [NB][re | im][row]
-  for (int i = lane; i < 2 * NB * row; i += 64) acc[i] = T(0);
+  if constexpr (!TABLE)
+    for (int i = lane; i < 2 * NB * row; i += 64) acc[i] = T(0);
   const double inv_lam = 1.0 / g.lam;
   const T* __restrict__ D = static_cast<const T*>(rec.D);
   const T* __restrict__ Pp = static_cast<const T*>(rec.Pp);
@@ -443,6 +207,14 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
           cs = __builtin_amdgcn_cosf(turns);
         }
         const T ea = a * cs, eb = a * sn;  // a e^{i phase}
+        if constexpr (TABLE) {
+          typename CplxOf<T>::type v;
+          v.x = ea;
+          v.y = eb;
+          tab[(size_t)j * g.N + m0 + m] = v;
+          nm = (nm + n) & pmask;
+          continue;
+        }
         const int pm = m + (m >> 3);
         for (int bb = 0; bb < NB; ++bb) {
           // lanes of one step own different points; LDS keeps the wavefront's accesses in order
@@ -453,6 +225,7 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
       }
     }
   }
+  if constexpr (TABLE) return;
   __syncthreads();
   T* acc0 = reinterpret_cast<T*>(lds_raw);
   for (int bb = 0; bb < nb; ++bb) {
@@ -650,8 +423,8 @@ static void launch_sum(const swkb_plan_s& pl, const dim3& grid, const DevModes& 
   const int row = sub * 64 + sub * 8;
   const size_t shmem = sizeof(T) * (size_t)kWaves * 2 * NB * row;
   const dim3 g3(grid.x, grid.y, (batch + NB - 1) / NB);
-  hipLaunchKernelGGL((superpose_iv_kernel<T, NB>), g3, dim3(64 * kWaves), shmem, st, pl.g, md, pl.rec, pl.c, pl.part,
-                     ep, sub, batch);
+  hipLaunchKernelGGL((superpose_iv_kernel<T, NB, false>), g3, dim3(64 * kWaves), shmem, st, pl.g, md, pl.rec, pl.c,
+                     pl.part, static_cast<typename CplxOf<T>::type*>(nullptr), ep, sub, batch);
 }
 
 static Epi epi_of(const swkb_plan_s& pl) {
@@ -689,19 +462,20 @@ hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, 
 hipError_t launch_build_matrix(const swkb_plan_s& pl, hipStream_t st) {
   const Geometry& g = pl.g;
   const Epi ep = epi_of(pl);
-  const int sub = superpose_sub(g);
-  const int groups = superpose_groups(g);
+  const int sub = iv_sub(g, pl.precision);
+  const int groups = groups_for(g, sub);
   DevModes md{pl.xi, pl.pbar, pl.e1r, pl.frac};
-  const size_t red = sizeof(double2) * 64 * kWaves * kSub;
-  const dim3 grid(g.T / sub, groups);
+  const dim3 grid((g.T + sub - 1) / sub, groups);
+  // points a mode does not reach stay zero
+  const size_t bytes = (size_t)g.N * g.M * (pl.precision == SWKB_FP64 ? sizeof(double2) : sizeof(float2));
+  hipError_t e = hipMemsetAsync(pl.tmat, 0, bytes, st);
+  if (e != hipSuccess) return e;
   if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL((superpose_kernel<double, true, 1>), grid, dim3(64 * kWaves),
-                       red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<double>)), st, g, md, pl.rec,
-                       pl.c, pl.part, static_cast<double2*>(pl.tmat), ep, sub, 1);
+    hipLaunchKernelGGL((superpose_iv_kernel<double, 1, true>), grid, dim3(64 * kWaves), 0, st, g, md, pl.rec, pl.c,
+                       pl.part, static_cast<double2*>(pl.tmat), ep, sub, 1);
   else
-    hipLaunchKernelGGL((superpose_kernel<float, true, 1>), grid, dim3(64 * kWaves),
-                       red + kWaves * (kSub * 64 * sizeof(int) + 64 * sizeof(IvRec<float>)), st, g, md, pl.rec,
-                       pl.c, pl.part, static_cast<float2*>(pl.tmat), ep, sub, 1);
+    hipLaunchKernelGGL((superpose_iv_kernel<float, 1, true>), grid, dim3(64 * kWaves), 0, st, g, md, pl.rec, pl.c,
+                       pl.part, static_cast<float2*>(pl.tmat), ep, sub, 1);
   return hipGetLastError();
 }
 

@@ -41,8 +41,8 @@ struct DevRecords {
   void* G;        // q - xi at arrival, T
   void* A;        // transport factor a (> 0 live); -flag otherwise, T
   int* cz;        // first grid index m in [0, N] with z_m >= the ray's own arrival (live rays; march)
-  double* key;    // running maximum of live arrival heights (search keys)
-  int* cidx;      // first grid index m in [0, N] with z_m >= key, N + 1 if none (ray r owns [cidx_r, cidx_{r+1}))
+  int* cidx;      // first grid index m in [0, N] with z_m >= key_r, N + 1 if none, key_r = running
+                  // maximum of live arrival heights (ray r owns the points [cidx_r, cidx_{r+1}))
   int* tstart;    // [mode][tile 0..T]: largest r with key_r <= z of the tile's first point
   int* mflag;     // per mode: bit0 folded, bit1 has caustic rays
   int* mcaus;     // per mode: caustic rays this march
