@@ -99,9 +99,13 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
   const int npts = (t1 - t0) * 64;
   const int m0 = t0 * 64;                                // its first grid point
   const int row = sub * 64 + sub * 8;
-  T* acc = reinterpret_cast<T*>(lds_raw) + (size_t)w * 2 * NB * row;  // [NB][re | im][row]
+  using C2 = typename CplxOf<T>::type;
+  C2* acc = reinterpret_cast<C2*>(lds_raw) + (size_t)w * NB * row;  // [NB][row] (re, im)
   if constexpr (!TABLE)
-    for (int i = lane; i < 2 * NB * row; i += 64) acc[i] = T(0);
+    for (int i = lane; i < NB * row; i += 64) {
+      acc[i].x = T(0);
+      acc[i].y = T(0);
+    }
   const double inv_lam = 1.0 / g.lam;
   const T* __restrict__ D = static_cast<const T*>(rec.D);
   const T* __restrict__ Pp = static_cast<const T*>(rec.Pp);
@@ -218,8 +222,10 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
         const int pm = m + (m >> 3);
         for (int bb = 0; bb < NB; ++bb) {
           // lanes of one step own different points; LDS keeps the wavefront's accesses in order
-          acc[(2 * bb) * row + pm] += cjr[bb] * ea - cji[bb] * eb;
-          acc[(2 * bb + 1) * row + pm] += cjr[bb] * eb + cji[bb] * ea;
+          C2 v = acc[bb * row + pm];
+          v.x += cjr[bb] * ea - cji[bb] * eb;
+          v.y += cjr[bb] * eb + cji[bb] * ea;
+          acc[bb * row + pm] = v;
         }
         nm = (nm + n) & pmask;
       }
@@ -227,14 +233,15 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
   }
   if constexpr (TABLE) return;
   __syncthreads();
-  T* acc0 = reinterpret_cast<T*>(lds_raw);
+  const C2* acc0 = reinterpret_cast<const C2*>(lds_raw);
   for (int bb = 0; bb < nb; ++bb) {
     for (int m = threadIdx.x; m < npts; m += blockDim.x) {
       const int pm = m + (m >> 3);
       double sr = 0.0, si = 0.0;
       for (int k = 0; k < kWaves; ++k) {
-        sr += (double)acc0[((size_t)k * 2 * NB + 2 * bb) * row + pm];
-        si += (double)acc0[((size_t)k * 2 * NB + 2 * bb + 1) * row + pm];
+        const C2 v = acc0[((size_t)k * NB + bb) * row + pm];
+        sr += (double)v.x;
+        si += (double)v.y;
       }
       part[((size_t)(b0 + bb) * gridDim.y + gi) * g.N + m0 + m] = make_double2(sr, si);
     }
