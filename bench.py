@@ -75,7 +75,7 @@ def bench_serving(torch, np, W, Plan, Server, FP64, MIXED, n_req=24):
     dev = torch.device("cuda:0")
     u0s = [W.incident_field(c) for _, c in reqs]
     work = sum(c["n_modes"] * c["n_z"] * c["n_screens"] for _, c in reqs)
-    srv = Server(200 << 30, max_active=8, screens_per_round=16)
+    srv = Server(200 << 30, max_active=16, screens_per_round=1, mode_points_per_round=2e9)
     ids, done, nxt = {}, {}, 0
     t0 = time.perf_counter()
     while len(done) < n_req:
@@ -119,7 +119,7 @@ def bench_serving(torch, np, W, Plan, Server, FP64, MIXED, n_req=24):
         "mixed_served": {"wall_s": wall, "requests_per_s": n_req / wall, "mode_points_per_s": work / wall,
                          "latency_ms_p50": float(np.percentile(lat, 50)) * 1e3,
                          "latency_ms_p99": float(np.percentile(lat, 99)) * 1e3,
-                         "max_active": 8, "screens_per_round": 16},
+                         "max_active": 16, "mode_points_per_round": 2e9},
         "fp64_serial": {"wall_s": end64, "service_s_sum": float(sum(service)),
                         "requests_per_s": n_req / end64, "mode_points_per_s": work / float(sum(service)),
                         "latency_ms_p50": float(np.percentile(lat64, 50)) * 1e3,

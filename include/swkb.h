@@ -247,14 +247,20 @@ int32_t swkb_uses_matrix(swkb_plan_t plan);
  * device footprint (workspace + field) fits hbm_budget_bytes and fewer than
  * max_active are admitted; each admitted request gets its own plan,
  * workspace (hipMalloc) and stream, and every swkb_server_step advances each
- * admitted request whose previous chunk has finished by screens_per_round
- * screens, so the requests' work overlaps on the device.  The result of a
+ * admitted request whose previous chunk has finished by one chunk of
+ * screens, so the requests' work overlaps on the device.  A chunk holds
+ * about mode_points_per_round mode-point evaluations (M N per screen), at
+ * least screens_per_round screens: every admitted request gets a similar
+ * share of the device per round, so short requests finish within a few
+ * rounds instead of waiting behind long ones.  The result of a
  * request does not depend on what else is being served.  Not thread-safe:
  * one host thread drives a server. */
 typedef struct swkb_server_config {
   size_t hbm_budget_bytes;   /* device bytes the admitted requests may hold (> 0) */
   int32_t max_active;        /* most requests admitted at once (>= 1)            */
-  int32_t screens_per_round; /* screens enqueued per request and step (>= 1)     */
+  int32_t screens_per_round; /* fewest screens per chunk (>= 1)                  */
+  double mode_points_per_round; /* M N per screen times screens per chunk (0: chunks
+                                   of screens_per_round screens)                  */
 } swkb_server_config;
 
 typedef struct swkb_request_info {

@@ -4,9 +4,11 @@
 // and stream; requests are admitted in arrival order as long as their
 // device footprint fits the budget and a slot is free, and every scheduling
 // round advances each admitted request by a chunk of screens on its stream,
-// so the work of all admitted requests overlaps on the device.  A request
-// keeps at most one chunk in flight, so a newly admitted request gets GPU
-// time within one chunk of the others.  Results do not depend on the mix:
+// so the work of all admitted requests overlaps on the device.  Chunks hold
+// about the same number of mode-point evaluations for every request (a
+// processor-sharing quantum), and a request keeps at most one chunk in
+// flight, so a newly admitted or short request gets GPU time within one
+// round of the others and is not stuck behind long ones.  Results do not depend on the mix:
 // every request runs the same deterministic kernels on its own data.
 #include <chrono>
 #include <cstring>
@@ -117,7 +119,13 @@ bool admit(swkb_server_s* s, Request* r) {
 // field back into the pinned host buffer.
 bool advance(swkb_server_s* s, Request* r) {
   const int Q = r->p.n_screens;
-  const int q1 = r->q_next + s->cfg.screens_per_round < Q ? r->q_next + s->cfg.screens_per_round : Q;
+  int chunk = s->cfg.screens_per_round;
+  if (s->cfg.mode_points_per_round > 0.0) {
+    const double per_screen = (double)r->p.n_modes * (double)r->p.n_z;
+    const double k = s->cfg.mode_points_per_round / per_screen;
+    if (k > chunk) chunk = k < (double)Q ? (int)k : Q;
+  }
+  const int q1 = Q - r->q_next > chunk ? r->q_next + chunk : Q;
   const swkb_status ps = swkb_propagate(r->plan, r->q_next == 0 ? r->u_dev : nullptr, r->q_next, q1, nullptr, r->st);
   if (ps != SWKB_OK) {
     fail_request(s, r, std::string("propagate: ") + swkb_last_error());
@@ -143,8 +151,11 @@ extern "C" {
 swkb_status swkb_server_create(const swkb_server_config* cfg, swkb_server_t* out) {
   if (!out) return SWKB_ERR_ARG;
   *out = nullptr;
-  if (!cfg || cfg->hbm_budget_bytes == 0 || cfg->max_active < 1 || cfg->screens_per_round < 1) {
-    swkb::set_error("server config needs hbm_budget_bytes > 0, max_active >= 1, screens_per_round >= 1");
+  if (!cfg || cfg->hbm_budget_bytes == 0 || cfg->max_active < 1 || cfg->screens_per_round < 1 ||
+      !(cfg->mode_points_per_round >= 0.0)) {
+    swkb::set_error(
+        "server config needs hbm_budget_bytes > 0, max_active >= 1, screens_per_round >= 1, "
+        "mode_points_per_round >= 0");
     return SWKB_ERR_ARG;
   }
   swkb_server_s* s = new (std::nothrow) swkb_server_s();

@@ -62,7 +62,8 @@ class Timing(C.Structure):
 
 
 class ServerConfig(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_active", C.c_int32), ("screens_per_round", C.c_int32)]
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_active", C.c_int32), ("screens_per_round", C.c_int32),
+                ("mode_points_per_round", C.c_double)]
 
 
 class RequestInfo(C.Structure):
@@ -328,10 +329,11 @@ class Server:
     problems, admitted by device footprint and advanced together in chunks
     of screens on their own streams.  Fields are host numpy complex128."""
 
-    def __init__(self, hbm_budget_bytes, max_active=16, screens_per_round=8):
+    def __init__(self, hbm_budget_bytes, max_active=16, screens_per_round=8, mode_points_per_round=0.0):
         lib = load()
         cfg = ServerConfig(hbm_budget_bytes=int(hbm_budget_bytes), max_active=int(max_active),
-                           screens_per_round=int(screens_per_round))
+                           screens_per_round=int(screens_per_round),
+                           mode_points_per_round=float(mode_points_per_round))
         h = C.c_void_p()
         _check(lib.swkb_server_create(C.byref(cfg), C.byref(h)))
         self._h = h

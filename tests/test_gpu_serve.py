@@ -50,9 +50,9 @@ def standalone(swkb, cfg, prec):
     return out
 
 
-def serve(swkb, cfgs, precs, budget, max_active, spr, late=()):
+def serve(swkb, cfgs, precs, budget, max_active, spr, late=(), quantum=0.0):
     """Submit all but the `late` indices at once, the late ones after a few rounds."""
-    srv = swkb.Server(budget, max_active=max_active, screens_per_round=spr)
+    srv = swkb.Server(budget, max_active=max_active, screens_per_round=spr, mode_points_per_round=quantum)
     ids = {}
     for i, (c, pr) in enumerate(zip(cfgs, precs)):
         if i not in late:
@@ -79,11 +79,15 @@ def serve(swkb, cfgs, precs, budget, max_active, spr, late=()):
     return results, most_active, st
 
 
-def test_served_equals_standalone(swkb):
+@pytest.mark.parametrize("spr,quantum", [(3, 0.0), (1, 4e6)])
+def test_served_equals_standalone(swkb, spr, quantum):
+    """Chunks of 3 screens, or chunks of about 4e6 mode-points (processor
+    sharing: small requests take many screens per chunk, large ones few)."""
     cfgs = requests()
     precs = [swkb.MIXED, swkb.FP64] * 3
     ref = [standalone(swkb, c, p) for c, p in zip(cfgs, precs)]
-    results, most_active, st = serve(swkb, cfgs, precs, budget=64 << 30, max_active=4, spr=3, late=(1, 4))
+    results, most_active, st = serve(swkb, cfgs, precs, budget=64 << 30, max_active=4, spr=spr, late=(1, 4),
+                                     quantum=quantum)
     say(f"[serve] most admitted at once {most_active}, stats {st}")
     assert most_active >= 2  # work of several requests in flight together
     assert st["completed"] == len(cfgs)
