@@ -205,6 +205,16 @@ int32_t swkb_current_screen(swkb_plan_t plan);
  * SWKB_ERR_CAUSTIC if out->significant > 0, else SWKB_OK. */
 swkb_status swkb_diagnostics(swkb_plan_t plan, void* hip_stream, swkb_counters* out);
 
+/* Enable (1) or disable (0) HIP graphs for swkb_propagate: the first call
+ * with a given (u_in, q_begin, q_end, history) captures its whole screen
+ * sequence (FFT, march, scan, sums; both streams) into a graph on a stream of
+ * the plan's own, later calls with the same arguments replay it (up to 4
+ * graphs are kept).  A replay launches the same kernels with the same
+ * arguments, so it gives the same fields as an eager call; it reads u_in and
+ * writes history when it runs.  Ignored while profiling.  Disabling waits
+ * for replays in flight and frees the graphs.  Host only. */
+swkb_status swkb_graphs(swkb_plan_t plan, int32_t enable);
+
 /* Enable (1) or disable (0) event timing of every kernel the plan launches.
  * Host only; events are recorded on the stream of each launch. */
 swkb_status swkb_profile(swkb_plan_t plan, int32_t enable);

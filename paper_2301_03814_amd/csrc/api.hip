@@ -362,6 +362,115 @@ static swkb_status pipelined(swkb_plan_s* pl, int q_begin, int q_end, hipStream_
   return SWKB_OK;
 }
 
+// Screens q_begin .. q_end-1 of one field on stream st (the body of
+// swkb_propagate).
+static swkb_status enqueue_screens(swkb_plan_s* pl, const void* u_in, int q_begin, int q_end, void* history,
+                                   hipStream_t st) {
+  const Geometry& g = pl->g;
+  const double2* src = u_in ? static_cast<const double2*>(u_in) : pl->u;
+  auto field = [&](int q) {
+    hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, 1, st); });
+    if (e != hipSuccess) return e;
+    double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * g.N : nullptr;
+    if (pl->use_matrix)
+      e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->u, hist, 1, st); });
+    else
+      e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->u, hist, 1, st); });
+    src = pl->u;
+    pl->cur_q = q + 1;
+    return e;
+  };
+  if (overlap(pl)) return pipelined(pl, q_begin, q_end, st, field);
+  for (int q = q_begin; q < q_end; ++q) {
+    if (!pl->use_matrix) {
+      swkb_status s = ensure_rays(pl, q, st);
+      if (s != SWKB_OK) return s;
+    }
+    const hipError_t e = field(q);
+    if (e != hipSuccess) return hip_fail(e, "screen launch");
+  }
+  return SWKB_OK;
+}
+
+static void destroy_graphs(swkb_plan_s* pl) {
+  for (auto& ge : pl->graphs) {
+    (void)hipGraphExecDestroy(ge.exec);
+    (void)hipGraphDestroy(ge.graph);
+  }
+  pl->graphs.clear();
+  if (pl->ev_g0) (void)hipEventDestroy(pl->ev_g0);
+  if (pl->ev_g1) (void)hipEventDestroy(pl->ev_g1);
+  if (pl->cs) (void)hipStreamDestroy(pl->cs);
+  pl->ev_g0 = pl->ev_g1 = nullptr;
+  pl->cs = nullptr;
+}
+
+// The same screens through a HIP graph: captured on the plan's capture
+// stream the first time a (u_in, q_begin, q_end, history) combination is
+// seen, replayed afterwards.  The captured sequence marches every screen
+// itself (the ray slots are not reused across calls) and holds no memset;
+// the caller's stream is joined to the capture stream by events.
+static swkb_status propagate_graph(swkb_plan_s* pl, const void* u_in, int q_begin, int q_end, void* history,
+                                   hipStream_t st) {
+  swkb_plan_s::GraphEntry* hit = nullptr;
+  for (auto& ge : pl->graphs)
+    if (ge.u_in == u_in && ge.q0 == q_begin && ge.q1 == q_end && ge.hist == history) hit = &ge;
+  hipError_t e = hipSuccess;
+  if (!hit) {
+    // rays that do not change with x are marched outside the graph
+    if (!pl->use_matrix && pl->x_invariant) {
+      swkb_status s = ensure_rays(pl, q_begin, st);
+      if (s != SWKB_OK) return s;
+    }
+    if (pl->graphs.size() >= 4) {
+      (void)hipGraphExecDestroy(pl->graphs.front().exec);
+      (void)hipGraphDestroy(pl->graphs.front().graph);
+      pl->graphs.erase(pl->graphs.begin());
+    }
+    // the capture starts after the caller's earlier work
+    e = hipEventRecord(pl->ev_g0, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(pl->cs, pl->ev_g0, 0);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    if (pl->nslots == 2)
+      for (int k = 0; k < 2; ++k) set_slot_q(pl, k, -1);
+    e = hipStreamBeginCapture(pl->cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    const int keep_q = pl->cur_q;
+    swkb_status s = enqueue_screens(pl, u_in, q_begin, q_end, history, pl->cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(pl->cs, &graph);
+    if (s != SWKB_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      pl->cur_q = keep_q;
+      for (int k = 0; k < pl->nslots; ++k) set_slot_q(pl, k, -1);
+      return s != SWKB_OK ? s : hip_fail(e, "graph capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(e, "graph instantiate");
+    }
+    pl->graphs.push_back({u_in, q_begin, q_end, history, graph, exec});
+    hit = &pl->graphs.back();
+  } else {
+    e = hipEventRecord(pl->ev_g0, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(pl->cs, pl->ev_g0, 0);
+  }
+  if (e == hipSuccess) e = hipGraphLaunch(hit->exec, pl->cs);
+  if (e == hipSuccess) e = hipEventRecord(pl->ev_g1, pl->cs);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, pl->ev_g1, 0);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  // host state as after the eager sequence
+  pl->cur_q = q_end;
+  if (pl->nslots == 2) {
+    for (int k = 0; k < 2; ++k) set_slot_q(pl, k, -1);
+    for (int q = q_end - 2 > q_begin ? q_end - 2 : q_begin; q < q_end; ++q) set_slot_q(pl, q & 1, q);
+    select_slot(pl, (q_end - 1) & 1);
+  }
+  return SWKB_OK;
+}
+
 extern "C" {
 
 size_t swkb_workspace_bytes(const swkb_params* p) {
@@ -448,6 +557,9 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     }
     select_slot(pl, 0);
     pl->ms = nullptr;
+    pl->cs = nullptr;
+    pl->ev_g0 = pl->ev_g1 = nullptr;
+    pl->graphs_on = 0;
     for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = nullptr;
     if (pl->nslots == 2) {
       bool ok = hipStreamCreateWithFlags(&pl->ms, hipStreamNonBlocking) == hipSuccess;
@@ -575,38 +687,16 @@ swkb_status swkb_propagate(swkb_plan_t pl, const void* u_in, int32_t q_begin, in
   if (!u_in && pl->cur_q != q_begin)
     return fail(SWKB_ERR_STATE, "u_in is NULL but the plan's field is not on screen q_begin");
   hipStream_t st = (hipStream_t)hip_stream;
-  const Geometry& g = pl->g;
-  const double2* src = u_in ? static_cast<const double2*>(u_in) : pl->u;
   if (q_end == q_begin) {
     if (u_in) {
-      hipError_t e = hipMemcpyAsync(pl->u, u_in, sizeof(double2) * g.N, hipMemcpyDeviceToDevice, st);
+      hipError_t e = hipMemcpyAsync(pl->u, u_in, sizeof(double2) * pl->g.N, hipMemcpyDeviceToDevice, st);
       if (e != hipSuccess) return hip_fail(e, "field copy");
     }
     pl->cur_q = q_begin;
     return SWKB_OK;
   }
-  auto field = [&](int q) {
-    hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, 1, st); });
-    if (e != hipSuccess) return e;
-    double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * g.N : nullptr;
-    if (pl->use_matrix)
-      e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->u, hist, 1, st); });
-    else
-      e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->u, hist, 1, st); });
-    src = pl->u;
-    pl->cur_q = q + 1;
-    return e;
-  };
-  if (overlap(pl)) return pipelined(pl, q_begin, q_end, st, field);
-  for (int q = q_begin; q < q_end; ++q) {
-    if (!pl->use_matrix) {
-      swkb_status s = ensure_rays(pl, q, st);
-      if (s != SWKB_OK) return s;
-    }
-    const hipError_t e = field(q);
-    if (e != hipSuccess) return hip_fail(e, "screen launch");
-  }
-  return SWKB_OK;
+  if (pl->graphs_on && !pl->prof_on) return propagate_graph(pl, u_in, q_begin, q_end, history, st);
+  return enqueue_screens(pl, u_in, q_begin, q_end, history, st);
 }
 
 swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch, int32_t q_begin, int32_t q_end,
@@ -767,6 +857,26 @@ swkb_status swkb_diagnostics(swkb_plan_t pl, void* hip_stream, swkb_counters* ou
   return SWKB_OK;
 }
 
+swkb_status swkb_graphs(swkb_plan_t pl, int32_t enable) {
+  if (!pl) return fail(SWKB_ERR_ARG, "plan is NULL");
+  if (enable && !pl->cs) {
+    hipError_t e = hipStreamCreateWithFlags(&pl->cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_g0, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_g1, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      destroy_graphs(pl);
+      return hip_fail(e, "graph stream");
+    }
+  }
+  if (!enable) {
+    // the plan's streams may still run a replay: wait before releasing the graphs
+    if (pl->cs) (void)hipStreamSynchronize(pl->cs);
+    destroy_graphs(pl);
+  }
+  pl->graphs_on = enable ? 1 : 0;
+  return SWKB_OK;
+}
+
 swkb_status swkb_profile(swkb_plan_t pl, int32_t enable) {
   if (!pl) return fail(SWKB_ERR_ARG, "plan is NULL");
   pl->prof_on = enable ? 1 : 0;
@@ -806,6 +916,8 @@ void swkb_destroy(swkb_plan_t pl) {
   if (!pl) return;
   if (pl->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(pl->blas));
   for (hipEvent_t ev : pl->ev_pool) (void)hipEventDestroy(ev);
+  if (pl->cs) (void)hipStreamSynchronize(pl->cs);
+  destroy_graphs(pl);
   destroy_streams(pl);
   delete pl;
 }

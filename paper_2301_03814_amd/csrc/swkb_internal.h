@@ -117,6 +117,18 @@ struct swkb_plan_s {
   int nslots;
   hipStream_t ms;                // march stream (default priority), or NULL
   hipEvent_t ev_ready[2], ev_free[2];
+  // screen ranges captured into HIP graphs (swkb_graphs)
+  struct GraphEntry {
+    const void* u_in;
+    int q0, q1;
+    void* hist;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  int graphs_on;
+  hipStream_t cs;                // capture and replay stream, or NULL
+  hipEvent_t ev_g0, ev_g1;
   // event timing
   int prof_on;
   std::vector<hipEvent_t> ev_pool;

@@ -26,7 +26,7 @@ EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", 
            "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays", "swkb_profile", "swkb_profile_read",
            "swkb_uses_matrix", "swkb_propagate_batch", "swkb_propagate_stations", "swkb_modal_reference",
            "swkb_server_create", "swkb_server_submit", "swkb_server_step", "swkb_server_poll",
-           "swkb_server_stats", "swkb_server_destroy"]
+           "swkb_server_stats", "swkb_server_destroy", "swkb_graphs"]
 
 
 class Params(C.Structure):
@@ -121,6 +121,8 @@ def load(path: str = LIB_PATH):
     lib.swkb_num_rays.argtypes = [vp]
     lib.swkb_num_rays.restype = i32
     lib.swkb_profile.argtypes = [vp, i32]
+    lib.swkb_graphs.argtypes = [vp, i32]
+    lib.swkb_graphs.restype = C.c_int
     lib.swkb_uses_matrix.argtypes = [vp]
     lib.swkb_uses_matrix.restype = i32
     lib.swkb_profile_read.argtypes = [vp, vp, C.POINTER(Timing)]
@@ -293,6 +295,10 @@ class Plan:
         if st not in (SWKB_OK, SWKB_ERR_CAUSTIC) or (raise_on_caustic and st != SWKB_OK):
             _check(st)
         return {f: int(getattr(cnt, f)) for f, _ in Counters._fields_}
+
+    def graphs(self, enable=True):
+        """Capture screen ranges into HIP graphs and replay them (swkb_graphs)."""
+        _check(_lib.swkb_graphs(self._h, 1 if enable else 0))
 
     def profile(self, enable=True):
         """Record HIP events around every kernel launch of this plan."""

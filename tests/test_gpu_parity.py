@@ -210,6 +210,45 @@ def test_overlapped_march_equals_serial(torch_dev, swkb, prec):
     p.close()
 
 
+@pytest.mark.parametrize("name,prop", [("random_medium_N1024", "auto"), ("duct_dirichlet_N2048", "auto"),
+                                       ("linear_caustic_N512", "recompute")])
+def test_graph_replay_equals_eager(torch_dev, swkb, name, prop):
+    """Screen ranges captured into HIP graphs: every replay (with eager work
+    and synchronisations in between) gives the eager fields bit for bit, for
+    an x-varying medium (two streams), the mode-function matrix and rays
+    marched once; chained ranges continue from the plan's field."""
+    torch, dev = torch_dev
+    cfg = CASES[name]()
+    if prop == "recompute":
+        cfg = W.with_overrides(cfg, propagator=2)
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    Q = cfg["n_screens"]
+    p = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
+    other = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
+    eager = p.propagate(u0, 0, Q).clone()
+    p.graphs(True)
+    out = torch.empty_like(eager)
+    for rep in range(3):
+        out.zero_()
+        p.propagate(u0, 0, Q, out=out)
+        assert torch.equal(out, eager), f"replay {rep} differs"
+        assert p.current_screen == Q
+        other.propagate(u0, 0, 3)  # eager work of another plan between replays
+        torch.cuda.synchronize()
+    # two chained ranges, each captured once and replayed once
+    qs = Q // 2
+    h1, h2 = torch.empty_like(eager[:qs]), torch.empty_like(eager[qs:])
+    for rep in range(2):
+        p.propagate(u0, 0, qs, out=h1)
+        p.propagate(None, qs, Q, out=h2)
+        torch.cuda.synchronize()
+        assert torch.equal(torch.cat([h1, h2]), eager)
+    p.graphs(False)
+    assert torch.equal(p.propagate(u0, 0, Q), eager)
+    p.close()
+    other.close()
+
+
 def test_zero_screens_and_state_errors(torch_dev, swkb):
     torch, dev = torch_dev
     cfg = W.linear_caustic()
