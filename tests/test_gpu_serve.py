@@ -110,3 +110,16 @@ def test_admission_by_footprint(swkb):
     assert most_active == 1
     for i, (field, _) in results.items():
         assert np.array_equal(field, ref[i])
+
+
+def test_uneven_duct_batch_served(swkb):
+    """The first problems of the seeded uneven duct batch (1-10 GHz, duct
+    depth 10-100 m, 200-500 m high, N_z 2048-16384), ranges cut to 6 screens:
+    served together they equal their standalone runs bit for bit."""
+    cfgs = [W.with_overrides(c, n_screens=6) for c in W.duct_batch(seed=4, n_problems=4)]
+    precs = [swkb.MIXED] * len(cfgs)
+    ref = [standalone(swkb, c, p) for c, p in zip(cfgs, precs)]
+    results, most_active, st = serve(swkb, cfgs, precs, budget=64 << 30, max_active=4, spr=1, quantum=2e8)
+    say(f"[serve] duct batch N_z {[c['n_z'] for c in cfgs]}: most admitted at once {most_active}")
+    for i, (field, _) in results.items():
+        assert np.array_equal(field, ref[i])
