@@ -36,8 +36,11 @@ FLOPS_PER_RHS = 51
 FLOPS_PER_MEDIUM = 7
 FLOPS_PER_TERM = 22
 FLOPS_PER_TABLE = 30
-PEAK_FP32_VECTOR = 157.3e12   # MI355X published dense FP32 vector FLOP/s
+PEAK_FP32_VECTOR = 157.3e12   # MI355X published dense FP32 vector FLOP/s (counts packed FP32)
 PEAK_FP64_VECTOR = 78.6e12
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz: the FP32 ceiling of
+# code without packed FP32 instructions (this build excludes them)
+PEAK_ALU_NONPACKED = 256 * 4 * 16 * 2 * 2.4e9
 
 
 def kernel_source_hash():
@@ -247,6 +250,8 @@ def main():
                 "kernel": "march_table_kernel" if w["table_evals"] else
                           f"march_gauss_kernel<{'float' if prec == 'mixed' else 'double'}>",
                 "table_share": round(w["table_evals"] / max(1, w["table_evals"] + w["medium_evals"]), 4),
+                "peak_nonpacked": round(PEAK_ALU_NONPACKED / 1e12, 1),
+                "frac_of_nonpacked": round(achieved * 1e12 / PEAK_ALU_NONPACKED, 4),
                 "flops_per_launch": per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
 
     res = {}
