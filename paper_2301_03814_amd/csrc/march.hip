@@ -184,16 +184,23 @@ struct TableMedium {
   }
 };
 
-// Right-hand side at stage k.  Returns kLive, kDead or kCaustic.
+// Right-hand side at stage k.  Returns false, with st set to kCaustic or
+// kDead, when the ray stops there.
 template <typename T, typename MED>
-__device__ inline int rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, T Zs, T Qs,
-                         double p2_floor, Deriv<T>& d, Work& c) {
-  if (!(Zs > 0.0)) return kCaustic;
+__device__ inline bool rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, T Zs, T Qs, T p2_floor,
+                          Deriv<T>& d, Work& c, int& st) {
+  if (!(Zs > T(0))) {
+    st = kCaustic;
+    return false;
+  }
   const Med<T> m = med.eval(k, dz, c);
   const T xi = (T)mc.xi;
   const T q = xi + dq;
   const T p2 = (T)mc.omx2 + m.e1 - dq * (T(2) * xi + dq);
-  if (!(p2 > (T)p2_floor)) return kDead;
+  if (!(p2 > p2_floor)) {
+    st = kDead;
+    return false;
+  }
   const T ip = fast_rsqrt<T>(p2);
   const T p = p2 * ip;
   d.dz = q * ip;
@@ -206,7 +213,7 @@ __device__ inline int rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, T 
   const T c21 = m.hzz * ip - m.hz * m.hz * ip3;                   // eps_zz/(2p) - eps_z^2/(4p^3)
   d.Zs = c12 * Qs - qe * Zs;
   d.Qs = c21 * Zs + qe * Qs;
-  return kLive;
+  return true;
 }
 
 // First grid index m in [0, N] with z_m = z_a + m h >= key (N + 1 if none,
@@ -239,18 +246,19 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
     const double p0 = (double)sqrt(p02);
     const double hx = g.dx / g.S;
     const T hh = (T)(0.5 * hx), hf = (T)hx, h6 = (T)(hx / 6.0);
+    const T pfl = (T)g.p2_floor;
     const T hd2 = (T)(0.5 * hx), hd6 = (T)(hx / 6.0);
     Deriv<T> k1, k2, k3, k4;
     for (int i = 0; i < g.S; ++i) {
-      if ((st = rhs<T>(med, mc, 2 * i, dz, dq, Zs, Qs, g.p2_floor, k1, c))) break;
-      if ((st = rhs<T>(med, mc, 2 * i + 1, dz + hh * k1.dz, dq + hh * k1.dq, Zs + hd2 * k1.Zs, Qs + hd2 * k1.Qs,
-                       g.p2_floor, k2, c)))
+      if (!rhs<T>(med, mc, 2 * i, dz, dq, Zs, Qs, pfl, k1, c, st)) break;
+      if (!rhs<T>(med, mc, 2 * i + 1, dz + hh * k1.dz, dq + hh * k1.dq, Zs + hd2 * k1.Zs, Qs + hd2 * k1.Qs, pfl,
+                  k2, c, st))
         break;
-      if ((st = rhs<T>(med, mc, 2 * i + 1, dz + hh * k2.dz, dq + hh * k2.dq, Zs + hd2 * k2.Zs, Qs + hd2 * k2.Qs,
-                       g.p2_floor, k3, c)))
+      if (!rhs<T>(med, mc, 2 * i + 1, dz + hh * k2.dz, dq + hh * k2.dq, Zs + hd2 * k2.Zs, Qs + hd2 * k2.Qs, pfl,
+                  k3, c, st))
         break;
-      if ((st = rhs<T>(med, mc, 2 * i + 2, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hf * k3.Zs, Qs + hf * k3.Qs,
-                       g.p2_floor, k4, c)))
+      if (!rhs<T>(med, mc, 2 * i + 2, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hf * k3.Zs, Qs + hf * k3.Qs, pfl,
+                  k4, c, st))
         break;
       c.rhs += 4;
       dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
@@ -260,7 +268,7 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
       Qs += hd6 * (k1.Qs + T(2) * k2.Qs + T(2) * k3.Qs + k4.Qs);
     }
     if (st == kLive) {
-      if (!(Zs > 0.0)) {
+      if (!(Zs > T(0))) {
         st = kCaustic;
       } else {
         const Med<T> m1 = med.eval(2 * g.S, dz, c);

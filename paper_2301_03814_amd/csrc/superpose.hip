@@ -293,21 +293,71 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_kernel(Geometry g,
   }
 }
 
+// The same product for complex64 T with 16-byte loads: lane l of a
+// wavefront reads points m0 + 128 u + 2 l and + 1 (two complex64 in one
+// float4), u < 4, so a workgroup covers 512 points and each load moves 1 KB
+// per wavefront; four modes are in flight per loop trip.  N % 512 == 0.
+__global__ void __launch_bounds__(64 * kWaves) apply_matrix_c64_kernel(Geometry g, const float4* __restrict__ tab,
+                                                                       const double2* __restrict__ c,
+                                                                       double2* __restrict__ part) {
+  extern __shared__ double2 red[];  // [kWaves][4][64][2] pairs of (re, im)
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int gi = blockIdx.y;
+  const int jstep = (int)gridDim.y * kWaves;
+  const int m0 = blockIdx.x * 512;
+  float ar[4][2], ai[4][2];
+  for (int u = 0; u < 4; ++u) ar[u][0] = ar[u][1] = ai[u][0] = ai[u][1] = 0.0f;
+  const size_t row4 = (size_t)g.N / 2;  // float4 per row of T
+#pragma unroll 4
+  for (int j = gi * kWaves + w; j < g.M; j += jstep) {
+    const double2 cj = c[j];
+    const float cr = (float)cj.x, ci = (float)cj.y;
+    const float4* col = tab + (size_t)j * row4 + m0 / 2 + lane;
+    for (int u = 0; u < 4; ++u) {
+      const float4 v = col[u * 64];
+      ar[u][0] += cr * v.x - ci * v.y;
+      ai[u][0] += cr * v.y + ci * v.x;
+      ar[u][1] += cr * v.z - ci * v.w;
+      ai[u][1] += cr * v.w + ci * v.z;
+    }
+  }
+  for (int u = 0; u < 4; ++u)
+    for (int h = 0; h < 2; ++h)
+      red[((w * 4 + u) * 64 + lane) * 2 + h] = make_double2((double)ar[u][h], (double)ai[u][h]);
+  __syncthreads();
+  // points m0 + 128 u + 2 l + h, summed over the wavefronts in order
+  for (int idx = threadIdx.x; idx < 512; idx += blockDim.x) {
+    const int u = idx >> 7, l = (idx >> 1) & 63, h = idx & 1;
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < kWaves; ++k) {
+      const double2 v = red[((k * 4 + u) * 64 + l) * 2 + h];
+      sr += v.x;
+      si += v.y;
+    }
+    part[(size_t)gi * g.N + m0 + idx] = make_double2(sr, si);
+  }
+}
+
 // Sum of the mode-group partials in a fixed order (four threads per point,
 // each over every fourth group, then combined in order), exit taper, field
 // and history writes, for field blockIdx.y of the batch (part is
 // [batch][groups][N] of PT = double2 or float2).  The last block of field 0
 // accumulates the screen's diagnostics; a mode is significant when its
 // energy summed over the batch exceeds caustic_tol^2 times the largest.
+constexpr int kFinThreads = 512;  // 128 points per workgroup, 4 threads per point
+constexpr int kFinWaves = kFinThreads / 64;
+
 template <typename PT>
-__global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords rec, const double2* __restrict__ c,
-                                                       const PT* __restrict__ part, int groups, int batch,
-                                                       double2* __restrict__ out, double2* __restrict__ hist,
-                                                       unsigned long long* __restrict__ counters, Epi ep) {
+__global__ void __launch_bounds__(kFinThreads) finalize_kernel(Geometry g, DevRecords rec,
+                                                               const double2* __restrict__ c,
+                                                               const PT* __restrict__ part, int groups, int batch,
+                                                               double2* __restrict__ out, double2* __restrict__ hist,
+                                                               unsigned long long* __restrict__ counters, Epi ep) {
   const int b = blockIdx.y;
   if (blockIdx.x + 1 < gridDim.x) {
     const int sub = threadIdx.x & 3;
-    const int m = blockIdx.x * 64 + (threadIdx.x >> 2);
+    const int m = blockIdx.x * (kFinThreads / 4) + (threadIdx.x >> 2);
     const PT* pb = part + (size_t)b * groups * g.N;
     double sr = 0.0, si = 0.0;
     if (m < g.N) {
@@ -332,26 +382,32 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
     return;
   }
   if (b != 0) return;
-  // diagnostics: wavefront reductions, then the four wavefronts in order
-  __shared__ double sm[4];
-  __shared__ unsigned long long cnt[4][8];
+  // Diagnostics of the screen (last workgroup of field 0, 512 threads so
+  // that each loop below is one or two rounds of independent loads): the
+  // largest mode energy (summed over the batch), then the counts, with
+  // wavefront reductions and the wavefronts combined in order.
+  __shared__ double sm[kFinWaves];
+  __shared__ unsigned long long cnt[kFinWaves][8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double emax = 0.0;
-  for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
+#pragma unroll 4
+  for (int j = threadIdx.x; j < g.M; j += kFinThreads) {
     double e = 0.0;
     for (int bb = 0; bb < batch; ++bb) {
-      const double2 v = c[(size_t)bb * g.M + j];
-      e += v.x * v.x + v.y * v.y;
+      const double2 cv = c[(size_t)bb * g.M + j];
+      e += cv.x * cv.x + cv.y * cv.y;
     }
     emax = fmax(emax, e);
   }
   for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off, 64));
   if (lane == 0) sm[wv] = emax;
   __syncthreads();
-  emax = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+  emax = 0.0;
+  for (int k = 0; k < kFinWaves; ++k) emax = fmax(emax, sm[k]);
   const double thr = ep.caustic_tol * ep.caustic_tol * emax;
-  unsigned long long v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int j = threadIdx.x; j < g.M; j += blockDim.x) {
+  unsigned v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // a thread's sums fit 32 bits; 64-bit from the wavefront on
+#pragma unroll 4
+  for (int j = threadIdx.x; j < g.M; j += kFinThreads) {
     const int f = rec.mflag[j];
     v[0] += rec.mcaus[j];
     v[1] += rec.mdead[j];
@@ -369,14 +425,16 @@ __global__ void __launch_bounds__(256) finalize_kernel(Geometry g, DevRecords re
     v[6] += (unsigned)rec.mwork[4 * j + 2];
     v[7] += (unsigned)rec.mwork[4 * j + 3];
   }
-  for (int k = 0; k < 8; ++k)
-    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-  if (lane == 0)
-    for (int k = 0; k < 8; ++k) cnt[wv][k] = v[k];
+  for (int k = 0; k < 8; ++k) {
+    unsigned long long w64 = v[k];
+    for (int off = 32; off > 0; off >>= 1) w64 += __shfl_xor(w64, off, 64);
+    if (lane == 0) cnt[wv][k] = w64;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long t[8];
-    for (int k = 0; k < 8; ++k) t[k] = ((cnt[0][k] + cnt[1][k]) + cnt[2][k]) + cnt[3][k];
+    unsigned long long t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int w = 0; w < kFinWaves; ++w)
+      for (int k = 0; k < 8; ++k) t[k] += cnt[w][k];
     for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], t[k]);
     atomicAdd(&counters[4], 1ull);
     for (int k = 4; k < 8; ++k) atomicAdd(&counters[k + 1], t[k]);
@@ -461,7 +519,7 @@ hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + 63) / 64 + 1, batch), dim3(256), 0, st, g, pl.rec, pl.c,
+  hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, batch), dim3(kFinThreads), 0, st, g, pl.rec, pl.c,
                      pl.part, groups, batch, out, hist, pl.counters, ep);
   return hipGetLastError();
 }
@@ -490,6 +548,17 @@ hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* his
   const Geometry& g = pl.g;
   const Epi ep = epi_of(pl);
   const int sub = superpose_sub(g);
+  if (batch == 1 && pl.precision != SWKB_FP64 && g.N % 512 == 0) {
+    const int groups = groups_for(g, 8);  // 512-point workgroups
+    hipLaunchKernelGGL(apply_matrix_c64_kernel, dim3(g.N / 512, groups), dim3(64 * kWaves),
+                       sizeof(double2) * kWaves * 4 * 64 * 2, st, g, static_cast<const float4*>(pl.tmat), pl.c,
+                       pl.part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, 1), dim3(kFinThreads), 0, st, g, pl.rec, pl.c,
+                       pl.part, groups, 1, out, hist, pl.counters, ep);
+    return hipGetLastError();
+  }
   if (batch == 1) {
     const int groups = superpose_groups(g);
     const size_t red = sizeof(double2) * 64 * kWaves * kSub;
@@ -502,7 +571,7 @@ hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* his
                          static_cast<const float2*>(pl.tmat), pl.c, pl.part, sub);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + 63) / 64 + 1, 1), dim3(256), 0, st, g, pl.rec, pl.c,
+    hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, 1), dim3(kFinThreads), 0, st, g, pl.rec, pl.c,
                        pl.part, groups, 1, out, hist, pl.counters, ep);
     return hipGetLastError();
   }
@@ -510,10 +579,10 @@ hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* his
   hipError_t e = gemm_fields(pl, batch, st);
   if (e != hipSuccess) return e;
   if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + 63) / 64 + 1, batch), dim3(256), 0, st, g, pl.rec,
+    hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, batch), dim3(kFinThreads), 0, st, g, pl.rec,
                        pl.c, pl.part, 1, batch, out, hist, pl.counters, ep);
   else
-    hipLaunchKernelGGL(finalize_kernel<float2>, dim3((g.N + 63) / 64 + 1, batch), dim3(256), 0, st, g, pl.rec,
+    hipLaunchKernelGGL(finalize_kernel<float2>, dim3((g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, batch), dim3(kFinThreads), 0, st, g, pl.rec,
                        pl.c, reinterpret_cast<const float2*>(pl.part), 1, batch, out, hist, pl.counters, ep);
   return hipGetLastError();
 }
