@@ -119,8 +119,12 @@ int ilog2(int x) {
 
 hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, int batch, hipStream_t st) {
   const Geometry& g = pl.g;
-  const int CA = g.P2 < 16 ? g.P2 : 16;
-  int RB = 2048 / g.P2;
+  // about 512 elements per workgroup: one butterfly per thread and stage, and
+  // P / 512 workgroups working on the latency-bound stages in parallel
+  int CA = 512 / g.P1;
+  if (CA < 1) CA = 1;
+  if (CA > g.P2) CA = g.P2;
+  int RB = 512 / g.P2;
   if (RB < 1) RB = 1;
   if (RB > g.P1) RB = g.P1;
   hipLaunchKernelGGL(fft_cols, dim3(g.P2 / CA, batch), dim3(256), sizeof(double2) * (CA * g.P1 + g.P1 / 2), st, u,
