@@ -248,6 +248,10 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
   }
 }
 
+// Native vector types for non-temporal loads.
+typedef float F4 __attribute__((ext_vector_type(4)));
+typedef double D2 __attribute__((ext_vector_type(2)));
+
 // One screen from the mode-function matrix: part[gi][m] = sum over the
 // group's modes of c_j T[j][m], in the same grid/partial layout as the
 // superposition (a streaming read of T, coalesced along m).
@@ -272,7 +276,14 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_kernel(Geometry g,
     const typename CplxOf<T>::type* col = tab + (size_t)j * g.N + m0 + lane;
     for (int u = 0; u < kSub; ++u) {
       if (u < sub) {
-        const typename CplxOf<T>::type v = col[u * 64];
+        typename CplxOf<T>::type v;
+        if constexpr (std::is_same<T, double>::value) {
+          const D2 d = __builtin_nontemporal_load(reinterpret_cast<const D2*>(col + u * 64));
+          v.x = d.x;
+          v.y = d.y;
+        } else {
+          v = col[u * 64];
+        }
         acc_re[u] += cr * v.x - ci * v.y;
         acc_im[u] += cr * v.y + ci * v.x;
       }
@@ -315,7 +326,8 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_c64_kernel(Geometry 
     const float cr = (float)cj.x, ci = (float)cj.y;
     const float4* col = tab + (size_t)j * row4 + m0 / 2 + lane;
     for (int u = 0; u < 4; ++u) {
-      const float4 v = col[u * 64];
+      // T is streamed once per screen: non-temporal loads keep it out of the caches
+      const F4 v = __builtin_nontemporal_load(reinterpret_cast<const F4*>(col + u * 64));
       ar[u][0] += cr * v.x - ci * v.y;
       ai[u][0] += cr * v.y + ci * v.x;
       ar[u][1] += cr * v.z - ci * v.w;
