@@ -51,6 +51,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def traffic_from_profiles(precision):
     """HBM bytes per launch of the march kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
@@ -340,6 +351,14 @@ def main():
                "sample": f"screens {list(samples)} of the same workload (FP64 oracle, OpenMP over modes, "
                          f"{threads} threads), each started from the GPU FP64 field on that screen",
                "seconds": round(tc, 2), "fp64_gpu_vs_oracle_rel_l2_max": max(errs)}
+        # the same oracle on one thread (the paper's timings are single-core), screen 0 only
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.screen(cfg, 0, W.incident_field(cfg))
+        t1c = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        cpu["one_thread"] = {"value": M * N / t1c, "seconds": round(t1c, 2), "sample": "screen 0"}
+        cpu["host"] = {"cpu_model": cpu_model(), "logical_cpus": os.cpu_count()}
 
     duct = None
     if not args.no_duct:
