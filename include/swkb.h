@@ -249,6 +249,81 @@ int32_t swkb_num_rays(swkb_plan_t plan);
 /* 1 if the plan holds the mode-function matrix T (SWKB_PROP_*), else 0. */
 int32_t swkb_uses_matrix(swkb_plan_t plan);
 
+/* ---- many problems in one launch per stage -------------------------- */
+
+/* Several independent problems in media that do not depend on x (each with
+ * its own plan: frequency, profile, height, grid, range), all carried from
+ * their first screen to their last together.  Every screen step is one
+ * launch per stage for all problems still running: the FFT column and row
+ * passes, the product of the mode-function matrix with the modes (Sec.
+ * 2.1.2, eq. ray_bundle_q_plus_1 with the mode functions tabulated once), and
+ * the exit epilogue; each workgroup finds its problem and its place in it in
+ * a device table.  Problems are ordered by screen count, so the problems
+ * still running at step q are a prefix of the table and the launches of
+ * step q cover exactly them.  With graphs enabled the whole sequence of
+ * steps is captured once into a HIP graph and replayed as one launch.
+ *
+ * Requirements per plan: mode-function matrix in use (swkb_uses_matrix),
+ * SWKB_MIXED precision, n_z a multiple of 512; at most 4095 plans, each
+ * listed once.  The plans stay owned by the caller, must outlive the group
+ * and must not be used otherwise while a group call is in flight.  The
+ * group allocates its own device memory (hipMalloc: a problem table, the
+ * workgroup maps and the partial sums of the product). */
+typedef struct swkb_multi_s* swkb_multi_t;
+
+/* Launch shapes per size class (problems with the same n_z), picked by
+ * swkb_multi_tune or set by the caller.  fft_elems: elements per FFT
+ * workgroup (256, 512 or 1024); apply_groups: workgroups along the modes
+ * of the product (>= 1; each covers every apply_groups-th set of
+ * four modes; clamped to (n_modes + 3) / 4 per problem); the defaults
+ * equal the single-problem path's choices, which makes every field
+ * bit-identical to a separate swkb_propagate. */
+#define SWKB_MULTI_MAX_CLASSES 16
+typedef struct swkb_multi_tuning {
+  int32_t n_classes;                            /* distinct n_z, ascending   */
+  int32_t class_n_z[SWKB_MULTI_MAX_CLASSES];
+  int32_t fft_elems[SWKB_MULTI_MAX_CLASSES];
+  int32_t apply_groups[SWKB_MULTI_MAX_CLASSES];
+  int32_t graphs;                               /* 1: capture and replay     */
+  double fft_us[SWKB_MULTI_MAX_CLASSES];        /* tuner: best FFT time of the class's screen (both passes) */
+  double apply_us[SWKB_MULTI_MAX_CLASSES];      /* tuner: best product time of the class's screen           */
+} swkb_multi_tuning;
+
+/* Host only (uploads the problem table and maps with a synchronous copy).
+ * SWKB_ERR_ARG if a plan does not meet the requirements above or more than
+ * SWKB_MULTI_MAX_CLASSES distinct n_z occur. */
+swkb_status swkb_multi_create(const swkb_plan_t* plans, int32_t n, swkb_multi_t* out);
+
+/* Current launch shapes into *out (host). */
+swkb_status swkb_multi_get_tuning(swkb_multi_t m, swkb_multi_tuning* out);
+
+/* Set launch shapes: class_n_z must list the group's classes as
+ * swkb_multi_get_tuning returns them; values outside the ranges above give
+ * SWKB_ERR_ARG.  Drops a captured graph. */
+swkb_status swkb_multi_set_tuning(swkb_multi_t m, const swkb_multi_tuning* t);
+
+/* Autotuner: for each size class, times every FFT blocking and every
+ * product blocking in a candidate set with HIP events on hip_stream (each
+ * candidate launched `reps` times over that class's problems alone, best
+ * average kept), applies the fastest and writes the result to *out (may be
+ * NULL).  Overwrites the plans' current fields (zeroed first) and leaves
+ * them without a current field; counters are not touched.  Synchronises
+ * hip_stream.  reps >= 1. */
+swkb_status swkb_multi_tune(swkb_multi_t m, int32_t reps, void* hip_stream, swkb_multi_tuning* out);
+
+/* Carry every problem from screen 0 to its last screen (Algorithm 1).
+ * u_in: host array of n device pointers, complex128[n_z_i] each, the fields
+ * on screen 0 in the order the plans were given; history: host array of n
+ * device pointers (complex128[n_screens_i][n_z_i] receiving screens
+ * 1 .. n_screens_i, entries may be NULL) or NULL.  Afterwards each plan's
+ * current field is on its last screen (swkb_field) and its counters include
+ * the run (swkb_diagnostics).  Asynchronous on hip_stream, except that the
+ * host waits until the previous call's problem table has been copied. */
+swkb_status swkb_multi_propagate(swkb_multi_t m, const void* const* u_in, void* const* history, void* hip_stream);
+
+/* Waits for the group's work, frees its device memory and graph. */
+void swkb_multi_destroy(swkb_multi_t m);
+
 /* ---- serving loop ----------------------------------------------------- */
 
 /* Continuous batching of independent propagation requests on the current

@@ -58,14 +58,13 @@ __device__ void lds_fft(double2* L, int nb, int len, const double2* wl) {
   }
 }
 
-__global__ void __launch_bounds__(256) fft_cols(const double2* __restrict__ u, double2* __restrict__ Y,
-                                                const double2* __restrict__ tw, int N, int bc, int P, int P1,
-                                                int P2, int logP1, int CA) {
-  extern __shared__ double2 L[];  // CA sequences of length P1, then P1 / 2 twiddles
+// Column pass of one field: workgroup bx of P2 / CA.  L holds CA sequences of
+// length P1, then P1 / 2 twiddles.
+__device__ inline void fft_cols_body(const double2* __restrict__ u, double2* __restrict__ Y,
+                                     const double2* __restrict__ tw, int N, int bc, int P, int P1, int P2,
+                                     int logP1, int CA, int bx, double2* L) {
   double2* wl = L + CA * P1;
-  const int c0 = blockIdx.x * CA;
-  u += (size_t)blockIdx.y * N;  // field of this batch member
-  Y += (size_t)blockIdx.y * P;
+  const int c0 = bx * CA;
   for (int k = threadIdx.x; k < P1 / 2; k += blockDim.x) wl[k] = tw[k * (P / P1)];
   for (int idx = threadIdx.x; idx < CA * P1; idx += blockDim.x) {
     const int cc = idx % CA, m1 = idx / CA;
@@ -79,14 +78,12 @@ __global__ void __launch_bounds__(256) fft_cols(const double2* __restrict__ u, d
   }
 }
 
-__global__ void __launch_bounds__(256) fft_rows(const double2* __restrict__ Y, double2* __restrict__ c,
-                                                const double2* __restrict__ tw, int P, int P1, int P2,
-                                                int logP2, int RB, int M) {
-  extern __shared__ double2 L[];  // RB sequences of length P2, then P2 / 2 twiddles
+// Row pass of one field: workgroup bx of P1 / RB; writes the M kept bins.
+__device__ inline void fft_rows_body(const double2* __restrict__ Y, double2* __restrict__ c,
+                                     const double2* __restrict__ tw, int P, int P1, int P2, int logP2, int RB,
+                                     int M, int bx, double2* L) {
   double2* wl = L + RB * P2;
-  const int r0 = blockIdx.x * RB;
-  Y += (size_t)blockIdx.y * P;  // batch member
-  c += (size_t)blockIdx.y * M;
+  const int r0 = bx * RB;
   for (int k = threadIdx.x; k < P2 / 2; k += blockDim.x) wl[k] = tw[k * (P / P2)];
   for (int idx = threadIdx.x; idx < RB * P2; idx += blockDim.x) {
     const int rr = idx / P2, m2 = idx - rr * P2;
@@ -109,24 +106,67 @@ __global__ void __launch_bounds__(256) fft_rows(const double2* __restrict__ Y, d
   }
 }
 
+__global__ void __launch_bounds__(256) fft_cols(const double2* __restrict__ u, double2* __restrict__ Y,
+                                                const double2* __restrict__ tw, int N, int bc, int P, int P1,
+                                                int P2, int logP1, int CA) {
+  extern __shared__ double2 L[];
+  fft_cols_body(u + (size_t)blockIdx.y * N, Y + (size_t)blockIdx.y * P, tw, N, bc, P, P1, P2, logP1, CA,
+                blockIdx.x, L);
+}
+
+__global__ void __launch_bounds__(256) fft_rows(const double2* __restrict__ Y, double2* __restrict__ c,
+                                                const double2* __restrict__ tw, int P, int P1, int P2,
+                                                int logP2, int RB, int M) {
+  extern __shared__ double2 L[];
+  fft_rows_body(Y + (size_t)blockIdx.y * P, c + (size_t)blockIdx.y * M, tw, P, P1, P2, logP2, RB, M, blockIdx.x,
+                L);
+}
+
+// The two passes for many problems in one launch each: workgroup b runs
+// local workgroup map[b] & 0xfffff of problem map[b] >> 20.  A screen's
+// input is u_in on the problem's first step, its field u afterwards.
+__global__ void __launch_bounds__(256) fft_cols_multi(const MultiProblem* __restrict__ mp,
+                                                      const unsigned* __restrict__ map, int first) {
+  extern __shared__ double2 L[];
+  const unsigned e = map[blockIdx.x];
+  const MultiProblem& p = mp[e >> 20];
+  fft_cols_body(first ? p.u_in : p.u, p.Y, p.tw, p.g.N, p.g.bc, p.g.P, p.g.P1, p.g.P2, p.logP1, p.CA, e & 0xfffff,
+                L);
+}
+
+__global__ void __launch_bounds__(256) fft_rows_multi(const MultiProblem* __restrict__ mp,
+                                                      const unsigned* __restrict__ map) {
+  extern __shared__ double2 L[];
+  const unsigned e = map[blockIdx.x];
+  const MultiProblem& p = mp[e >> 20];
+  fft_rows_body(p.Y, p.c, p.tw, p.g.P, p.g.P1, p.g.P2, p.logP2, p.RB, p.g.M, e & 0xfffff, L);
+}
+
+}  // namespace
+
 int ilog2(int x) {
   int l = 0;
   while ((1 << l) < x) ++l;
   return l;
 }
 
-}  // namespace
+void fft_blocking(const Geometry& g, int elems, int* CA, int* RB) {
+  int ca = elems / g.P1;
+  if (ca < 1) ca = 1;
+  if (ca > g.P2) ca = g.P2;
+  int rb = elems / g.P2;
+  if (rb < 1) rb = 1;
+  if (rb > g.P1) rb = g.P1;
+  *CA = ca;
+  *RB = rb;
+}
 
 hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, int batch, hipStream_t st) {
   const Geometry& g = pl.g;
   // about 512 elements per workgroup: one butterfly per thread and stage, and
   // P / 512 workgroups working on the latency-bound stages in parallel
-  int CA = 512 / g.P1;
-  if (CA < 1) CA = 1;
-  if (CA > g.P2) CA = g.P2;
-  int RB = 512 / g.P2;
-  if (RB < 1) RB = 1;
-  if (RB > g.P1) RB = g.P1;
+  int CA, RB;
+  fft_blocking(g, kFftElems, &CA, &RB);
   hipLaunchKernelGGL(fft_cols, dim3(g.P2 / CA, batch), dim3(256), sizeof(double2) * (CA * g.P1 + g.P1 / 2), st, u,
                      pl.Y, pl.tw,
                      g.N, g.bc, g.P, g.P1, g.P2, ilog2(g.P1), CA);
@@ -135,6 +175,15 @@ hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, int batch, 
   hipLaunchKernelGGL(fft_rows, dim3(g.P1 / RB, batch), dim3(256), sizeof(double2) * (RB * g.P2 + g.P2 / 2), st,
                      pl.Y, pl.c, pl.tw,
                      g.P, g.P1, g.P2, ilog2(g.P2), RB, g.M);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_multi(const MultiProblem* mp, const unsigned* map_cols, int n_cols, const unsigned* map_rows,
+                            int n_rows, int first, size_t lds_cols, size_t lds_rows, hipStream_t st) {
+  hipLaunchKernelGGL(fft_cols_multi, dim3(n_cols), dim3(256), lds_cols, st, mp, map_cols, first);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fft_rows_multi, dim3(n_rows), dim3(256), lds_rows, st, mp, map_rows);
   return hipGetLastError();
 }
 

@@ -19,12 +19,6 @@
 namespace swkb {
 namespace {
 
-struct Epi {
-  double absorber_bot, absorber_top;
-  double caustic_tol;
-  int mprime_off;  // m' = m + mprime_off (grid index from the phase origin)
-};
-
 __device__ inline double taper(const Geometry& g, const Epi& e, double z) {
   double w = 1.0;
   if (e.absorber_bot > 0.0 && z < g.z_a + e.absorber_bot) {
@@ -468,15 +462,13 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_kernel(Geometry g,
 // wavefront reads points m0 + 128 u + 2 l and + 1 (two complex64 in one
 // float4), u < 4, so a workgroup covers 512 points and each load moves 1 KB
 // per wavefront; four modes are in flight per loop trip.  N % 512 == 0.
-__global__ void __launch_bounds__(64 * kWaves) apply_matrix_c64_kernel(Geometry g, const float4* __restrict__ tab,
-                                                                       const double2* __restrict__ c,
-                                                                       double2* __restrict__ part) {
-  extern __shared__ double2 red[];  // [kWaves][4][64][2] pairs of (re, im)
+__device__ inline void apply_c64_body(const Geometry& g, const float4* __restrict__ tab,
+                                      const double2* __restrict__ c, double2* __restrict__ part, int bx, int gi,
+                                      int groups, double2* red) {  // red: [kWaves][4][64][2] pairs of (re, im)
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int gi = blockIdx.y;
-  const int jstep = (int)gridDim.y * kWaves;
-  const int m0 = blockIdx.x * 512;
+  const int jstep = groups * kWaves;
+  const int m0 = bx * 512;
   float ar[4][2], ai[4][2];
   for (int u = 0; u < 4; ++u) ar[u][0] = ar[u][1] = ai[u][0] = ai[u][1] = 0.0f;
   const size_t row4 = (size_t)g.N / 2;  // float4 per row of T
@@ -511,6 +503,13 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_c64_kernel(Geometry 
   }
 }
 
+__global__ void __launch_bounds__(64 * kWaves) apply_matrix_c64_kernel(Geometry g, const float4* __restrict__ tab,
+                                                                       const double2* __restrict__ c,
+                                                                       double2* __restrict__ part) {
+  extern __shared__ double2 red[];
+  apply_c64_body(g, tab, c, part, blockIdx.x, blockIdx.y, gridDim.y, red);
+}
+
 // Sum of the mode-group partials in a fixed order (four threads per point,
 // each over every fourth group, then combined in order), exit taper, field
 // and history writes, for field blockIdx.y of the batch (part is
@@ -521,15 +520,13 @@ constexpr int kFinThreads = 512;  // 128 points per workgroup, 4 threads per poi
 constexpr int kFinWaves = kFinThreads / 64;
 
 template <typename PT>
-__global__ void __launch_bounds__(kFinThreads) finalize_kernel(Geometry g, DevRecords rec,
-                                                               const double2* __restrict__ c,
-                                                               const PT* __restrict__ part, int groups, int batch,
-                                                               double2* __restrict__ out, double2* __restrict__ hist,
-                                                               unsigned long long* __restrict__ counters, Epi ep) {
-  const int b = blockIdx.y;
-  if (blockIdx.x + 1 < gridDim.x) {
+__device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, const double2* __restrict__ c,
+                                     const PT* __restrict__ part, int groups, int batch, double2* __restrict__ out,
+                                     double2* __restrict__ hist, unsigned long long* __restrict__ counters,
+                                     const Epi& ep, int bx, int nbx, int b) {
+  if (bx + 1 < nbx) {
     const int sub = threadIdx.x & 3;
-    const int m = blockIdx.x * (kFinThreads / 4) + (threadIdx.x >> 2);
+    const int m = bx * (kFinThreads / 4) + (threadIdx.x >> 2);
     const PT* pb = part + (size_t)b * groups * g.N;
     double sr = 0.0, si = 0.0;
     if (m < g.N) {
@@ -613,6 +610,36 @@ __global__ void __launch_bounds__(kFinThreads) finalize_kernel(Geometry g, DevRe
   }
 }
 
+template <typename PT>
+__global__ void __launch_bounds__(kFinThreads) finalize_kernel(Geometry g, DevRecords rec,
+                                                               const double2* __restrict__ c,
+                                                               const PT* __restrict__ part, int groups, int batch,
+                                                               double2* __restrict__ out, double2* __restrict__ hist,
+                                                               unsigned long long* __restrict__ counters, Epi ep) {
+  finalize_body<PT>(g, rec, c, part, groups, batch, out, hist, counters, ep, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
+// The matrix product and the epilogue of one screen for many problems, one
+// launch each: workgroup b runs local workgroup map[b] & 0xfffff of problem
+// map[b] >> 20 (product: local = gi * (N / 512) + point block).
+__global__ void __launch_bounds__(64 * kWaves) apply_c64_multi(const MultiProblem* __restrict__ mp,
+                                                               const unsigned* __restrict__ map) {
+  extern __shared__ double2 red[];
+  const unsigned e = map[blockIdx.x];
+  const MultiProblem& p = mp[e >> 20];
+  const int local = (int)(e & 0xfffff), nx = p.g.N >> 9;
+  apply_c64_body(p.g, p.tmat, p.c, p.part, local % nx, local / nx, p.groups, red);
+}
+
+__global__ void __launch_bounds__(kFinThreads) finalize_multi(const MultiProblem* __restrict__ mp,
+                                                              const unsigned* __restrict__ map, int step) {
+  const unsigned e = map[blockIdx.x];
+  const MultiProblem& p = mp[e >> 20];
+  double2* hist = p.hist ? p.hist + (size_t)step * p.g.N : nullptr;
+  finalize_body<double2>(p.g, p.rec, p.c, p.part, p.groups, 1, p.u, hist, p.counters, p.ep, (int)(e & 0xfffff),
+                         (p.g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, 0);
+}
+
 // c [batch][M] complex128 -> complex64 for the FP32 matrix product.
 __global__ void to_c64_kernel(const double2* __restrict__ c, float2* __restrict__ cf, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -679,7 +706,7 @@ static void launch_sum(const swkb_plan_s& pl, const dim3& grid, const DevModes& 
                      md, pl.rec, pl.c, pl.part, ep, sub, batch);
 }
 
-static Epi epi_of(const swkb_plan_s& pl) {
+Epi epi_of(const swkb_plan_s& pl) {
   Epi ep;
   ep.absorber_bot = pl.p.absorber_bot;
   ep.absorber_top = pl.p.absorber_top;
@@ -778,6 +805,25 @@ hipError_t launch_to_c64(const swkb_plan_s& pl, int batch, hipStream_t st) {
   const int n = batch * pl.g.M;
   hipLaunchKernelGGL(to_c64_kernel, dim3((n + 255) / 256), dim3(256), 0, st, pl.c, pl.cf, n);
   return hipGetLastError();
+}
+
+int finalize_blocks(const Geometry& g) { return (g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1; }
+
+int apply_multi_groups(const Geometry& g) { return groups_for(g, 8); }
+
+hipError_t launch_apply_multi(const MultiProblem* mp, const unsigned* map_apply, int n_apply,
+                              const unsigned* map_fin, int n_fin, int step, hipStream_t st) {
+  if (n_apply > 0) {
+    hipLaunchKernelGGL(apply_c64_multi, dim3(n_apply), dim3(64 * kWaves), sizeof(double2) * kWaves * 4 * 64 * 2, st,
+                       mp, map_apply);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (n_fin > 0) {
+    hipLaunchKernelGGL(finalize_multi, dim3(n_fin), dim3(kFinThreads), 0, st, mp, map_fin, step);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 }  // namespace swkb

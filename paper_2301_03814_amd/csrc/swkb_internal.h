@@ -67,6 +67,35 @@ struct Geometry {
   double z_a, z_b, h, k, lam, dx, p2_floor;
 };
 
+// Exit epilogue of a plan: absorber layers, the caustic significance
+// threshold, and the offset of the grid index from the phase origin.
+struct Epi {
+  double absorber_bot, absorber_top;
+  double caustic_tol;
+  int mprime_off;  // m' = m + mprime_off
+};
+
+// Elements per FFT workgroup on the single-problem path.
+constexpr int kFftElems = 512;
+
+// One problem of a multi-problem launch (entry of a device table): the
+// plan's buffers and the blocking the launch uses for it.
+struct MultiProblem {
+  Geometry g;
+  Epi ep;
+  DevRecords rec;
+  const double2* tw;
+  double2* Y;
+  double2* c;
+  const float4* tmat;    // complex64 mode-function matrix [M][N]
+  double2* part;         // [groups][N] partial sums of the product
+  double2* u;            // the problem's field
+  const double2* u_in;   // field on the problem's first screen
+  double2* hist;         // [n_screens][N] or NULL
+  unsigned long long* counters;
+  int logP1, logP2, CA, RB, groups;
+};
+
 }  // namespace swkb
 
 struct swkb_plan_s {
@@ -159,6 +188,17 @@ hipError_t launch_to_c64(const swkb_plan_s& pl, int batch, hipStream_t st);
 // U[b][m] = sum_j C[b][j] T[j][m] for batch > 1 into pl.part (rocBLAS GEMM)
 hipError_t gemm_fields(const swkb_plan_s& pl, int batch, hipStream_t st);
 hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st);
+// Multi-problem launches (tables and workgroup maps in device memory; map
+// entries are problem << 20 | local workgroup).
+void fft_blocking(const Geometry& g, int elems, int* CA, int* RB);
+int ilog2(int x);
+Epi epi_of(const swkb_plan_s& pl);
+int finalize_blocks(const Geometry& g);
+int apply_multi_groups(const Geometry& g);
+hipError_t launch_fft_multi(const MultiProblem* mp, const unsigned* map_cols, int n_cols, const unsigned* map_rows,
+                            int n_rows, int first, size_t lds_cols, size_t lds_rows, hipStream_t st);
+hipError_t launch_apply_multi(const MultiProblem* mp, const unsigned* map_apply, int n_apply,
+                              const unsigned* map_fin, int n_fin, int step, hipStream_t st);
 hipError_t launch_export_rays(const swkb_plan_s& pl, int q, double* Z, double* psi, double* qz,
                               double* amp, int* flag, hipStream_t st);
 

@@ -26,7 +26,11 @@ EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", 
            "swkb_stage_modes", "swkb_stage_rays", "swkb_num_rays", "swkb_profile", "swkb_profile_read",
            "swkb_uses_matrix", "swkb_propagate_batch", "swkb_propagate_stations", "swkb_modal_reference",
            "swkb_server_create", "swkb_server_submit", "swkb_server_step", "swkb_server_poll",
-           "swkb_server_stats", "swkb_server_destroy", "swkb_graphs"]
+           "swkb_server_stats", "swkb_server_destroy", "swkb_graphs", "swkb_multi_create",
+           "swkb_multi_get_tuning", "swkb_multi_set_tuning", "swkb_multi_tune", "swkb_multi_propagate",
+           "swkb_multi_destroy"]
+
+MULTI_MAX_CLASSES = 16
 
 
 class Params(C.Structure):
@@ -74,6 +78,13 @@ class ServerStats(C.Structure):
     _fields_ = [("completed", C.c_int64), ("screens", C.c_int64), ("mode_points", C.c_int64),
                 ("device_bytes_in_use", C.c_size_t), ("active", C.c_int32), ("pending", C.c_int32),
                 ("seconds", C.c_double)]
+
+
+class MultiTuning(C.Structure):
+    _fields_ = [("n_classes", C.c_int32), ("class_n_z", C.c_int32 * MULTI_MAX_CLASSES),
+                ("fft_elems", C.c_int32 * MULTI_MAX_CLASSES), ("apply_groups", C.c_int32 * MULTI_MAX_CLASSES),
+                ("graphs", C.c_int32), ("fft_us", C.c_double * MULTI_MAX_CLASSES),
+                ("apply_us", C.c_double * MULTI_MAX_CLASSES)]
 
 
 REQ_PENDING, REQ_ACTIVE, REQ_DONE, REQ_FAILED = range(4)
@@ -133,6 +144,16 @@ def load(path: str = LIB_PATH):
     lib.swkb_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
     lib.swkb_server_destroy.argtypes = [vp]
     lib.swkb_server_destroy.restype = None
+    lib.swkb_multi_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp)]
+    lib.swkb_multi_get_tuning.argtypes = [vp, C.POINTER(MultiTuning)]
+    lib.swkb_multi_set_tuning.argtypes = [vp, C.POINTER(MultiTuning)]
+    lib.swkb_multi_tune.argtypes = [vp, i32, vp, C.POINTER(MultiTuning)]
+    lib.swkb_multi_propagate.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
+    lib.swkb_multi_destroy.argtypes = [vp]
+    lib.swkb_multi_destroy.restype = None
+    for name in ("swkb_multi_create", "swkb_multi_get_tuning", "swkb_multi_set_tuning", "swkb_multi_tune",
+                 "swkb_multi_propagate"):
+        getattr(lib, name).restype = C.c_int
     for name in ("swkb_plan", "swkb_propagate", "swkb_field", "swkb_diagnostics", "swkb_stage_modes",
                  "swkb_stage_rays", "swkb_profile", "swkb_profile_read", "swkb_server_create",
                  "swkb_server_submit", "swkb_server_step", "swkb_server_poll", "swkb_server_stats"):
@@ -328,6 +349,85 @@ class Plan:
                                     _stream_handle(stream)))
         del n
         return arrs
+
+
+class Multi:
+    """Several x-invariant problems (each a mixed-precision matrix Plan) carried
+    to their last screens together, one launch per stage per screen step for
+    all problems still running (swkb_multi_*).  The plans must outlive it."""
+
+    def __init__(self, plans):
+        lib = load()
+        self.plans = list(plans)
+        arr = (C.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = C.c_void_p()
+        _check(lib.swkb_multi_create(arr, len(self.plans), C.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def _tuning_dict(t):
+        n = t.n_classes
+        return {"n_z": list(t.class_n_z[:n]), "fft_elems": list(t.fft_elems[:n]),
+                "apply_groups": list(t.apply_groups[:n]), "graphs": bool(t.graphs),
+                "fft_us": list(t.fft_us[:n]), "apply_us": list(t.apply_us[:n])}
+
+    def tuning(self):
+        t = MultiTuning()
+        _check(_lib.swkb_multi_get_tuning(self._h, C.byref(t)))
+        return self._tuning_dict(t)
+
+    def set_tuning(self, fft_elems=None, apply_groups=None, graphs=None):
+        """Change launch shapes: per-class lists (ascending n_z) or None to keep."""
+        t = MultiTuning()
+        _check(_lib.swkb_multi_get_tuning(self._h, C.byref(t)))
+        for name, vals in (("fft_elems", fft_elems), ("apply_groups", apply_groups)):
+            if vals is not None:
+                if len(vals) != t.n_classes:
+                    raise ValueError(f"{name} needs {t.n_classes} values")
+                for i, v in enumerate(vals):
+                    getattr(t, name)[i] = int(v)
+        if graphs is not None:
+            t.graphs = 1 if graphs else 0
+        _check(_lib.swkb_multi_set_tuning(self._h, C.byref(t)))
+
+    def tune(self, reps=10, stream=None):
+        """Autotune the launch shapes on the device; returns the chosen tuning."""
+        t = MultiTuning()
+        _check(_lib.swkb_multi_tune(self._h, int(reps), _stream_handle(stream), C.byref(t)))
+        return self._tuning_dict(t)
+
+    def propagate(self, u0s, history=False, stream=None):
+        """u0s: one complex128[n_z] device tensor per plan (screen 0).
+        history: False, True (every problem) or a collection of plan indices.
+        Returns a list with each problem's history (complex128 [n_screens,
+        n_z]) or None; the final fields are then available from each plan's
+        field()."""
+        import torch
+        if len(u0s) != len(self.plans):
+            raise ValueError("one incident field per plan")
+        ptrs = [_dev_ptr(u, torch.complex128, p.n_z, f"u0s[{i}]").value
+                for i, (u, p) in enumerate(zip(u0s, self.plans))]
+        uin = (C.c_void_p * len(ptrs))(*ptrs)
+        hists = None
+        hp = None
+        if history is not False and history is not None:
+            want = set(range(len(self.plans))) if history is True else set(history)
+            hists = [torch.empty((p.cfg["n_screens"], p.n_z), dtype=torch.complex128, device=p.device)
+                     if i in want else None for i, p in enumerate(self.plans)]
+            hp = (C.c_void_p * len(hists))(*[h.data_ptr() if h is not None else None for h in hists])
+        _check(_lib.swkb_multi_propagate(self._h, uin, hp, _stream_handle(stream)))
+        return hists
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.swkb_multi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -42,7 +42,8 @@ def test_every_declared_symbol_is_exported(lib):
 @pytest.mark.parametrize("cname,pyname", [("swkb_params", "Params"), ("swkb_counters", "Counters"),
                                            ("swkb_timing", "Timing"), ("swkb_server_config", "ServerConfig"),
                                            ("swkb_request_info", "RequestInfo"),
-                                           ("swkb_server_stats_t", "ServerStats")])
+                                           ("swkb_server_stats_t", "ServerStats"),
+                                           ("swkb_multi_tuning", "MultiTuning")])
 def test_struct_layout_matches_header(tmp_path, cname, pyname):
     from paper_2301_03814_amd import swkb
     S = getattr(swkb, pyname)
@@ -142,3 +143,19 @@ def test_server_host_side_errors(lib):
     assert lib.swkb_server_stats(h, C.byref(st)) == swkb.SWKB_OK and st.pending == 0
     assert lib.swkb_server_poll(h, 12345, None, None) == swkb.SWKB_ERR_ARG
     lib.swkb_server_destroy(h)
+
+
+def test_multi_host_side_errors(lib):
+    """Group creation rejects empty or NULL plan lists on the host."""
+    from paper_2301_03814_amd import swkb
+    h = C.c_void_p()
+    assert lib.swkb_multi_create(None, 1, C.byref(h)) == swkb.SWKB_ERR_ARG
+    arr = (C.c_void_p * 2)(None, None)
+    assert lib.swkb_multi_create(arr, 0, C.byref(h)) == swkb.SWKB_ERR_ARG
+    assert lib.swkb_multi_create(arr, 2, C.byref(h)) == swkb.SWKB_ERR_ARG
+    assert b"NULL" in lib.swkb_last_error() and not h.value
+    assert lib.swkb_multi_create(arr, 5000, C.byref(h)) == swkb.SWKB_ERR_ARG
+    t = swkb.MultiTuning()
+    assert lib.swkb_multi_get_tuning(None, C.byref(t)) == swkb.SWKB_ERR_ARG
+    assert lib.swkb_multi_propagate(None, None, None, None) == swkb.SWKB_ERR_ARG
+    lib.swkb_multi_destroy(None)
