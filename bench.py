@@ -31,11 +31,11 @@ METRIC = "mode×point evals/s; range km/s at 1e-3 rel err vs FP64 plain; p50/p99
 #   per evaluation of eps, eps_z/2, eps_zz/2 from the index deviation 7
 #   per Gaussian term inside its cutoff (distance, exp, 3 sums)      22
 #   per medium value read from the per-screen table (node index and
-#     offset 4, quintic and its two derivatives by Horner 24, scaling 2)  30
+#     offset 4, cubic and its two derivatives by Horner 12, scaling 2)   18
 FLOPS_PER_RHS = 51
 FLOPS_PER_MEDIUM = 7
 FLOPS_PER_TERM = 22
-FLOPS_PER_TABLE = 30
+FLOPS_PER_TABLE = 18
 PEAK_FP32_VECTOR = 157.3e12   # MI355X published dense FP32 vector FLOP/s (counts packed FP32)
 PEAK_FP64_VECTOR = 78.6e12
 PEAK_HBM = 8.0e12            # MI355X published HBM3E bandwidth, bytes/s

@@ -157,7 +157,7 @@ bool gauss_fast(const swkb_params* p, const std::vector<int>& off) {
 // p^2 > p2_floor and eps <= 1 + max(0, sum of bump amplitudes)^2 terms).
 // Returns n = 0 where the direct evaluation is used.
 MedTab med_table(const swkb_params* p, const Geometry& g) {
-  MedTab t{nullptr, nullptr, 0, 0.0, 0.0};
+  MedTab t{nullptr, 0, 0.0, 0.0};
   if (p->medium_kind != SWKB_MEDIUM_GAUSSSUM || p->bc != SWKB_BC_PERIODIC || p->precision != SWKB_MIXED) return t;
   const int ng = (int)p->medium_params[0];
   if (ng < 1) return t;
@@ -172,7 +172,7 @@ MedTab med_table(const swkb_params* p, const Geometry& g) {
   t.dz = smin / 40.0;
   t.z_lo = g.z_a - margin;
   const double n = std::ceil(((g.z_b - g.z_a) + 2.0 * margin) / t.dz) + 2.0;
-  if (n > (double)(1 << 22)) return MedTab{nullptr, nullptr, 0, 0.0, 0.0};  // too fine: evaluate directly
+  if (n > (double)(1 << 22)) return MedTab{nullptr, 0, 0.0, 0.0};  // too fine: evaluate directly
   t.n = (int)n;
   return t;
 }
@@ -211,7 +211,7 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   // ray-record slots: two for media that change with x (march and sum overlap)
   L.slot0 = o;
   o = 0;
-  L.mtab = take((sizeof(float4) + sizeof(float2)) * (size_t)med_table(p, g).n * (2 * g.S + 1));
+  L.mtab = take(sizeof(float4) * (size_t)med_table(p, g).n * (2 * g.S + 1));
   L.D = take(ts * MR);
   L.Pp = take(ts * MR);
   L.G = take(ts * MR);
@@ -551,7 +551,6 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
       sl.mtab = med_table(p, g);
       if (sl.mtab.n > 0) {
         sl.mtab.tab = reinterpret_cast<const float4*>(sb + L.mtab);
-        sl.mtab.tb = reinterpret_cast<const float2*>(sl.mtab.tab + (size_t)(2 * g.S + 1) * (sl.mtab.n - 1));
       }
       sl.q = -1;
     }

@@ -56,8 +56,7 @@ constexpr int kWaveCounts = 6;
 
 // Per-screen medium table of the mixed Gaussian-sum march (tab == NULL: none).
 struct MedTab {
-  const float4* tab;  // quintic coefficients of eps - 1 per interval: c0..c3 [(2S+1)][n - 1]
-  const float2* tb;   // c4, c5 [(2S+1)][n - 1]
+  const float4* tab;  // cubic coefficients of eps - 1 per interval: c0..c3 [(2S+1)][n - 1]
   int n;              // z-nodes
   double z_lo, dz;    // node i at z_lo + i dz
 };
