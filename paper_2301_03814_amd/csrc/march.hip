@@ -44,7 +44,9 @@ struct Deriv {
 enum { kLive = 0, kDeadLaunch = 1, kDead = 2, kCaustic = 3 };
 
 // Work of one ray: RK4 stage evaluations, direct medium evaluations,
-// Gaussian terms inside their cutoff, medium values read from a table.
+// Gaussian terms inside their cutoff, medium values read from a table (a
+// medium with kTableReads sets the last from the ray's evaluation count at
+// the end of the march instead of counting each read).
 struct Work {
   int rhs = 0, med = 0, terms = 0, tab = 0;
 };
@@ -66,6 +68,7 @@ __device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(
 // Medium evaluated through the generic device function (any kind, mirror).
 template <typename T>
 struct GenericMedium {
+  static constexpr bool kTableReads = false;
   DevMedium md;
   double x_q, hx2;  // stage k sits at x_q + k * hx2
   double s;         // launch height of this lane's ray
@@ -93,6 +96,7 @@ __device__ inline float bump_exp<float>(float arg) { return __builtin_amdgcn_exp
 
 template <typename T>
 struct GaussMedium {
+  static constexpr bool kTableReads = false;
   const T2<T>* __restrict__ stage;
   const T2<T>* __restrict__ term;
   const T* __restrict__ czl;
@@ -145,6 +149,7 @@ struct GaussMedium {
 // only enters the ray-tube amplitude, within 1e-4 relative.  Heights
 // outside the table fall back to the direct evaluation.
 struct TableMedium {
+  static constexpr bool kTableReads = true;
   const float4* __restrict__ ta;  // [(2S+1)][ni]
   unsigned ni;                    // intervals
   float inv_dz, half_inv_dz;      // 1/dz_t, 1/(2 dz_t)
@@ -158,7 +163,6 @@ struct TableMedium {
     // unsigned wrap sends heights below the table (and saturated conversions) out of range too
     const unsigned iv = (unsigned)j0 + (unsigned)(int)tf;
     if (!(iv < ni)) return direct.eval(k, dz, c);
-    ++c.tab;
     const float u = t - tf;
     const size_t o = (size_t)k * ni + iv;
     const float4 a = ta[o];
@@ -177,35 +181,35 @@ struct TableMedium {
   }
 };
 
-// Right-hand side at stage k.  Returns false, with st set to kCaustic or
-// kDead, when the ray stops there.
+// Right-hand side at stage k, the n-th evaluation of its RK4 step.
+// Returns false when the ray stops there, with st = kCaustic (Z_s <= 0 at
+// the stage) or else kDead (p^2 <= p2_floor), plus 4 n; the medium is
+// evaluated in either case, so that both tests are taken on one branch
+// that a wavefront of live rays skips.
 template <typename T, typename MED>
-__device__ inline bool rhs(const MED& med, const ModeC& mc, int k, T dz, T dq, T Zs, T Qs, T p2_floor,
+__device__ inline bool rhs(const MED& med, const ModeC& mc, int k, int n, T dz, T dq, T Zs, T Qs, T p2_floor,
                           Deriv<T>& d, Work& c, int& st) {
-  if (!(Zs > T(0))) {
-    st = kCaustic;
-    return false;
-  }
   const Med<T> m = med.eval(k, dz, c);
   const T xi = (T)mc.xi;
   const T q = xi + dq;
-  const T p2 = (T)mc.omx2 + m.e1 - dq * (T(2) * xi + dq);
-  if (!(p2 > p2_floor)) {
-    st = kDead;
+  const T s2 = T(2) * xi + dq;  // q + xi
+  const T p2 = (T)mc.omx2 + m.e1 - dq * s2;
+  const bool ok = (Zs > T(0)) & (p2 > p2_floor);
+  if (__builtin_expect(!ok, 0)) {
+    st = (Zs > T(0) ? kDead : kCaustic) + 4 * n;
     return false;
   }
   const T ip = fast_rsqrt<T>(p2);
   const T p = p2 * ip;
   d.dz = q * ip;
   d.dq = m.hz * ip;
-  d.dps = ((m.e1 - (T)mc.e1r) - dq * (q + xi)) * fast_rcp<T>(p + (T)mc.pbar) + q * dq * ip;
-  // ray-tube variations
+  d.dps = ((m.e1 - (T)mc.e1r) - dq * s2) * fast_rcp<T>(p + (T)mc.pbar) + q * dq * ip;
+  // ray-tube variations:
+  //   Z_s' = (eps Q_s - q (eps_z/2) Z_s) / p^3,
+  //   Q_s' = (eps_zz/2) Z_s / p + (eps_z/2) (q Q_s - (eps_z/2) Z_s) / p^3
   const T ip3 = ip * ip * ip;
-  const T qe = q * m.hz * ip3;                                    // q eps_z / (2 p^3)
-  const T c12 = (T(1) + m.e1) * ip3;                              // eps / p^3
-  const T c21 = m.hzz * ip - m.hz * m.hz * ip3;                   // eps_zz/(2p) - eps_z^2/(4p^3)
-  d.Zs = c12 * Qs - qe * Zs;
-  d.Qs = c21 * Zs + qe * Qs;
+  d.Zs = ip3 * ((Qs + m.e1 * Qs) - (q * m.hz) * Zs);
+  d.Qs = (m.hzz * ip) * Zs + ip3 * (m.hz * (q * Qs - m.hz * Zs));
   return true;
 }
 
@@ -232,6 +236,7 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
   st = kLive;
   if (!active) return;
   const Med<T> m0 = med.eval(0, T(0), c);
+  int evals = 1;  // medium evaluations of this ray
   const T p02 = (T)mc.omx2 + m0.e1;
   if (!(p02 > (T)g.p2_floor)) {
     st = kDeadLaunch;
@@ -243,15 +248,15 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
     const T hd2 = (T)(0.5 * hx), hd6 = (T)(hx / 6.0);
     Deriv<T> k1, k2, k3, k4;
     for (int i = 0; i < g.S; ++i) {
-      if (!rhs<T>(med, mc, 2 * i, dz, dq, Zs, Qs, pfl, k1, c, st)) break;
-      if (!rhs<T>(med, mc, 2 * i + 1, dz + hh * k1.dz, dq + hh * k1.dq, Zs + hd2 * k1.Zs, Qs + hd2 * k1.Qs, pfl,
-                  k2, c, st))
+      if (!rhs<T>(med, mc, 2 * i, 1, dz, dq, Zs, Qs, pfl, k1, c, st)) break;
+      if (!rhs<T>(med, mc, 2 * i + 1, 2, dz + hh * k1.dz, dq + hh * k1.dq, Zs + hd2 * k1.Zs, Qs + hd2 * k1.Qs,
+                  pfl, k2, c, st))
         break;
-      if (!rhs<T>(med, mc, 2 * i + 1, dz + hh * k2.dz, dq + hh * k2.dq, Zs + hd2 * k2.Zs, Qs + hd2 * k2.Qs, pfl,
-                  k3, c, st))
+      if (!rhs<T>(med, mc, 2 * i + 1, 3, dz + hh * k2.dz, dq + hh * k2.dq, Zs + hd2 * k2.Zs, Qs + hd2 * k2.Qs,
+                  pfl, k3, c, st))
         break;
-      if (!rhs<T>(med, mc, 2 * i + 2, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hf * k3.Zs, Qs + hf * k3.Qs, pfl,
-                  k4, c, st))
+      if (!rhs<T>(med, mc, 2 * i + 2, 4, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hf * k3.Zs, Qs + hf * k3.Qs,
+                  pfl, k4, c, st))
         break;
       c.rhs += 4;
       dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
@@ -260,10 +265,14 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
       Zs += hd6 * (k1.Zs + T(2) * k2.Zs + T(2) * k3.Zs + k4.Zs);
       Qs += hd6 * (k1.Qs + T(2) * k2.Qs + T(2) * k3.Qs + k4.Qs);
     }
+    // completed steps, and the evaluations of the step where the ray stopped
+    evals += c.rhs + (st >> 2);
+    st &= 3;
     if (st == kLive) {
       if (!(Zs > T(0))) {
         st = kCaustic;
       } else {
+        ++evals;
         const Med<T> m1 = med.eval(2 * g.S, dz, c);
         const T xi = (T)mc.xi;
         const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
@@ -272,6 +281,7 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
       }
     }
   }
+  if constexpr (MED::kTableReads) c.tab = evals - c.med;
   static_cast<T*>(rec.D)[o] = dz;
   static_cast<T*>(rec.Pp)[o] = dps;
   static_cast<T*>(rec.G)[o] = dq;
