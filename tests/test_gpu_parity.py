@@ -16,6 +16,12 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-10
 MIXED_TOL = 1e-3
+# Regression bound for the mixed path on the small cases below, whose
+# measured errors against the oracle are 6e-7 .. 6e-6: FP32 rounding of the
+# ray state, interpolation and phase.  A mistake in an FP32-only code path
+# (an interpolation variable not advanced, a wrong coefficient) shows up here
+# long before it reaches the 1e-3 bar.
+MIXED_REGRESSION = 5e-5
 
 
 @pytest.fixture(scope="module")
@@ -104,6 +110,8 @@ def test_propagation_matches_oracle(torch_dev, swkb, oracle_runs, name, prec, pr
     err = rel(got, ref)
     say(f"[parity] {name} {prec} rel_l2={err:.3e} diag={diag} oracle={cnt}")
     assert err <= (FP64_TOL if prec == "fp64" else MIXED_TOL)
+    if prec == "mixed":
+        assert err <= MIXED_REGRESSION
     assert diag["screens"] == cfg["n_screens"]
     if prec == "fp64":
         # discrete decisions (dead / caustic rays, folded modes) agree with the oracle
