@@ -195,7 +195,7 @@ def bench_duct(args, torch, np, W, Plan, FP64, MIXED):
     return out
 
 
-def bench_multi(torch, np, W, Plan, Multi, MIXED, n_problems=64):
+def bench_multi(torch, np, W, Plan, Multi, MIXED, n_problems=64, graphs=True):
     """The seeded batch of uneven duct problems (1-10 GHz, duct depth 10-100
     m, 200-500 m high, 10-100 km, N_z 2048-16384, M = N_z/4, mixed): every
     problem one after another through its own plan (HIP graphs), then all of
@@ -223,7 +223,7 @@ def bench_multi(torch, np, W, Plan, Multi, MIXED, n_problems=64):
         return time.perf_counter() - t
 
     for p in plans:
-        p.graphs(True)
+        p.graphs(graphs)
     t_seq = timed(lambda: [p.propagate(u, 0, c["n_screens"], history=False) for p, u, c in zip(plans, u0s, cfgs)])
     seq_fields = [p.field() for p in plans]
     for p in plans:
@@ -234,7 +234,7 @@ def bench_multi(torch, np, W, Plan, Multi, MIXED, n_problems=64):
     t0 = time.perf_counter()
     tun = m.tune(reps=5)
     t_tune = time.perf_counter() - t0
-    m.set_tuning(graphs=True)
+    m.set_tuning(graphs=graphs)
     t_tuned = timed(lambda: m.propagate(u0s))
     dev_max = max(float(torch.linalg.vector_norm(p.field() - f) / torch.linalg.vector_norm(f))
                   for p, f in zip(plans, seq_fields))
@@ -276,6 +276,10 @@ def main():
     ap.add_argument("--no-multi", action="store_true", help="skip the uneven duct batch measurement")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the step with per-kernel events (kernels one after another), for rocprofv3")
+    ap.add_argument("--only", choices=("duct", "multi"), default=None,
+                    help="run only that section and print its JSON (for rocprofv3 summaries)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="uneven batch without HIP graphs (for rocprofv3 counter collection)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy kernel over BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -301,6 +305,14 @@ def main():
 
     import workloads as W
     from paper_2301_03814_amd import FP64, MIXED, Plan
+
+    if args.only == "duct":
+        print(json.dumps(bench_duct(args, torch, np, W, Plan, FP64, MIXED)))
+        return
+    if args.only == "multi":
+        from paper_2301_03814_amd import Multi
+        print(json.dumps(bench_multi(torch, np, W, Plan, Multi, MIXED, graphs=not args.no_graphs)))
+        return
 
     cfg = W.random_medium()
     N, M, Q = cfg["n_z"], cfg["n_modes"], cfg["n_screens"]
