@@ -673,10 +673,13 @@ static int groups_for(const Geometry& g, int sub) {
 int superpose_groups(const Geometry& g) { return groups_for(g, superpose_sub(g)); }
 
 // Interval-owner sum: a pass handles 61 intervals, so a super-tile spans
-// about 48 ray spacings (rho points each) and fits one pass unless rays
-// crowd; at most 512 points (FP32) or 256 (FP64) for the LDS accumulators.
+// about 56 ray spacings (rho points each): most lanes own an interval and
+// the tile still fits one pass unless rays crowd (random medium, N = 8192:
+// 39.2 us per screen against 42.2 us at 48 spacings, 45.7 at 40 and 49.6 at
+// 64, where a second pass is common); at most 512 points (FP32) or 256
+// (FP64) for the LDS accumulators.
 static int iv_sub(const Geometry& g, int precision) {
-  int s = (48 * g.rho) / 64;
+  int s = (56 * g.rho) / 64;
   const int smax = precision == SWKB_FP64 ? 4 : 8;
   if (s > smax) s = smax;
   if (s < 1) s = 1;
