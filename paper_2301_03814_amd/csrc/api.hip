@@ -288,10 +288,12 @@ static void destroy_streams(swkb_plan_s* pl) {
   for (int k = 0; k < 2; ++k) {
     if (pl->ev_ready[k]) (void)hipEventDestroy(pl->ev_ready[k]);
     if (pl->ev_free[k]) (void)hipEventDestroy(pl->ev_free[k]);
+    if (pl->ev_marched[k]) (void)hipEventDestroy(pl->ev_marched[k]);
   }
   if (pl->ms) (void)hipStreamDestroy(pl->ms);
-  pl->ms = nullptr;
-  for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = nullptr;
+  if (pl->ss) (void)hipStreamDestroy(pl->ss);
+  pl->ms = pl->ss = nullptr;
+  for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = pl->ev_marched[k] = nullptr;
 }
 
 static int slot_of(const swkb_plan_s* pl, int q) { return pl->nslots == 2 ? (q & 1) : 0; }
@@ -326,13 +328,14 @@ static bool overlap(const swkb_plan_s* pl) {
 }
 
 // Screens [q_begin, q_end) of an x-varying medium with march and scan on
-// their own stream.  Slot k = q & 1 holds screen q's rays.  The caller's
-// stream st builds the medium table of screen q (into slot k, once the sum
-// of screen q - 2 has released it); after the march and scan of screen q on
-// the march stream it runs the FFT and the sum of screen q.  field(q)
-// launches the screen's FFT and sum.
-template <typename F>
-static swkb_status pipelined(swkb_plan_s* pl, int q_begin, int q_end, hipStream_t st, F&& field) {
+// streams of their own.  Slot k = q & 1 holds screen q's rays.  The
+// caller's stream st builds the medium table of screen q (into slot k, once
+// the sum of screen q - 2 has released it); the march stream marches screen
+// q, the scan stream scans it, and st runs the FFT of screen q (which needs
+// only the field) and, after the scan, its sum.  fft(q) and sum(q) launch
+// those two parts.
+template <typename F, typename G>
+static swkb_status pipelined(swkb_plan_s* pl, int q_begin, int q_end, hipStream_t st, F&& fft, G&& sum) {
   hipError_t e = hipSuccess;
   // table of screen q into its slot on st, then the slot is open for the march
   auto prepare = [&](int q) {
@@ -347,15 +350,19 @@ static swkb_status pipelined(swkb_plan_s* pl, int q_begin, int q_end, hipStream_
   for (int q = q_begin; q < q_end && e == hipSuccess; ++q) {
     const int k = q & 1;
     select_slot(pl, k);
-    if (pl->slots[k].q != q) {
+    const bool march = pl->slots[k].q != q;
+    if (march) {
       e = hipStreamWaitEvent(pl->ms, pl->ev_free[k], 0);
       if (e == hipSuccess) e = launch_march(*pl, q, pl->ms);
-      if (e == hipSuccess) e = launch_scan(*pl, pl->ms);
-      if (e == hipSuccess) e = hipEventRecord(pl->ev_ready[k], pl->ms);
-      if (e == hipSuccess) e = hipStreamWaitEvent(st, pl->ev_ready[k], 0);
+      if (e == hipSuccess) e = hipEventRecord(pl->ev_marched[k], pl->ms);
+      if (e == hipSuccess) e = hipStreamWaitEvent(pl->ss, pl->ev_marched[k], 0);
+      if (e == hipSuccess) e = launch_scan(*pl, pl->ss);
+      if (e == hipSuccess) e = hipEventRecord(pl->ev_ready[k], pl->ss);
       set_slot_q(pl, k, e == hipSuccess ? q : -1);
     }
-    if (e == hipSuccess) e = field(q);
+    if (e == hipSuccess) e = fft(q);
+    if (e == hipSuccess && march) e = hipStreamWaitEvent(st, pl->ev_ready[k], 0);
+    if (e == hipSuccess) e = sum(q);
     if (e == hipSuccess && q + 2 < q_end) e = prepare(q + 2);
   }
   if (e != hipSuccess) return hip_fail(e, "screen launch");
@@ -368,9 +375,9 @@ static swkb_status enqueue_screens(swkb_plan_s* pl, const void* u_in, int q_begi
                                    hipStream_t st) {
   const Geometry& g = pl->g;
   const double2* src = u_in ? static_cast<const double2*>(u_in) : pl->u;
-  auto field = [&](int q) {
-    hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, 1, st); });
-    if (e != hipSuccess) return e;
+  auto fft = [&](int) { return timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, 1, st); }); };
+  auto sum = [&](int q) {
+    hipError_t e;
     double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * g.N : nullptr;
     if (pl->use_matrix)
       e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->u, hist, 1, st); });
@@ -380,13 +387,14 @@ static swkb_status enqueue_screens(swkb_plan_s* pl, const void* u_in, int q_begi
     pl->cur_q = q + 1;
     return e;
   };
-  if (overlap(pl)) return pipelined(pl, q_begin, q_end, st, field);
+  if (overlap(pl)) return pipelined(pl, q_begin, q_end, st, fft, sum);
   for (int q = q_begin; q < q_end; ++q) {
     if (!pl->use_matrix) {
       swkb_status s = ensure_rays(pl, q, st);
       if (s != SWKB_OK) return s;
     }
-    const hipError_t e = field(q);
+    hipError_t e = fft(q);
+    if (e == hipSuccess) e = sum(q);
     if (e != hipSuccess) return hip_fail(e, "screen launch");
   }
   return SWKB_OK;
@@ -559,12 +567,15 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->cs = nullptr;
     pl->ev_g0 = pl->ev_g1 = nullptr;
     pl->graphs_on = 0;
-    for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = nullptr;
+    pl->ss = nullptr;
+    for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = pl->ev_marched[k] = nullptr;
     if (pl->nslots == 2) {
-      bool ok = hipStreamCreateWithFlags(&pl->ms, hipStreamNonBlocking) == hipSuccess;
+      bool ok = hipStreamCreateWithFlags(&pl->ms, hipStreamNonBlocking) == hipSuccess &&
+                hipStreamCreateWithFlags(&pl->ss, hipStreamNonBlocking) == hipSuccess;
       for (int k = 0; k < 2 && ok; ++k)
         ok = hipEventCreateWithFlags(&pl->ev_ready[k], hipEventDisableTiming) == hipSuccess &&
-             hipEventCreateWithFlags(&pl->ev_free[k], hipEventDisableTiming) == hipSuccess;
+             hipEventCreateWithFlags(&pl->ev_free[k], hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&pl->ev_marched[k], hipEventDisableTiming) == hipSuccess;
       if (!ok) {
         destroy_streams(pl);
         delete pl;
@@ -737,9 +748,9 @@ swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch
     pl->blas = h;
   }
   const double2* src = static_cast<const double2*>(u_in);
-  auto field = [&](int q) {
-    hipError_t e = timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, batch, st); });
-    if (e != hipSuccess) return e;
+  auto fft = [&](int) { return timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, batch, st); }); };
+  auto sum = [&](int q) {
+    hipError_t e;
     double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * batch * g.N : nullptr;
     if (pl->use_matrix)
       e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->ub, hist, batch, st); });
@@ -749,7 +760,7 @@ swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch
     return e;
   };
   if (overlap(pl)) {
-    swkb_status s = pipelined(pl, q_begin, q_end, st, field);
+    swkb_status s = pipelined(pl, q_begin, q_end, st, fft, sum);
     if (s != SWKB_OK) return s;
   } else {
     for (int q = q_begin; q < q_end; ++q) {
@@ -757,7 +768,8 @@ swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch
         swkb_status s = ensure_rays(pl, q, st);
         if (s != SWKB_OK) return s;
       }
-      const hipError_t e = field(q);
+      hipError_t e = fft(q);
+      if (e == hipSuccess) e = sum(q);
       if (e != hipSuccess) return hip_fail(e, "batched screen launch");
     }
   }

@@ -483,10 +483,11 @@ constexpr int kScanRun = 6;  // most consecutive rays per thread
 template <typename T>
 __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecords rec,
                                                             const int* __restrict__ wcount, int waves_per_mode) {
-  constexpr int kChunk = kScanThreads * kScanRun;
-  // the chunk's rays staged in LDS so that global loads and stores stay coalesced
-  __shared__ T sA[kChunk], sD[kChunk];
-  __shared__ int sC[kChunk], sI[kChunk];
+  // the chunk's rays staged in LDS so that global loads and stores stay
+  // coalesced: sA, sD (T) and sC, sI (int) of kScanThreads * run entries each,
+  // sized by the launch (scan_lds_bytes) so that as many workgroups as
+  // possible are resident at once
+  extern __shared__ double scan_lds[];
   __shared__ double wtot[kScanThreads / 64];
   __shared__ int wci[kScanThreads / 64];
   __shared__ int sfold;
@@ -499,7 +500,18 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecor
   const int* __restrict__ CZ = rec.cz + base;
   int run = (g.R + kScanThreads - 1) / kScanThreads;
   if (run > kScanRun) run = kScanRun;
+  const int chunk = kScanThreads * run;
+  T* sA = reinterpret_cast<T*>(scan_lds);
+  T* sD = sA + chunk;
+  int* sC = reinterpret_cast<int*>(sD + chunk);
+  int* sI = sC + chunk;
   if (tid == 0) sfold = 0;
+  // the mode's per-wavefront counts, loaded now so that their latency
+  // overlaps the scan's
+  int v[kWaveCounts] = {0, 0, 0, 0, 0, 0};
+  if (tid < 64)
+    for (int w = tid; w < waves_per_mode; w += 64)
+      for (int k = 0; k < kWaveCounts; ++k) v[k] += wcount[kWaveCounts * ((size_t)j * waves_per_mode + w) + k];
   double carry = -INFINITY;  // key of the last ray before this chunk
   int carry_ci = 0;          // its first point
   bool fold = false;
@@ -584,9 +596,6 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecor
   if (fold) sfold = 1;
   // counts
   if (tid < 64) {
-    int v[kWaveCounts] = {0, 0, 0, 0, 0, 0};
-    for (int w = tid; w < waves_per_mode; w += 64)
-      for (int k = 0; k < kWaveCounts; ++k) v[k] += wcount[kWaveCounts * ((size_t)j * waves_per_mode + w) + k];
     for (int off = 32; off > 0; off >>= 1)
       for (int k = 0; k < kWaveCounts; ++k) v[k] += __shfl_down(v[k], off, 64);
     if (tid == 0) {
@@ -703,14 +712,23 @@ hipError_t launch_medium_table(const swkb_plan_s& pl, int q, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Dynamic LDS of the scan: four arrays of kScanThreads * run entries.
+static size_t scan_lds_bytes(const Geometry& g, size_t tsize) {
+  int run = (g.R + kScanThreads - 1) / kScanThreads;
+  if (run > kScanRun) run = kScanRun;
+  return (size_t)kScanThreads * run * (2 * tsize + 2 * sizeof(int));
+}
+
 hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st) {
   const Geometry& g = pl.g;
   const int wpm = waves_per_mode(g);
   const int* wcount = pl.wcount;
   if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL(scan_kernel<double>, dim3(g.M), dim3(kScanThreads), 0, st, g, pl.rec, wcount, wpm);
+    hipLaunchKernelGGL(scan_kernel<double>, dim3(g.M), dim3(kScanThreads), scan_lds_bytes(g, sizeof(double)), st, g,
+                       pl.rec, wcount, wpm);
   else
-    hipLaunchKernelGGL(scan_kernel<float>, dim3(g.M), dim3(kScanThreads), 0, st, g, pl.rec, wcount, wpm);
+    hipLaunchKernelGGL(scan_kernel<float>, dim3(g.M), dim3(kScanThreads), scan_lds_bytes(g, sizeof(float)), st, g,
+                       pl.rec, wcount, wpm);
   return hipGetLastError();
 }
 

@@ -132,9 +132,11 @@ struct swkb_plan_s {
   double* frac_st;               // per-station range phases [rk4_steps][M]
   // Ray records of two screens (x-varying media): the march of screen q + 1
   // fills one slot on stream `ms` while screen q is summed from the other on
-  // the caller's stream.  rec, wcount and mtab above are the active slot.
-  // ev_free[k]: slot k's table is built and its last sum done (march may
-  // start); ev_ready[k]: its march is done.
+  // the caller's stream; the scan of each march runs on stream `ss`, so the
+  // march stream goes on to the next screen.  rec, wcount and mtab above are
+  // the active slot.  ev_free[k]: slot k's table is built and its last sum
+  // done (march may start); ev_marched[k]: its march is done (scan may
+  // start); ev_ready[k]: its scan is done (sum may start).
   struct Slot {
     swkb::DevRecords rec;
     int* wcount;
@@ -144,7 +146,8 @@ struct swkb_plan_s {
   Slot slots[2];
   int nslots;
   hipStream_t ms;                // march stream (default priority), or NULL
-  hipEvent_t ev_ready[2], ev_free[2];
+  hipStream_t ss;                // scan stream (default priority), or NULL
+  hipEvent_t ev_ready[2], ev_free[2], ev_marched[2];
   // screen ranges captured into HIP graphs (swkb_graphs)
   struct GraphEntry {
     const void* u_in;
