@@ -74,6 +74,7 @@ def _load():
         lib.or_screen.argtypes = [pp, C.c_int, dp, dp, C.POINTER(Counters)]
         lib.or_run.argtypes = [pp, dp, C.c_int, C.c_int, dp, C.POINTER(Counters)]
         lib.or_medium.argtypes = [pp, C.c_int, dp, dp, dp, dp, dp]
+        lib.or_taper.argtypes = [pp, dp]
         lib.or_set_threads.argtypes = [C.c_int]
         lib.or_max_threads.restype = C.c_int
         _lib = lib
@@ -154,6 +155,13 @@ def screen(cfg, q, u_in):
     _check(_load().or_screen(C.byref(_params(cfg)), int(q), _dp(u_in.view(np.float64)),
                              _dp(out.view(np.float64)), C.byref(cnt)))
     return out, cnt.as_dict()
+
+
+def taper(cfg, u):
+    """The exit taper W(z_m) of cfg applied to a copy of u (complex128[N])."""
+    out = np.array(u, dtype=np.complex128, copy=True)
+    _check(_load().or_taper(C.byref(_params(cfg)), _dp(out.view(np.float64))))
+    return out
 
 
 def run(cfg, u0, q_begin=0, q_end=None):

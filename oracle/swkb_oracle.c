@@ -495,6 +495,19 @@ int or_run(const or_params* P, const double* u0, int q_begin, int q_end, double*
   return 0;
 }
 
+/* The exit taper alone: u (N complex values on the grid z_a + m h) times
+ * W(z_m), as applied at the end of a screen step. */
+int or_taper(const or_params* P, double* u) {
+  if (check(P)) return OR_ERR_ARG;
+  double h = grid_h(P);
+  for (int m = 0; m < P->n_z; ++m) {
+    double w = taper(P, P->z_a + m * h);
+    u[2 * m] *= w;
+    u[2 * m + 1] *= w;
+  }
+  return 0;
+}
+
 /* Medium evaluation as the rays see it (for unit tests). */
 int or_medium(const or_params* P, int n, const double* x, const double* z, double* e, double* ez, double* ezz) {
   if (check(P)) return OR_ERR_ARG;
