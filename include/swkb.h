@@ -324,6 +324,56 @@ swkb_status swkb_multi_propagate(swkb_multi_t m, const void* const* u_in, void* 
 /* Waits for the group's work, frees its device memory and graph. */
 void swkb_multi_destroy(swkb_multi_t m);
 
+/* ---- overlapping patches ---------------------------------------------- */
+
+/* The screen step on overlapping patches (Sec. 2.4): the vertical interval
+ * is covered by n_patches patches with cores [c_p, c_{p+1}],
+ * c_p = z_a + p K h (K = n_z / n_patches cells), blended by the smooth
+ * partition of unity sigma_p(z) = erfc(-(z - c_p) / width) / 2,
+ * S^0 = 1 - sigma_1, S^p = sigma_p - sigma_{p+1}, S^{P-1} = sigma_{P-1}.
+ * A screen step windows the field (S^p u), runs the screen step of
+ * swkb_propagate on each piece over a sub-domain of n_p points (a power of
+ * two holding the core and e = ceil((6 width + margin) / h) cells on each
+ * side, centred on the core; the bottom patch keeps the ground mirror and
+ * starts at z_a), adds the pieces' outputs on the global grid in patch order
+ * and applies the global exit taper.  Sub-domains keep the global largest
+ * vertical slowness (n_modes_p = 2 floor(n_modes P_p / (2 P) + 1/2) with P_p, P
+ * the FFT lengths) and have no absorbers.  The windowed pieces vanish near
+ * their sub-domain ends, so the periodic step applies to them without the
+ * paper's Fourier continuation; width sets how fast the windows' spectra
+ * decay (exp(-(pi width xi / lambda)^2)) and margin must cover the drift of
+ * the fields over one screen.  Cost per screen: the sum over patches of
+ * n_modes_p n_p instead of n_modes n_z. */
+typedef struct swkb_patch_config {
+  int32_t n_patches;  /* >= 1, divides n_z                        */
+  double width;       /* window scale (z units), > 0              */
+  double margin;      /* extra sub-domain cells' extent, >= 0 (z) */
+} swkb_patch_config;
+
+typedef struct swkb_patch_s* swkb_patch_t;
+
+/* Host; builds one plan per patch (swkb_plan) in device memory the patch
+ * plan allocates itself (hipMalloc) and frees in swkb_patch_destroy; p must
+ * have max_batch = 1.  Synchronises hip_stream.  SWKB_ERR_ARG for invalid
+ * parameters, including a sub-domain the library cannot plan. */
+swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, void* hip_stream, swkb_patch_t* out);
+
+/* First global grid index, points and modes of patch `patch`'s sub-domain
+ * (any pointer may be NULL). */
+swkb_status swkb_patch_info(swkb_patch_t pp, int32_t patch, int32_t* start, int32_t* n_z, int32_t* n_modes);
+
+/* Screens q_begin .. q_end-1 by the patch step; arguments and history as in
+ * swkb_propagate (device complex128 arrays of the global n_z).  Asynchronous
+ * on hip_stream. */
+swkb_status swkb_patch_propagate(swkb_patch_t pp, const void* u_in, int32_t q_begin, int32_t q_end, void* history,
+                                 void* hip_stream);
+
+/* The current global field into out (device complex128[n_z]). */
+swkb_status swkb_patch_field(swkb_patch_t pp, void* out, void* hip_stream);
+
+/* Waits for the device, frees the sub-plans and the patch plan's memory. */
+void swkb_patch_destroy(swkb_patch_t pp);
+
 /* ---- serving loop ----------------------------------------------------- */
 
 /* Continuous batching of independent propagation requests on the current

@@ -71,7 +71,7 @@ def layout(cfg, n_patches, width, margin):
             sub["bc"] = BC_PERIODIC
         P_p = n if sub["bc"] == BC_PERIODIC else 2 * n
         sub["n_z"] = n
-        sub["n_modes"] = max(2, 2 * int(round(M * P_p / (2.0 * P_g))))
+        sub["n_modes"] = max(2, 2 * int(math.floor(M * P_p / (2.0 * P_g) + 0.5)))
         sub["z_a"] = cfg["z_a"] + start * h
         sub["z_b"] = cfg["z_a"] + (start + n) * h
         sub["absorber_bot"] = 0.0

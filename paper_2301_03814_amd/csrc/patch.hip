@@ -1,0 +1,304 @@
+// Overlapping-patch screened WKB (Sec. 2.4): the vertical interval is
+// covered by P patches with cores [c_p, c_{p+1}], c_p = z_a + p K h
+// (K = N / P cells), blended by the smooth partition of unity
+//   sigma_p(z) = erfc(-(z - c_p) / w) / 2,
+//   S^0 = 1 - sigma_1,  S^p = sigma_p - sigma_{p+1},  S^{P-1} = sigma_{P-1},
+// which sums to one and falls below 1e-17 more than 6 w outside each core.
+// A screen step windows the field, u_p = S^p u, runs the ordinary screen
+// step (Sec. 2.1, with the ground mirror of Sec. 2.3 on the bottom patch)
+// on each piece over a sub-domain that holds the core plus e = ceil((6 w +
+// margin) / h) cells on each side (rounded up to a power of two, centred on
+// the core), adds the pieces' outputs on the global grid in patch order and
+// applies the global exit taper.  Each sub-domain keeps the global largest
+// vertical slowness (M_p = 2 floor(M P_p / (2 P_g) + 1/2), P_p and P_g the FFT
+// lengths) and has no absorbers of its own.  The per-screen cost is the sum
+// of the sub-domains' M_p n_p instead of M N.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "swkb_internal.h"
+
+namespace {
+
+struct PatchView {
+  int start, n;        // global index of the sub-domain's first point, its points
+  const double2* f;    // the sub-plan's field after its screen step
+};
+
+swkb_status fail(swkb_status s, const std::string& msg) {
+  swkb::set_error(msg);
+  return s;
+}
+
+swkb_status hip_fail(hipError_t e, const char* what) {
+  swkb::set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return SWKB_ERR_DEVICE;
+}
+
+// v[i] = S[i] u[start + i] inside the global grid, 0 outside.
+__global__ void patch_window_kernel(const double2* __restrict__ u, int N, int start, int n,
+                                    const double* __restrict__ S, double2* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = start + i;
+  double2 r = make_double2(0.0, 0.0);
+  if (m >= 0 && m < N) {
+    const double2 x = u[m];
+    r = make_double2(S[i] * x.x, S[i] * x.y);
+  }
+  v[i] = r;
+}
+
+// u'[m] = W[m] sum_p f_p[m - start_p] (patches in order), and the history row.
+__global__ void patch_add_kernel(const PatchView* __restrict__ views, int P, int N, const double* __restrict__ W,
+                                 double2* __restrict__ out, double2* __restrict__ hist) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  double re = 0.0, im = 0.0;
+  for (int p = 0; p < P; ++p) {
+    const int i = m - views[p].start;
+    if (i >= 0 && i < views[p].n) {
+      const double2 x = views[p].f[i];
+      re += x.x;
+      im += x.y;
+    }
+  }
+  const double2 r = make_double2(W[m] * re, W[m] * im);
+  out[m] = r;
+  if (hist) hist[m] = r;
+}
+
+int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p *= 2;
+  return p;
+}
+
+}  // namespace
+
+struct swkb_patch_s {
+  swkb_params p;
+  std::vector<double> mparams;
+  int P = 0, N = 0;
+  double width = 0.0, margin = 0.0, h = 0.0;
+  struct Sub {
+    int start = 0, n = 0;
+    swkb_params sp{};
+    void* ws = nullptr;
+    swkb_plan_t plan = nullptr;
+    double2* v = nullptr;  // windowed field [n]
+    double* S = nullptr;   // window at the sub-domain's points [n] (0 outside the grid)
+  };
+  std::vector<Sub> subs;
+  double2* u = nullptr;    // current field [N]
+  double* W = nullptr;     // global exit taper [N]
+  PatchView* views = nullptr;
+  int cur_q = -1;
+};
+
+namespace {
+
+void destroy_patch(swkb_patch_s* pp) {
+  for (auto& s : pp->subs) {
+    if (s.plan) swkb_destroy(s.plan);
+    if (s.ws) (void)hipFree(s.ws);
+    if (s.v) (void)hipFree(s.v);
+    if (s.S) (void)hipFree(s.S);
+  }
+  if (pp->u) (void)hipFree(pp->u);
+  if (pp->W) (void)hipFree(pp->W);
+  if (pp->views) (void)hipFree(pp->views);
+  delete pp;
+}
+
+// Partition of unity S^p at height z.
+double window(const swkb_patch_s* pp, int p, double z) {
+  if (pp->P == 1) return 1.0;
+  const int K = pp->N / pp->P;
+  auto sigma = [&](int q) { return 0.5 * std::erfc(-(z - (pp->p.z_a + (double)(q * K) * pp->h)) / pp->width); };
+  if (p == 0) return 1.0 - sigma(1);
+  if (p == pp->P - 1) return sigma(pp->P - 1);
+  return sigma(p) - sigma(p + 1);
+}
+
+// Exit taper of the global problem (cos^2 over each absorber layer).
+double exit_taper(const swkb_params& p, double z) {
+  double w = 1.0;
+  if (p.absorber_bot > 0.0 && z < p.z_a + p.absorber_bot) {
+    const double c = std::cos(0.5 * M_PI * ((p.z_a + p.absorber_bot - z) / p.absorber_bot));
+    w *= c * c;
+  }
+  if (p.absorber_top > 0.0 && z > p.z_b - p.absorber_top) {
+    const double c = std::cos(0.5 * M_PI * ((z - (p.z_b - p.absorber_top)) / p.absorber_top));
+    w *= c * c;
+  }
+  return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, void* hip_stream,
+                            swkb_patch_t* out) {
+  if (!out) return fail(SWKB_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!p || !pc) return fail(SWKB_ERR_ARG, "NULL argument");
+  if (swkb_workspace_bytes(p) == 0) return fail(SWKB_ERR_ARG, "invalid swkb_params (swkb_workspace_bytes is 0)");
+  if (pc->n_patches < 1 || p->n_z % pc->n_patches != 0)
+    return fail(SWKB_ERR_ARG, "n_patches must be >= 1 and divide n_z");
+  if (!(pc->width > 0.0) || !(pc->margin >= 0.0) || !std::isfinite(pc->width) || !std::isfinite(pc->margin))
+    return fail(SWKB_ERR_ARG, "width must be > 0 and margin >= 0");
+  if (p->max_batch != 1) return fail(SWKB_ERR_ARG, "patch plans carry one field (max_batch = 1)");
+  hipStream_t st = (hipStream_t)hip_stream;
+  swkb_patch_s* pp = new (std::nothrow) swkb_patch_s();
+  if (!pp) return fail(SWKB_ERR_NOMEM, "host allocation failed");
+  try {
+    pp->p = *p;
+    pp->mparams.assign(p->medium_params, p->medium_params + p->n_medium_params);
+    pp->p.medium_params = pp->mparams.data();
+    pp->P = pc->n_patches;
+    pp->N = p->n_z;
+    pp->width = pc->width;
+    pp->margin = pc->margin;
+    pp->h = (p->z_b - p->z_a) / p->n_z;
+    const int K = pp->N / pp->P;
+    const int e = (int)std::ceil((6.0 * pc->width + pc->margin) / pp->h);
+    const int P_g = p->bc == SWKB_BC_PERIODIC ? pp->N : 2 * pp->N;
+    pp->subs.resize(pp->P);
+    for (int q = 0; q < pp->P; ++q) {
+      auto& s = pp->subs[q];
+      s.sp = pp->p;
+      if (q == 0 && p->bc != SWKB_BC_PERIODIC) {
+        s.n = pow2_at_least(K + e);
+        s.start = 0;
+      } else {
+        const int need = K + 2 * e;
+        s.n = pow2_at_least(need);
+        s.start = q * K - e - (s.n - need) / 2;
+        s.sp.bc = SWKB_BC_PERIODIC;
+      }
+      const int P_p = s.sp.bc == SWKB_BC_PERIODIC ? s.n : 2 * s.n;
+      s.sp.n_z = s.n;
+      s.sp.n_modes = std::max(2, 2 * (int)std::floor((double)p->n_modes * P_p / (2.0 * P_g) + 0.5));
+      s.sp.z_a = p->z_a + (double)s.start * pp->h;
+      s.sp.z_b = p->z_a + (double)(s.start + s.n) * pp->h;
+      s.sp.absorber_bot = 0.0;
+      s.sp.absorber_top = 0.0;
+    }
+  } catch (const std::exception&) {
+    delete pp;
+    return fail(SWKB_ERR_NOMEM, "host allocation failed");
+  }
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&pp->u), sizeof(double2) * pp->N);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pp->W), sizeof(double) * pp->N);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pp->views), sizeof(PatchView) * pp->P);
+  if (e != hipSuccess) {
+    destroy_patch(pp);
+    return hip_fail(e, "swkb_patch_plan");
+  }
+  std::vector<PatchView> views(pp->P);
+  for (int q = 0; q < pp->P; ++q) {
+    auto& s = pp->subs[q];
+    const size_t wb = swkb_workspace_bytes(&s.sp);
+    if (wb == 0) {
+      destroy_patch(pp);
+      return fail(SWKB_ERR_ARG, "sub-domain " + std::to_string(q) + " has invalid parameters (n_z " +
+                                    std::to_string(pp->subs[q].n) + ", n_modes " +
+                                    std::to_string(pp->subs[q].sp.n_modes) + ")");
+    }
+    e = hipMalloc(&s.ws, wb);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s.v), sizeof(double2) * s.n);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s.S), sizeof(double) * s.n);
+    if (e != hipSuccess) {
+      destroy_patch(pp);
+      return hip_fail(e, "swkb_patch_plan: sub-domain allocation");
+    }
+    const swkb_status ps = swkb_plan(&s.sp, s.ws, wb, st, &s.plan);
+    if (ps != SWKB_OK) {
+      const std::string why = std::string("sub-domain ") + std::to_string(q) + ": " + swkb_last_error();
+      destroy_patch(pp);
+      return fail(ps, why);
+    }
+    std::vector<double> S(s.n, 0.0);
+    for (int i = 0; i < s.n; ++i) {
+      const int m = s.start + i;
+      if (m >= 0 && m < pp->N) S[i] = window(pp, q, p->z_a + (double)m * pp->h);
+    }
+    e = hipMemcpy(s.S, S.data(), sizeof(double) * s.n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      destroy_patch(pp);
+      return hip_fail(e, "swkb_patch_plan: window upload");
+    }
+    views[q] = PatchView{s.start, s.n, s.plan->u};
+  }
+  std::vector<double> W(pp->N);
+  for (int m = 0; m < pp->N; ++m) W[m] = exit_taper(pp->p, p->z_a + (double)m * pp->h);
+  e = hipMemcpy(pp->W, W.data(), sizeof(double) * pp->N, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(pp->views, views.data(), sizeof(PatchView) * pp->P, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    destroy_patch(pp);
+    return hip_fail(e, "swkb_patch_plan: upload");
+  }
+  *out = pp;
+  return SWKB_OK;
+}
+
+swkb_status swkb_patch_info(swkb_patch_t pp, int32_t patch, int32_t* start, int32_t* n_z, int32_t* n_modes) {
+  if (!pp || patch < 0 || patch >= pp->P) return fail(SWKB_ERR_ARG, "no such patch");
+  const auto& s = pp->subs[patch];
+  if (start) *start = s.start;
+  if (n_z) *n_z = s.n;
+  if (n_modes) *n_modes = s.sp.n_modes;
+  return SWKB_OK;
+}
+
+swkb_status swkb_patch_propagate(swkb_patch_t pp, const void* u_in, int32_t q_begin, int32_t q_end, void* history,
+                                 void* hip_stream) {
+  if (!pp) return fail(SWKB_ERR_ARG, "patch plan is NULL");
+  if (q_begin < 0 || q_end < q_begin || q_end > pp->p.n_screens)
+    return fail(SWKB_ERR_ARG, "need 0 <= q_begin <= q_end <= n_screens");
+  if (!u_in && pp->cur_q != q_begin)
+    return fail(SWKB_ERR_STATE, "u_in is NULL but the plan's field is not on screen q_begin");
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = hipSuccess;
+  if (u_in) e = hipMemcpyAsync(pp->u, u_in, sizeof(double2) * pp->N, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: field copy");
+  pp->cur_q = q_begin;
+  for (int q = q_begin; q < q_end; ++q) {
+    for (auto& s : pp->subs) {
+      hipLaunchKernelGGL(patch_window_kernel, dim3((s.n + 255) / 256), dim3(256), 0, st, pp->u, pp->N, s.start, s.n,
+                         s.S, s.v);
+      e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: window");
+      const swkb_status ps = swkb_propagate(s.plan, s.v, q, q + 1, nullptr, st);
+      if (ps != SWKB_OK) return ps;
+    }
+    double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * pp->N : nullptr;
+    hipLaunchKernelGGL(patch_add_kernel, dim3((pp->N + 255) / 256), dim3(256), 0, st, pp->views, pp->P, pp->N, pp->W,
+                       pp->u, hist);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: overlap-add");
+    pp->cur_q = q + 1;
+  }
+  return SWKB_OK;
+}
+
+swkb_status swkb_patch_field(swkb_patch_t pp, void* out, void* hip_stream) {
+  if (!pp || !out) return fail(SWKB_ERR_ARG, "NULL argument");
+  if (pp->cur_q < 0) return fail(SWKB_ERR_STATE, "no field yet");
+  const hipError_t e =
+      hipMemcpyAsync(out, pp->u, sizeof(double2) * pp->N, hipMemcpyDeviceToDevice, (hipStream_t)hip_stream);
+  return e == hipSuccess ? SWKB_OK : hip_fail(e, "swkb_patch_field");
+}
+
+void swkb_patch_destroy(swkb_patch_t pp) {
+  if (!pp) return;
+  (void)hipDeviceSynchronize();
+  destroy_patch(pp);
+}
+
+}  // extern "C"

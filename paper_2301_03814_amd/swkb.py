@@ -28,7 +28,8 @@ EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", 
            "swkb_server_create", "swkb_server_submit", "swkb_server_step", "swkb_server_poll",
            "swkb_server_stats", "swkb_server_destroy", "swkb_graphs", "swkb_multi_create",
            "swkb_multi_get_tuning", "swkb_multi_set_tuning", "swkb_multi_tune", "swkb_multi_propagate",
-           "swkb_multi_destroy"]
+           "swkb_multi_destroy", "swkb_patch_plan", "swkb_patch_info", "swkb_patch_propagate",
+           "swkb_patch_field", "swkb_patch_destroy"]
 
 MULTI_MAX_CLASSES = 16
 
@@ -85,6 +86,10 @@ class MultiTuning(C.Structure):
                 ("fft_elems", C.c_int32 * MULTI_MAX_CLASSES), ("apply_groups", C.c_int32 * MULTI_MAX_CLASSES),
                 ("graphs", C.c_int32), ("fft_us", C.c_double * MULTI_MAX_CLASSES),
                 ("apply_us", C.c_double * MULTI_MAX_CLASSES)]
+
+
+class PatchConfig(C.Structure):
+    _fields_ = [("n_patches", C.c_int32), ("width", C.c_double), ("margin", C.c_double)]
 
 
 REQ_PENDING, REQ_ACTIVE, REQ_DONE, REQ_FAILED = range(4)
@@ -151,6 +156,14 @@ def load(path: str = LIB_PATH):
     lib.swkb_multi_propagate.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
     lib.swkb_multi_destroy.argtypes = [vp]
     lib.swkb_multi_destroy.restype = None
+    lib.swkb_patch_plan.argtypes = [pp, C.POINTER(PatchConfig), vp, C.POINTER(vp)]
+    lib.swkb_patch_info.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    lib.swkb_patch_propagate.argtypes = [vp, vp, i32, i32, vp, vp]
+    lib.swkb_patch_field.argtypes = [vp, vp, vp]
+    lib.swkb_patch_destroy.argtypes = [vp]
+    lib.swkb_patch_destroy.restype = None
+    for name in ("swkb_patch_plan", "swkb_patch_info", "swkb_patch_propagate", "swkb_patch_field"):
+        getattr(lib, name).restype = C.c_int
     for name in ("swkb_multi_create", "swkb_multi_get_tuning", "swkb_multi_set_tuning", "swkb_multi_tune",
                  "swkb_multi_propagate"):
         getattr(lib, name).restype = C.c_int
@@ -421,6 +434,62 @@ class Multi:
     def close(self):
         if getattr(self, "_h", None):
             _lib.swkb_multi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PatchPlan:
+    """The screen step on overlapping patches (swkb_patch_*): the field is
+    windowed by a smooth partition of unity, each piece propagated on its own
+    sub-domain, the pieces added back."""
+
+    def __init__(self, cfg, n_patches, width, margin, precision=FP64, stream=None):
+        lib = load()
+        self.cfg = cfg
+        self.n_z = cfg["n_z"]
+        self._params = make_params(cfg, precision)
+        pc = PatchConfig(n_patches=int(n_patches), width=float(width), margin=float(margin))
+        h = C.c_void_p()
+        _check(lib.swkb_patch_plan(C.byref(self._params), C.byref(pc), _stream_handle(stream), C.byref(h)))
+        self._h = h
+        self.n_patches = int(n_patches)
+
+    def info(self):
+        """[(start index, points, modes)] of the sub-domains."""
+        out = []
+        for p in range(self.n_patches):
+            a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+            _check(_lib.swkb_patch_info(self._h, p, C.byref(a), C.byref(b), C.byref(c)))
+            out.append((a.value, b.value, c.value))
+        return out
+
+    def propagate(self, u0=None, q_begin=0, q_end=None, history=True, stream=None):
+        import torch
+        if q_end is None:
+            q_end = self.cfg["n_screens"]
+        up = C.c_void_p(0) if u0 is None else _dev_ptr(u0, torch.complex128, self.n_z, "u0")
+        hist = None
+        hp = C.c_void_p(0)
+        if history:
+            hist = torch.empty((q_end - q_begin, self.n_z), dtype=torch.complex128, device="cuda")
+            hp = C.c_void_p(hist.data_ptr())
+        _check(_lib.swkb_patch_propagate(self._h, up, int(q_begin), int(q_end), hp, _stream_handle(stream)))
+        return hist
+
+    def field(self, stream=None):
+        import torch
+        out = torch.empty(self.n_z, dtype=torch.complex128, device="cuda")
+        _check(_lib.swkb_patch_field(self._h, C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.swkb_patch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -43,7 +43,8 @@ def test_every_declared_symbol_is_exported(lib):
                                            ("swkb_timing", "Timing"), ("swkb_server_config", "ServerConfig"),
                                            ("swkb_request_info", "RequestInfo"),
                                            ("swkb_server_stats_t", "ServerStats"),
-                                           ("swkb_multi_tuning", "MultiTuning")])
+                                           ("swkb_multi_tuning", "MultiTuning"),
+                                           ("swkb_patch_config", "PatchConfig")])
 def test_struct_layout_matches_header(tmp_path, cname, pyname):
     from paper_2301_03814_amd import swkb
     S = getattr(swkb, pyname)
@@ -159,3 +160,19 @@ def test_multi_host_side_errors(lib):
     assert lib.swkb_multi_get_tuning(None, C.byref(t)) == swkb.SWKB_ERR_ARG
     assert lib.swkb_multi_propagate(None, None, None, None) == swkb.SWKB_ERR_ARG
     lib.swkb_multi_destroy(None)
+
+
+def test_patch_plan_host_side_errors(lib):
+    """Patch plans reject bad decompositions before touching the device."""
+    from paper_2301_03814_amd import swkb
+    h = C.c_void_p()
+    p = swkb.make_params(W.linear_caustic())
+    for n, w, m in ((0, 1.0, 1.0), (3, 1.0, 1.0), (2, 0.0, 1.0), (2, 1.0, -1.0)):
+        pc = swkb.PatchConfig(n_patches=n, width=w, margin=m)
+        assert lib.swkb_patch_plan(C.byref(p), C.byref(pc), None, C.byref(h)) == swkb.SWKB_ERR_ARG
+        assert not h.value
+    bad = swkb.make_params(W.with_overrides(W.linear_caustic(), n_z=100))
+    pc = swkb.PatchConfig(n_patches=2, width=1.0, margin=1.0)
+    assert lib.swkb_patch_plan(C.byref(bad), C.byref(pc), None, C.byref(h)) == swkb.SWKB_ERR_ARG
+    assert lib.swkb_patch_propagate(None, None, 0, 1, None, None) == swkb.SWKB_ERR_ARG
+    lib.swkb_patch_destroy(None)

@@ -1,0 +1,91 @@
+"""The screen step on overlapping patches (swkb_patch_*) through the C ABI
+against the oracle's patch step: the sub-domain layout bit for bit, FP64
+fields to 1e-10, mixed fields to 1e-3 (regression bound 5e-5)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-3
+MIXED_REGRESSION = 5e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import oracle
+    oracle.build()
+    import oracle.patches as OP
+    import paper_2301_03814_amd as pkg
+    pkg.load()
+    return torch, pkg, OP
+
+
+# (config, patches, window width, margin): periodic linear caustic, a
+# Dirichlet and a Neumann duct over a ground (bottom patch mirrored), and an
+# x-varying random medium
+CASES = {
+    "linear_caustic_P4": lambda: (W.linear_caustic(n_screens=3), 4, 3.0, 16.0),
+    "duct_dirichlet_P2": lambda: (W.surface_duct(n_screens=3, n_z=2048, n_modes=512, height=60.0, ext_m=4.0),
+                                  2, 0.15, 4.0),
+    "duct_neumann_P4": lambda: (W.surface_duct(n_screens=2, n_z=2048, n_modes=512, height=60.0, ext_m=4.0,
+                                               bc=W.BC_NEUMANN), 4, 0.15, 4.0),
+    "random_medium_P2": lambda: (W.random_medium(n_screens=3, n_z=1024, n_modes=256, height=125.0, seed=7,
+                                                 n_gauss=12, x_len=30.0), 2, 3.0, 20.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_patch_step_matches_oracle(env, name, prec):
+    torch, pkg, OP = env
+    cfg, P, width, margin = CASES[name]()
+    say(f"[patch] {name} {prec} N={cfg['n_z']} P={P}")
+    pp = pkg.PatchPlan(cfg, P, width, margin, precision=pkg.FP64 if prec == "fp64" else pkg.MIXED)
+    lay = OP.layout(cfg, P, width, margin)
+    assert pp.info() == [(s, sub["n_z"], sub["n_modes"]) for s, sub in lay]
+    u0 = W.incident_field(cfg)
+    hist = pp.propagate(torch.from_numpy(u0).cuda(), 0, cfg["n_screens"]).cpu().numpy()
+    ref = OP.run(cfg, u0, P, width, margin)
+    err = rel(hist, ref)
+    say(f"[patch] {name} {prec} rel_l2={err:.3e}")
+    if prec == "fp64":
+        assert err <= FP64_TOL
+    else:
+        assert err <= MIXED_TOL and err <= MIXED_REGRESSION
+    assert torch.equal(pp.field().cpu(), torch.from_numpy(hist[-1]))
+    pp.close()
+
+
+def test_resume_and_state(env):
+    """Screens in two calls equal one call; continuing without a field on the
+    right screen is refused."""
+    torch, pkg, OP = env
+    cfg, P, width, margin = CASES["linear_caustic_P4"]()
+    u0 = torch.from_numpy(W.incident_field(cfg)).cuda()
+    pp = pkg.PatchPlan(cfg, P, width, margin)
+    h_all = pp.propagate(u0, 0, 3)
+    pp2 = pkg.PatchPlan(cfg, P, width, margin)
+    h1 = pp2.propagate(u0, 0, 1)
+    h2 = pp2.propagate(None, 1, 3)
+    assert torch.equal(torch.cat([h1, h2]), h_all)
+    with pytest.raises(pkg.SwkbError):
+        pp2.propagate(None, 1, 2)
+    pp.close()
+    pp2.close()
