@@ -265,6 +265,71 @@ def bench_multi(torch, np, W, Plan, Multi, MIXED, n_problems=64, graphs=True):
     return out
 
 
+def bench_patches(torch, np, W, Plan, PatchPlan, MIXED, n_patches=8):
+    """Tall surface ducts (6 GHz, 1000 screens of 100 m, Dirichlet ground,
+    mixed): 0-600 m (N_z = 32768, 8192 modes) by the single-domain step and by
+    the overlapping-patch step (8 patches, windows of 1 m, margins of 20 m),
+    and 0-1200 m (N_z = 65536, 16384 modes: beyond one plan's grid) by
+    patches only."""
+    dev = torch.device("cuda:0")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    def run_patches(cfg):
+        Q = cfg["n_screens"]
+        u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pp = PatchPlan(cfg, n_patches, 1.0, 20.0, precision=MIXED)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        info = pp.info()
+        dt, h = timed(lambda: pp.propagate(u0, 0, Q, history=True))
+        got = h[::50].cpu().numpy()
+        del h
+        pp.close()
+        work = sum(n * m for _, n, m in info)
+        return got, {"seconds": dt, "n_patches": n_patches, "window_m": 1.0, "margin_m": 20.0,
+                     "sub_domains": [{"start": a, "n_z": b, "n_modes": c} for a, b, c in info],
+                     "mode_points_per_screen": work, "plan_build_s": round(tb, 3),
+                     "range_km_per_s": 100.0 / dt,
+                     "global_mode_point_evals_per_s": cfg["n_z"] * cfg["n_modes"] * Q / dt}
+
+    cfg = W.surface_duct(n_z=32768, n_modes=8192, height=600.0)
+    N, M, Q = cfg["n_z"], cfg["n_modes"], cfg["n_screens"]
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    full = Plan(cfg, precision=MIXED, device=dev)
+    torch.cuda.synchronize()
+    tb_full = time.perf_counter() - t0
+    dt_full, h = timed(lambda: full.propagate(u0, 0, Q, history=True))
+    ref = h[::50].cpu().numpy()
+    del h
+    full.close()
+    got, pat = run_patches(cfg)
+    out = {"workload": "surface ducts: lambda=0.05 m, M-profile -0.3/+0.118 M/m, 1000 screens of 100 m (100 km), "
+                       "Dirichlet ground, mixed; 0-600 m with N_z=32768, 8192 modes; 0-1200 m with N_z=65536, "
+                       "16384 modes",
+           "h600": {"single_domain": {"seconds": dt_full, "mode_points_per_screen": N * M,
+                                      "plan_build_s": round(tb_full, 3), "range_km_per_s": 100.0 / dt_full,
+                                      "mode_point_evals_per_s": N * M * Q / dt_full},
+                    "patches": pat,
+                    "speedup_patches_vs_single_domain": dt_full / pat["seconds"],
+                    "rel_diff_patches_vs_single_domain_every_50th_screen":
+                        float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}}
+    _, pat2 = run_patches(W.surface_duct(n_z=65536, n_modes=16384, height=1200.0))
+    out["h1200"] = {"patches": pat2, "single_domain": "beyond one plan's grid (n_z <= 32768)"}
+    print(f"[bench] patches: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,9 +339,10 @@ def main():
     ap.add_argument("--no-duct", action="store_true", help="skip the surface-duct measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-multi", action="store_true", help="skip the uneven duct batch measurement")
+    ap.add_argument("--no-patches", action="store_true", help="skip the overlapping-patch measurement")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the step with per-kernel events (kernels one after another), for rocprofv3")
-    ap.add_argument("--only", choices=("duct", "multi"), default=None,
+    ap.add_argument("--only", choices=("duct", "multi", "patches"), default=None,
                     help="run only that section and print its JSON (for rocprofv3 summaries)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="uneven batch without HIP graphs (for rocprofv3 counter collection)")
@@ -308,6 +374,10 @@ def main():
 
     if args.only == "duct":
         print(json.dumps(bench_duct(args, torch, np, W, Plan, FP64, MIXED)))
+        return
+    if args.only == "patches":
+        from paper_2301_03814_amd import PatchPlan
+        print(json.dumps(bench_patches(torch, np, W, Plan, PatchPlan, MIXED)))
         return
     if args.only == "multi":
         from paper_2301_03814_amd import Multi
@@ -451,6 +521,10 @@ def main():
     if not args.no_multi:
         from paper_2301_03814_amd import Multi
         multi = bench_multi(torch, np, W, Plan, Multi, MIXED)
+    patches = None
+    if not args.no_patches:
+        from paper_2301_03814_amd import PatchPlan
+        patches = bench_patches(torch, np, W, Plan, PatchPlan, MIXED)
     serving = None
     if not args.no_serving:
         from paper_2301_03814_amd import Server
@@ -490,6 +564,7 @@ def main():
         "cpu_baseline": cpu,
         "surface_duct": duct,
         "uneven_duct_batch": multi,
+        "tall_duct_patches": patches,
         "serving": serving,
     }
     print(json.dumps(line))

@@ -354,8 +354,10 @@ typedef struct swkb_patch_s* swkb_patch_t;
 
 /* Host; builds one plan per patch (swkb_plan) in device memory the patch
  * plan allocates itself (hipMalloc) and frees in swkb_patch_destroy; p must
- * have max_batch = 1.  Synchronises hip_stream.  SWKB_ERR_ARG for invalid
- * parameters, including a sub-domain the library cannot plan. */
+ * have max_batch = 1.  The global n_z need only be in [64, 2^24] and a
+ * multiple of n_patches (it may exceed a single plan's limit); every
+ * sub-domain must be a valid plan.  Synchronises hip_stream.  SWKB_ERR_ARG
+ * for invalid parameters, including a sub-domain the library cannot plan. */
 swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, void* hip_stream, swkb_patch_t* out);
 
 /* First global grid index, points and modes of patch `patch`'s sub-domain

@@ -522,3 +522,25 @@ void swkb_multi_destroy(swkb_multi_t m) {
 }
 
 }  // extern "C"
+
+// For other parts of the library: every problem of the group reads its field
+// from inputs[i] (caller order) on each step; synchronous upload.
+hipError_t swkb::multi_set_inputs(swkb_multi_s* m, const double2* const* inputs) {
+  hipError_t e = hipEventSynchronize(m->ev_done);
+  if (e != hipSuccess) return e;
+  drop_graph(m);
+  const int n = (int)m->plans.size();
+  for (int s = 0; s < n; ++s) m->hp[s].u_in = inputs[m->order[s]];
+  return hipMemcpy(m->d_prob, m->hp.data(), sizeof(MultiProblem) * n, hipMemcpyHostToDevice);
+}
+
+// One screen step (screen q) of every problem from its input, on stream st.
+hipError_t swkb::multi_step(swkb_multi_s* m, int q, hipStream_t st) {
+  const int n = (int)m->plans.size();
+  hipError_t e = launch_fft_multi(m->d_prob, map_of(m, kCols), m->off[kCols][n], map_of(m, kRows), m->off[kRows][n], 1,
+                                  m->lds_cols, m->lds_rows, st);
+  if (e == hipSuccess)
+    e = launch_apply_multi(m->d_prob, map_of(m, kApply), m->off[kApply][n], map_of(m, kFin), m->off[kFin][n], q, st);
+  if (e == hipSuccess) e = hipEventRecord(m->ev_done, st);
+  return e;
+}

@@ -5,7 +5,9 @@
 //   S^0 = 1 - sigma_1,  S^p = sigma_p - sigma_{p+1},  S^{P-1} = sigma_{P-1},
 // which sums to one and falls below 1e-17 more than 6 w outside each core.
 // A screen step windows the field, u_p = S^p u, runs the ordinary screen
-// step (Sec. 2.1, with the ground mirror of Sec. 2.3 on the bottom patch)
+// step (Sec. 2.1, with the ground mirror of Sec. 2.3 on the bottom patch;
+// for media that do not depend on x in mixed precision all patches' steps run
+// as one multi-problem group, one launch per stage)
 // on each piece over a sub-domain that holds the core plus e = ceil((6 w +
 // margin) / h) cells on each side (rounded up to a power of two, centred on
 // the core), adds the pieces' outputs on the global grid in patch order and
@@ -26,6 +28,8 @@ namespace {
 struct PatchView {
   int start, n;        // global index of the sub-domain's first point, its points
   const double2* f;    // the sub-plan's field after its screen step
+  const double* S;     // window at the sub-domain's points
+  double2* v;          // windowed field (the sub-plan's input)
 };
 
 swkb_status fail(swkb_status s, const std::string& msg) {
@@ -50,6 +54,20 @@ __global__ void patch_window_kernel(const double2* __restrict__ u, int N, int st
     r = make_double2(S[i] * x.x, S[i] * x.y);
   }
   v[i] = r;
+}
+
+// The same for every patch in one launch (patch blockIdx.y).
+__global__ void patch_window_all_kernel(const double2* __restrict__ u, int N, const PatchView* __restrict__ views) {
+  const PatchView& pv = views[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pv.n) return;
+  const int m = pv.start + i;
+  double2 r = make_double2(0.0, 0.0);
+  if (m >= 0 && m < N) {
+    const double2 x = u[m];
+    r = make_double2(pv.S[i] * x.x, pv.S[i] * x.y);
+  }
+  pv.v[i] = r;
 }
 
 // u'[m] = W[m] sum_p f_p[m - start_p] (patches in order), and the history row.
@@ -96,12 +114,17 @@ struct swkb_patch_s {
   double2* u = nullptr;    // current field [N]
   double* W = nullptr;     // global exit taper [N]
   PatchView* views = nullptr;
+  int max_n = 0;
+  // media that do not depend on x, mixed precision: the sub-plans' steps as
+  // one multi-problem group (one launch per stage for all patches)
+  swkb_multi_t grp = nullptr;
   int cur_q = -1;
 };
 
 namespace {
 
 void destroy_patch(swkb_patch_s* pp) {
+  if (pp->grp) swkb_multi_destroy(pp->grp);
   for (auto& s : pp->subs) {
     if (s.plan) swkb_destroy(s.plan);
     if (s.ws) (void)hipFree(s.ws);
@@ -147,9 +170,20 @@ swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, v
   if (!out) return fail(SWKB_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!p || !pc) return fail(SWKB_ERR_ARG, "NULL argument");
-  if (swkb_workspace_bytes(p) == 0) return fail(SWKB_ERR_ARG, "invalid swkb_params (swkb_workspace_bytes is 0)");
+  // the global grid is only windowed and summed; every sub-domain is
+  // validated as a plan of its own below (so n_z may exceed a single plan's)
+  if (p->n_z < 64 || p->n_z > (1 << 24)) return fail(SWKB_ERR_ARG, "n_z must be in [64, 2^24]");
   if (pc->n_patches < 1 || p->n_z % pc->n_patches != 0)
     return fail(SWKB_ERR_ARG, "n_patches must be >= 1 and divide n_z");
+  {
+    const long P_g = p->bc == SWKB_BC_PERIODIC ? p->n_z : 2L * p->n_z;
+    if (p->n_modes < 2 || (p->n_modes & 1) || p->n_modes > P_g) return fail(SWKB_ERR_ARG, "n_modes must be even and in [2, P]");
+    if (!(p->z_b > p->z_a) || !(p->k > 0.0) || !std::isfinite(p->k)) return fail(SWKB_ERR_ARG, "need z_b > z_a and k > 0");
+    if (!(p->absorber_bot >= 0.0 && p->absorber_top >= 0.0 && p->absorber_bot + p->absorber_top <= p->z_b - p->z_a))
+      return fail(SWKB_ERR_ARG, "absorber thicknesses must be >= 0 and fit in [z_a, z_b]");
+    if (p->bc < 0 || p->bc > 2 || !p->medium_params || p->n_medium_params < 1)
+      return fail(SWKB_ERR_ARG, "invalid bc or medium parameters");
+  }
   if (!(pc->width > 0.0) || !(pc->margin >= 0.0) || !std::isfinite(pc->width) || !std::isfinite(pc->margin))
     return fail(SWKB_ERR_ARG, "width must be > 0 and margin >= 0");
   if (p->max_batch != 1) return fail(SWKB_ERR_ARG, "patch plans carry one field (max_batch = 1)");
@@ -233,7 +267,8 @@ swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, v
       destroy_patch(pp);
       return hip_fail(e, "swkb_patch_plan: window upload");
     }
-    views[q] = PatchView{s.start, s.n, s.plan->u};
+    views[q] = PatchView{s.start, s.n, s.plan->u, s.S, s.v};
+    pp->max_n = std::max(pp->max_n, s.n);
   }
   std::vector<double> W(pp->N);
   for (int m = 0; m < pp->N; ++m) W[m] = exit_taper(pp->p, p->z_a + (double)m * pp->h);
@@ -242,6 +277,28 @@ swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, v
   if (e != hipSuccess) {
     destroy_patch(pp);
     return hip_fail(e, "swkb_patch_plan: upload");
+  }
+  // sub-plans that a multi-problem group can carry: one group, autotuned
+  bool grouped = true;
+  for (auto& s : pp->subs)
+    grouped = grouped && s.plan->use_matrix && s.plan->precision == SWKB_MIXED && s.n % 512 == 0;
+  if (grouped) {
+    std::vector<swkb_plan_t> plans;
+    std::vector<const double2*> inputs;
+    for (auto& s : pp->subs) {
+      plans.push_back(s.plan);
+      inputs.push_back(s.v);
+    }
+    swkb_status gs = swkb_multi_create(plans.data(), pp->P, &pp->grp);
+    if (gs == SWKB_OK) gs = swkb_multi_tune(pp->grp, 3, st, nullptr);
+    if (gs == SWKB_OK) {
+      e = swkb::multi_set_inputs(pp->grp, inputs.data());
+      if (e != hipSuccess) gs = hip_fail(e, "swkb_patch_plan: group inputs");
+    }
+    if (gs != SWKB_OK) {
+      destroy_patch(pp);
+      return gs;
+    }
   }
   *out = pp;
   return SWKB_OK;
@@ -269,13 +326,21 @@ swkb_status swkb_patch_propagate(swkb_patch_t pp, const void* u_in, int32_t q_be
   if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: field copy");
   pp->cur_q = q_begin;
   for (int q = q_begin; q < q_end; ++q) {
-    for (auto& s : pp->subs) {
-      hipLaunchKernelGGL(patch_window_kernel, dim3((s.n + 255) / 256), dim3(256), 0, st, pp->u, pp->N, s.start, s.n,
-                         s.S, s.v);
+    if (pp->grp) {
+      hipLaunchKernelGGL(patch_window_all_kernel, dim3((pp->max_n + 255) / 256, pp->P), dim3(256), 0, st, pp->u,
+                         pp->N, pp->views);
       e = hipGetLastError();
-      if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: window");
-      const swkb_status ps = swkb_propagate(s.plan, s.v, q, q + 1, nullptr, st);
-      if (ps != SWKB_OK) return ps;
+      if (e == hipSuccess) e = swkb::multi_step(pp->grp, q, st);
+      if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: grouped step");
+    } else {
+      for (auto& s : pp->subs) {
+        hipLaunchKernelGGL(patch_window_kernel, dim3((s.n + 255) / 256), dim3(256), 0, st, pp->u, pp->N, s.start,
+                           s.n, s.S, s.v);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: window");
+        const swkb_status ps = swkb_propagate(s.plan, s.v, q, q + 1, nullptr, st);
+        if (ps != SWKB_OK) return ps;
+      }
     }
     double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * pp->N : nullptr;
     hipLaunchKernelGGL(patch_add_kernel, dim3((pp->N + 255) / 256), dim3(256), 0, st, pp->views, pp->P, pp->N, pp->W,

@@ -201,6 +201,10 @@ hipError_t launch_fft_multi(const MultiProblem* mp, const unsigned* map_cols, in
                             int n_rows, int first, size_t lds_cols, size_t lds_rows, hipStream_t st);
 hipError_t launch_apply_multi(const MultiProblem* mp, const unsigned* map_apply, int n_apply,
                               const unsigned* map_fin, int n_fin, int step, hipStream_t st);
+// Inside the library: a multi-problem group whose problems read their fields
+// from fixed inputs, one screen step at a time (multi.hip).
+hipError_t multi_set_inputs(swkb_multi_s* m, const double2* const* inputs);
+hipError_t multi_step(swkb_multi_s* m, int q, hipStream_t st);
 hipError_t launch_export_rays(const swkb_plan_s& pl, int q, double* Z, double* psi, double* qz,
                               double* amp, int* flag, hipStream_t st);
 
