@@ -370,6 +370,15 @@ swkb_status swkb_patch_info(swkb_patch_t pp, int32_t patch, int32_t* start, int3
 swkb_status swkb_patch_propagate(swkb_patch_t pp, const void* u_in, int32_t q_begin, int32_t q_end, void* history,
                                  void* hip_stream);
 
+/* Enable (1) or disable (0) HIP graphs for swkb_patch_propagate when the
+ * patches run as one group (media that do not depend on x, mixed
+ * precision): the first call with a given (u_in, q_begin, q_end, history)
+ * captures the screen range on a stream of the plan's own, later calls
+ * replay it (up to 4 graphs kept; a replay gives the fields of an eager
+ * call).  Disabling waits for replays in flight and frees the graphs.
+ * Host only; ignored for patch plans that do not run as a group. */
+swkb_status swkb_patch_graphs(swkb_patch_t pp, int32_t enable);
+
 /* The current global field into out (device complex128[n_z]). */
 swkb_status swkb_patch_field(swkb_patch_t pp, void* out, void* hip_stream);
 

@@ -541,6 +541,12 @@ hipError_t swkb::multi_step(swkb_multi_s* m, int q, hipStream_t st) {
                                   m->lds_cols, m->lds_rows, st);
   if (e == hipSuccess)
     e = launch_apply_multi(m->d_prob, map_of(m, kApply), m->off[kApply][n], map_of(m, kFin), m->off[kFin][n], q, st);
-  if (e == hipSuccess) e = hipEventRecord(m->ev_done, st);
+  // under stream capture the caller marks the end of the replay instead
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (e == hipSuccess) e = hipStreamIsCapturing(st, &cap);
+  if (e == hipSuccess && cap == hipStreamCaptureStatusNone) e = hipEventRecord(m->ev_done, st);
   return e;
 }
+
+// Marks the group's work enqueued on st so far as the latest (for a replay).
+hipError_t swkb::multi_mark(swkb_multi_s* m, hipStream_t st) { return hipEventRecord(m->ev_done, st); }

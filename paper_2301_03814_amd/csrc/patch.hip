@@ -119,11 +119,35 @@ struct swkb_patch_s {
   // one multi-problem group (one launch per stage for all patches)
   swkb_multi_t grp = nullptr;
   int cur_q = -1;
+  // screen ranges of the grouped path captured into HIP graphs
+  struct Graph {
+    const void* u_in;
+    int q0, q1;
+    void* hist;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  int graphs_on = 0;
+  hipStream_t cs = nullptr;
+  hipEvent_t g0 = nullptr, g1 = nullptr;
 };
 
 namespace {
 
+void drop_graphs(swkb_patch_s* pp) {
+  for (auto& g : pp->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  pp->graphs.clear();
+}
+
 void destroy_patch(swkb_patch_s* pp) {
+  drop_graphs(pp);
+  if (pp->g0) (void)hipEventDestroy(pp->g0);
+  if (pp->g1) (void)hipEventDestroy(pp->g1);
+  if (pp->cs) (void)hipStreamDestroy(pp->cs);
   if (pp->grp) swkb_multi_destroy(pp->grp);
   for (auto& s : pp->subs) {
     if (s.plan) swkb_destroy(s.plan);
@@ -159,6 +183,38 @@ double exit_taper(const swkb_params& p, double z) {
     w *= c * c;
   }
   return w;
+}
+
+// Screens q_begin .. q_end-1 on stream st (the body of swkb_patch_propagate).
+swkb_status enqueue_screens(swkb_patch_s* pp, const void* u_in, int q_begin, int q_end, void* history,
+                            hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (u_in) e = hipMemcpyAsync(pp->u, u_in, sizeof(double2) * pp->N, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: field copy");
+  for (int q = q_begin; q < q_end; ++q) {
+    if (pp->grp) {
+      hipLaunchKernelGGL(patch_window_all_kernel, dim3((pp->max_n + 255) / 256, pp->P), dim3(256), 0, st, pp->u,
+                         pp->N, pp->views);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = swkb::multi_step(pp->grp, q, st);
+      if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: grouped step");
+    } else {
+      for (auto& s : pp->subs) {
+        hipLaunchKernelGGL(patch_window_kernel, dim3((s.n + 255) / 256), dim3(256), 0, st, pp->u, pp->N, s.start,
+                           s.n, s.S, s.v);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: window");
+        const swkb_status ps = swkb_propagate(s.plan, s.v, q, q + 1, nullptr, st);
+        if (ps != SWKB_OK) return ps;
+      }
+    }
+    double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * pp->N : nullptr;
+    hipLaunchKernelGGL(patch_add_kernel, dim3((pp->N + 255) / 256), dim3(256), 0, st, pp->views, pp->P, pp->N, pp->W,
+                       pp->u, hist);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: overlap-add");
+  }
+  return SWKB_OK;
 }
 
 }  // namespace
@@ -321,34 +377,64 @@ swkb_status swkb_patch_propagate(swkb_patch_t pp, const void* u_in, int32_t q_be
   if (!u_in && pp->cur_q != q_begin)
     return fail(SWKB_ERR_STATE, "u_in is NULL but the plan's field is not on screen q_begin");
   hipStream_t st = (hipStream_t)hip_stream;
-  hipError_t e = hipSuccess;
-  if (u_in) e = hipMemcpyAsync(pp->u, u_in, sizeof(double2) * pp->N, hipMemcpyDeviceToDevice, st);
-  if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: field copy");
-  pp->cur_q = q_begin;
-  for (int q = q_begin; q < q_end; ++q) {
-    if (pp->grp) {
-      hipLaunchKernelGGL(patch_window_all_kernel, dim3((pp->max_n + 255) / 256, pp->P), dim3(256), 0, st, pp->u,
-                         pp->N, pp->views);
-      e = hipGetLastError();
-      if (e == hipSuccess) e = swkb::multi_step(pp->grp, q, st);
-      if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: grouped step");
-    } else {
-      for (auto& s : pp->subs) {
-        hipLaunchKernelGGL(patch_window_kernel, dim3((s.n + 255) / 256), dim3(256), 0, st, pp->u, pp->N, s.start,
-                           s.n, s.S, s.v);
-        e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: window");
-        const swkb_status ps = swkb_propagate(s.plan, s.v, q, q + 1, nullptr, st);
-        if (ps != SWKB_OK) return ps;
-      }
-    }
-    double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * pp->N : nullptr;
-    hipLaunchKernelGGL(patch_add_kernel, dim3((pp->N + 255) / 256), dim3(256), 0, st, pp->views, pp->P, pp->N, pp->W,
-                       pp->u, hist);
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: overlap-add");
-    pp->cur_q = q + 1;
+  if (!(pp->graphs_on && pp->grp && q_end > q_begin)) {
+    const swkb_status s = enqueue_screens(pp, u_in, q_begin, q_end, history, st);
+    if (s == SWKB_OK) pp->cur_q = q_end;
+    return s;
   }
+  swkb_patch_s::Graph* hit = nullptr;
+  for (auto& g : pp->graphs)
+    if (g.u_in == u_in && g.q0 == q_begin && g.q1 == q_end && g.hist == history) hit = &g;
+  hipError_t e = hipEventRecord(pp->g0, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(pp->cs, pp->g0, 0);
+  if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: graph");
+  if (!hit) {
+    if (pp->graphs.size() >= 4) {
+      (void)hipGraphExecDestroy(pp->graphs.front().exec);
+      (void)hipGraphDestroy(pp->graphs.front().graph);
+      pp->graphs.erase(pp->graphs.begin());
+    }
+    e = hipStreamBeginCapture(pp->cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: capture");
+    const swkb_status s = enqueue_screens(pp, u_in, q_begin, q_end, history, pp->cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(pp->cs, &graph);
+    if (s != SWKB_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s != SWKB_OK ? s : hip_fail(e, "swkb_patch_propagate: capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(e, "swkb_patch_propagate: graph instantiate");
+    }
+    pp->graphs.push_back({u_in, q_begin, q_end, history, graph, exec});
+    hit = &pp->graphs.back();
+  }
+  e = hipGraphLaunch(hit->exec, pp->cs);
+  if (e == hipSuccess) e = swkb::multi_mark(pp->grp, pp->cs);
+  if (e == hipSuccess) e = hipEventRecord(pp->g1, pp->cs);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, pp->g1, 0);
+  if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: graph launch");
+  pp->cur_q = q_end;
+  return SWKB_OK;
+}
+
+swkb_status swkb_patch_graphs(swkb_patch_t pp, int32_t enable) {
+  if (!pp) return fail(SWKB_ERR_ARG, "patch plan is NULL");
+  if (enable && !pp->cs) {
+    hipError_t e = hipStreamCreateWithFlags(&pp->cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pp->g0, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pp->g1, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "swkb_patch_graphs");
+  }
+  if (!enable && pp->cs) {
+    const hipError_t e = hipStreamSynchronize(pp->cs);
+    if (e != hipSuccess) return hip_fail(e, "swkb_patch_graphs");
+    drop_graphs(pp);
+  }
+  pp->graphs_on = enable ? 1 : 0;
   return SWKB_OK;
 }
 
@@ -362,7 +448,7 @@ swkb_status swkb_patch_field(swkb_patch_t pp, void* out, void* hip_stream) {
 
 void swkb_patch_destroy(swkb_patch_t pp) {
   if (!pp) return;
-  (void)hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();  // replays and sub-plan work in flight
   destroy_patch(pp);
 }
 

@@ -205,6 +205,7 @@ hipError_t launch_apply_multi(const MultiProblem* mp, const unsigned* map_apply,
 // from fixed inputs, one screen step at a time (multi.hip).
 hipError_t multi_set_inputs(swkb_multi_s* m, const double2* const* inputs);
 hipError_t multi_step(swkb_multi_s* m, int q, hipStream_t st);
+hipError_t multi_mark(swkb_multi_s* m, hipStream_t st);
 hipError_t launch_export_rays(const swkb_plan_s& pl, int q, double* Z, double* psi, double* qz,
                               double* amp, int* flag, hipStream_t st);
 

@@ -29,7 +29,7 @@ EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", 
            "swkb_server_stats", "swkb_server_destroy", "swkb_graphs", "swkb_multi_create",
            "swkb_multi_get_tuning", "swkb_multi_set_tuning", "swkb_multi_tune", "swkb_multi_propagate",
            "swkb_multi_destroy", "swkb_patch_plan", "swkb_patch_info", "swkb_patch_propagate",
-           "swkb_patch_field", "swkb_patch_destroy"]
+           "swkb_patch_field", "swkb_patch_destroy", "swkb_patch_graphs"]
 
 MULTI_MAX_CLASSES = 16
 
@@ -160,6 +160,8 @@ def load(path: str = LIB_PATH):
     lib.swkb_patch_info.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.swkb_patch_propagate.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.swkb_patch_field.argtypes = [vp, vp, vp]
+    lib.swkb_patch_graphs.argtypes = [vp, i32]
+    lib.swkb_patch_graphs.restype = C.c_int
     lib.swkb_patch_destroy.argtypes = [vp]
     lib.swkb_patch_destroy.restype = None
     for name in ("swkb_patch_plan", "swkb_patch_info", "swkb_patch_propagate", "swkb_patch_field"):
@@ -468,18 +470,27 @@ class PatchPlan:
             out.append((a.value, b.value, c.value))
         return out
 
-    def propagate(self, u0=None, q_begin=0, q_end=None, history=True, stream=None):
+    def propagate(self, u0=None, q_begin=0, q_end=None, history=True, out=None, stream=None):
+        """Screens q_begin..q_end-1; returns the history [q_end-q_begin, N]
+        (into `out` if given) when history is True, else None."""
         import torch
         if q_end is None:
             q_end = self.cfg["n_screens"]
         up = C.c_void_p(0) if u0 is None else _dev_ptr(u0, torch.complex128, self.n_z, "u0")
         hist = None
         hp = C.c_void_p(0)
-        if history:
+        if out is not None:
+            hist = out
+            hp = _dev_ptr(out, torch.complex128, (q_end - q_begin) * self.n_z, "out")
+        elif history:
             hist = torch.empty((q_end - q_begin, self.n_z), dtype=torch.complex128, device="cuda")
             hp = C.c_void_p(hist.data_ptr())
         _check(_lib.swkb_patch_propagate(self._h, up, int(q_begin), int(q_end), hp, _stream_handle(stream)))
         return hist
+
+    def graphs(self, enable=True):
+        """Capture screen ranges into HIP graphs and replay them (swkb_patch_graphs)."""
+        _check(_lib.swkb_patch_graphs(self._h, 1 if enable else 0))
 
     def field(self, stream=None):
         import torch

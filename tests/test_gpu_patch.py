@@ -89,3 +89,27 @@ def test_resume_and_state(env):
         pp2.propagate(None, 1, 2)
     pp.close()
     pp2.close()
+
+
+def test_graph_replays_equal_eager(env):
+    """The grouped patch step (x-invariant medium, mixed) captured and replayed
+    three times, with eager work between the replays, equals the eager run."""
+    torch, pkg, OP = env
+    cfg, P, width, margin = CASES["duct_neumann_P4"]()
+    u0 = torch.from_numpy(W.incident_field(cfg)).cuda()
+    eager = pkg.PatchPlan(cfg, P, width, margin, precision=pkg.MIXED)
+    ref = eager.propagate(u0, 0, cfg["n_screens"]).cpu()
+    pp = pkg.PatchPlan(cfg, P, width, margin, precision=pkg.MIXED)
+    pp.graphs(True)
+    out = torch.empty((cfg["n_screens"], cfg["n_z"]), dtype=torch.complex128, device="cuda")
+    for r in range(3):
+        say(f"[patch] graph replay {r}")
+        out.zero_()
+        pp.propagate(u0, 0, cfg["n_screens"], out=out)  # the same arguments: one capture, then replays
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        assert torch.equal(out.cpu(), ref), r
+    pp.graphs(False)
+    pp.close()
+    eager.close()
