@@ -159,11 +159,14 @@ struct TableMedium {
   GaussMedium<float> direct;
   __device__ Med<float> eval(int k, float dz, Work& c) const {
     const float t = dz * inv_dz + tl;
-    const float tf = floorf(t);
+    // node index floor(t) in one instruction (a saturating conversion, like
+    // the one of floorf(t) to int) and the offset t - floor(t) in another
+    int ti;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(ti) : "v"(t));
     // unsigned wrap sends heights below the table (and saturated conversions) out of range too
-    const unsigned iv = (unsigned)j0 + (unsigned)(int)tf;
+    const unsigned iv = (unsigned)j0 + (unsigned)ti;
     if (!(iv < ni)) return direct.eval(k, dz, c);
-    const float u = t - tf;
+    const float u = __builtin_amdgcn_fractf(t);
     const size_t o = (size_t)k * ni + iv;
     const float4 a = ta[o];
     // Horner for p, p' and p''/2 together
