@@ -142,7 +142,11 @@ size_t swkb_workspace_bytes(const swkb_params* p);
 swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_bytes,
                       void* hip_stream, swkb_plan_t* out);
 
-/* Propagate screens q_begin .. q_end-1 (Algorithm 1 per screen).
+/* Propagate screens q_begin .. q_end-1 (Algorithm 1 per screen).  For media
+ * that change with x the march and the scan of each screen run on a march
+ * and a scan stream that all plans on the device share (default priority),
+ * ordered against hip_stream by events of the plan; the plan's results are
+ * complete when hip_stream reaches the end of the call's work.
  * u_in: device complex128[N], the field on screen q_begin; NULL continues
  * from the plan's current field, which must then be on screen q_begin.
  * history: device complex128[(q_end - q_begin) * N] receiving the field on
@@ -207,12 +211,13 @@ swkb_status swkb_diagnostics(swkb_plan_t plan, void* hip_stream, swkb_counters* 
 
 /* Enable (1) or disable (0) HIP graphs for swkb_propagate: the first call
  * with a given (u_in, q_begin, q_end, history) captures its whole screen
- * sequence (FFT, march, scan, sums; both streams) into a graph on a stream of
- * the plan's own, later calls with the same arguments replay it (up to 4
- * graphs are kept).  A replay launches the same kernels with the same
- * arguments, so it gives the same fields as an eager call; it reads u_in and
- * writes history when it runs.  Ignored while profiling.  Disabling waits
- * for replays in flight and frees the graphs.  Host only. */
+ * sequence (FFT, march, scan, sums; all streams) into a graph on the capture
+ * stream the device's plans share, later calls with the same arguments
+ * replay it (up to 4 graphs are kept).  A replay launches the same kernels
+ * with the same arguments, so it gives the same fields as an eager call; it
+ * reads u_in and writes history when it runs.  Ignored while profiling.
+ * Disabling waits for replays in flight and frees the graphs.  Host only;
+ * capture is not thread-safe across plans of one device. */
 swkb_status swkb_graphs(swkb_plan_t plan, int32_t enable);
 
 /* Enable (1) or disable (0) event timing of every kernel the plan launches.

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -284,15 +285,49 @@ static void set_slot_q(swkb_plan_s* pl, int k, int q) {
   if (pl->rec.D == pl->slots[k].rec.D) pl->march_valid_q = q;
 }
 
+// March, scan and graph-capture streams shared by every plan on a device.
+// A process gets few hardware queues, and streams that share a queue run in
+// submission order (an event wait on one holds up the others), so streams of
+// its own for every plan would serialise the pipelines of plans created
+// later.  Created on first use, kept until the process ends.  Every plan
+// orders its work on them with events of its own; each wait refers to an
+// event recorded earlier in host order, so sharing cannot deadlock.
+struct SharedStreams {
+  hipStream_t ms = nullptr, ss = nullptr, cs = nullptr;
+};
+static std::mutex g_streams_mu;
+static std::vector<SharedStreams> g_streams;  // by device
+
+static hipError_t shared_streams(SharedStreams* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_streams_mu);
+  if ((int)g_streams.size() <= dev) g_streams.resize(dev + 1);
+  SharedStreams& s = g_streams[dev];
+  if (!s.ms) {
+    SharedStreams n;
+    e = hipStreamCreateWithFlags(&n.ms, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&n.ss, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&n.cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      for (hipStream_t x : {n.ms, n.ss, n.cs})
+        if (x) (void)hipStreamDestroy(x);
+      return e;
+    }
+    s = n;
+  }
+  *out = s;
+  return hipSuccess;
+}
+
 static void destroy_streams(swkb_plan_s* pl) {
   for (int k = 0; k < 2; ++k) {
     if (pl->ev_ready[k]) (void)hipEventDestroy(pl->ev_ready[k]);
     if (pl->ev_free[k]) (void)hipEventDestroy(pl->ev_free[k]);
     if (pl->ev_marched[k]) (void)hipEventDestroy(pl->ev_marched[k]);
   }
-  if (pl->ms) (void)hipStreamDestroy(pl->ms);
-  if (pl->ss) (void)hipStreamDestroy(pl->ss);
-  pl->ms = pl->ss = nullptr;
+  pl->ms = pl->ss = nullptr;  // shared, not the plan's
   for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = pl->ev_marched[k] = nullptr;
 }
 
@@ -408,9 +443,8 @@ static void destroy_graphs(swkb_plan_s* pl) {
   pl->graphs.clear();
   if (pl->ev_g0) (void)hipEventDestroy(pl->ev_g0);
   if (pl->ev_g1) (void)hipEventDestroy(pl->ev_g1);
-  if (pl->cs) (void)hipStreamDestroy(pl->cs);
   pl->ev_g0 = pl->ev_g1 = nullptr;
-  pl->cs = nullptr;
+  pl->cs = nullptr;  // shared, not the plan's
 }
 
 // The same screens through a HIP graph: captured on the plan's capture
@@ -570,8 +604,10 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->ss = nullptr;
     for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = pl->ev_marched[k] = nullptr;
     if (pl->nslots == 2) {
-      bool ok = hipStreamCreateWithFlags(&pl->ms, hipStreamNonBlocking) == hipSuccess &&
-                hipStreamCreateWithFlags(&pl->ss, hipStreamNonBlocking) == hipSuccess;
+      SharedStreams ss;
+      bool ok = shared_streams(&ss) == hipSuccess;
+      pl->ms = ss.ms;
+      pl->ss = ss.ss;
       for (int k = 0; k < 2 && ok; ++k)
         ok = hipEventCreateWithFlags(&pl->ev_ready[k], hipEventDisableTiming) == hipSuccess &&
              hipEventCreateWithFlags(&pl->ev_free[k], hipEventDisableTiming) == hipSuccess &&
@@ -871,7 +907,9 @@ swkb_status swkb_diagnostics(swkb_plan_t pl, void* hip_stream, swkb_counters* ou
 swkb_status swkb_graphs(swkb_plan_t pl, int32_t enable) {
   if (!pl) return fail(SWKB_ERR_ARG, "plan is NULL");
   if (enable && !pl->cs) {
-    hipError_t e = hipStreamCreateWithFlags(&pl->cs, hipStreamNonBlocking);
+    SharedStreams ss;
+    hipError_t e = shared_streams(&ss);
+    pl->cs = ss.cs;
     if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_g0, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_g1, hipEventDisableTiming);
     if (e != hipSuccess) {

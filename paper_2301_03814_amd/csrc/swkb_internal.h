@@ -145,8 +145,8 @@ struct swkb_plan_s {
   };
   Slot slots[2];
   int nslots;
-  hipStream_t ms;                // march stream (default priority), or NULL
-  hipStream_t ss;                // scan stream (default priority), or NULL
+  hipStream_t ms;                // march stream (default priority, shared by the device's plans), or NULL
+  hipStream_t ss;                // scan stream (likewise), or NULL
   hipEvent_t ev_ready[2], ev_free[2], ev_marched[2];
   // screen ranges captured into HIP graphs (swkb_graphs)
   struct GraphEntry {
@@ -158,7 +158,7 @@ struct swkb_plan_s {
   };
   std::vector<GraphEntry> graphs;
   int graphs_on;
-  hipStream_t cs;                // capture and replay stream, or NULL
+  hipStream_t cs;                // capture and replay stream (shared by the device's plans), or NULL
   hipEvent_t ev_g0, ev_g1;
   // event timing
   int prof_on;
