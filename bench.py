@@ -519,6 +519,32 @@ def main():
         oracle.set_threads(threads)
         cpu["one_thread"] = {"value": M * N / t1c, "seconds": round(t1c, 2), "sample": "screen 0"}
         cpu["host"] = {"cpu_model": cpu_model(), "logical_cpus": os.cpu_count()}
+        # the small case in full (linear caustic: N_z = 512, 128 modes, 32
+        # screens): the oracle beside the GPU plans, and their agreement
+        c1 = W.linear_caustic()
+        u1 = W.incident_field(c1)
+        t0 = time.perf_counter()
+        ref1, cnt1 = oracle.run(c1, u1)
+        t_or = time.perf_counter() - t0
+        small = {"workload": "linear caustic: lambda=1, eps=1+0.02z, z in [0,64], N_z=512, 128 modes, 32 screens "
+                             "of 8, beam width 4 at z=16 tilted 10 degrees down",
+                 "oracle_seconds": round(t_or, 3), "oracle_threads": threads}
+        u1d = torch.from_numpy(u1).to(dev)
+        for name, prec in (("fp64", FP64), ("mixed", MIXED)):
+            pl1 = Plan(c1, precision=prec, device=dev)
+            pl1.propagate(u1d, 0, c1["n_screens"])
+            d0 = pl1.diagnostics()  # counters of the warm-up run (synchronises)
+            t0 = time.perf_counter()
+            h1 = pl1.propagate(u1d, 0, c1["n_screens"])
+            torch.cuda.synchronize()
+            dt1 = time.perf_counter() - t0
+            d1 = pl1.diagnostics()
+            same = all(d1[k] - d0[k] == cnt1[k] for k in ("caustic_rays", "dead_rays"))
+            small[name] = {"seconds": round(dt1, 5),
+                           "rel_l2_vs_oracle": float(np.linalg.norm(h1.cpu().numpy() - ref1) / np.linalg.norm(ref1)),
+                           "caustic_and_dead_rays_equal_oracle": bool(same)}
+            pl1.close()
+        cpu["small_case"] = small
 
     duct = None
     if not args.no_duct:
