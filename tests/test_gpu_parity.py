@@ -538,3 +538,36 @@ def test_swkb_accuracy_against_gpu_modal_reference(torch_dev, swkb):
     assert rel(hist, ref) < 4e-4
     assert errs[0] < 1e-5
     plan.close()
+
+
+def test_mixed_amplitude_near_turning_points(torch_dev, swkb):
+    """The mixed path integrates the ray tube (Z_s, Q_s) in FP32 and forms the
+    amplitude sqrt(p0 / (p Z_s)) in FP64.  On the linear caustic, rays whose
+    vertical slowness changes sign within the screen (they pass a turning
+    point) keep amplitudes within 1e-4 relative of the oracle's FP64 march."""
+    import oracle
+    torch, dev = torch_dev
+    cfg = CASES["linear_caustic_N512"]()
+    plan = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
+    q = 1
+    rays = {k: v.cpu().numpy() for k, v in plan.stage_rays(q).items()}
+    worst_turn, worst_all, n_turn = 0.0, 0.0, 0
+    for j in range(cfg["n_modes"]):
+        ref = oracle.march_mode(cfg, q, j)
+        live = (ref["flag"] == 0) & (rays["flag"][j] == 0)
+        if not live.any():
+            continue
+        err = np.abs(rays["a"][j][live] - ref["a"][live]) / np.abs(ref["a"][live])
+        worst_all = max(worst_all, float(err.max()))
+        # launched with q = xi_n; turned when the arrival slowness has the other sign
+        xi_n = 2.0 * math.pi * (j - cfg["n_modes"] // 2) / (cfg["k"] * (cfg["z_b"] - cfg["z_a"]))  # P h = L
+        turned = live & (ref["q"] * xi_n < 0.0)
+        if turned.any():
+            n_turn += int(turned.sum())
+            e = np.abs(rays["a"][j][turned] - ref["a"][turned]) / np.abs(ref["a"][turned])
+            worst_turn = max(worst_turn, float(e.max()))
+    say(f"[rays] mixed amplitude: {n_turn} turning rays, max rel err {worst_turn:.2e}; all live rays {worst_all:.2e}")
+    assert n_turn > 0
+    assert worst_turn <= 1e-4
+    assert worst_all <= 1e-4
+    plan.close()
