@@ -231,25 +231,48 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
       const T zr = iv.zr, c0 = iv.c0, c1 = iv.c1, c2 = iv.c2, c3 = iv.c3, q0 = iv.q0, q1 = iv.q1, q2 = iv.q2,
               q3 = iv.q3;
       const int mlo = iv.mlo, mhi = iv.mhi;  // owned points [m0 + mlo, m0 + mhi)
+      constexpr bool kF64 = std::is_same<T, double>::value;
       int nm = (nm0 + n * mlo) & pmask;
       // offset of point m above the interval's first ray; FP32 steps by h
       T tau;
-      if constexpr (std::is_same<T, double>::value) tau = 0.0;
+      if constexpr (kF64) tau = 0.0;
       else tau = (float)mlo * (float)g.h - zr;
-      const T hstep = std::is_same<T, double>::value ? T(0) : (T)g.h;
+      const T hstep = kF64 ? T(0) : (T)g.h;
+      // FP32: the phase in turns from the deviation's coefficients scaled to
+      // turns once per interval (range phase folded into the constant), and the
+      // grid phase (n m' mod P) / P carried as a float: multiples of 1/P below
+      // one and their sums are exact in FP32, so fract(gt + n/P) equals it at
+      // the next point
+      float gt = 0.0f, gstep = 0.0f, e0 = 0.0f, e1 = 0.0f, e2 = 0.0f, e3 = 0.0f;
+      if constexpr (!kF64) {
+        const float il = (float)inv_lam, invP = 1.0f / (float)g.P;
+        gt = (float)nm * invP;
+        gstep = (float)(n & pmask) * invP;
+        e0 = c0 * il + fj;
+        e1 = c1 * il;
+        e2 = c2 * il;
+        e3 = c3 * il;
+      }
       for (int m = mlo; m < mhi; ++m, tau += hstep) {
-        if constexpr (std::is_same<T, double>::value) tau = (double)m * g.h - zr;
-        const T dps = ((c3 * tau + c2) * tau + c1) * tau + c0;
-        const T a = ((q3 * tau + q2) * tau + q1) * tau + q0;
         T sn, cs;
-        phase_of<T>(nm, g, fj, fjd, dps, inv_lam, sn, cs);
+        if constexpr (kF64) {
+          tau = (double)m * g.h - zr;
+          const T dps = ((c3 * tau + c2) * tau + c1) * tau + c0;
+          phase_of<T>(nm, g, fj, fjd, dps, inv_lam, sn, cs);
+          nm = (nm + n) & pmask;
+        } else {
+          const float turns = __builtin_amdgcn_fractf(gt + (((e3 * tau + e2) * tau + e1) * tau + e0));
+          sn = __builtin_amdgcn_sinf(turns);  // argument in revolutions
+          cs = __builtin_amdgcn_cosf(turns);
+          gt = __builtin_amdgcn_fractf(gt + gstep);
+        }
+        const T a = ((q3 * tau + q2) * tau + q1) * tau + q0;
         const T ea = a * cs, eb = a * sn;  // a e^{i phase}
         if constexpr (TABLE) {
           typename CplxOf<T>::type v;
           v.x = ea;
           v.y = eb;
           tab[(size_t)j * g.N + m0 + m] = v;
-          nm = (nm + n) & pmask;
           continue;
         }
         const int pm = m + (m >> 3);
@@ -260,7 +283,6 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
           v.y = fma_t(cjr[bb], eb, fma_t(cji[bb], ea, v.y));
           acc[bb * row + pm] = v;
         }
-        nm = (nm + n) & pmask;
       }
     }
   }
