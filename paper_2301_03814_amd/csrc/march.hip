@@ -33,6 +33,7 @@ namespace {
 struct ModeC {
   double xi, omx2;  // xi, 1 - xi^2
   double pbar, e1r; // reference p and eps - 1 of the mode
+  double pb2;       // pbar^2 = 1 - xi^2 + e1r
 };
 
 template <typename T>
@@ -76,6 +77,8 @@ struct GenericMedium {
     ++c.med;
     return medium_eval<T>(md, x_q + k * hx2, s, dz, c.terms);
   }
+  __device__ static constexpr T hz_scale() { return T(1); }
+  __device__ static constexpr T hzz_scale() { return T(1); }
 };
 
 // Gaussian-sum medium from the per-screen tables (wavefront-uniform, read
@@ -133,6 +136,8 @@ struct GaussMedium {
     for (; i < nl; ++i) this->bump(z, czl[i], st[i], term[i], dn, nz, nzz, nterms);
     return from_index<T>(dn, nz, nzz);
   }
+  __device__ static constexpr T hz_scale() { return T(1); }
+  __device__ static constexpr T hzz_scale() { return T(1); }
 };
 
 // Gaussian-sum medium read from a per-screen table (mixed path).  At each
@@ -148,12 +153,17 @@ struct GaussMedium {
 // FP32 ulp of 5e-10 in eps - 1, 3e-7 relative in eps_z) and eps_zz, which
 // only enters the ray-tube amplitude, within 1e-4 relative.  Heights
 // outside the table fall back to the direct evaluation.
+//
+// eval returns hz = p' and hzz = p''/2 in node units; hz_scale() and
+// hzz_scale() take them to eps_z / 2 and eps_zz / 2, so that the scales
+// ride on products the right-hand side forms anyway.
 struct TableMedium {
   static constexpr bool kTableReads = true;
   const float4* __restrict__ ta;  // [(2S+1)][ni]
   unsigned ni;                    // intervals
   float inv_dz, half_inv_dz;      // 1/dz_t, 1/(2 dz_t)
   float inv_dz2;                  // 1/dz_t^2
+  float two_dz, dz_sq;            // 2 dz_t, dz_t^2 (direct values into node units)
   int j0;      // node at or below the wavefront's reference height z_w
   float tl;    // this lane's launch height above node j0, in node spacings
   GaussMedium<float> direct;
@@ -165,7 +175,12 @@ struct TableMedium {
     asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(ti) : "v"(t));
     // unsigned wrap sends heights below the table (and saturated conversions) out of range too
     const unsigned iv = (unsigned)j0 + (unsigned)ti;
-    if (!(iv < ni)) return direct.eval(k, dz, c);
+    if (!(iv < ni)) {
+      Med<float> m = direct.eval(k, dz, c);
+      m.hz *= two_dz;
+      m.hzz *= dz_sq;
+      return m;
+    }
     const float u = __builtin_amdgcn_fractf(t);
     const size_t o = (size_t)k * ni + iv;
     const float4 a = ta[o];
@@ -178,10 +193,12 @@ struct TableMedium {
     p = p * u + a.x;
     Med<float> m;
     m.e1 = p;
-    m.hz = d1 * half_inv_dz;
-    m.hzz = d2 * inv_dz2;
+    m.hz = d1;
+    m.hzz = d2;
     return m;
   }
+  __device__ float hz_scale() const { return half_inv_dz; }
+  __device__ float hzz_scale() const { return inv_dz2; }
 };
 
 // Right-hand side at stage k, the n-th evaluation of its RK4 step.
@@ -194,25 +211,26 @@ __device__ inline bool rhs(const MED& med, const ModeC& mc, int k, int n, T dz, 
                           Deriv<T>& d, Work& c, int& st) {
   const Med<T> m = med.eval(k, dz, c);
   const T xi = (T)mc.xi;
-  const T q = xi + dq;
-  const T s2 = T(2) * xi + dq;  // q + xi
-  const T p2 = (T)mc.omx2 + m.e1 - dq * s2;
+  const T w = dq * (T(2) * xi + dq);          // q^2 - xi^2
+  const T num = (m.e1 - (T)mc.e1r) - w;       // p^2 - pbar^2, in small quantities
+  const T p2 = num + (T)mc.pb2;
   const bool ok = (Zs > T(0)) & (p2 > p2_floor);
   if (__builtin_expect(!ok, 0)) {
     st = (Zs > T(0) ? kDead : kCaustic) + 4 * n;
     return false;
   }
   const T ip = fast_rsqrt<T>(p2);
-  const T p = p2 * ip;
+  const T q = xi + dq;
   d.dz = q * ip;
-  d.dq = m.hz * ip;
-  d.dps = ((m.e1 - (T)mc.e1r) - dq * s2) * fast_rcp<T>(p + (T)mc.pbar) + q * dq * ip;
+  d.dps = num * fast_rcp<T>(p2 * ip + (T)mc.pbar) + dq * d.dz;
+  d.dq = m.hz * (med.hz_scale() * ip);        // (eps_z/2) / p
   // ray-tube variations:
   //   Z_s' = (eps Q_s - q (eps_z/2) Z_s) / p^3,
-  //   Q_s' = (eps_zz/2) Z_s / p + (eps_z/2) (q Q_s - (eps_z/2) Z_s) / p^3
-  const T ip3 = ip * ip * ip;
-  d.Zs = ip3 * ((Qs + m.e1 * Qs) - (q * m.hz) * Zs);
-  d.Qs = (m.hzz * ip) * Zs + ip3 * (m.hz * (q * Qs - m.hz * Zs));
+  //   Q_s' = ((eps_zz/2) - (eps_z/2)^2 / p^2) Z_s / p + q (eps_z/2) Q_s / p^3
+  const T ip2 = ip * ip, ip3 = ip2 * ip;
+  const T qa = q * (ip2 * d.dq);              // q (eps_z/2) / p^3
+  d.Zs = (ip3 + ip3 * m.e1) * Qs - qa * Zs;
+  d.Qs = (m.hzz * med.hzz_scale() - d.dq * d.dq) * ip * Zs + qa * Qs;
   return true;
 }
 
@@ -319,6 +337,7 @@ __device__ inline ModeC load_mode(const DevModes& modes, int j) {
   mc.omx2 = 1.0 - mc.xi * mc.xi;
   mc.pbar = modes.pbar[j];
   mc.e1r = modes.e1r[j];
+  mc.pb2 = mc.omx2 + mc.e1r;
   return mc;
 }
 
@@ -456,6 +475,8 @@ __global__ void __launch_bounds__(256) march_table_kernel(Geometry g, GaussTabs<
   med.inv_dz = (float)(1.0 / mt.dz);
   med.half_inv_dz = (float)(0.5 / mt.dz);
   med.inv_dz2 = (float)(1.0 / (mt.dz * mt.dz));
+  med.two_dz = (float)(2.0 * mt.dz);
+  med.dz_sq = (float)(mt.dz * mt.dz);
   const double rel = (g.z_a + (double)(w * 64 * g.rho - g.E) * g.h) - mt.z_lo;  // z_w above the table's base
   med.j0 = (int)floor(rel / mt.dz);
   med.tl = (float)((rel - (double)med.j0 * mt.dz + (double)(lane * g.rho) * g.h) / mt.dz);
