@@ -137,7 +137,7 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, part, tmat, counters;
+  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, cpol, part, tmat, counters;
   // one ray-record slot (offsets from its start); nslots of them from slot0
   size_t mtab, D, Pp, G, A, cz, cidx, tstart, mflag, mcaus, mdead, mwork, wcount;
   size_t slot0, slot_bytes;
@@ -206,6 +206,7 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.Y = take(sizeof(double2) * g.P * B);
   L.c = take(sizeof(double2) * g.M * B);
   L.cf = take(B > 1 && use_matrix(p) && p->precision == SWKB_MIXED ? sizeof(float2) * g.M * B : 0);
+  L.cpol = take(p->precision == SWKB_MIXED ? sizeof(float2) * g.M : 0);
   L.part = take(sizeof(double2) * (size_t)g.N * partial_groups(g) * B);
   L.tmat = take(use_matrix(p) ? matrix_bytes(p) : 0);
   L.counters = take(sizeof(unsigned long long) * 32);
@@ -567,6 +568,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->u = reinterpret_cast<double2*>(ws + L.u);
     pl->ub = reinterpret_cast<double2*>(ws + L.ub);
     pl->cf = reinterpret_cast<float2*>(ws + L.cf);
+    pl->cpol = p->precision == SWKB_MIXED ? reinterpret_cast<float2*>(ws + L.cpol) : nullptr;
     pl->max_batch = p->max_batch;
     pl->blas = nullptr;
     pl->Y = reinterpret_cast<double2*>(ws + L.Y);

@@ -79,9 +79,12 @@ __device__ inline void fft_cols_body(const double2* __restrict__ u, double2* __r
 }
 
 // Row pass of one field: workgroup bx of P1 / RB; writes the M kept bins.
+// With cp set (one field), each kept bin is also written in polar form for
+// the FP32 interval sum: modulus, and argument in turns in [0, 1), both
+// rounded once from FP64.
 __device__ inline void fft_rows_body(const double2* __restrict__ Y, double2* __restrict__ c,
                                      const double2* __restrict__ tw, int P, int P1, int P2, int logP2, int RB,
-                                     int M, int bx, double2* L) {
+                                     int M, int bx, double2* L, float2* __restrict__ cp = nullptr) {
   double2* wl = L + RB * P2;
   const int r0 = bx * RB;
   for (int k = threadIdx.x; k < P2 / 2; k += blockDim.x) wl[k] = tw[k * (P / P2)];
@@ -101,7 +104,13 @@ __device__ inline void fft_rows_body(const double2* __restrict__ Y, double2* __r
     else if (n >= P - halfM) j = n - P + halfM;
     if (j >= 0) {
       const double2 x = L[rr * P2 + n2];
-      c[j] = make_double2(x.x * inv, x.y * inv);
+      const double cr = x.x * inv, ci = x.y * inv;
+      c[j] = make_double2(cr, ci);
+      if (cp) {
+        double t = atan2(ci, cr) * (0.5 / M_PI);
+        t -= floor(t);
+        cp[j] = make_float2((float)sqrt(cr * cr + ci * ci), (float)t);
+      }
     }
   }
 }
@@ -116,10 +125,10 @@ __global__ void __launch_bounds__(256) fft_cols(const double2* __restrict__ u, d
 
 __global__ void __launch_bounds__(256) fft_rows(const double2* __restrict__ Y, double2* __restrict__ c,
                                                 const double2* __restrict__ tw, int P, int P1, int P2,
-                                                int logP2, int RB, int M) {
+                                                int logP2, int RB, int M, float2* __restrict__ cp) {
   extern __shared__ double2 L[];
   fft_rows_body(Y + (size_t)blockIdx.y * P, c + (size_t)blockIdx.y * M, tw, P, P1, P2, logP2, RB, M, blockIdx.x,
-                L);
+                L, cp);
 }
 
 // The two passes for many problems in one launch each: workgroup b runs
@@ -174,7 +183,7 @@ hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, int batch, 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fft_rows, dim3(g.P1 / RB, batch), dim3(256), sizeof(double2) * (RB * g.P2 + g.P2 / 2), st,
                      pl.Y, pl.c, pl.tw,
-                     g.P, g.P1, g.P2, ilog2(g.P2), RB, g.M);
+                     g.P, g.P1, g.P2, ilog2(g.P2), RB, g.M, batch == 1 ? pl.cpol : nullptr);
   return hipGetLastError();
 }
 

@@ -70,7 +70,11 @@ struct IvRec {
 
 // Lane l of a pass holds ray rl = a0 - 1 + l (values dl, al, pl, gl, first
 // point cl); the neighbours come through shuffles, so lanes 1..61 can own
-// intervals [a0, a1].
+// intervals [a0, a1].  Every lane evaluates the same straight-line
+// formulas and a lane without a live interval gets an empty point range; a
+// value of a ray outside [0, R) enters only terms that are then not selected
+// (the ownership and cubic tests check the indices), so such lanes may hold
+// any ray's data.
 template <typename T>
 __device__ inline IvRec<T> build_interval(const Geometry& g, int rl, int a0, int a1, int m0, int npts, double zs0,
                                           T dl, T al, T pl, T gl, int cl) {
@@ -80,9 +84,6 @@ __device__ inline IvRec<T> build_interval(const Geometry& g, int rl, int a0, int
   const T pp1 = wave_shfl(pl, lane + 1), gp1 = wave_shfl(gl, lane + 1);
   const int cp1 = __shfl(cl, lane + 1, 64);
   IvRec<T> r;
-  r.mlo = r.mhi = 0;
-  r.zr = r.c0 = r.c1 = r.c2 = r.c3 = r.q0 = r.q1 = r.q2 = r.q3 = T(0);
-  if (!(rl >= a0 && rl <= a1 && al > T(0) && ap1 > T(0))) return r;
   T H, xm, x3;
   if constexpr (std::is_same<T, double>::value) {
     const double Zl = (g.z_a + (double)(rl * g.rho - g.E) * g.h) + dl;
@@ -99,7 +100,7 @@ __device__ inline IvRec<T> build_interval(const Geometry& g, int rl, int a0, int
     xm = -rh + (dm1 - dl);
     x3 = T(2) * rh + (dp2 - dl);
   }
-  if (!(H > T(0))) return r;
+  const bool own = rl >= a0 && rl <= a1 && al > T(0) && ap1 > T(0) && H > T(0);
   const T iH = rcp_t<T>(H);
   const T dlt = (pp1 - pl) * iH;
   r.c0 = pl;
@@ -108,22 +109,18 @@ __device__ inline IvRec<T> build_interval(const Geometry& g, int rl, int a0, int
   r.c3 = (gl + gp1 - T(2) * dlt) * iH * iH;
   const bool cubic = rl >= 1 && rl + 2 < g.R && am1 > T(0) && ap2 > T(0);
   const T f01 = (ap1 - al) * iH;
+  // Newton form on nodes 0, H, xm (ray r-1), x3 (ray r+2), then powers of tau
+  const T f12 = (am1 - ap1) * rcp_t<T>(xm - H);
+  const T f23 = (ap2 - am1) * rcp_t<T>(x3 - xm);
+  const T f012 = (f12 - f01) * rcp_t<T>(xm);
+  const T f123 = (f23 - f12) * rcp_t<T>(x3 - H);
+  const T f0123 = (f123 - f012) * rcp_t<T>(x3);
   r.q0 = al;
-  if (cubic) {
-    // Newton form on nodes 0, H, xm (ray r-1), x3 (ray r+2), then powers of tau
-    const T f12 = (am1 - ap1) * rcp_t<T>(xm - H);
-    const T f23 = (ap2 - am1) * rcp_t<T>(x3 - xm);
-    const T f012 = (f12 - f01) * rcp_t<T>(xm);
-    const T f123 = (f23 - f12) * rcp_t<T>(x3 - H);
-    const T f0123 = (f123 - f012) * rcp_t<T>(x3);
-    r.q1 = f01 - H * f012 + H * xm * f0123;
-    r.q2 = f012 - (H + xm) * f0123;
-    r.q3 = f0123;
-  } else {
-    r.q1 = f01;
-  }
-  r.mlo = cl - m0 > 0 ? cl - m0 : 0;
-  r.mhi = cp1 - m0 < npts ? cp1 - m0 : npts;
+  r.q1 = cubic ? f01 - H * f012 + H * xm * f0123 : f01;
+  r.q2 = cubic ? f012 - (H + xm) * f0123 : T(0);
+  r.q3 = cubic ? f0123 : T(0);
+  r.mlo = own ? (cl - m0 > 0 ? cl - m0 : 0) : 0;
+  r.mhi = own ? (cp1 - m0 < npts ? cp1 - m0 : npts) : 0;
   return r;
 }
 
@@ -166,12 +163,18 @@ __device__ inline void phase_of(int nm, const Geometry& g, T fj, double fjd, T d
 // TABLE = true: write the mode functions T[j][m] = a e^{2 pi i turns} of an
 // x-invariant medium instead (entries without an owning interval must be
 // zero beforehand); c, part and the accumulators are not used.
+//
+// One FP32 field (POLAR): the mode's coefficient comes in polar form, its
+// argument joins the phase constant and its modulus the amplitude
+// polynomial, so a point adds |c| a (cos, sin) with two FMAs.
 template <typename T, int NB, bool TABLE>
 __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, DevModes modes, DevRecords rec,
                                                                    const double2* __restrict__ c,
+                                                                   const float2* __restrict__ cpol,
                                                                    double2* __restrict__ part,
                                                                    typename CplxOf<T>::type* __restrict__ tab, Epi ep,
                                                                    int sub, int batch) {
+  constexpr bool POLAR = std::is_same<T, float>::value && NB == 1 && !TABLE;
   extern __shared__ double2 lds_raw[];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -211,25 +214,34 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
     const int n = j - (g.M >> 1);
     const int nm0 = (n * mp0) & pmask;
     T cjr[NB], cji[NB];
-    for (int bb = 0; bb < NB; ++bb) {
-      const double2 v = bb < nb ? c[(size_t)(b0 + bb) * g.M + j] : make_double2(0.0, 0.0);
-      cjr[bb] = (T)v.x;
-      cji[bb] = (T)v.y;
-    }
+    float cmod = 0.0f, carg = 0.0f;  // POLAR: |c|, arg c in turns plus the range phase
     const T fj = (T)modes.frac[j];
     const double fjd = modes.frac[j];
+    if constexpr (POLAR) {
+      const float2 pc = cpol[j];
+      cmod = pc.x;
+      carg = pc.y + fj;
+    } else {
+      for (int bb = 0; bb < NB; ++bb) {
+        const double2 v = bb < nb ? c[(size_t)(b0 + bb) * g.M + j] : make_double2(0.0, 0.0);
+        cjr[bb] = (T)v.x;
+        cji[bb] = (T)v.y;
+      }
+    }
     for (int a0 = ia; a0 <= ib; a0 += 61) {
       const int a1 = a0 + 60 < ib ? a0 + 60 : ib;  // intervals [a0, a1] in this pass
       const int rl = a0 - 1 + lane;                 // ray held by this lane
-      const bool in = rl >= 0 && rl < g.R;
-      const T dl = in ? D[base + rl] : T(0);
-      const T al = in ? A[base + rl] : T(-1);
-      const T pl = in ? Pp[base + rl] : T(0);
-      const T gl = in ? G[base + rl] : T(0);
-      const int cl = in ? rec.cidx[base + rl] : 0;
+      const int rc = rl < 0 ? 0 : (rl < g.R ? rl : g.R - 1);
+      const T dl = D[base + rc], al = A[base + rc], pl = Pp[base + rc], gl = G[base + rc];
+      const int cl = rec.cidx[base + rc];
       const IvRec<T> iv = build_interval<T>(g, rl, a0, a1, m0, npts, zs0, dl, al, pl, gl, cl);
-      const T zr = iv.zr, c0 = iv.c0, c1 = iv.c1, c2 = iv.c2, c3 = iv.c3, q0 = iv.q0, q1 = iv.q1, q2 = iv.q2,
-              q3 = iv.q3;
+      T zr = iv.zr, c0 = iv.c0, c1 = iv.c1, c2 = iv.c2, c3 = iv.c3, q0 = iv.q0, q1 = iv.q1, q2 = iv.q2, q3 = iv.q3;
+      if constexpr (POLAR) {
+        q0 *= cmod;
+        q1 *= cmod;
+        q2 *= cmod;
+        q3 *= cmod;
+      }
       const int mlo = iv.mlo, mhi = iv.mhi;  // owned points [m0 + mlo, m0 + mhi)
       constexpr bool kF64 = std::is_same<T, double>::value;
       int nm = (nm0 + n * mlo) & pmask;
@@ -248,7 +260,7 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
         const float il = (float)inv_lam, invP = 1.0f / (float)g.P;
         gt = (float)nm * invP;
         gstep = (float)(n & pmask) * invP;
-        e0 = c0 * il + fj;
+        e0 = c0 * il + (POLAR ? carg : fj);
         e1 = c1 * il;
         e2 = c2 * il;
         e3 = c3 * il;
@@ -276,6 +288,13 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
           continue;
         }
         const int pm = m + (m >> 3);
+        if constexpr (POLAR) {
+          C2 v = acc[pm];
+          v.x = fma_t(a, cs, v.x);
+          v.y = fma_t(a, sn, v.y);
+          acc[pm] = v;
+          continue;
+        }
         for (int bb = 0; bb < NB; ++bb) {
           // lanes of one step own different points; LDS keeps the wavefront's accesses in order
           C2 v = acc[bb * row + pm];
@@ -734,11 +753,12 @@ template <typename T, int NB, int SUBMAX>
 static void launch_sum(const swkb_plan_s& pl, const dim3& grid, const DevModes& md, const Epi& ep, int sub, int batch,
                        hipStream_t st) {
   if constexpr (std::is_same<T, float>::value && NB == 1) {
+    if (!pl.cpol) return;  // reported by launch_superpose
     const int row = sub * 64 + sub * 8;
     const size_t shmem = sizeof(T) * (size_t)kWaves * 2 * NB * row;
     hipLaunchKernelGGL((superpose_iv_kernel<T, NB, false>), dim3(grid.x, grid.y, 1), dim3(64 * kWaves), shmem, st,
-                       pl.g, md, pl.rec, pl.c, pl.part, static_cast<typename CplxOf<T>::type*>(nullptr), ep, sub,
-                       batch);
+                       pl.g, md, pl.rec, pl.c, pl.cpol, pl.part, static_cast<typename CplxOf<T>::type*>(nullptr), ep,
+                       sub, batch);
     return;
   }
   struct alignas(16) LRec {
@@ -763,6 +783,8 @@ Epi epi_of(const swkb_plan_s& pl) {
 hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st) {
   const Geometry& g = pl.g;
   const Epi ep = epi_of(pl);
+  // the one-field FP32 sum reads the modes in polar form
+  if (pl.precision != SWKB_FP64 && batch == 1 && !pl.cpol) return hipErrorInvalidValue;
   // batches keep the accumulators of NB fields in LDS: 256-point super-tiles
   int sub = iv_sub(g, pl.precision);
   if (batch > 1 && sub > 4) sub = 4;
@@ -796,10 +818,10 @@ hipError_t launch_build_matrix(const swkb_plan_s& pl, hipStream_t st) {
   if (e != hipSuccess) return e;
   if (pl.precision == SWKB_FP64)
     hipLaunchKernelGGL((superpose_iv_kernel<double, 1, true>), grid, dim3(64 * kWaves), 0, st, g, md, pl.rec, pl.c,
-                       pl.part, static_cast<double2*>(pl.tmat), ep, sub, 1);
+                       nullptr, pl.part, static_cast<double2*>(pl.tmat), ep, sub, 1);
   else
     hipLaunchKernelGGL((superpose_iv_kernel<float, 1, true>), grid, dim3(64 * kWaves), 0, st, g, md, pl.rec, pl.c,
-                       pl.part, static_cast<float2*>(pl.tmat), ep, sub, 1);
+                       nullptr, pl.part, static_cast<float2*>(pl.tmat), ep, sub, 1);
   return hipGetLastError();
 }
 

@@ -121,6 +121,8 @@ struct swkb_plan_s {
   double2 *Y, *c;                // FFT scratch [B][P], modes [B][M]
   double2* part;                 // superposition partials [B][mode groups][N]
   float2* cf;                    // modes as complex64 [B][M] (FP32 matrix product)
+  float2* cpol;                  // one field's modes in polar form [M]: |c|, frac(arg c / (2 pi))
+                                 // (FP32 interval sum; mixed-precision plans only)
   int max_batch;
   void* blas;                    // rocBLAS handle for batched matrix products (created on first use)
   int use_matrix;                // mode functions tabulated once (x-invariant medium)
