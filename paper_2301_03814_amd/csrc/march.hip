@@ -52,6 +52,13 @@ struct Work {
   int rhs = 0, med = 0, terms = 0, tab = 0;
 };
 
+// Wavefront-uniform constants of a march, computed once on the host.
+struct MarchK {
+  double hx, h6;   // RK4 step dx / S and hx / 6
+  double inv_h;    // 1 / h
+  double inv_dzt;  // 1 / dz_t of the medium table (table march only)
+};
+
 template <typename T>
 __device__ inline T fast_rsqrt(T x);
 template <>
@@ -249,8 +256,8 @@ __device__ inline int first_point_at_or_above(const Geometry& g, double key, dou
 // One wavefront lane per ray: RK4 across the screen.  Writes the arrival
 // record and returns the lane's status and work counts.
 template <typename T, typename MED>
-__device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry& g, bool active, size_t o,
-                                 double s_launch, DevRecords& rec, int& st, Work& c) {
+__device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry& g, const MarchK& mk, bool active,
+                                 size_t o, double s_launch, DevRecords& rec, int& st, Work& c) {
   T dz = T(0), dq = T(0), dps = T(0);
   T Zs = T(1), Qs = T(0);
   double amp = 0.0;
@@ -262,11 +269,10 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
   if (!(p02 > (T)g.p2_floor)) {
     st = kDeadLaunch;
   } else {
-    const double p0 = (double)sqrt(p02);
-    const double hx = g.dx / g.S;
-    const T hh = (T)(0.5 * hx), hf = (T)hx, h6 = (T)(hx / 6.0);
+    const T p0 = sqrt(p02);
+    const T hh = (T)(0.5 * mk.hx), hf = (T)mk.hx, h6 = (T)mk.h6;
     const T pfl = (T)g.p2_floor;
-    const T hd2 = (T)(0.5 * hx), hd6 = (T)(hx / 6.0);
+    const T hd2 = hh, hd6 = h6;
     Deriv<T> k1, k2, k3, k4;
     for (int i = 0; i < g.S; ++i) {
       if (!rhs<T>(med, mc, 2 * i, 1, dz, dq, Zs, Qs, pfl, k1, c, st)) break;
@@ -298,7 +304,7 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
         const T xi = (T)mc.xi;
         const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
         if (!(p2 > (T)g.p2_floor)) st = kDead;
-        else amp = sqrt(p0 / ((double)sqrt(p2) * (double)Zs));
+        else amp = (double)sqrt(p0 / (sqrt(p2) * Zs));  // in T, like the march
       }
     }
   }
@@ -308,17 +314,34 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
   static_cast<T*>(rec.G)[o] = dq;
   static_cast<T*>(rec.A)[o] = st == kLive ? (T)amp : (T)(-st);
   // first grid point at or above the arrival (the scan's running maximum of these gives the brackets)
-  rec.cz[o] = st == kLive ? first_point_at_or_above(g, s_launch + (double)dz, 1.0 / g.h) : 0;
+  rec.cz[o] = st == kLive ? first_point_at_or_above(g, s_launch + (double)dz, mk.inv_h) : 0;
 }
 
-__device__ inline void wave_counts(int* __restrict__ wcount, size_t slot, int lane, bool active, int st, Work c) {
+// Wavefront sums of the lanes' work counts.  With S <= 250 a lane makes at
+// most 4 S + 2 < 1024 evaluations, so the RK4 and table counts of 64 lanes
+// fit 16 bits each and share one reduction; the direct-evaluation counts are
+// reduced only when some lane has any.
+__device__ inline void wave_counts(int* __restrict__ wcount, size_t slot, int lane, bool active, int st, Work c,
+                                   int S) {
   const unsigned long long bc = __ballot(active && st == kCaustic);
   const unsigned long long bd = __ballot(active && (st == kDead || st == kDeadLaunch));
-  for (int off = 32; off > 0; off >>= 1) {
-    c.rhs += __shfl_xor(c.rhs, off);
-    c.med += __shfl_xor(c.med, off);
-    c.terms += __shfl_xor(c.terms, off);
-    c.tab += __shfl_xor(c.tab, off);
+  if (S <= 250) {
+    // sums at most 64 (4 S + 2) = 64128 < 2^16 per field, so the word stays below 2^32
+    unsigned rt = (unsigned)c.rhs | ((unsigned)c.tab << 16);
+    for (int off = 32; off > 0; off >>= 1) rt += __shfl_xor(rt, off);
+    c.rhs = (int)(rt & 0xffffu);
+    c.tab = (int)(rt >> 16);
+  } else {
+    for (int off = 32; off > 0; off >>= 1) {
+      c.rhs += __shfl_xor(c.rhs, off);
+      c.tab += __shfl_xor(c.tab, off);
+    }
+  }
+  if (__ballot(c.med != 0 || c.terms != 0)) {
+    for (int off = 32; off > 0; off >>= 1) {
+      c.med += __shfl_xor(c.med, off);
+      c.terms += __shfl_xor(c.terms, off);
+    }
   }
   if (lane == 0) {
     int* wc = wcount + kWaveCounts * slot;
@@ -344,8 +367,9 @@ __device__ inline ModeC load_mode(const DevModes& modes, int j) {
 // Any medium kind, ground mirror allowed.  Wavefront w of the grid marches
 // rays w_in_mode * 64 + lane of mode j.
 template <typename T>
-__global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, DevModes modes, DevRecords rec,
-                                                    int* __restrict__ wcount, double x_q, int waves_per_mode) {
+__global__ void __launch_bounds__(256) march_kernel(Geometry g, MarchK mk, DevMedium md, DevModes modes,
+                                                    DevRecords rec, int* __restrict__ wcount, double x_q,
+                                                    int waves_per_mode) {
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   const int j = wave / waves_per_mode;
@@ -357,12 +381,12 @@ __global__ void __launch_bounds__(256) march_kernel(Geometry g, DevMedium md, De
   GenericMedium<T> med;
   med.md = md;
   med.x_q = x_q;
-  med.hx2 = 0.5 * g.dx / g.S;
+  med.hx2 = 0.5 * mk.hx;
   med.s = g.z_a + (double)(r * g.rho - g.E) * g.h;
   int st;
   Work c;
-  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec, st, c);
-  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
+  march_ray<T>(med, mc, g, mk, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec, st, c);
+  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c, g.S);
 }
 
 // Per-screen Gaussian tables in device memory.
@@ -378,8 +402,8 @@ struct GaussTabs {
 // wavefront's first launch height z_w, so FP32 never carries an absolute
 // coordinate; all table reads are wavefront-uniform.
 template <typename T>
-__global__ void __launch_bounds__(256) march_gauss_kernel(Geometry g, GaussTabs<T> tabs, DevModes modes,
-                                                          DevRecords rec, int* __restrict__ wcount,
+__global__ void __launch_bounds__(256) march_gauss_kernel(Geometry g, MarchK mk, GaussTabs<T> tabs,
+                                                          DevModes modes, DevRecords rec, int* __restrict__ wcount,
                                                           int waves_per_mode) {
   const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int lane = threadIdx.x & 63;
@@ -397,8 +421,8 @@ __global__ void __launch_bounds__(256) march_gauss_kernel(Geometry g, GaussTabs<
   med.zl0 = (T)((double)(lane * g.rho) * g.h);
   int st;
   Work c;
-  march_ray<T>(med, mc, g, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec, st, c);
-  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
+  march_ray<T>(med, mc, g, mk, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec, st, c);
+  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c, g.S);
 }
 
 // Per-screen medium table of the mixed Gaussian-sum march.  Node values at
@@ -457,9 +481,9 @@ __global__ void __launch_bounds__(kTabNodes) medium_table_kernel(const double* _
 // SIMD (the compiler then keeps to 64 VGPRs and fewer SGPRs; at its own
 // choice, 106 SGPRs, the SGPR file allowed 7): random medium N = 8192,
 // 109.5 -> 106.2 us per screen.
-__global__ void __launch_bounds__(256, 8) march_table_kernel(Geometry g, GaussTabs<float> tabs, MedTab mt,
-                                                          DevModes modes, DevRecords rec, int* __restrict__ wcount,
-                                                          int waves_per_mode) {
+__global__ void __launch_bounds__(256, 8) march_table_kernel(Geometry g, MarchK mk, GaussTabs<float> tabs,
+                                                             MedTab mt, DevModes modes, DevRecords rec,
+                                                             int* __restrict__ wcount, int waves_per_mode) {
   const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int lane = threadIdx.x & 63;
   const int j = wave / waves_per_mode;
@@ -482,13 +506,13 @@ __global__ void __launch_bounds__(256, 8) march_table_kernel(Geometry g, GaussTa
   med.two_dz = (float)(2.0 * mt.dz);
   med.dz_sq = (float)(mt.dz * mt.dz);
   const double rel = (g.z_a + (double)(w * 64 * g.rho - g.E) * g.h) - mt.z_lo;  // z_w above the table's base
-  med.j0 = (int)floor(rel / mt.dz);
-  med.tl = (float)((rel - (double)med.j0 * mt.dz + (double)(lane * g.rho) * g.h) / mt.dz);
+  med.j0 = (int)floor(rel * mk.inv_dzt);
+  med.tl = (float)((rel - (double)med.j0 * mt.dz + (double)(lane * g.rho) * g.h) * mk.inv_dzt);
   int st;
   Work c;
-  march_ray<float>(med, mc, g, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec, st,
-                   c);
-  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c);
+  march_ray<float>(med, mc, g, mk, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec,
+                   st, c);
+  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c, g.S);
 }
 
 // One workgroup per mode: running maximum of live arrival heights (search
@@ -693,6 +717,11 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
   const dim3 grid((unsigned)((waves + 3) / 4));
   const double x_q = pl.p.x0 + q * pl.p.dx;
   int* wcount = pl.wcount;
+  MarchK mk;
+  mk.hx = g.dx / g.S;
+  mk.h6 = mk.hx / 6.0;
+  mk.inv_h = 1.0 / g.h;
+  mk.inv_dzt = pl.mtab.tab ? 1.0 / pl.mtab.dz : 0.0;
   if (pl.gfast) {
     const int nl = pl.goff[q + 1] - pl.goff[q];
     const size_t off = (size_t)pl.goff[q];
@@ -701,30 +730,30 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
       GaussTabs<double> t{reinterpret_cast<const T2<double>*>(pl.gstage) + off * nst,
                           reinterpret_cast<const T2<double>*>(pl.gterm) + off,
                           static_cast<const double*>(pl.gczl) + off * wpm, nl};
-      hipLaunchKernelGGL(march_gauss_kernel<double>, grid, dim3(256), 0, st, g, t, modes_of(pl), pl.rec, wcount,
-                         wpm);
+      hipLaunchKernelGGL(march_gauss_kernel<double>, grid, dim3(256), 0, st, g, mk, t, modes_of(pl), pl.rec,
+                         wcount, wpm);
     } else if (pl.mtab.tab) {
       GaussTabs<float> t{reinterpret_cast<const T2<float>*>(pl.gstage) + off * nst,
                          reinterpret_cast<const T2<float>*>(pl.gterm) + off,
                          static_cast<const float*>(pl.gczl) + off * wpm, nl};
       // reads the table launch_medium_table built for screen q
-      hipLaunchKernelGGL(march_table_kernel, grid, dim3(256), 0, st, g, t, pl.mtab, modes_of(pl), pl.rec, wcount,
-                         wpm);
+      hipLaunchKernelGGL(march_table_kernel, grid, dim3(256), 0, st, g, mk, t, pl.mtab, modes_of(pl), pl.rec,
+                         wcount, wpm);
     } else {
       GaussTabs<float> t{reinterpret_cast<const T2<float>*>(pl.gstage) + off * nst,
                          reinterpret_cast<const T2<float>*>(pl.gterm) + off,
                          static_cast<const float*>(pl.gczl) + off * wpm, nl};
-      hipLaunchKernelGGL(march_gauss_kernel<float>, grid, dim3(256), 0, st, g, t, modes_of(pl), pl.rec, wcount,
-                         wpm);
+      hipLaunchKernelGGL(march_gauss_kernel<float>, grid, dim3(256), 0, st, g, mk, t, modes_of(pl), pl.rec,
+                         wcount, wpm);
     }
     return hipGetLastError();
   }
   if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL(march_kernel<double>, grid, dim3(256), 0, st, g, medium_for(pl, q), modes_of(pl), pl.rec,
-                       wcount, x_q, wpm);
+    hipLaunchKernelGGL(march_kernel<double>, grid, dim3(256), 0, st, g, mk, medium_for(pl, q), modes_of(pl),
+                       pl.rec, wcount, x_q, wpm);
   else
-    hipLaunchKernelGGL(march_kernel<float>, grid, dim3(256), 0, st, g, medium_for(pl, q), modes_of(pl), pl.rec,
-                       wcount, x_q, wpm);
+    hipLaunchKernelGGL(march_kernel<float>, grid, dim3(256), 0, st, g, mk, medium_for(pl, q), modes_of(pl),
+                       pl.rec, wcount, x_q, wpm);
   return hipGetLastError();
 }
 
