@@ -18,8 +18,8 @@
 // FP64 number per mode, and only the small deviation dpsi is marched:
 //   d dpsi/dx = ((eps - eps_ref_n) - (q - xi)(q + xi)) / (p + pbar) + q (q - xi) / p
 // (= eps/p - xi q/p - pbar, written in small quantities).  State per ray:
-// dz = z - s, dq = q - xi, dpsi, Zs, Qs in T (FP32 in the mixed path); the
-// amplitude on arrival in FP64.
+// dz = z - s, dq = q - xi, dpsi, Zs, Qs and the amplitude on arrival in T
+// (FP32 in the mixed path).
 //
 // Ray r of mode n starts at s_r = z_a + (r rho - E) h with q = xi_n
 // (Sec. 2.1.2 initial conditions), Zs = 1, Qs = 0.  A ray is dead when

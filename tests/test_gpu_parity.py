@@ -541,8 +541,8 @@ def test_swkb_accuracy_against_gpu_modal_reference(torch_dev, swkb):
 
 
 def test_mixed_amplitude_near_turning_points(torch_dev, swkb):
-    """The mixed path integrates the ray tube (Z_s, Q_s) in FP32 and forms the
-    amplitude sqrt(p0 / (p Z_s)) in FP64.  On the linear caustic, rays whose
+    """The mixed path integrates the ray tube (Z_s, Q_s) and forms the
+    amplitude sqrt(p0 / (p Z_s)) in FP32.  On the linear caustic, rays whose
     vertical slowness changes sign within the screen (they pass a turning
     point) keep amplitudes within 1e-4 relative of the oracle's FP64 march."""
     import oracle
