@@ -56,7 +56,8 @@ struct Work {
 struct MarchK {
   double hx, h6;   // RK4 step dx / S and hx / 6
   double inv_h;    // 1 / h
-  double inv_dzt;  // 1 / dz_t of the medium table (table march only)
+  double inv_dzt;  // 1 / dz_t of the medium table (table march only), and in FP32:
+  float inv_dz, half_inv_dz, inv_dz2, two_dz, dz_sq;  // 1/dz_t, 1/(2 dz_t), 1/dz_t^2, 2 dz_t, dz_t^2
 };
 
 template <typename T>
@@ -500,11 +501,11 @@ __global__ void __launch_bounds__(256, 8) march_table_kernel(Geometry g, MarchK 
   med.direct.zl0 = (float)((double)(lane * g.rho) * g.h);
   med.ni = (unsigned)(mt.n - 1);
   med.ta = mt.tab;
-  med.inv_dz = (float)(1.0 / mt.dz);
-  med.half_inv_dz = (float)(0.5 / mt.dz);
-  med.inv_dz2 = (float)(1.0 / (mt.dz * mt.dz));
-  med.two_dz = (float)(2.0 * mt.dz);
-  med.dz_sq = (float)(mt.dz * mt.dz);
+  med.inv_dz = mk.inv_dz;
+  med.half_inv_dz = mk.half_inv_dz;
+  med.inv_dz2 = mk.inv_dz2;
+  med.two_dz = mk.two_dz;
+  med.dz_sq = mk.dz_sq;
   const double rel = (g.z_a + (double)(w * 64 * g.rho - g.E) * g.h) - mt.z_lo;  // z_w above the table's base
   med.j0 = (int)floor(rel * mk.inv_dzt);
   med.tl = (float)((rel - (double)med.j0 * mt.dz + (double)(lane * g.rho) * g.h) * mk.inv_dzt);
@@ -722,6 +723,11 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
   mk.h6 = mk.hx / 6.0;
   mk.inv_h = 1.0 / g.h;
   mk.inv_dzt = pl.mtab.tab ? 1.0 / pl.mtab.dz : 0.0;
+  mk.inv_dz = (float)mk.inv_dzt;
+  mk.half_inv_dz = pl.mtab.tab ? (float)(0.5 / pl.mtab.dz) : 0.0f;
+  mk.inv_dz2 = pl.mtab.tab ? (float)(1.0 / (pl.mtab.dz * pl.mtab.dz)) : 0.0f;
+  mk.two_dz = (float)(2.0 * pl.mtab.dz);
+  mk.dz_sq = (float)(pl.mtab.dz * pl.mtab.dz);
   if (pl.gfast) {
     const int nl = pl.goff[q + 1] - pl.goff[q];
     const size_t off = (size_t)pl.goff[q];
