@@ -410,6 +410,7 @@ static swkb_status pipelined(swkb_plan_s* pl, int q_begin, int q_end, hipStream_
 static swkb_status enqueue_screens(swkb_plan_s* pl, const void* u_in, int q_begin, int q_end, void* history,
                                    hipStream_t st) {
   const Geometry& g = pl->g;
+  pl->sum_fields = 1;
   const double2* src = u_in ? static_cast<const double2*>(u_in) : pl->u;
   auto fft = [&](int) { return timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, 1, st); }); };
   auto sum = [&](int q) {
@@ -570,6 +571,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->cf = reinterpret_cast<float2*>(ws + L.cf);
     pl->cpol = p->precision == SWKB_MIXED ? reinterpret_cast<float2*>(ws + L.cpol) : nullptr;
     pl->max_batch = p->max_batch;
+    pl->sum_fields = 1;
     pl->blas = nullptr;
     pl->Y = reinterpret_cast<double2*>(ws + L.Y);
     pl->c = reinterpret_cast<double2*>(ws + L.c);
@@ -786,6 +788,7 @@ swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch
     pl->blas = h;
   }
   const double2* src = static_cast<const double2*>(u_in);
+  pl->sum_fields = batch;
   auto fft = [&](int) { return timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, batch, st); }); };
   auto sum = [&](int q) {
     hipError_t e;
@@ -848,6 +851,7 @@ swkb_status swkb_propagate_stations(swkb_plan_t pl, const void* u, int32_t q, co
                          hipMemcpyHostToDevice, st);
       for (int s = s0; s < s0 + cnt && e == hipSuccess; ++s) {
         swkb_plan_s tmp = *pl;  // same plan, a screen of width i hx marched with i steps
+        tmp.sum_fields = 1;
         tmp.g.S = stations[s];
         tmp.g.dx = stations[s] * hx;
         tmp.frac = pl->frac_st + (size_t)(s - s0) * g.M;

@@ -477,14 +477,10 @@ __global__ void __launch_bounds__(kTabNodes) medium_table_kernel(const double* _
   ta[o] = make_float4((float)p.x, (float)p.y, (float)(3.0 * D - 2.0 * p.y - q.y), (float)(-2.0 * D + p.y + q.y));
 }
 
-// Mixed-path Gaussian-sum march through the screen's medium table.  Every
-// stage waits on its table read, so the kernel asks for 8 wavefronts per
-// SIMD (the compiler then keeps to 64 VGPRs and fewer SGPRs; at its own
-// choice, 106 SGPRs, the SGPR file allowed 7): random medium N = 8192,
-// 109.5 -> 106.2 us per screen.
-__global__ void __launch_bounds__(256, 8) march_table_kernel(Geometry g, MarchK mk, GaussTabs<float> tabs,
-                                                             MedTab mt, DevModes modes, DevRecords rec,
-                                                             int* __restrict__ wcount, int waves_per_mode) {
+// Mixed-path Gaussian-sum march through the screen's medium table.
+__device__ inline void march_table_body(const Geometry& g, const MarchK& mk, const GaussTabs<float>& tabs,
+                                        const MedTab& mt, const DevModes& modes, DevRecords& rec,
+                                        int* __restrict__ wcount, int waves_per_mode) {
   const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int lane = threadIdx.x & 63;
   const int j = wave / waves_per_mode;
@@ -514,6 +510,26 @@ __global__ void __launch_bounds__(256, 8) march_table_kernel(Geometry g, MarchK 
   march_ray<float>(med, mc, g, mk, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec,
                    st, c);
   wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c, g.S);
+}
+
+// Two launch shapes of the same march.  Every stage waits on its table
+// read, so beside the one-field FP32 sum the march asks for 8 wavefronts
+// per SIMD (the compiler then keeps to 64 VGPRs and fewer SGPRs; at its own
+// choice, 106 SGPRs, the SGPR file allows 7): random medium N = 8192, step
+// 58.0 -> 56.7 ms per 400 screens.  Beside the sum of several fields (the
+// owner-map kernel, 4 wavefronts per SIMD) the march at 8 wavefronts per
+// SIMD crowds that sum out of the CUs it shares, so there the compiler's own
+// choice runs: 4 fields, 80.2 -> 71.6 ms per 400 screens.
+__global__ void __launch_bounds__(256, 8) march_table_kernel(Geometry g, MarchK mk, GaussTabs<float> tabs,
+                                                             MedTab mt, DevModes modes, DevRecords rec,
+                                                             int* __restrict__ wcount, int waves_per_mode) {
+  march_table_body(g, mk, tabs, mt, modes, rec, wcount, waves_per_mode);
+}
+
+__global__ void __launch_bounds__(256) march_table_batch_kernel(Geometry g, MarchK mk, GaussTabs<float> tabs,
+                                                                MedTab mt, DevModes modes, DevRecords rec,
+                                                                int* __restrict__ wcount, int waves_per_mode) {
+  march_table_body(g, mk, tabs, mt, modes, rec, wcount, waves_per_mode);
 }
 
 // One workgroup per mode: running maximum of live arrival heights (search
@@ -743,8 +759,12 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
                          reinterpret_cast<const T2<float>*>(pl.gterm) + off,
                          static_cast<const float*>(pl.gczl) + off * wpm, nl};
       // reads the table launch_medium_table built for screen q
-      hipLaunchKernelGGL(march_table_kernel, grid, dim3(256), 0, st, g, mk, t, pl.mtab, modes_of(pl), pl.rec,
-                         wcount, wpm);
+      if (pl.sum_fields > 1)
+        hipLaunchKernelGGL(march_table_batch_kernel, grid, dim3(256), 0, st, g, mk, t, pl.mtab, modes_of(pl),
+                           pl.rec, wcount, wpm);
+      else
+        hipLaunchKernelGGL(march_table_kernel, grid, dim3(256), 0, st, g, mk, t, pl.mtab, modes_of(pl), pl.rec,
+                           wcount, wpm);
     } else {
       GaussTabs<float> t{reinterpret_cast<const T2<float>*>(pl.gstage) + off * nst,
                          reinterpret_cast<const T2<float>*>(pl.gterm) + off,

@@ -124,6 +124,7 @@ struct swkb_plan_s {
   float2* cpol;                  // one field's modes in polar form [M]: |c|, frac(arg c / (2 pi))
                                  // (FP32 interval sum; mixed-precision plans only)
   int max_batch;
+  int sum_fields;                // fields summed per screen by the running propagation (march shape)
   void* blas;                    // rocBLAS handle for batched matrix products (created on first use)
   int use_matrix;                // mode functions tabulated once (x-invariant medium)
   void* tmat;                    // T[mode][point], complex T (double2 or float2)
