@@ -104,8 +104,9 @@ __device__ inline T bump_exp(T arg);
 // Cody-Waite reduction x = n ln2 + r, with ln2 split into a 32-bit head
 // (n ln2_head exact for |n| < 2^21) and the remainder, |r| <= ln2 / 2; e^r
 // from its Taylor polynomial of degree 12 by Horner; then the factor 2^n.
-// Relative error at most 3.1e-16 over [-32, 0] (against a 50-digit exp at
-// 20000 points, the FMAs emulated exactly); no overflow or underflow there.
+// Relative error at most 3.1e-16 over [-32, 0] (the FMAs emulated with one
+// exact rounding each, against a 50-digit exp: tests/test_exp_constants.py);
+// no overflow or underflow there.
 template <>
 __device__ inline double bump_exp<double>(double x) {
   constexpr double kInvLn2 = 1.4426950408889634;
