@@ -272,8 +272,12 @@ __device__ inline int first_point_at_or_above(const Geometry& g, double key, dou
   if (key == -INFINITY) return 0;
   const double x = (key - g.z_a) * inv_h;
   int ci = x <= 0.0 ? 0 : (x >= (double)(g.N + 1) ? g.N + 1 : (int)ceil(x));
-  // exact decisions with the same arithmetic as z_m = z_a + m h
+  // exact decisions with the same arithmetic as z_m = z_a + m h; the
+  // estimate is off by at most one step in practice, so the loops stay
+  // plain (not unrolled for long runs)
+#pragma unroll 1
   while (ci > 0 && g.z_a + (double)(ci - 1) * g.h >= key) --ci;
+#pragma unroll 1
   while (ci <= g.N && g.z_a + (double)ci * g.h < key) ++ci;
   return ci;
 }
@@ -342,31 +346,29 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
   rec.cz[o] = st == kLive ? first_point_at_or_above(g, s_launch + (double)dz, mk.inv_h) : 0;
 }
 
-// Wavefront sums of the lanes' work counts.  With S <= 250 a lane makes at
-// most 4 S + 2 < 1024 evaluations, so the RK4 and table counts of 64 lanes
-// fit 16 bits each and share one reduction; the direct-evaluation counts are
-// reduced only when some lane has any.
+// Wavefront sums of the lanes' work counts (the device library's wavefront
+// reduction, all 64 lanes taking part).  With S <= 250 a lane makes at most
+// 4 S + 2 < 1024 evaluations, so the RK4 and table counts of 64 lanes fit 16
+// bits each and share one reduction; the direct-evaluation counts are reduced
+// only when some lane has any.
+extern "C" __device__ unsigned int __ockl_wfred_add_u32(unsigned int);
+
 __device__ inline void wave_counts(int* __restrict__ wcount, size_t slot, int lane, bool active, int st, Work c,
                                    int S) {
   const unsigned long long bc = __ballot(active && st == kCaustic);
   const unsigned long long bd = __ballot(active && (st == kDead || st == kDeadLaunch));
   if (S <= 250) {
     // sums at most 64 (4 S + 2) = 64128 < 2^16 per field, so the word stays below 2^32
-    unsigned rt = (unsigned)c.rhs | ((unsigned)c.tab << 16);
-    for (int off = 32; off > 0; off >>= 1) rt += __shfl_xor(rt, off);
+    const unsigned rt = __ockl_wfred_add_u32((unsigned)c.rhs | ((unsigned)c.tab << 16));
     c.rhs = (int)(rt & 0xffffu);
     c.tab = (int)(rt >> 16);
   } else {
-    for (int off = 32; off > 0; off >>= 1) {
-      c.rhs += __shfl_xor(c.rhs, off);
-      c.tab += __shfl_xor(c.tab, off);
-    }
+    c.rhs = (int)__ockl_wfred_add_u32((unsigned)c.rhs);
+    c.tab = (int)__ockl_wfred_add_u32((unsigned)c.tab);
   }
   if (__ballot(c.med != 0 || c.terms != 0)) {
-    for (int off = 32; off > 0; off >>= 1) {
-      c.med += __shfl_xor(c.med, off);
-      c.terms += __shfl_xor(c.terms, off);
-    }
+    c.med = (int)__ockl_wfred_add_u32((unsigned)c.med);
+    c.terms = (int)__ockl_wfred_add_u32((unsigned)c.terms);
   }
   if (lane == 0) {
     int* wc = wcount + kWaveCounts * slot;

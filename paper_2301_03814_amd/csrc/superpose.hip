@@ -759,16 +759,16 @@ static void launch_sum(const swkb_plan_s& pl, const dim3& grid, const DevModes& 
     hipLaunchKernelGGL((superpose_iv_kernel<T, NB, false>), dim3(grid.x, grid.y, 1), dim3(64 * kWaves), shmem, st,
                        pl.g, md, pl.rec, pl.c, pl.cpol, pl.part, static_cast<typename CplxOf<T>::type*>(nullptr), ep,
                        sub, batch);
-    return;
+  } else {
+    struct alignas(16) LRec {
+      T v[9];
+    };
+    const size_t work = (size_t)kWaves * (64 * sizeof(LRec) + SUBMAX * 64 * sizeof(int));
+    const size_t red = sizeof(T) * 2 * (size_t)kWaves * NB * SUBMAX * 64;
+    const dim3 g3(grid.x, grid.y, (batch + NB - 1) / NB);
+    hipLaunchKernelGGL((superpose_own_kernel<T, NB, SUBMAX>), g3, dim3(64 * kWaves), work > red ? work : red, st,
+                       pl.g, md, pl.rec, pl.c, pl.part, ep, sub, batch);
   }
-  struct alignas(16) LRec {
-    T v[9];
-  };
-  const size_t work = (size_t)kWaves * (64 * sizeof(LRec) + SUBMAX * 64 * sizeof(int));
-  const size_t red = sizeof(T) * 2 * (size_t)kWaves * NB * SUBMAX * 64;
-  const dim3 g3(grid.x, grid.y, (batch + NB - 1) / NB);
-  hipLaunchKernelGGL((superpose_own_kernel<T, NB, SUBMAX>), g3, dim3(64 * kWaves), work > red ? work : red, st, pl.g,
-                     md, pl.rec, pl.c, pl.part, ep, sub, batch);
 }
 
 Epi epi_of(const swkb_plan_s& pl) {
