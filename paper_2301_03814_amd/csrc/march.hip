@@ -691,8 +691,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecor
   if (fold) sfold = 1;
   // counts
   if (tid < 64) {
-    for (int off = 32; off > 0; off >>= 1)
-      for (int k = 0; k < kWaveCounts; ++k) v[k] += __shfl_down(v[k], off, 64);
+    for (int k = 0; k < kWaveCounts; ++k) v[k] = (int)__ockl_wfred_add_u32((unsigned)v[k]);
     if (tid == 0) {
       rec.mcaus[j] = v[0];
       rec.mdead[j] = v[1];
