@@ -272,13 +272,18 @@ __device__ inline int first_point_at_or_above(const Geometry& g, double key, dou
   if (key == -INFINITY) return 0;
   const double x = (key - g.z_a) * inv_h;
   int ci = x <= 0.0 ? 0 : (x >= (double)(g.N + 1) ? g.N + 1 : (int)ceil(x));
-  // exact decisions with the same arithmetic as z_m = z_a + m h; the
-  // estimate is off by at most one step in practice, so the loops stay
-  // plain (not unrolled for long runs)
-#pragma unroll 1
-  while (ci > 0 && g.z_a + (double)(ci - 1) * g.h >= key) --ci;
-#pragma unroll 1
-  while (ci <= g.N && g.z_a + (double)ci * g.h < key) ++ci;
+  // exact decisions with the same arithmetic as z_m = z_a + m h.  The
+  // estimate's rounding is a few 1e-11 grid steps here (|x| <= 2^17), so it
+  // is at most one step off while |z_a| / h stays far below 2^48: one
+  // correction either way, a check, and the stepping loops only for a
+  // geometry that needs more
+  auto reaches = [&](int m) { return g.z_a + (double)m * g.h >= key; };
+  if (ci > 0 && reaches(ci - 1)) --ci;
+  else if (ci <= g.N && !reaches(ci)) ++ci;
+  if (__builtin_expect(!((ci == 0 || !reaches(ci - 1)) && (ci > g.N || reaches(ci))), 0)) {
+    while (ci > 0 && reaches(ci - 1)) --ci;
+    while (ci <= g.N && !reaches(ci)) ++ci;
+  }
   return ci;
 }
 
