@@ -479,6 +479,40 @@ def test_fields_between_screens_match_oracle(torch_dev, swkb, name):
     plan.close()
 
 
+@pytest.mark.parametrize("name", ["random_medium_N1024", "linear_caustic_N512", "duct_dirichlet_N2048"])
+def test_fields_between_screens_mixed(torch_dev, swkb, name):
+    """Stations in the mixed path: the one-field FP32 sum takes each mode's
+    coefficient in polar form and adds the station's own range phase (not the
+    screen's); held against the FP64 stations and the oracle.  The
+    x-invariant duct runs its stations through the recomputing sum although
+    the plan itself uses the mode-function matrix."""
+    import oracle
+    torch, dev = torch_dev
+    cfg = CASES[name]()
+    S = cfg["rk4_steps"]
+    q = 2
+    p64 = swkb.Plan(cfg, precision=swkb.FP64, device=dev)
+    p32 = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    hist = p64.propagate(u0, 0, q + 1)
+    own32 = p32.propagate(u0, 0, q + 1)
+    uq = hist[q - 1].contiguous()
+    st = [1, S // 2, S]
+    g64 = p64.stations(uq, q, st).cpu().numpy()
+    g32 = p32.stations(uq, q, st).cpu().numpy()
+    for k, i in enumerate(st):
+        c_i = W.with_overrides(cfg, dx=i * (cfg["dx"] / S), rk4_steps=i)
+        c_i["x0"] = cfg["x0"] + q * cfg["dx"] - q * c_i["dx"]
+        ref, _ = oracle.screen(c_i, q, uq.cpu().numpy())
+        e64, eor = rel(g32[k], g64[k]), rel(g32[k], ref)
+        say(f"[stations] {name} mixed i={i} vs fp64 {e64:.2e} vs oracle {eor:.2e}")
+        assert e64 <= 1e-4 and eor <= 1e-4
+    # the mixed plan's own propagation is unaffected afterwards
+    assert torch.equal(p32.propagate(u0, 0, q + 1), own32)
+    p64.close()
+    p32.close()
+
+
 def _np_modal(cfg, u0, xs):
     """numpy separation of variables on the same grid (mirror: doubled grid,
     reflected eps, odd/even extension) -- independent of the GPU solver."""
