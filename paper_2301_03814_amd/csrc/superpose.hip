@@ -510,7 +510,9 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_kernel(Geometry g,
 // The same product for complex64 T with 16-byte loads: lane l of a
 // wavefront reads points m0 + 128 u + 2 l and + 1 (two complex64 in one
 // float4), u < 4, so a workgroup covers 512 points and each load moves 1 KB
-// per wavefront; four modes are in flight per loop trip.  N % 512 == 0.
+// per wavefront.  The mode loop is not unrolled: at 57 VGPRs eight
+// wavefronts per SIMD keep enough loads in flight (unrolled by 4: 102 VGPRs,
+// four wavefronts, the 64-problem batch 1.486 -> 1.469 s without).  N % 512 == 0.
 __device__ inline void apply_c64_body(const Geometry& g, const float4* __restrict__ tab,
                                       const double2* __restrict__ c, double2* __restrict__ part, int bx, int gi,
                                       int groups, double2* red) {  // red: [kWaves][4][64][2] pairs of (re, im)
@@ -521,7 +523,7 @@ __device__ inline void apply_c64_body(const Geometry& g, const float4* __restric
   float ar[4][2], ai[4][2];
   for (int u = 0; u < 4; ++u) ar[u][0] = ar[u][1] = ai[u][0] = ai[u][1] = 0.0f;
   const size_t row4 = (size_t)g.N / 2;  // float4 per row of T
-#pragma unroll 4
+#pragma unroll 1
   for (int j = gi * kWaves + w; j < g.M; j += jstep) {
     const double2 cj = c[j];
     const float cr = (float)cj.x, ci = (float)cj.y;

@@ -93,13 +93,14 @@ def test_resume_and_state(env):
 
 def test_graph_replays_equal_eager(env):
     """The grouped patch step (x-invariant medium, mixed) captured and replayed
-    three times, with eager work between the replays, equals the eager run."""
+    three times, with eager work between the replays, equals the eager run of
+    the same plan (a second plan runs its own autotuner, whose timing-based
+    choice of launch shapes may differ and change the rounding)."""
     torch, pkg, OP = env
     cfg, P, width, margin = CASES["duct_neumann_P4"]()
     u0 = torch.from_numpy(W.incident_field(cfg)).cuda()
-    eager = pkg.PatchPlan(cfg, P, width, margin, precision=pkg.MIXED)
-    ref = eager.propagate(u0, 0, cfg["n_screens"]).cpu()
     pp = pkg.PatchPlan(cfg, P, width, margin, precision=pkg.MIXED)
+    ref = pp.propagate(u0, 0, cfg["n_screens"]).cpu()
     pp.graphs(True)
     out = torch.empty((cfg["n_screens"], cfg["n_z"]), dtype=torch.complex128, device="cuda")
     for r in range(3):
@@ -112,4 +113,3 @@ def test_graph_replays_equal_eager(env):
         assert torch.equal(out.cpu(), ref), r
     pp.graphs(False)
     pp.close()
-    eager.close()
