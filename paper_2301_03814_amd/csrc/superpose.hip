@@ -335,8 +335,13 @@ typedef double D2 __attribute__((ext_vector_type(2)));
 // owner's record.  Every lane then does the same number of evaluations per
 // pass, and each lane accumulates its points in registers across modes; the
 // wavefronts' sums meet in LDS at the end and are added in a fixed order.
+//
+// FP32 (batches of fields) asks for 5 wavefronts per SIMD (96 VGPRs, no
+// spills; at the compiler's own choice 101 VGPRs and 4): 4-field batch on the
+// random medium 71.3 -> 68.4 ms per 400 screens.  FP64 keeps the compiler's
+// choice (fewer registers spill there).
 template <typename T, int NB, int SUBMAX>
-__global__ void __launch_bounds__(64 * kWaves) superpose_own_kernel(Geometry g, DevModes modes, DevRecords rec,
+__global__ void __launch_bounds__(64 * kWaves, (std::is_same<T, float>::value ? 5 : 1)) superpose_own_kernel(Geometry g, DevModes modes, DevRecords rec,
                                                                     const double2* __restrict__ c,
                                                                     double2* __restrict__ part, Epi ep, int sub,
                                                                     int batch) {
