@@ -98,36 +98,32 @@ struct GenericMedium {
 template <typename T>
 struct T2 { T x, y; };
 
-template <typename T>
-__device__ inline T bump_exp(T arg);
-// e^x for a Gaussian term inside its 8-sigma cutoff (x in [-32, 0]), FP64:
-// Cody-Waite reduction x = n ln2 + r, with ln2 split into a 32-bit head
-// (n ln2_head exact for |n| < 2^21) and the remainder, |r| <= ln2 / 2; e^r
-// from its Taylor polynomial of degree 12 by Horner; then the factor 2^n.
-// Relative error at most 3.1e-16 over [-32, 0] (the FMAs emulated with one
-// exact rounding each, against a 50-digit exp: tests/test_exp_constants.py);
-// no overflow or underflow there.
-template <>
-__device__ inline double bump_exp<double>(double x) {
-  constexpr double kInvLn2 = 1.4426950408889634;
-  constexpr double kLn2Head = 0.6931471803691238;      // 0x1.62e42fee00000p-1
-  constexpr double kLn2Tail = 1.9082149292705877e-10;  // ln2 - kLn2Head
-  // 1/k!, k = 12 .. 0
-  constexpr double kC[13] = {2.08767569878681e-09,  2.505210838544172e-08, 2.755731922398589e-07,
-                             2.7557319223985893e-06, 2.48015873015873e-05,  0.0001984126984126984,
-                             0.001388888888888889,  0.008333333333333333,  0.041666666666666664,
-                             0.16666666666666666,   0.5,                   1.0,
-                             1.0};
-  const double n = rint(x * kInvLn2);
-  double r = fma(-n, kLn2Head, x);
-  r = fma(-n, kLn2Tail, r);
+// e^x for a Gaussian term inside its 8-sigma cutoff (x in [-32, 0]).
+// FP32: the hardware exp2 (the tables carry the factor log2 e).  FP64:
+// Cody-Waite reduction x = k ln2/64 + r, with ln2/64 split into a 32-bit head
+// (k ln2/64_head exact for |k| < 2^21) and the remainder, |r| <= ln2/128;
+// e^r from its Taylor polynomial of degree 5 by Horner; then
+// e^x = 2^(k >> 6) 2^((k & 63) / 64) e^r with the 64 powers 2^(j/64) from a
+// table in LDS (filled by the kernel with the device exp2).  Relative error
+// at most 2.9e-16 over [-32, 0] with correctly rounded table entries (the
+// FMAs emulated with one exact rounding each, against a 50-digit exp:
+// tests/test_exp_constants.py), plus the table's own rounding; no overflow
+// or underflow there.
+__device__ inline double exp_gauss(double x, const double* __restrict__ pow2_64) {
+  constexpr double k64InvLn2 = 92.33248261689366;
+  constexpr double kLn2Head = 0.01083042469326756;     // 0x1.62e42fee00000p-7
+  constexpr double kLn2Tail = 2.9815858269852933e-12;  // ln2/64 - kLn2Head
+  // 1/k!, k = 5 .. 0
+  constexpr double kC[6] = {0.008333333333333333, 0.041666666666666664, 0.16666666666666666, 0.5, 1.0, 1.0};
+  const double kf = rint(x * k64InvLn2);
+  double r = fma(-kf, kLn2Head, x);
+  r = fma(-kf, kLn2Tail, r);
   double p = kC[0];
 #pragma unroll
-  for (int k = 1; k < 13; ++k) p = fma(p, r, kC[k]);
-  return ldexp(p, (int)n);
+  for (int i = 1; i < 6; ++i) p = fma(p, r, kC[i]);
+  const int k = (int)kf;
+  return ldexp(pow2_64[k & 63] * p, k >> 6);
 }
-template <>
-__device__ inline float bump_exp<float>(float arg) { return __builtin_amdgcn_exp2f(arg); }
 
 template <typename T>
 struct GaussMedium {
@@ -137,12 +133,16 @@ struct GaussMedium {
   const T* __restrict__ czl;
   int nl;
   T zl0;  // launch height of this lane's ray relative to the wavefront reference
+  const double* __restrict__ pow2_64 = nullptr;  // FP64: 2^(j/64), j < 64, in LDS
   __device__ inline void bump(T z, T c, T2<T> ac, T2<T> tk, T& dn, T& nz, T& nzz, int& nterms) const {
     const T ddz = z - c;
     const T d2 = ddz * ddz;
     if (d2 > ac.y) return;
     ++nterms;
-    const T gg = ac.x * bump_exp<T>(d2 * tk.x);
+    T ex;
+    if constexpr (std::is_same<T, double>::value) ex = exp_gauss(d2 * tk.x, pow2_64);
+    else ex = __builtin_amdgcn_exp2f(d2 * tk.x);
+    const T gg = ac.x * ex;
     dn += gg;
     const T t = tk.y * gg;
     nz -= ddz * t;
@@ -437,6 +437,11 @@ template <typename T>
 __global__ void __launch_bounds__(256) march_gauss_kernel(Geometry g, MarchK mk, GaussTabs<T> tabs,
                                                           DevModes modes, DevRecords rec, int* __restrict__ wcount,
                                                           int waves_per_mode) {
+  __shared__ double pow2_64[64];
+  if constexpr (std::is_same<T, double>::value) {
+    if (threadIdx.x < 64) pow2_64[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 64.0));
+    __syncthreads();
+  }
   const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int lane = threadIdx.x & 63;
   const int j = wave / waves_per_mode;
@@ -446,6 +451,7 @@ __global__ void __launch_bounds__(256) march_gauss_kernel(Geometry g, MarchK mk,
   const bool active = r < g.R;
   const ModeC mc = load_mode(modes, j);
   GaussMedium<T> med;
+  med.pow2_64 = pow2_64;
   med.stage = tabs.stage;
   med.term = tabs.term;
   med.czl = tabs.czl + (size_t)w * tabs.nl;
