@@ -433,8 +433,11 @@ struct GaussTabs {
 // Gaussian-sum medium without a mirror.  Bump heights are relative to each
 // wavefront's first launch height z_w, so FP32 never carries an absolute
 // coordinate; all table reads are wavefront-uniform.
+// FP64 asks for 5 wavefronts per SIMD (96 VGPRs and a 36-byte spill outside
+// the bump loop; at the compiler's choice 101 VGPRs and 4): random medium,
+// 1448 -> 1404 us per screen.
 template <typename T>
-__global__ void __launch_bounds__(256) march_gauss_kernel(Geometry g, MarchK mk, GaussTabs<T> tabs,
+__global__ void __launch_bounds__(256, (std::is_same<T, double>::value ? 5 : 1)) march_gauss_kernel(Geometry g, MarchK mk, GaussTabs<T> tabs,
                                                           DevModes modes, DevRecords rec, int* __restrict__ wcount,
                                                           int waves_per_mode) {
   __shared__ double pow2_64[64];
