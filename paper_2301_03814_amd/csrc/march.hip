@@ -576,7 +576,7 @@ __global__ void __launch_bounds__(256) march_table_batch_kernel(Geometry g, Marc
 // keys), the first grid point at or above each key, the fold test (live
 // arrivals must increase strictly), the per-tile search windows and the
 // mode's ray counts.  Each thread takes `run` consecutive rays (run =
-// ceil(R / 256), at most 8; longer ray sets are taken in several chunks):
+// ceil(R / 128), at most 9; longer ray sets are taken in several chunks):
 // the thread's maximum, a workgroup exclusive prefix maximum over threads
 // plus the carry of the previous chunk, then the thread's keys in order.
 //
@@ -586,8 +586,12 @@ __global__ void __launch_bounds__(256) march_table_batch_kernel(Geometry g, Marc
 // 64 t) therefore starts in the interval of ray r - 1 for
 // ceil(ci_{r-1} / 64) <= t < ceil(ci_r / 64) (ci_{-1} = 0), and tiles at or
 // above ceil(ci_{R-1} / 64) in that of ray R - 1.
-constexpr int kScanThreads = 256;
-constexpr int kScanRun = 6;  // most consecutive rays per thread
+// 128 threads with up to 9 rays each: the per-wavefront prefix and count
+// work is spread over more rays (random medium, 1091 rays per mode: 18.3 ->
+// 16.4 us per screen against 256 threads with 5 rays; 64 threads with 18:
+// 19.8 us)
+constexpr int kScanThreads = 128;
+constexpr int kScanRun = 9;  // most consecutive rays per thread
 
 template <typename T>
 __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecords rec,
