@@ -344,6 +344,117 @@ def test_mirror_equals_periodic_run_of_the_odd_extension(oracle_mod):
     assert rel_l2(out, out2[256:]) < 1e-13
 
 
+# ------------------------------------------- symmetries of the whole method
+#
+# The mode expansion (Sec. 2.1.1), the characteristic system (Sec. 2.1.2) and
+# the interpolation and superposition (Sec. 2.1.3) are built from the medium
+# and the field alone, so moving both rigidly in z moves the result with them.
+# A slip in an absolute height (the launch grid, the phase origin z_a, a
+# record's base point) breaks the translation; a sign slip in xi or q, or a
+# one-sided choice in the ray-interval search, breaks the reflection.
+
+
+def _bumps(seed, amp, s_range, n_g=8, cx=(0.0, 60.0), cz=(85.0, 115.0)):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(-amp, amp, n_g), rng.uniform(*s_range, n_g), rng.uniform(*cx, n_g),
+                     rng.uniform(*cz, n_g)], axis=1)
+
+
+def _bump_cfg(bumps, n_screens=6):
+    """Gaussian-sum medium on [0, 200] (N = 512, M = 128, rho = 8) without
+    absorbers; every bump's 8-sigma disc stays inside (37, 163), so the medium
+    is homogeneous near both ends of the launch range."""
+    cfg = W.random_medium(n_screens=n_screens, n_z=512, n_modes=128, height=200.0)
+    prm = np.concatenate([[len(bumps)], np.asarray(bumps, dtype=np.float64).reshape(-1)])
+    cfg = W.with_overrides(cfg, medium_params=prm, absorber_bot=0.0, absorber_top=0.0)
+    cfg["source"] = dict(z0=92.0, width=8.0, xi0=0.05)
+    return cfg
+
+
+def _band_limited(cfg, seed):
+    """Random field of the kept modes n = -M/2 + 1 .. M/2 - 1.  Mode -M/2 is
+    left out: its mirror image +M/2 is not kept, so it alone would break the
+    reflection."""
+    N, M = cfg["n_z"], cfg["n_modes"]
+    rng = np.random.default_rng(seed)
+    n = np.arange(-M // 2 + 1, M // 2)
+    cn = rng.normal(size=n.size) + 1j * rng.normal(size=n.size)
+    return np.exp(2j * np.pi * np.outer(np.arange(N), n) / N) @ cn
+
+
+@pytest.mark.parametrize("k", [8, 40, -24])
+def test_translation_moves_the_result(oracle_mod, k):
+    """Bumps raised by k cells and the beam rolled by k cells (k a multiple
+    of the ray stride, so every ray keeps its place relative to the medium):
+    three screens later the field is the rolled field, counters equal."""
+    bumps = _bumps(11, 0.02, (3.0, 6.0))
+    cfg = _bump_cfg(bumps)
+    h = 200.0 / cfg["n_z"]
+    assert k % cfg["ray_stride"] == 0
+    u = W.incident_field(cfg)
+    out, cnt = oracle_mod.run(cfg, u, 0, 3)
+    moved = bumps.copy()
+    moved[:, 3] += k * h
+    out2, cnt2 = oracle_mod.run(_bump_cfg(moved), np.roll(u, k), 0, 3)
+    assert rel_l2(out2[-1], np.roll(out[-1], k)) < 1e-12
+    assert cnt2 == cnt
+
+
+@pytest.mark.parametrize("q", [0, 3])
+def test_reflection_mirrors_each_screen(oracle_mod, q):
+    """Medium and field reflected about the middle of the periodic domain
+    (z -> 2 z_a + L - z, grid point m -> -m mod N): one screen of the
+    reflected problem gives the reflected output.  With the medium left
+    unreflected the result is far off, so the check sees the medium."""
+    bumps = _bumps(3, 0.1, (2.0, 4.0))
+    refl = bumps.copy()
+    refl[:, 3] = 200.0 - refl[:, 3]
+    cfg, cfg_r = _bump_cfg(bumps), _bump_cfg(refl)
+    v = _band_limited(cfg, 5)
+    m = (-np.arange(cfg["n_z"])) % cfg["n_z"]
+    out, cnt = oracle_mod.screen(cfg, q, v)
+    out_r, cnt_r = oracle_mod.screen(cfg_r, q, v[m])
+    assert rel_l2(out_r, out[m]) < 1e-12
+    assert cnt_r == cnt
+    wrong, _ = oracle_mod.screen(cfg, q, v[m])
+    assert rel_l2(wrong, out[m]) > 1e-2
+
+
+def test_reflection_mirrors_rays_through_caustics(oracle_mod):
+    """Linear medium eps = 1 + 0.02 z and its reflection 1 + 0.02 (2 z_a + L)
+    - 0.02 z, with a band-limited field so that rays of every kept slope
+    reach turning points.  Mode j (n = j - M/2) of one problem is mode M - j
+    of the other; its R rays come in reverse order, with arrival heights
+    reflected, slopes q negated and amplitudes equal, and the same dead and
+    caustic flags.  The screen's output is the reflected output."""
+    cfg = W.linear_caustic(n_screens=4)
+    L = cfg["z_b"] - cfg["z_a"]
+    H2 = 2.0 * cfg["z_a"] + L
+    cfg_r = W.with_overrides(cfg, medium_params=[1.0 + 0.02 * H2, -0.02])
+    cfg["caustic_tol"] = cfg_r["caustic_tol"] = 2.0  # report only
+    N, M = cfg["n_z"], cfg["n_modes"]
+    R = oracle_mod.num_rays(cfg)
+    assert (R - 1) * cfg["ray_stride"] == N + 2 * cfg["launch_ext_cells"]  # the launch grid is symmetric
+    n_caustic = 0
+    for j in range(1, M):
+        a = oracle_mod.march_mode(cfg, 1, j)
+        b = oracle_mod.march_mode(cfg_r, 1, M - j)
+        np.testing.assert_array_equal(b["flag"][::-1], a["flag"])
+        live = a["flag"] == 0
+        n_caustic += int(np.count_nonzero(a["flag"] == 3))  # caustic: Z_s <= 0
+        assert np.abs(b["Z"][::-1][live] - (H2 - a["Z"][live])).max(initial=0.0) < 1e-11
+        assert np.abs(b["q"][::-1][live] + a["q"][live]).max(initial=0.0) < 1e-12
+        amax = np.abs(a["a"][live]).max(initial=1.0)
+        assert np.abs(b["a"][::-1][live] - a["a"][live]).max(initial=0.0) < 1e-12 * max(amax, 1.0)
+    assert n_caustic > 500  # the case does reach caustics
+    v = _band_limited(cfg, 2)
+    m = (-np.arange(N)) % N
+    out, cnt = oracle_mod.screen(cfg, 1, v)
+    out_r, _ = oracle_mod.screen(cfg_r, 1, v[m])
+    assert cnt["caustic_rays"] > 0 and cnt["dead_rays"] > 0
+    assert rel_l2(out_r, out[m]) < 1e-12
+
+
 # ------------------------------------- accuracy against the paper's reference
 
 @pytest.mark.parametrize("name", ["linear", "expgauss"])
