@@ -411,6 +411,77 @@ def test_random_medium_full_size_reflection(torch_dev, swkb, prec):
     pb.close()
 
 
+def test_maximum_grid_stages_match_oracle(torch_dev, swkb):
+    """The largest grid one plan takes (N = 32768, M = 8192; the 0-600 m
+    duct over its Dirichlet ground, FFT length 65536): mode amplitudes of a
+    random field against the oracle's direct DFT, and the ray arrivals of
+    sampled modes (the evanescent edges, the middle, a quarter) against the
+    oracle's march of those modes."""
+    import oracle
+    torch, dev = torch_dev
+    cfg = W.surface_duct(n_screens=2, n_z=32768, n_modes=8192, height=600.0)
+    N, M = cfg["n_z"], cfg["n_modes"]
+    say(f"[max] stages N={N} M={M}")
+    rng = np.random.default_rng(32768)
+    u = rng.normal(size=N) + 1j * rng.normal(size=N)
+    plan = swkb.Plan(cfg, precision=swkb.FP64, device=dev)
+    c = plan.stage_modes(torch.from_numpy(u).to(dev)).cpu().numpy()
+    err = rel(c, oracle.modes(cfg, u))
+    say(f"[max] modes rel={err:.2e}")
+    assert err < 1e-13
+    q = 1
+    rays = plan.stage_rays(q)
+    for j in (0, 1, M // 4, M // 2 - 1, M // 2, 3 * M // 4, M - 1):
+        got = {k: v[j].cpu().numpy() for k, v in rays.items()}
+        ref = oracle.march_mode(cfg, q, j)
+        assert np.array_equal(got["flag"] == 0, ref["flag"] == 0), f"liveness differs in mode {j}"
+        assert np.array_equal(got["flag"] == 3, ref["flag"] == 3), f"caustics differ in mode {j}"
+        live = ref["flag"] == 0
+        assert np.abs(got["Z"][live] - ref["Z"][live]).max(initial=0) < 1e-12 * cfg["z_b"]
+        assert np.abs(got["q"][live] - ref["q"][live]).max(initial=0) < 1e-12
+        psi_scale = max(1.0, np.abs(ref["psi"][live]).max(initial=1.0))
+        assert np.abs(got["psi"][live] - ref["psi"][live]).max(initial=0) < 1e-12 * psi_scale
+        assert np.abs(got["a"][live] - ref["a"][live]).max(initial=0) < 1e-11
+    say(f"[max] rays ok R={plan.num_rays}")
+    del rays
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_maximum_grid_homogeneous_is_exact(torch_dev, swkb, prec):
+    """eps = 1 on the largest grid (N = 32768, M = 8192, periodic): rays are
+    straight and the amplitude is 1, so one screen of 100 m at 6 GHz is the
+    exact propagator of the kept plane waves; the input is a random field
+    over every kept mode except -M/2.  The launch extension (40 m) exceeds
+    the steepest kept mode's drift over the screen (36 m), so every grid
+    point has rays of every mode on both sides."""
+    torch, dev = torch_dev
+    cfg = W.with_overrides(W.surface_duct(n_screens=2, n_z=32768, n_modes=8192, height=600.0, ext_m=40.0),
+                           bc=W.BC_PERIODIC, medium_kind=W.MEDIUM_LINEAR, medium_params=[1.0, 0.0],
+                           eps_ref=1.0, absorber_bot=0.0, absorber_top=0.0)
+    N, M = cfg["n_z"], cfg["n_modes"]
+    say(f"[max] homogeneous {prec} N={N} M={M}")
+    n = np.arange(-M // 2 + 1, M // 2)
+    rng = np.random.default_rng(6)
+    spec = np.zeros(N, complex)
+    spec[n % N] = rng.normal(size=n.size) + 1j * rng.normal(size=n.size)
+    v = np.fft.ifft(spec) * N
+    xi = 2 * np.pi * n / (cfg["k"] * (cfg["z_b"] - cfg["z_a"]))
+    assert (1.0 - xi ** 2).min() > cfg["p2_floor"]  # every kept mode propagates
+    h = (cfg["z_b"] - cfg["z_a"]) / N
+    assert cfg["dx"] * xi.max() / np.sqrt(1.0 - xi.max() ** 2) < cfg["launch_ext_cells"] * h
+    out_spec = np.zeros(N, complex)
+    out_spec[n % N] = spec[n % N] * np.exp(1j * cfg["k"] * np.sqrt(1.0 - xi ** 2) * cfg["dx"])
+    exact = np.fft.ifft(out_spec) * N
+    plan = swkb.Plan(cfg, precision=swkb.FP64 if prec == "fp64" else swkb.MIXED, device=dev)
+    out = plan.propagate(torch.from_numpy(v).to(dev), 0, 1)[0].cpu().numpy()
+    err = rel(out, exact)
+    say(f"[max] homogeneous {prec} rel={err:.3e}")
+    # measured: FP64 6.5e-13 (phases of ~1.2e4 rad), mixed 3.6e-7
+    assert err <= (FP64_TOL if prec == "fp64" else MIXED_REGRESSION)
+    plan.close()
+
+
 @pytest.mark.slow
 def test_surface_duct_full_size_sampled_screen(torch_dev, swkb):
     """Full surface duct (N = 16384, M = 4096, 1000 screens, Dirichlet ground)
