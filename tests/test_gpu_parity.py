@@ -411,6 +411,41 @@ def test_random_medium_full_size_reflection(torch_dev, swkb, prec):
     pb.close()
 
 
+def test_random_medium_full_size_batch(torch_dev, swkb):
+    """Four sources (heights 350-650) through the full-size random medium in
+    one batched propagation, the launch configuration the benchmark times
+    (one march per screen, the several-field sum): over the first 40 screens
+    each field equals its own single-field run, and field 0 stays within
+    the mixed bound of the FP64 run."""
+    torch, dev = torch_dev
+    cfg = W.random_medium()
+    Q, B = 40, 4
+    srcs = []
+    for b in range(B):
+        c = W.with_overrides(cfg)
+        c["source"] = dict(cfg["source"], z0=350.0 + 100.0 * b)
+        srcs.append(W.incident_field(c))
+    U0 = np.stack(srcs)
+    say(f"[full-batch] {B} fields, {Q} screens")
+    pb = swkb.Plan(W.with_overrides(cfg, max_batch=B), precision=swkb.MIXED, device=dev)
+    hist, _ = pb.propagate_batch(torch.from_numpy(U0).to(dev), 0, Q)
+    hist = hist.cpu().numpy()
+    pb.close()
+    ps = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
+    for b in range(B):
+        ref = ps.propagate(torch.from_numpy(U0[b]).to(dev), 0, Q).cpu().numpy()
+        err = rel(hist[:, b, :], ref)
+        say(f"[full-batch] field {b} batch vs single rel={err:.2e}")
+        assert err <= 2e-5  # measured 3.0e-6 .. 4.0e-6 (FP32 rounding of two sum kernels)
+    ps.close()
+    p64 = swkb.Plan(cfg, precision=swkb.FP64, device=dev)
+    ref64 = p64.propagate(torch.from_numpy(U0[0]).to(dev), 0, Q).cpu().numpy()
+    err = rel(hist[:, 0, :], ref64)
+    say(f"[full-batch] field 0 batch vs fp64 rel={err:.2e}")
+    assert err <= MIXED_REGRESSION
+    p64.close()
+
+
 def test_maximum_grid_stages_match_oracle(torch_dev, swkb):
     """The largest grid one plan takes (N = 32768, M = 8192; the 0-600 m
     duct over its Dirichlet ground, FFT length 65536): mode amplitudes of a
