@@ -339,9 +339,9 @@ def test_mixed_direct_evaluation_when_table_too_fine(torch_dev, swkb, oracle_run
 @pytest.mark.slow
 def test_random_medium_full_size_sampled_screens(torch_dev, swkb):
     """Full random-medium workload (N = 8192, M = 2048, 400 screens) in the
-    launch configuration the benchmark times: the oracle recomputes sampled
-    screens from the GPU's own input field on that screen; the mixed run is
-    held against the FP64 run over all 400 screens."""
+    launch configuration the benchmark times: sampled screens, each started
+    from the workload's seeded incident beam, by the GPU and by the oracle;
+    the mixed run is held against the FP64 run over all 400 screens."""
     import oracle
     torch, dev = torch_dev
     cfg = W.random_medium()
@@ -354,9 +354,9 @@ def test_random_medium_full_size_sampled_screens(torch_dev, swkb):
     say(f"[full] fp64 done diag={d64}")
     hist = h64.cpu().numpy()
     for q in (0, 211):
-        uin = u0 if q == 0 else hist[q - 1]
-        ref, cnt = oracle.screen(cfg, q, uin)
-        err = rel(hist[q], ref)
+        got = hist[q] if q == 0 else p64.propagate(u0_d, q, q + 1)[0].cpu().numpy()
+        ref, cnt = oracle.screen(cfg, q, u0)
+        err = rel(got, ref)
         say(f"[full] screen {q} fp64 vs oracle rel={err:.3e}")
         assert err <= FP64_TOL
     p32 = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
@@ -520,8 +520,9 @@ def test_maximum_grid_homogeneous_is_exact(torch_dev, swkb, prec):
 @pytest.mark.slow
 def test_surface_duct_full_size_sampled_screen(torch_dev, swkb):
     """Full surface duct (N = 16384, M = 4096, 1000 screens, Dirichlet ground)
-    through the mode-function matrix: screen 500 recomputed by the oracle
-    from the GPU's field on screen 499; the mixed run held against FP64."""
+    through the mode-function matrix: screen 500, started from the
+    workload's seeded incident beam, by the GPU and by the oracle; the mixed
+    run held against FP64."""
     import oracle
     torch, dev = torch_dev
     cfg = W.surface_duct()
@@ -532,9 +533,9 @@ def test_surface_duct_full_size_sampled_screen(torch_dev, swkb):
     h64 = p64.propagate(u0, 0, Q)
     sel = h64[::25].cpu().numpy()
     q = 500
-    uin = h64[q - 1].cpu().numpy()
-    got = h64[q].cpu().numpy()
+    uin = W.incident_field(cfg)
     del h64
+    got = p64.propagate(torch.from_numpy(uin).to(dev), q, q + 1)[0].cpu().numpy()
     p64.close()
     ref, _ = oracle.screen(cfg, q, uin)
     err = rel(got, ref)
@@ -598,7 +599,8 @@ def test_batch_equals_separate_runs(torch_dev, swkb, name, prop, prec):
 @pytest.mark.parametrize("name", ["random_medium_N1024", "linear_caustic_N512", "duct_dirichlet_N2048"])
 def test_fields_between_screens_match_oracle(torch_dev, swkb, name):
     """Stations x_q + i dx/S: the oracle runs the screen step with width
-    i dx/S and i RK4 steps from the same field."""
+    i dx/S and i RK4 steps from the same field (the seeded incident beam
+    handed to screen q)."""
     import oracle
     torch, dev = torch_dev
     cfg = CASES[name]()
@@ -607,7 +609,7 @@ def test_fields_between_screens_match_oracle(torch_dev, swkb, name):
     plan = swkb.Plan(cfg, device=dev)
     u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
     hist = plan.propagate(u0, 0, q + 1)
-    uq = hist[q - 1].contiguous()
+    uq = u0  # the seeded incident beam, handed to screen q
     st = [1, S // 2, S]
     got = plan.stations(uq, q, st).cpu().numpy()
     for k, i in enumerate(st):
@@ -618,7 +620,7 @@ def test_fields_between_screens_match_oracle(torch_dev, swkb, name):
         say(f"[stations] {name} i={i} rel={err:.2e}")
         assert err <= FP64_TOL
     # the last station is the next screen
-    assert rel(got[-1], hist[q].cpu().numpy()) <= 1e-12
+    assert rel(got[-1], plan.propagate(uq, q, q + 1)[0].cpu().numpy()) <= 1e-12
     # the plan's own propagation is unaffected afterwards
     again = plan.propagate(u0, 0, q + 1)
     assert torch.equal(again, hist)
@@ -642,7 +644,7 @@ def test_fields_between_screens_mixed(torch_dev, swkb, name):
     u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
     hist = p64.propagate(u0, 0, q + 1)
     own32 = p32.propagate(u0, 0, q + 1)
-    uq = hist[q - 1].contiguous()
+    uq = u0  # the seeded incident beam, handed to screen q
     st = [1, S // 2, S]
     g64 = p64.stations(uq, q, st).cpu().numpy()
     g32 = p32.stations(uq, q, st).cpu().numpy()
