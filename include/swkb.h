@@ -26,7 +26,11 @@
  *     caller memory.  The plan lives in a caller-provided device workspace.
  *   - Every call returns swkb_status; no C++ exception crosses the ABI.
  *     swkb_last_error() gives a message for the last failure on the
- *     calling thread.
+ *     calling thread, swkb_plan_error() the last failure on a plan.
+ *   - A plan is used from one stream at a time.  A call on a plan returns
+ *     SWKB_ERR_BUSY, without doing anything, while another thread is inside
+ *     a call on the same plan, or when it names a stream other than the
+ *     previous call's and that call's work has not finished.
  */
 #ifndef SWKB_H
 #define SWKB_H
@@ -44,7 +48,13 @@ typedef enum swkb_status {
   SWKB_ERR_NOMEM = 2,   /* workspace smaller than swkb_workspace_bytes()          */
   SWKB_ERR_DEVICE = 3,  /* a HIP runtime call or kernel launch failed             */
   SWKB_ERR_CAUSTIC = 4, /* a mode above caustic_tol crossed a caustic in a screen */
-  SWKB_ERR_STATE = 5    /* call out of order (e.g. continue without a field)      */
+  SWKB_ERR_STATE = 5,   /* call out of order (e.g. continue without a field)      */
+  SWKB_ERR_EVANESCENT = 6, /* a mode above caustic_tol had no live ray: every ray of
+                              it was evanescent (p^2 <= p2_floor) at launch or on
+                              the way, so its contribution was lost                */
+  SWKB_ERR_BUSY = 7     /* the plan is in use: another host thread is inside a
+                           call on it, or its previous call's work is still
+                           running on another stream (a plan is single-stream)  */
 } swkb_status;
 
 /* Arithmetic of a plan.  SWKB_FP64: every step in FP64.  SWKB_MIXED: the
@@ -107,6 +117,9 @@ typedef struct swkb_params {
                                bytes (mixed) of workspace                                     */
   int32_t max_batch;        /* largest number of fields swkb_propagate_batch carries at once
                                (>= 1); workspace for the fields grows with it               */
+  int32_t keep_history;     /* 1: the plan keeps the field of every screen it reaches in its
+                               workspace ((n_screens + 1) N complex128 more), so that
+                               swkb_field can return any of them; 0: only the current one  */
 } swkb_params;
 
 /* Device-side health counters, summed over all screens propagated so far. */
@@ -123,6 +136,8 @@ typedef struct swkb_counters {
   int64_t medium_terms; /* Gaussian terms inside their cutoff evaluated (GAUSSSUM)        */
   int64_t table_evals;  /* evaluations read from the per-screen medium table (mixed
                            precision, GAUSSSUM, periodic)                                */
+  int64_t evanescent_modes; /* modes of which no ray arrived live (all dead)              */
+  int64_t significant_evanescent; /* of those, modes with |c_n| > caustic_tol max|c|     */
 } swkb_counters;
 
 /* Device time per kernel class, from HIP events recorded on the launch
@@ -139,6 +154,12 @@ typedef struct swkb_plan_s* swkb_plan_t;
 /* Bytes of device workspace a plan for *p needs (0 if *p is invalid).
  * Host only. */
 size_t swkb_workspace_bytes(const swkb_params* p);
+
+/* Device bytes one propagation request for *p holds while it runs: the
+ * plan's workspace plus one field of n_z complex128 for its input and a
+ * small allowance for the runtime's per-stream state (0 if *p is invalid).
+ * The serving loop admits requests by this figure.  Host only. */
+size_t swkb_footprint(const swkb_params* p);
 
 /* Build a plan: validates *p (SWKB_ERR_ARG with a message otherwise),
  * derives the mode tables (xi_n = 2 pi n / (k P h), Sec. 2.1.1-2.1.2), the
@@ -206,15 +227,24 @@ swkb_status swkb_propagate_stations(swkb_plan_t plan, const void* u, int32_t q, 
 swkb_status swkb_modal_reference(const swkb_params* p, const void* u0, const double* xs, int32_t nx, void* out,
                                  void* hip_stream);
 
-/* Copy the plan's current field (device complex128[N]) into out (device).
- * Returns SWKB_ERR_STATE before the first swkb_propagate. */
-swkb_status swkb_field(swkb_plan_t plan, void* out, void* hip_stream);
+/* Copy the field on screen q (device complex128[N]) into out (device): the
+ * field on Gamma_q, q = 0 .. n_screens (Sec. 2.1.2: the method yields the
+ * field on the screens).  q = -1 asks for the plan's current field (screen
+ * swkb_current_screen).  Other screens are held only with keep_history = 1:
+ * every screen a propagation passed through or ended on (the input of
+ * swkb_propagate included) since the plan was built, the latest value of each.
+ * SWKB_ERR_STATE if screen q is not held (before the first swkb_propagate,
+ * or keep_history = 0 and q is not the current screen); SWKB_ERR_ARG for q
+ * outside [-1, n_screens]. */
+swkb_status swkb_field(swkb_plan_t plan, int32_t q, void* out, void* hip_stream);
 
 /* Current screen index of the plan's field (-1 before the first propagate). */
 int32_t swkb_current_screen(swkb_plan_t plan);
 
 /* Synchronises hip_stream, copies the counters to *out (host) and returns
- * SWKB_ERR_CAUSTIC if out->significant > 0, else SWKB_OK. */
+ * SWKB_ERR_CAUSTIC if out->significant > 0 (a mode that matters met a
+ * caustic inside a screen, against the Remark of Sec. 2.1.2), else
+ * SWKB_ERR_EVANESCENT if out->significant_evanescent > 0, else SWKB_OK. */
 swkb_status swkb_diagnostics(swkb_plan_t plan, void* hip_stream, swkb_counters* out);
 
 /* Enable (1) or disable (0) HIP graphs for swkb_propagate: the first call
@@ -240,7 +270,12 @@ swkb_status swkb_profile_read(swkb_plan_t plan, void* hip_stream, swkb_timing* o
 void swkb_destroy(swkb_plan_t plan);
 
 const char* swkb_status_string(swkb_status s);
+/* Message of the last failure on the calling thread (any entry point). */
 const char* swkb_last_error(void);
+/* Message of the last failure of a call on this plan (from any thread; ""
+ * if none).  The string stays valid until the next failing call on the plan
+ * or swkb_destroy. */
+const char* swkb_plan_error(swkb_plan_t plan);
 
 /* ---- stage entry points, for checking each step on its own ---------- */
 

@@ -40,7 +40,8 @@ class _Params(C.Structure):
 
 class Counters(C.Structure):
     _fields_ = [("caustic_rays", C.c_int64), ("dead_rays", C.c_int64),
-                ("folded_modes", C.c_int64), ("significant", C.c_int64)]
+                ("folded_modes", C.c_int64), ("significant", C.c_int64),
+                ("evanescent_modes", C.c_int64), ("significant_evanescent", C.c_int64)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -88,6 +88,8 @@ typedef struct {
   int64_t dead_rays;     /* rays dead at launch or on the way             */
   int64_t folded_modes;  /* modes whose live arrivals are not increasing  */
   int64_t significant;   /* caustic/folded modes with |c_n| > caustic_tol max|c| */
+  int64_t evanescent_modes;       /* modes of which no ray arrived live       */
+  int64_t significant_evanescent; /* of those, modes with |c_n| > caustic_tol max|c| */
 } or_counters;
 
 typedef struct { double z, q, psi, Zs, Qs; } ray_state;
@@ -436,6 +438,7 @@ int or_screen(const or_params* P, int q, const double* u_in, double* u_out, or_c
   int32_t* flag = (int32_t*)malloc(sizeof(int32_t) * MR);
   int32_t* fold = (int32_t*)malloc(sizeof(int32_t) * M);
   int32_t* caus = (int32_t*)malloc(sizeof(int32_t) * M);
+  int32_t* nolive = (int32_t*)malloc(sizeof(int32_t) * M);
   int64_t n_caustic = 0, n_dead = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : n_caustic, n_dead)
   for (int j = 0; j < M; ++j) {
@@ -444,10 +447,12 @@ int or_screen(const or_params* P, int q, const double* u_in, double* u_out, or_c
     fold[j] = folded(R, Z + o, flag + o);
     search_keys(R, Z + o, flag + o, key + o);
     caus[j] = fold[j];
+    int dead_here = 0;
     for (int r = 0; r < R; ++r) {
       if (flag[o + r] == OR_RAY_CAUSTIC) { ++n_caustic; caus[j] = 1; }
-      if (flag[o + r] == OR_RAY_DEAD || flag[o + r] == OR_RAY_DEAD_LAUNCH) ++n_dead;
+      if (flag[o + r] == OR_RAY_DEAD || flag[o + r] == OR_RAY_DEAD_LAUNCH) { ++n_dead; ++dead_here; }
     }
+    nolive[j] = dead_here == R; /* every ray evanescent: the mode carries nothing across */
   }
   if (cnt) {
     double cmax = 0.0;
@@ -457,6 +462,8 @@ int or_screen(const or_params* P, int q, const double* u_in, double* u_out, or_c
     for (int j = 0; j < M; ++j) {
       cnt->folded_modes += fold[j];
       if (caus[j] && hypot(c[2 * j], c[2 * j + 1]) > P->caustic_tol * cmax) cnt->significant++;
+      cnt->evanescent_modes += nolive[j];
+      if (nolive[j] && hypot(c[2 * j], c[2 * j + 1]) > P->caustic_tol * cmax) cnt->significant_evanescent++;
     }
   }
   /* step 4: u'(z_m) = sum_n c_n a_n(z_m) exp(i k psi_n(z_m)), summed in mode order */
@@ -478,7 +485,7 @@ int or_screen(const or_params* P, int q, const double* u_in, double* u_out, or_c
     u_out[2 * m] = w * re;
     u_out[2 * m + 1] = w * im;
   }
-  free(c); free(Z); free(psi); free(qq); free(amp); free(key); free(flag); free(fold); free(caus);
+  free(c); free(Z); free(psi); free(qq); free(amp); free(key); free(flag); free(fold); free(caus); free(nolive);
   return 0;
 }
 

@@ -5,4 +5,4 @@ HIP sources in csrc/ by ``paper_2301_03814_amd.build``; ``swkb`` is its thin
 Python binding.
 """
 from .swkb import (BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC, FP64, MIXED, Multi, PatchPlan, Plan, Server, SwkbError,  # noqa: F401
-                   load, make_params, modal_reference, workspace_bytes)
+                   footprint, load, make_params, modal_reference, workspace_bytes)

@@ -11,6 +11,7 @@
 
 #include <rocblas/rocblas.h>
 
+#include "plan_guard.h"
 #include "swkb_internal.h"
 
 namespace swkb {
@@ -74,6 +75,7 @@ std::string validate(const swkb_params* p) {
   if (p->propagator == SWKB_PROP_MATRIX && p->medium_kind == SWKB_MEDIUM_GAUSSSUM)
     return "SWKB_PROP_MATRIX needs a medium that does not depend on x";
   if (p->max_batch < 1 || p->max_batch > 4096) return "max_batch must be in [1, 4096]";
+  if (p->keep_history != 0 && p->keep_history != 1) return "keep_history must be 0 or 1";
   return "";
 }
 
@@ -137,7 +139,8 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, cpol, part, tmat, counters;
+  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, cpol, part, tmat, hist,
+      counters;
   // one ray-record slot (offsets from its start); nslots of them from slot0
   size_t mtab, D, Pp, G, A, cz, cidx, tstart, mflag, mcaus, mdead, mwork, wcount;
   size_t slot0, slot_bytes;
@@ -209,6 +212,7 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.cpol = take(p->precision == SWKB_MIXED ? sizeof(float2) * g.M : 0);
   L.part = take(sizeof(double2) * (size_t)g.N * partial_groups(g) * B);
   L.tmat = take(use_matrix(p) ? matrix_bytes(p) : 0);
+  L.hist = take(p->keep_history ? sizeof(double2) * (size_t)g.N * (size_t)(p->n_screens + 1) : 0);
   L.counters = take(sizeof(unsigned long long) * 32);
   // ray-record slots: two for media that change with x (march and sum overlap)
   L.slot0 = o;
@@ -415,7 +419,9 @@ static swkb_status enqueue_screens(swkb_plan_s* pl, const void* u_in, int q_begi
   auto fft = [&](int) { return timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, 1, st); }); };
   auto sum = [&](int q) {
     hipError_t e;
-    double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * g.N : nullptr;
+    double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * g.N
+                    : pl->hist_on   ? pl->H + (size_t)(q + 1) * g.N
+                                    : nullptr;
     if (pl->use_matrix)
       e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->u, hist, 1, st); });
     else
@@ -450,22 +456,26 @@ static void destroy_graphs(swkb_plan_s* pl) {
 }
 
 // The same screens through a HIP graph: captured on the plan's capture
-// stream the first time a (u_in, q_begin, q_end, history) combination is
-// seen, replayed afterwards.  The captured sequence marches every screen
+// stream the first time a (u_in, q_begin, q_end, history, field buffer)
+// combination is seen, replayed afterwards.  The captured sequence marches every screen
 // itself (the ray slots are not reused across calls) and holds no memset;
 // the caller's stream is joined to the capture stream by events.
 static swkb_status propagate_graph(swkb_plan_s* pl, const void* u_in, int q_begin, int q_end, void* history,
                                    hipStream_t st) {
   swkb_plan_s::GraphEntry* hit = nullptr;
   for (auto& ge : pl->graphs)
-    if (ge.u_in == u_in && ge.q0 == q_begin && ge.q1 == q_end && ge.hist == history) hit = &ge;
+    if (ge.u_in == u_in && ge.q0 == q_begin && ge.q1 == q_end && ge.hist == history && ge.u == pl->u &&
+        ge.hist_on == pl->hist_on)
+      hit = &ge;
+  // Rays that do not change with x are marched outside the graph, once;
+  // other calls (fields between screens) may have put other rays into the
+  // slot since, so the check runs before every replay too.
+  if (!pl->use_matrix && pl->x_invariant) {
+    swkb_status s = ensure_rays(pl, q_begin, st);
+    if (s != SWKB_OK) return s;
+  }
   hipError_t e = hipSuccess;
   if (!hit) {
-    // rays that do not change with x are marched outside the graph
-    if (!pl->use_matrix && pl->x_invariant) {
-      swkb_status s = ensure_rays(pl, q_begin, st);
-      if (s != SWKB_OK) return s;
-    }
     if (pl->graphs.size() >= 4) {
       (void)hipGraphExecDestroy(pl->graphs.front().exec);
       (void)hipGraphDestroy(pl->graphs.front().graph);
@@ -495,7 +505,7 @@ static swkb_status propagate_graph(swkb_plan_s* pl, const void* u_in, int q_begi
       (void)hipGraphDestroy(graph);
       return hip_fail(e, "graph instantiate");
     }
-    pl->graphs.push_back({u_in, q_begin, q_end, history, graph, exec});
+    pl->graphs.push_back({u_in, q_begin, q_end, history, pl->u, pl->hist_on, graph, exec});
     hit = &pl->graphs.back();
   } else {
     e = hipEventRecord(pl->ev_g0, st);
@@ -513,6 +523,54 @@ static swkb_status propagate_graph(swkb_plan_s* pl, const void* u_in, int q_begi
     select_slot(pl, (q_end - 1) & 1);
   }
   return SWKB_OK;
+}
+
+// Body of swkb_propagate (the caller holds the plan).
+swkb_status swkb::propagate_impl(swkb_plan_s* pl, const void* u_in, int q_begin, int q_end, void* history,
+                                 hipStream_t st) {
+  if (q_begin < 0 || q_end < q_begin || q_end > pl->p.n_screens)
+    return fail(SWKB_ERR_ARG, "need 0 <= q_begin <= q_end <= n_screens");
+  if (!u_in && pl->cur_q != q_begin)
+    return fail(SWKB_ERR_STATE, "u_in is NULL but the plan's field is not on screen q_begin");
+  if (q_end == q_begin) {
+    if (u_in) {
+      hipError_t e = hipMemcpyAsync(pl->u, u_in, sizeof(double2) * pl->g.N, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "field copy");
+    }
+    pl->cur_q = q_begin;
+    return SWKB_OK;
+  }
+  if (pl->graphs_on && !pl->prof_on) return propagate_graph(pl, u_in, q_begin, q_end, history, st);
+  return enqueue_screens(pl, u_in, q_begin, q_end, history, st);
+}
+
+// A public call on plan pl that enqueues on stream st (use_stream = false:
+// host-only call).  SWKB_ERR_BUSY without running body while another thread
+// is inside a call on the plan, or while the previous call's work on
+// another stream has not finished; afterwards the end of the call's work is
+// marked on st.  Failures are also kept as the plan's last error.
+template <typename F>
+static swkb_status plan_call(swkb_plan_s* pl, hipStream_t st, bool use_stream, F&& body) {
+  PlanGuard guard(&pl->busy);
+  if (!guard.held()) {
+    set_error("plan is in use by another thread");
+    return SWKB_ERR_BUSY;
+  }
+  if (use_stream && pl->has_last && st != pl->last_st && hipEventQuery(pl->ev_done) == hipErrorNotReady) {
+    set_error("the plan's previous call is still running on another stream");
+    pl->err = g_err;
+    return SWKB_ERR_BUSY;
+  }
+  const swkb_status s = body();
+  if (s != SWKB_OK) pl->err = g_err;
+  if (use_stream) {
+    // a stream being captured by the caller gets no marker (its work runs at replay)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    pl->has_last = hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone &&
+                   hipEventRecord(pl->ev_done, st) == hipSuccess;
+    pl->last_st = st;
+  }
+  return s;
 }
 
 extern "C" {
@@ -567,8 +625,10 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->gterm = ws + L.gterm;
     pl->gczl = ws + L.gczl;
     pl->u = reinterpret_cast<double2*>(ws + L.u);
-    pl->ub = reinterpret_cast<double2*>(ws + L.ub);
-    pl->cf = reinterpret_cast<float2*>(ws + L.cf);
+    // buffers of zero size share their offset with the next one: leave them unset
+    pl->ub = p->max_batch > 1 ? reinterpret_cast<double2*>(ws + L.ub) : nullptr;
+    pl->cf = p->max_batch > 1 && use_matrix(p) && p->precision == SWKB_MIXED ? reinterpret_cast<float2*>(ws + L.cf)
+                                                                              : nullptr;
     pl->cpol = p->precision == SWKB_MIXED ? reinterpret_cast<float2*>(ws + L.cpol) : nullptr;
     pl->max_batch = p->max_batch;
     pl->sum_fields = 1;
@@ -626,6 +686,18 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->ev_used = 0;
     pl->counters = reinterpret_cast<unsigned long long*>(ws + L.counters);
     pl->counters_scratch = pl->counters + 16;
+    pl->H = p->keep_history ? reinterpret_cast<double2*>(ws + L.hist) : nullptr;
+    pl->hvalid.assign(p->keep_history ? (size_t)p->n_screens + 1 : 0, 0);
+    pl->hist_on = 0;
+    pl->busy = 0;
+    pl->last_st = nullptr;
+    pl->has_last = 0;
+    pl->ev_done = nullptr;
+    if (hipEventCreateWithFlags(&pl->ev_done, hipEventDisableTiming) != hipSuccess) {
+      destroy_streams(pl);
+      delete pl;
+      return fail(SWKB_ERR_DEVICE, "swkb_plan: event creation failed");
+    }
 
     // mode tables: xi_n = 2 pi n / (k P h); reference pbar and range phase
     std::vector<double> xi(g.M), pbar(g.M), e1r(g.M), frac(g.M);
@@ -718,10 +790,13 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host tables go out of scope
     if (e != hipSuccess) {
       destroy_streams(pl);
+      (void)hipEventDestroy(pl->ev_done);
       delete pl;
       return hip_fail(e, "swkb_plan upload");
     }
   } catch (const std::exception& ex) {
+    destroy_streams(pl);
+    if (pl->ev_done) (void)hipEventDestroy(pl->ev_done);
     delete pl;
     return fail(SWKB_ERR_NOMEM, std::string("swkb_plan: ") + ex.what());
   }
@@ -732,21 +807,25 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
 swkb_status swkb_propagate(swkb_plan_t pl, const void* u_in, int32_t q_begin, int32_t q_end, void* history,
                            void* hip_stream) {
   if (!pl) return fail(SWKB_ERR_ARG, "plan is NULL");
-  if (q_begin < 0 || q_end < q_begin || q_end > pl->p.n_screens)
-    return fail(SWKB_ERR_ARG, "need 0 <= q_begin <= q_end <= n_screens");
-  if (!u_in && pl->cur_q != q_begin)
-    return fail(SWKB_ERR_STATE, "u_in is NULL but the plan's field is not on screen q_begin");
   hipStream_t st = (hipStream_t)hip_stream;
-  if (q_end == q_begin) {
-    if (u_in) {
-      hipError_t e = hipMemcpyAsync(pl->u, u_in, sizeof(double2) * pl->g.N, hipMemcpyDeviceToDevice, st);
-      if (e != hipSuccess) return hip_fail(e, "field copy");
-    }
-    pl->cur_q = q_begin;
+  return plan_call(pl, st, true, [&]() -> swkb_status {
+    pl->hist_on = pl->H != nullptr;
+    const swkb_status s = propagate_impl(pl, u_in, q_begin, q_end, history, st);
+    pl->hist_on = 0;
+    if (s != SWKB_OK || !pl->H) return s;
+    // kept history: the input screen, and the caller's history rows (the
+    // kernels wrote the plan's rows directly when the caller gave none)
+    const size_t row = sizeof(double2) * pl->g.N;
+    hipError_t e = hipSuccess;
+    if (u_in)
+      e = hipMemcpyAsync(pl->H + (size_t)q_begin * pl->g.N, u_in, row, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && history && q_end > q_begin)
+      e = hipMemcpyAsync(pl->H + (size_t)(q_begin + 1) * pl->g.N, history, row * (q_end - q_begin),
+                         hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "kept history copy");
+    for (int q = q_begin; q <= q_end; ++q) pl->hvalid[q] = 1;
     return SWKB_OK;
-  }
-  if (pl->graphs_on && !pl->prof_on) return propagate_graph(pl, u_in, q_begin, q_end, history, st);
-  return enqueue_screens(pl, u_in, q_begin, q_end, history, st);
+  });
 }
 
 swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch, int32_t q_begin, int32_t q_end,
@@ -756,69 +835,73 @@ swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch
   if (q_begin < 0 || q_end <= q_begin || q_end > pl->p.n_screens)
     return fail(SWKB_ERR_ARG, "need 0 <= q_begin < q_end <= n_screens");
   hipStream_t st = (hipStream_t)hip_stream;
-  const Geometry& g = pl->g;
-  if (batch == 1) {
-    // one field: the single-field kernels, without touching the plan's field
-    double2* keep = pl->u;
-    pl->u = pl->ub ? pl->ub : pl->u;
-    const int keep_q = pl->cur_q;
-    swkb_status s = SWKB_OK;
-    if (pl->u == keep) {
-      // no separate batch buffer (max_batch == 1): the single-field state is consumed
-      s = swkb_propagate(pl, u_in, q_begin, q_end, history, hip_stream);
+  return plan_call(pl, st, true, [&]() -> swkb_status {
+    const Geometry& g = pl->g;
+    pl->hist_on = 0;  // a batch never writes the plan's kept history
+    if (batch == 1) {
+      // one field: the single-field kernels, without touching the plan's field
+      double2* keep = pl->u;
+      const int keep_q = pl->cur_q;
+      swkb_status s = SWKB_OK;
+      if (!pl->ub) {
+        // no separate batch buffer (max_batch == 1): the single-field state is consumed
+        s = propagate_impl(pl, u_in, q_begin, q_end, history, st);
+        if (s == SWKB_OK && u_out) {
+          hipError_t e = hipMemcpyAsync(u_out, pl->u, sizeof(double2) * g.N, hipMemcpyDeviceToDevice, st);
+          if (e != hipSuccess) s = hip_fail(e, "field copy");
+        }
+        pl->cur_q = -1;
+        return s;
+      }
+      pl->u = pl->ub;
+      s = propagate_impl(pl, u_in, q_begin, q_end, history, st);
       if (s == SWKB_OK && u_out) {
         hipError_t e = hipMemcpyAsync(u_out, pl->u, sizeof(double2) * g.N, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) s = hip_fail(e, "field copy");
       }
-      pl->cur_q = -1;
+      pl->u = keep;
+      pl->cur_q = keep_q;
       return s;
     }
-    s = swkb_propagate(pl, u_in, q_begin, q_end, history, hip_stream);
-    if (s == SWKB_OK && u_out) {
-      hipError_t e = hipMemcpyAsync(u_out, pl->u, sizeof(double2) * g.N, hipMemcpyDeviceToDevice, st);
-      if (e != hipSuccess) s = hip_fail(e, "field copy");
+    if (pl->use_matrix && !pl->blas) {
+      rocblas_handle h = nullptr;
+      if (rocblas_create_handle(&h) != rocblas_status_success)
+        return fail(SWKB_ERR_DEVICE, "rocblas_create_handle failed");
+      pl->blas = h;
     }
-    pl->u = keep;
-    pl->cur_q = keep_q;
-    return s;
-  }
-  if (pl->use_matrix && !pl->blas) {
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success) return fail(SWKB_ERR_DEVICE, "rocblas_create_handle failed");
-    pl->blas = h;
-  }
-  const double2* src = static_cast<const double2*>(u_in);
-  pl->sum_fields = batch;
-  auto fft = [&](int) { return timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, batch, st); }); };
-  auto sum = [&](int q) {
-    hipError_t e;
-    double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * batch * g.N : nullptr;
-    if (pl->use_matrix)
-      e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->ub, hist, batch, st); });
-    else
-      e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->ub, hist, batch, st); });
-    src = pl->ub;
-    return e;
-  };
-  if (overlap(pl)) {
-    swkb_status s = pipelined(pl, q_begin, q_end, st, fft, sum);
-    if (s != SWKB_OK) return s;
-  } else {
-    for (int q = q_begin; q < q_end; ++q) {
-      if (!pl->use_matrix) {
-        swkb_status s = ensure_rays(pl, q, st);
-        if (s != SWKB_OK) return s;
+    const double2* src = static_cast<const double2*>(u_in);
+    pl->sum_fields = batch;
+    auto fft = [&](int) { return timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, batch, st); }); };
+    auto sum = [&](int q) {
+      hipError_t e;
+      double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * batch * g.N : nullptr;
+      if (pl->use_matrix)
+        e = timed(pl, kProfSuper, st, [&] { return launch_apply_matrix(*pl, pl->ub, hist, batch, st); });
+      else
+        e = timed(pl, kProfSuper, st, [&] { return launch_superpose(*pl, pl->ub, hist, batch, st); });
+      src = pl->ub;
+      return e;
+    };
+    if (overlap(pl)) {
+      swkb_status s = pipelined(pl, q_begin, q_end, st, fft, sum);
+      if (s != SWKB_OK) return s;
+    } else {
+      for (int q = q_begin; q < q_end; ++q) {
+        if (!pl->use_matrix) {
+          swkb_status s = ensure_rays(pl, q, st);
+          if (s != SWKB_OK) return s;
+        }
+        hipError_t e = fft(q);
+        if (e == hipSuccess) e = sum(q);
+        if (e != hipSuccess) return hip_fail(e, "batched screen launch");
       }
-      hipError_t e = fft(q);
-      if (e == hipSuccess) e = sum(q);
-      if (e != hipSuccess) return hip_fail(e, "batched screen launch");
     }
-  }
-  if (u_out) {
-    hipError_t e = hipMemcpyAsync(u_out, pl->ub, sizeof(double2) * g.N * batch, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "field copy");
-  }
-  return SWKB_OK;
+    if (u_out) {
+      hipError_t e = hipMemcpyAsync(u_out, pl->ub, sizeof(double2) * g.N * batch, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "field copy");
+    }
+    return SWKB_OK;
+  });
 }
 
 swkb_status swkb_propagate_stations(swkb_plan_t pl, const void* u, int32_t q, const int32_t* stations, int32_t n,
@@ -829,6 +912,7 @@ swkb_status swkb_propagate_stations(swkb_plan_t pl, const void* u, int32_t q, co
   for (int s = 0; s < n; ++s)
     if (stations[s] < 1 || stations[s] > g.S) return fail(SWKB_ERR_ARG, "stations must be in [1, rk4_steps]");
   hipStream_t st = (hipStream_t)hip_stream;
+  return plan_call(pl, st, true, [&]() -> swkb_status {
   const double hx = pl->p.dx / pl->p.rk4_steps;
   const int k = pl->x_invariant ? 0 : slot_of(pl, q);  // slot the station rays go through
   select_slot(pl, k);
@@ -878,93 +962,120 @@ swkb_status swkb_propagate_stations(swkb_plan_t pl, const void* u, int32_t q, co
     return fail(SWKB_ERR_NOMEM, std::string("stations: ") + ex.what());
   }
   return SWKB_OK;
+  });
 }
 
-swkb_status swkb_field(swkb_plan_t pl, void* out, void* hip_stream) {
+swkb_status swkb_field(swkb_plan_t pl, int32_t q, void* out, void* hip_stream) {
   if (!pl || !out) return fail(SWKB_ERR_ARG, "plan or out is NULL");
-  if (pl->cur_q < 0) return fail(SWKB_ERR_STATE, "no field yet: call swkb_propagate first");
-  hipError_t e = hipMemcpyAsync(out, pl->u, sizeof(double2) * pl->g.N, hipMemcpyDeviceToDevice,
-                                (hipStream_t)hip_stream);
-  if (e != hipSuccess) return hip_fail(e, "field copy");
-  return SWKB_OK;
+  if (q < -1 || q > pl->p.n_screens) return fail(SWKB_ERR_ARG, "q must be in [-1, n_screens]");
+  hipStream_t st = (hipStream_t)hip_stream;
+  return plan_call(pl, st, true, [&]() -> swkb_status {
+    const double2* src = nullptr;
+    if (q == -1 || q == pl->cur_q) {
+      if (pl->cur_q < 0) return fail(SWKB_ERR_STATE, "no field yet: call swkb_propagate first");
+      src = pl->u;
+    } else if (pl->H && pl->hvalid[q]) {
+      src = pl->H + (size_t)q * pl->g.N;
+    } else {
+      return fail(SWKB_ERR_STATE, pl->H ? "screen q has not been reached by a propagation of this plan"
+                                        : "only the current screen is held (keep_history = 0)");
+    }
+    hipError_t e = hipMemcpyAsync(out, src, sizeof(double2) * pl->g.N, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "field copy");
+    return SWKB_OK;
+  });
 }
 
 int32_t swkb_current_screen(swkb_plan_t pl) { return pl ? pl->cur_q : -1; }
 
 swkb_status swkb_diagnostics(swkb_plan_t pl, void* hip_stream, swkb_counters* out) {
   if (!pl || !out) return fail(SWKB_ERR_ARG, "plan or out is NULL");
-  unsigned long long h[9];
-  hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
-  if (e == hipSuccess) e = hipMemcpy(h, pl->counters, sizeof(h), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "diagnostics");
-  out->caustic_rays = (int64_t)h[0];
-  out->dead_rays = (int64_t)h[1];
-  out->folded_modes = (int64_t)h[2];
-  out->significant = (int64_t)h[3];
-  out->screens = (int64_t)h[4];
-  out->rhs_evals = (int64_t)h[5];
-  out->medium_evals = (int64_t)h[6];
-  out->medium_terms = (int64_t)h[7];
-  out->table_evals = (int64_t)h[8];
-  if (out->significant > 0) return fail(SWKB_ERR_CAUSTIC, "a significant mode met a caustic inside a screen");
-  return SWKB_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  return plan_call(pl, st, true, [&]() -> swkb_status {
+    unsigned long long h[11];
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(h, pl->counters, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics");
+    out->caustic_rays = (int64_t)h[0];
+    out->dead_rays = (int64_t)h[1];
+    out->folded_modes = (int64_t)h[2];
+    out->significant = (int64_t)h[3];
+    out->screens = (int64_t)h[4];
+    out->rhs_evals = (int64_t)h[5];
+    out->medium_evals = (int64_t)h[6];
+    out->medium_terms = (int64_t)h[7];
+    out->table_evals = (int64_t)h[8];
+    out->evanescent_modes = (int64_t)h[9];
+    out->significant_evanescent = (int64_t)h[10];
+    if (out->significant > 0) return fail(SWKB_ERR_CAUSTIC, "a significant mode met a caustic inside a screen");
+    if (out->significant_evanescent > 0)
+      return fail(SWKB_ERR_EVANESCENT, "a significant mode had no live ray (evanescent)");
+    return SWKB_OK;
+  });
 }
 
 swkb_status swkb_graphs(swkb_plan_t pl, int32_t enable) {
   if (!pl) return fail(SWKB_ERR_ARG, "plan is NULL");
-  if (enable && !pl->cs) {
-    SharedStreams ss;
-    hipError_t e = shared_streams(&ss);
-    pl->cs = ss.cs;
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_g0, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_g1, hipEventDisableTiming);
-    if (e != hipSuccess) {
-      destroy_graphs(pl);
-      return hip_fail(e, "graph stream");
+  return plan_call(pl, nullptr, false, [&]() -> swkb_status {
+    if (enable && !pl->cs) {
+      SharedStreams ss;
+      hipError_t e = shared_streams(&ss);
+      pl->cs = ss.cs;
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_g0, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_g1, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        destroy_graphs(pl);
+        return hip_fail(e, "graph stream");
+      }
     }
-  }
-  if (!enable) {
-    // the plan's streams may still run a replay: wait before releasing the graphs
-    if (pl->cs) (void)hipStreamSynchronize(pl->cs);
-    destroy_graphs(pl);
-  }
-  pl->graphs_on = enable ? 1 : 0;
-  return SWKB_OK;
+    if (!enable) {
+      // the plan's streams may still run a replay: wait before releasing the graphs
+      if (pl->cs) (void)hipStreamSynchronize(pl->cs);
+      destroy_graphs(pl);
+    }
+    pl->graphs_on = enable ? 1 : 0;
+    return SWKB_OK;
+  });
 }
 
 swkb_status swkb_profile(swkb_plan_t pl, int32_t enable) {
   if (!pl) return fail(SWKB_ERR_ARG, "plan is NULL");
-  pl->prof_on = enable ? 1 : 0;
-  return SWKB_OK;
+  return plan_call(pl, nullptr, false, [&]() -> swkb_status {
+    pl->prof_on = enable ? 1 : 0;
+    return SWKB_OK;
+  });
 }
 
 swkb_status swkb_profile_read(swkb_plan_t pl, void* hip_stream, swkb_timing* out) {
   if (!pl || !out) return fail(SWKB_ERR_ARG, "plan or out is NULL");
-  hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
-  if (e != hipSuccess) return hip_fail(e, "profile read");
-  double ms[kProfClasses] = {0, 0, 0, 0, 0};
-  int64_t n[kProfClasses] = {0, 0, 0, 0, 0};
-  for (const auto& mk : pl->marks) {
-    float t = 0.f;
-    e = hipEventSynchronize(pl->ev_pool[mk.b]);
-    if (e == hipSuccess) e = hipEventElapsedTime(&t, pl->ev_pool[mk.a], pl->ev_pool[mk.b]);
+  hipStream_t st = (hipStream_t)hip_stream;
+  return plan_call(pl, st, true, [&]() -> swkb_status {
+    hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "profile read");
-    ms[mk.cls] += t;
-    n[mk.cls] += 1;
-  }
-  pl->marks.clear();
-  pl->ev_used = 0;
-  out->march_ms = ms[kProfMarch];
-  out->scan_ms = ms[kProfScan];
-  out->fft_ms = ms[kProfFft];
-  out->superpose_ms = ms[kProfSuper];
-  out->march_launches = n[kProfMarch];
-  out->scan_launches = n[kProfScan];
-  out->fft_launches = n[kProfFft];
-  out->superpose_launches = n[kProfSuper];
-  out->table_ms = ms[kProfTable];
-  out->table_launches = n[kProfTable];
-  return SWKB_OK;
+    double ms[kProfClasses] = {0, 0, 0, 0, 0};
+    int64_t n[kProfClasses] = {0, 0, 0, 0, 0};
+    for (const auto& mk : pl->marks) {
+      float t = 0.f;
+      e = hipEventSynchronize(pl->ev_pool[mk.b]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, pl->ev_pool[mk.a], pl->ev_pool[mk.b]);
+      if (e != hipSuccess) return hip_fail(e, "profile read");
+      ms[mk.cls] += t;
+      n[mk.cls] += 1;
+    }
+    pl->marks.clear();
+    pl->ev_used = 0;
+    out->march_ms = ms[kProfMarch];
+    out->scan_ms = ms[kProfScan];
+    out->fft_ms = ms[kProfFft];
+    out->superpose_ms = ms[kProfSuper];
+    out->march_launches = n[kProfMarch];
+    out->scan_launches = n[kProfScan];
+    out->fft_launches = n[kProfFft];
+    out->superpose_launches = n[kProfSuper];
+    out->table_ms = ms[kProfTable];
+    out->table_launches = n[kProfTable];
+    return SWKB_OK;
+  });
 }
 
 void swkb_destroy(swkb_plan_t pl) {
@@ -974,6 +1085,7 @@ void swkb_destroy(swkb_plan_t pl) {
   if (pl->cs) (void)hipStreamSynchronize(pl->cs);
   destroy_graphs(pl);
   destroy_streams(pl);
+  if (pl->ev_done) (void)hipEventDestroy(pl->ev_done);
   delete pl;
 }
 
@@ -985,19 +1097,31 @@ const char* swkb_status_string(swkb_status s) {
     case SWKB_ERR_DEVICE: return "HIP runtime error";
     case SWKB_ERR_CAUSTIC: return "caustic inside a screen";
     case SWKB_ERR_STATE: return "call out of order";
+    case SWKB_ERR_EVANESCENT: return "a significant mode was evanescent";
+    case SWKB_ERR_BUSY: return "plan busy";
   }
   return "unknown status";
 }
 
 const char* swkb_last_error(void) { return g_err.c_str(); }
 
+const char* swkb_plan_error(swkb_plan_t pl) { return pl ? pl->err.c_str() : ""; }
+
+size_t swkb_footprint(const swkb_params* p) {
+  const size_t ws = swkb_workspace_bytes(p);
+  if (ws == 0) return 0;
+  return ws + sizeof(double2) * (size_t)p->n_z + 4096;
+}
+
 swkb_status swkb_stage_modes(swkb_plan_t pl, const void* u, void* c, void* hip_stream) {
   if (!pl || !u || !c) return fail(SWKB_ERR_ARG, "NULL argument");
   hipStream_t st = (hipStream_t)hip_stream;
-  hipError_t e = launch_fft_modes(*pl, static_cast<const double2*>(u), 1, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c, pl->c, sizeof(double2) * pl->g.M, hipMemcpyDeviceToDevice, st);
-  if (e != hipSuccess) return hip_fail(e, "stage modes");
-  return SWKB_OK;
+  return plan_call(pl, st, true, [&]() -> swkb_status {
+    hipError_t e = launch_fft_modes(*pl, static_cast<const double2*>(u), 1, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c, pl->c, sizeof(double2) * pl->g.M, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "stage modes");
+    return SWKB_OK;
+  });
 }
 
 swkb_status swkb_stage_rays(swkb_plan_t pl, int32_t q, void* Z, void* psi, void* qz, void* amp, void* flag,
@@ -1005,12 +1129,15 @@ swkb_status swkb_stage_rays(swkb_plan_t pl, int32_t q, void* Z, void* psi, void*
   if (!pl || !Z || !psi || !qz || !amp || !flag) return fail(SWKB_ERR_ARG, "NULL argument");
   if (q < 0 || q >= pl->p.n_screens) return fail(SWKB_ERR_ARG, "q out of range");
   hipStream_t st = (hipStream_t)hip_stream;
-  swkb_status s = ensure_rays(pl, q, st);
-  if (s != SWKB_OK) return s;
-  hipError_t e = launch_export_rays(*pl, q, static_cast<double*>(Z), static_cast<double*>(psi),
-                                    static_cast<double*>(qz), static_cast<double*>(amp), static_cast<int*>(flag), st);
-  if (e != hipSuccess) return hip_fail(e, "stage rays");
-  return SWKB_OK;
+  return plan_call(pl, st, true, [&]() -> swkb_status {
+    swkb_status s = ensure_rays(pl, q, st);
+    if (s != SWKB_OK) return s;
+    hipError_t e = launch_export_rays(*pl, q, static_cast<double*>(Z), static_cast<double*>(psi),
+                                      static_cast<double*>(qz), static_cast<double*>(amp), static_cast<int*>(flag),
+                                      st);
+    if (e != hipSuccess) return hip_fail(e, "stage rays");
+    return SWKB_OK;
+  });
 }
 
 int32_t swkb_num_rays(swkb_plan_t pl) { return pl ? pl->g.R : 0; }

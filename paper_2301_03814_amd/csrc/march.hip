@@ -720,7 +720,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(Geometry g, DevRecor
     }
   }
   __syncthreads();
-  if (tid == 0) rec.mflag[j] = (sfold ? 1 : 0) | (rec.mcaus[j] > 0 ? 2 : 0);
+  if (tid == 0) rec.mflag[j] = (sfold ? 1 : 0) | (rec.mcaus[j] > 0 ? 2 : 0) | (rec.mdead[j] >= g.R ? 4 : 0);
 }
 
 // Full records in FP64 for the stage entry point.

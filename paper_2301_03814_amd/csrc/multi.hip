@@ -240,6 +240,7 @@ swkb_status swkb_multi_create(const swkb_plan_t* plans, int32_t n, swkb_multi_t*
     if (!pl->use_matrix || pl->precision != SWKB_MIXED || pl->g.N % 512 != 0)
       return fail(SWKB_ERR_ARG, "plan " + std::to_string(i) +
                                     " must use the mode-function matrix, SWKB_MIXED and n_z % 512 == 0");
+    if (pl->H) return fail(SWKB_ERR_ARG, "plan " + std::to_string(i) + " keeps its history (keep_history = 1)");
     for (int j = 0; j < i; ++j)
       if (plans[j] == pl) return fail(SWKB_ERR_ARG, "plan listed twice");
     if ((size_t)(pl->g.N / 512) * (size_t)max_groups(pl->g) >= (1u << kMapShift))

@@ -204,7 +204,7 @@ swkb_status enqueue_screens(swkb_patch_s* pp, const void* u_in, int q_begin, int
                            s.n, s.S, s.v);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: window");
-        const swkb_status ps = swkb_propagate(s.plan, s.v, q, q + 1, nullptr, st);
+        const swkb_status ps = swkb::propagate_impl(s.plan, s.v, q, q + 1, nullptr, st);
         if (ps != SWKB_OK) return ps;
       }
     }
@@ -278,6 +278,7 @@ swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, v
       s.sp.z_b = p->z_a + (double)(s.start + s.n) * pp->h;
       s.sp.absorber_bot = 0.0;
       s.sp.absorber_top = 0.0;
+      s.sp.keep_history = 0;
     }
   } catch (const std::exception&) {
     delete pp;

@@ -58,11 +58,7 @@ struct swkb_server_s {
 
 namespace {
 
-size_t request_footprint(const swkb_params* p) {
-  const size_t ws = swkb_workspace_bytes(p);
-  if (ws == 0) return 0;
-  return ws + sizeof(double2) * (size_t)p->n_z + 4096;
-}
+size_t request_footprint(const swkb_params* p) { return swkb_footprint(p); }
 
 void release(swkb_server_s* s, Request* r) {
   if (r->plan) swkb_destroy(r->plan);
@@ -133,7 +129,7 @@ bool advance(swkb_server_s* s, Request* r) {
   }
   r->q_next = q1;
   hipError_t e = hipSuccess;
-  if (q1 == Q) e = swkb_field(r->plan, r->u_dev, r->st) == SWKB_OK ? hipSuccess : hipErrorUnknown;
+  if (q1 == Q) e = swkb_field(r->plan, -1, r->u_dev, r->st) == SWKB_OK ? hipSuccess : hipErrorUnknown;
   if (e == hipSuccess && q1 == Q)
     e = hipMemcpyAsync(r->u0_host, r->u_dev, sizeof(double2) * r->p.n_z, hipMemcpyDeviceToHost, r->st);
   if (e == hipSuccess) e = hipEventRecord(r->ev, r->st);

@@ -612,7 +612,7 @@ __device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, c
   // largest mode energy (summed over the batch), then the counts, with
   // wavefront reductions and the wavefronts combined in order.
   __shared__ double sm[kFinWaves];
-  __shared__ unsigned long long cnt[kFinWaves][8];
+  __shared__ unsigned long long cnt[kFinWaves][10];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double emax = 0.0;
 #pragma unroll 4
@@ -630,39 +630,43 @@ __device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, c
   emax = 0.0;
   for (int k = 0; k < kFinWaves; ++k) emax = fmax(emax, sm[k]);
   const double thr = ep.caustic_tol * ep.caustic_tol * emax;
-  unsigned v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // a thread's sums fit 32 bits; 64-bit from the wavefront on
+  unsigned v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // a thread's sums fit 32 bits; 64-bit from the wavefront on
 #pragma unroll 4
   for (int j = threadIdx.x; j < g.M; j += kFinThreads) {
     const int f = rec.mflag[j];
     v[0] += rec.mcaus[j];
     v[1] += rec.mdead[j];
     v[2] += f & 1;
+    v[8] += (f >> 2) & 1;
     if (f) {
       double e = 0.0;
       for (int bb = 0; bb < batch; ++bb) {
         const double2 cv = c[(size_t)bb * g.M + j];
         e += cv.x * cv.x + cv.y * cv.y;
       }
-      if (e > thr) ++v[3];
+      if (e > thr) {
+        if (f & 3) ++v[3];  // caustic or folded
+        if (f & 4) ++v[9];  // no live ray
+      }
     }
     v[4] += (unsigned)rec.mwork[4 * j];
     v[5] += (unsigned)rec.mwork[4 * j + 1];
     v[6] += (unsigned)rec.mwork[4 * j + 2];
     v[7] += (unsigned)rec.mwork[4 * j + 3];
   }
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < 10; ++k) {
     unsigned long long w64 = v[k];
     for (int off = 32; off > 0; off >>= 1) w64 += __shfl_xor(w64, off, 64);
     if (lane == 0) cnt[wv][k] = w64;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int w = 0; w < kFinWaves; ++w)
-      for (int k = 0; k < 8; ++k) t[k] += cnt[w][k];
+      for (int k = 0; k < 10; ++k) t[k] += cnt[w][k];
     for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], t[k]);
     atomicAdd(&counters[4], 1ull);
-    for (int k = 4; k < 8; ++k) atomicAdd(&counters[k + 1], t[k]);
+    for (int k = 4; k < 10; ++k) atomicAdd(&counters[k + 1], t[k]);
   }
 }
 

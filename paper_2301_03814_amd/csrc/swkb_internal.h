@@ -44,7 +44,7 @@ struct DevRecords {
   int* cidx;      // first grid index m in [0, N] with z_m >= key_r, N + 1 if none, key_r = running
                   // maximum of live arrival heights (ray r owns the points [cidx_r, cidx_{r+1}))
   int* tstart;    // [mode][tile 0..T]: largest r with key_r <= z of the tile's first point
-  int* mflag;     // per mode: bit0 folded, bit1 has caustic rays
+  int* mflag;     // per mode: bit0 folded, bit1 has caustic rays, bit2 no live ray (all dead)
   int* mcaus;     // per mode: caustic rays this march
   int* mdead;     // per mode: dead rays this march
   int* mwork;     // per mode: RK4 evaluations, direct medium evaluations, medium terms, table reads (4 ints)
@@ -156,6 +156,8 @@ struct swkb_plan_s {
     const void* u_in;
     int q0, q1;
     void* hist;
+    double2* u;   // field buffer the graph writes (the plan's own, or the batch buffer)
+    int hist_on;  // the graph also writes the plan's kept history
     hipGraph_t graph;
     hipGraphExec_t exec;
   };
@@ -163,6 +165,19 @@ struct swkb_plan_s {
   int graphs_on;
   hipStream_t cs;                // capture and replay stream (shared by the device's plans), or NULL
   hipEvent_t ev_g0, ev_g1;
+  // fields on every screen reached (keep_history = 1): [n_screens + 1][N] in
+  // the workspace, and which of them hold a value; hist_on: the running
+  // propagation writes them (not for batches)
+  double2* H;
+  std::vector<char> hvalid;
+  int hist_on;
+  // single user: busy is taken by the thread inside a call (PlanGuard);
+  // ev_done is recorded on last_st at the end of every call
+  int busy;
+  hipEvent_t ev_done;
+  hipStream_t last_st;
+  int has_last;
+  std::string err;  // last failure of a call on this plan
   // event timing
   int prof_on;
   std::vector<hipEvent_t> ev_pool;
@@ -174,6 +189,10 @@ struct swkb_plan_s {
 namespace swkb {
 
 void set_error(const std::string& msg);
+// Screens q_begin .. q_end-1 of one field, without the single-user check of
+// the public entry point (for callers inside the library that hold the plan).
+swkb_status propagate_impl(swkb_plan_s* pl, const void* u_in, int q_begin, int q_end, void* history,
+                           hipStream_t st);
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, int batch, hipStream_t st);

@@ -15,7 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswkb.so")
 
-SWKB_OK, SWKB_ERR_ARG, SWKB_ERR_NOMEM, SWKB_ERR_DEVICE, SWKB_ERR_CAUSTIC, SWKB_ERR_STATE = range(6)
+(SWKB_OK, SWKB_ERR_ARG, SWKB_ERR_NOMEM, SWKB_ERR_DEVICE, SWKB_ERR_CAUSTIC, SWKB_ERR_STATE, SWKB_ERR_EVANESCENT,
+ SWKB_ERR_BUSY) = range(8)
 FP64, MIXED = 0, 1
 BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
 MEDIUM_LINEAR, MEDIUM_EXPGAUSS, MEDIUM_GAUSSSUM, MEDIUM_MPROFILE = 0, 1, 2, 3
@@ -29,7 +30,7 @@ EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", 
            "swkb_server_stats", "swkb_server_destroy", "swkb_graphs", "swkb_multi_create",
            "swkb_multi_get_tuning", "swkb_multi_set_tuning", "swkb_multi_tune", "swkb_multi_propagate",
            "swkb_multi_destroy", "swkb_patch_plan", "swkb_patch_info", "swkb_patch_propagate",
-           "swkb_patch_field", "swkb_patch_destroy", "swkb_patch_graphs"]
+           "swkb_patch_field", "swkb_patch_destroy", "swkb_patch_graphs", "swkb_footprint", "swkb_plan_error"]
 
 MULTI_MAX_CLASSES = 16
 
@@ -48,7 +49,7 @@ class Params(C.Structure):
         ("medium_params", C.POINTER(C.c_double)),
         ("n_medium_params", C.c_int32), ("precision", C.c_int32),
         ("eps_ref", C.c_double), ("caustic_tol", C.c_double),
-        ("propagator", C.c_int32), ("max_batch", C.c_int32),
+        ("propagator", C.c_int32), ("max_batch", C.c_int32), ("keep_history", C.c_int32),
     ]
 
 
@@ -56,7 +57,8 @@ class Counters(C.Structure):
     _fields_ = [("caustic_rays", C.c_int64), ("dead_rays", C.c_int64), ("folded_modes", C.c_int64),
                 ("significant", C.c_int64), ("screens", C.c_int64), ("rhs_evals", C.c_int64),
                 ("medium_evals", C.c_int64), ("medium_terms", C.c_int64),
-                ("table_evals", C.c_int64)]
+                ("table_evals", C.c_int64), ("evanescent_modes", C.c_int64),
+                ("significant_evanescent", C.c_int64)]
 
 
 class Timing(C.Structure):
@@ -115,9 +117,13 @@ def load(path: str = LIB_PATH):
     vp, i32, pp = C.c_void_p, C.c_int32, C.POINTER(Params)
     lib.swkb_workspace_bytes.argtypes = [pp]
     lib.swkb_workspace_bytes.restype = C.c_size_t
+    lib.swkb_footprint.argtypes = [pp]
+    lib.swkb_footprint.restype = C.c_size_t
+    lib.swkb_plan_error.argtypes = [vp]
+    lib.swkb_plan_error.restype = C.c_char_p
     lib.swkb_plan.argtypes = [pp, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.swkb_propagate.argtypes = [vp, vp, i32, i32, vp, vp]
-    lib.swkb_field.argtypes = [vp, vp, vp]
+    lib.swkb_field.argtypes = [vp, i32, vp, vp]
     lib.swkb_propagate_batch.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
     lib.swkb_propagate_batch.restype = C.c_int
     lib.swkb_propagate_stations.argtypes = [vp, vp, i32, C.POINTER(C.c_int32), i32, vp, vp]
@@ -193,13 +199,18 @@ def make_params(cfg, precision=FP64):
         absorber_top=cfg["absorber_top"], medium_params=mp.ctypes.data_as(C.POINTER(C.c_double)),
         n_medium_params=mp.size, precision=int(precision), eps_ref=cfg["eps_ref"],
         caustic_tol=cfg["caustic_tol"], propagator=int(cfg.get("propagator", PROP_AUTO)),
-        max_batch=int(cfg.get("max_batch", 1)))
+        max_batch=int(cfg.get("max_batch", 1)), keep_history=int(cfg.get("keep_history", 0)))
     p._keep = mp
     return p
 
 
 def workspace_bytes(cfg, precision=FP64) -> int:
     return int(load().swkb_workspace_bytes(C.byref(make_params(cfg, precision))))
+
+
+def footprint(cfg, precision=FP64) -> int:
+    """Device bytes one propagation request holds while it runs (swkb_footprint)."""
+    return int(load().swkb_footprint(C.byref(make_params(cfg, precision))))
 
 
 def _stream_handle(stream):
@@ -319,16 +330,23 @@ class Plan:
                                             C.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
-    def field(self, stream=None):
+    def field(self, q=-1, stream=None):
+        """The field on screen q (complex128 [N], device); q = -1: the current one."""
         import torch
         out = torch.empty(self.n_z, dtype=torch.complex128, device=self.device)
-        _check(_lib.swkb_field(self._h, C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        _check(_lib.swkb_field(self._h, int(q), C.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
+    @property
+    def last_error(self) -> str:
+        return _lib.swkb_plan_error(self._h).decode()
+
     def diagnostics(self, stream=None, raise_on_caustic=False):
+        """Counters summed over the screens so far.  raise_on_caustic: raise on
+        SWKB_ERR_CAUSTIC or SWKB_ERR_EVANESCENT instead of returning them."""
         cnt = Counters()
         st = _lib.swkb_diagnostics(self._h, _stream_handle(stream), C.byref(cnt))
-        if st not in (SWKB_OK, SWKB_ERR_CAUSTIC) or (raise_on_caustic and st != SWKB_OK):
+        if st not in (SWKB_OK, SWKB_ERR_CAUSTIC, SWKB_ERR_EVANESCENT) or (raise_on_caustic and st != SWKB_OK):
             _check(st)
         return {f: int(getattr(cnt, f)) for f, _ in Counters._fields_}
 

@@ -176,3 +176,87 @@ def test_patch_plan_host_side_errors(lib):
     assert lib.swkb_patch_plan(C.byref(bad), C.byref(pc), None, C.byref(h)) == swkb.SWKB_ERR_ARG
     assert lib.swkb_patch_propagate(None, None, 0, 1, None, None) == swkb.SWKB_ERR_ARG
     lib.swkb_patch_destroy(None)
+
+
+GUARD_HARNESS = r"""
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <thread>
+#include <vector>
+#include "plan_guard.h"
+
+int main() {
+  int flag = 0;
+  // one holder: a second try fails while the first holds, succeeds after
+  {
+    swkb::PlanGuard a(&flag);
+    if (!a.held()) return 1;
+    swkb::PlanGuard b(&flag);
+    if (b.held()) return 2;
+  }
+  {
+    swkb::PlanGuard c(&flag);
+    if (!c.held()) return 3;
+  }
+  // many threads: never two inside at once, and every thread gets in at least once
+  std::atomic<int> inside{0}, worst{0};
+  std::vector<int> got(8, 0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < 8; ++t)
+    th.emplace_back([&, t] {
+      for (int i = 0; i < 20000; ++i) {
+        swkb::PlanGuard g(&flag);
+        if (!g.held()) continue;
+        const int now = ++inside;
+        if (now > worst) worst = now;
+        ++got[t];
+        if ((i & 255) == 0) std::this_thread::sleep_for(std::chrono::microseconds(10));
+        --inside;
+      }
+    });
+  for (auto& x : th) x.join();
+  for (int t = 0; t < 8; ++t)
+    if (got[t] == 0) return 4;
+  if (worst.load() != 1) return 5;
+  if (flag != 0) return 6;
+  std::printf("ok\n");
+  return 0;
+}
+"""
+
+
+def test_plan_guard_admits_one_thread(tmp_path):
+    """The single-user guard behind SWKB_ERR_BUSY (csrc/plan_guard.h, host
+    code): compiled with g++ and driven by eight threads on the CPU."""
+    src = tmp_path / "guard.cpp"
+    src.write_text(GUARD_HARNESS)
+    exe = tmp_path / "guard"
+    subprocess.check_call(["g++", "-std=c++17", "-O2", "-pthread", "-I",
+                           os.path.join(ROOT, "paper_2301_03814_amd", "csrc"), "-o", str(exe), str(src)])
+    r = subprocess.run([str(exe)], stdout=subprocess.PIPE, timeout=60)
+    assert r.returncode == 0 and r.stdout.strip() == b"ok", r.returncode
+
+
+def test_footprint_and_kept_history(lib):
+    from paper_2301_03814_amd import swkb
+    cfg = W.linear_caustic()
+    ws = swkb.workspace_bytes(cfg)
+    fp = swkb.footprint(cfg)
+    assert fp >= ws + cfg["n_z"] * 16
+    kept = W.with_overrides(cfg, keep_history=1)
+    grow = swkb.workspace_bytes(kept) - ws
+    need = (cfg["n_screens"] + 1) * cfg["n_z"] * 16
+    assert need <= grow < need + 256
+    assert swkb.workspace_bytes(W.with_overrides(cfg, keep_history=2)) == 0
+    assert swkb.footprint(W.with_overrides(cfg, n_z=100)) == 0
+
+
+def test_new_status_codes(lib):
+    lib.swkb_status_string.restype = C.c_char_p
+    assert b"evanescent" in lib.swkb_status_string(6)
+    assert b"busy" in lib.swkb_status_string(7)
+    from paper_2301_03814_amd import swkb
+    assert swkb.SWKB_ERR_EVANESCENT == 6 and swkb.SWKB_ERR_BUSY == 7
+    lib.swkb_plan_error.restype = C.c_char_p
+    assert lib.swkb_plan_error(None) == b""

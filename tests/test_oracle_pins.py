@@ -294,6 +294,28 @@ def test_homogeneous_medium_is_exact_angular_spectrum(oracle_mod):
     assert cnt["caustic_rays"] == 0 and cnt["significant"] == 0
 
 
+def test_evanescent_mode_carries_nothing_and_is_counted(oracle_mod):
+    """A free-space beam aimed at grazing incidence (xi0 = -0.999): the kept
+    mode xi = -1 has p^2 = 0 on every ray, so it is dead and contributes
+    nothing; every other mode is carried exactly (the launch extension covers
+    the drift of the steepest live mode).  The oracle equals the exact
+    angular spectrum of the live modes and counts one evanescent mode per
+    screen, significant on the first screen only (the next screens' fields
+    hold no weight there)."""
+    cfg = _homog(launch_ext_cells=400, n_screens=2)
+    cfg["source"] = dict(cfg["source"], xi0=-0.999)
+    u0 = W.incident_field(cfg)
+    hist, cnt = oracle_mod.run(cfg, u0)
+    assert rel_l2(hist[-1], _angular_spectrum(cfg, u0, 16.0)) < 1e-12
+    assert cnt["evanescent_modes"] == 2 and cnt["significant_evanescent"] == 1
+    assert cnt["significant"] == 0
+    # the same beam aimed at 30 degrees puts no weight on the dead mode
+    cfg2 = _homog(launch_ext_cells=400, n_screens=2)
+    cfg2["source"] = dict(cfg2["source"], xi0=-0.5)
+    _, cnt2 = oracle_mod.run(cfg2, W.incident_field(cfg2))
+    assert cnt2["evanescent_modes"] == 2 and cnt2["significant_evanescent"] == 0
+
+
 def test_absorber_taper(oracle_mod):
     # every kept mode is covered by rays (drift dx*xi/p < E), so the only
     # difference to the exact propagator is the taper
