@@ -277,6 +277,35 @@ const char* swkb_last_error(void);
  * or swkb_destroy. */
 const char* swkb_plan_error(swkb_plan_t plan);
 
+/* ---- one propagation without device allocation ----------------------- */
+
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: work being captured into a HIP graph by the caller, tight
+ * serving loops, harnesses that forbid allocation): swkb_plan, swkb_propagate
+ * and swkb_destroy in one call, with the plan's workspace in a static device
+ * array of SWKB_STATIC_WORKSPACE_BYTES that the library holds on every GPU it
+ * runs on until the process ends.  Same kernels and launch shapes as
+ * swkb_propagate (one after another on hip_stream: no march stream), so the
+ * fields equal a plan's.
+ *   p:       as for swkb_plan; SWKB_ERR_NOMEM (message in swkb_last_error)
+ *            when swkb_workspace_bytes(p) > SWKB_STATIC_WORKSPACE_BYTES,
+ *            SWKB_ERR_ARG for invalid parameters;
+ *   u_in:    device complex128[n_z], the field on screen q_begin;
+ *   history: device complex128[(q_end - q_begin) n_z] (screens q_begin+1 ..
+ *            q_end) or NULL; u_out: device complex128[n_z] (screen q_end) or
+ *            NULL.  0 <= q_begin < q_end <= n_screens.
+ * Calls no hipMalloc, hipFree or allocating library routine.  Synchronises
+ * hip_stream once (upload of the plan tables, as swkb_plan); the propagation
+ * itself is asynchronous.  The array keeps the last call's contents; every
+ * table and counter a call reads is written by that call first.  Calls on
+ * one GPU share its array: the library orders them (each call's stream waits
+ * for the previous call's work, and host threads enter one at a time), so
+ * two calls whose work overlaps on the device would race; there is no plan
+ * left behind (no swkb_field or swkb_diagnostics afterwards). */
+#define SWKB_STATIC_WORKSPACE_BYTES (64u << 20)
+swkb_status swkb_propagate_static(const swkb_params* p, const void* u_in, int32_t q_begin, int32_t q_end,
+                                  void* history, void* u_out, void* hip_stream);
+
 /* ---- stage entry points, for checking each step on its own ---------- */
 
 /* Step 1 only: c (device complex128[M], c[j] for n = j - M/2) = the DFT of

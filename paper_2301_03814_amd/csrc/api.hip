@@ -556,14 +556,15 @@ static swkb_status plan_call(swkb_plan_s* pl, hipStream_t st, bool use_stream, F
     set_error("plan is in use by another thread");
     return SWKB_ERR_BUSY;
   }
-  if (use_stream && pl->has_last && st != pl->last_st && hipEventQuery(pl->ev_done) == hipErrorNotReady) {
+  if (use_stream && pl->ev_done && pl->has_last && st != pl->last_st &&
+      hipEventQuery(pl->ev_done) == hipErrorNotReady) {
     set_error("the plan's previous call is still running on another stream");
     pl->err = g_err;
     return SWKB_ERR_BUSY;
   }
   const swkb_status s = body();
   if (s != SWKB_OK) pl->err = g_err;
-  if (use_stream) {
+  if (use_stream && pl->ev_done) {
     // a stream being captured by the caller gets no marker (its work runs at replay)
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     pl->has_last = hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone &&
@@ -585,13 +586,22 @@ size_t swkb_workspace_bytes(const swkb_params* p) {
 
 swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_bytes, void* hip_stream,
                       swkb_plan_t* out) {
+  return plan_impl(p, workspace, workspace_bytes, (hipStream_t)hip_stream, true, out);
+}
+
+}  // extern "C"
+
+// Body of swkb_plan.  own_streams = false: the plan creates no streams and no
+// events (every kernel then runs on the caller's stream, one after another,
+// and the single-stream check is off).
+swkb_status swkb::plan_impl(const swkb_params* p, void* workspace, size_t workspace_bytes, hipStream_t st,
+                            bool own_streams, swkb_plan_t* out) {
   if (!out) return fail(SWKB_ERR_ARG, "out is NULL");
   *out = nullptr;
   const std::string why = validate(p);
   if (!why.empty()) return fail(SWKB_ERR_ARG, why);
   if (!workspace) return fail(SWKB_ERR_ARG, "workspace is NULL");
   if (((uintptr_t)workspace & 255) != 0) return fail(SWKB_ERR_ARG, "workspace must be 256-byte aligned");
-  hipStream_t st = (hipStream_t)hip_stream;
   swkb_plan_s* pl = new (std::nothrow) swkb_plan_s();
   if (!pl) return fail(SWKB_ERR_NOMEM, "host allocation failed");
   try {
@@ -667,7 +677,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->graphs_on = 0;
     pl->ss = nullptr;
     for (int k = 0; k < 2; ++k) pl->ev_ready[k] = pl->ev_free[k] = pl->ev_marched[k] = nullptr;
-    if (pl->nslots == 2) {
+    if (pl->nslots == 2 && own_streams) {
       SharedStreams ss;
       bool ok = shared_streams(&ss) == hipSuccess;
       pl->ms = ss.ms;
@@ -693,7 +703,7 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
     pl->last_st = nullptr;
     pl->has_last = 0;
     pl->ev_done = nullptr;
-    if (hipEventCreateWithFlags(&pl->ev_done, hipEventDisableTiming) != hipSuccess) {
+    if (own_streams && hipEventCreateWithFlags(&pl->ev_done, hipEventDisableTiming) != hipSuccess) {
       destroy_streams(pl);
       delete pl;
       return fail(SWKB_ERR_DEVICE, "swkb_plan: event creation failed");
@@ -803,6 +813,8 @@ swkb_status swkb_plan(const swkb_params* p, void* workspace, size_t workspace_by
   *out = pl;
   return SWKB_OK;
 }
+
+extern "C" {
 
 swkb_status swkb_propagate(swkb_plan_t pl, const void* u_in, int32_t q_begin, int32_t q_end, void* history,
                            void* hip_stream) {

@@ -189,6 +189,9 @@ struct swkb_plan_s {
 namespace swkb {
 
 void set_error(const std::string& msg);
+// Body of swkb_plan; own_streams = false creates no streams and no events.
+swkb_status plan_impl(const swkb_params* p, void* workspace, size_t workspace_bytes, hipStream_t st,
+                      bool own_streams, swkb_plan_t* out);
 // Screens q_begin .. q_end-1 of one field, without the single-user check of
 // the public entry point (for callers inside the library that hold the plan).
 swkb_status propagate_impl(swkb_plan_s* pl, const void* u_in, int q_begin, int q_end, void* history,

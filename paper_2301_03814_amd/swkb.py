@@ -30,7 +30,8 @@ EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", 
            "swkb_server_stats", "swkb_server_destroy", "swkb_graphs", "swkb_multi_create",
            "swkb_multi_get_tuning", "swkb_multi_set_tuning", "swkb_multi_tune", "swkb_multi_propagate",
            "swkb_multi_destroy", "swkb_patch_plan", "swkb_patch_info", "swkb_patch_propagate",
-           "swkb_patch_field", "swkb_patch_destroy", "swkb_patch_graphs", "swkb_footprint", "swkb_plan_error"]
+           "swkb_patch_field", "swkb_patch_destroy", "swkb_patch_graphs", "swkb_footprint", "swkb_plan_error",
+           "swkb_propagate_static"]
 
 MULTI_MAX_CLASSES = 16
 
@@ -121,6 +122,8 @@ def load(path: str = LIB_PATH):
     lib.swkb_footprint.restype = C.c_size_t
     lib.swkb_plan_error.argtypes = [vp]
     lib.swkb_plan_error.restype = C.c_char_p
+    lib.swkb_propagate_static.argtypes = [pp, vp, i32, i32, vp, vp, vp]
+    lib.swkb_propagate_static.restype = C.c_int
     lib.swkb_plan.argtypes = [pp, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.swkb_propagate.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.swkb_field.argtypes = [vp, i32, vp, vp]
@@ -211,6 +214,26 @@ def workspace_bytes(cfg, precision=FP64) -> int:
 def footprint(cfg, precision=FP64) -> int:
     """Device bytes one propagation request holds while it runs (swkb_footprint)."""
     return int(load().swkb_footprint(C.byref(make_params(cfg, precision))))
+
+
+STATIC_WORKSPACE_BYTES = 64 << 20  # SWKB_STATIC_WORKSPACE_BYTES
+
+
+def propagate_static(cfg, u0, q_begin=0, q_end=None, precision=FP64, history=True, stream=None):
+    """One propagation through swkb_propagate_static (no device allocation
+    inside the library): returns (history [q_end-q_begin, N] or None, field
+    on screen q_end [N]), complex128 on u0's device."""
+    import torch
+    if q_end is None:
+        q_end = cfg["n_screens"]
+    p = make_params(cfg, precision)
+    n = cfg["n_z"]
+    hist = torch.empty((q_end - q_begin, n), dtype=torch.complex128, device=u0.device) if history else None
+    out = torch.empty(n, dtype=torch.complex128, device=u0.device)
+    _check(load().swkb_propagate_static(C.byref(p), _dev_ptr(u0, torch.complex128, n, "u0"), int(q_begin),
+                                        int(q_end), C.c_void_p(hist.data_ptr()) if hist is not None else None,
+                                        C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return hist, out
 
 
 def _stream_handle(stream):
