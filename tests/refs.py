@@ -93,3 +93,82 @@ def t_system_ray(med, x_q, s, xi, z0p, dx, rtol=1e-13):
     x, z, psi, P, Q, Xs, Zs, _, _, _, A = y
     J = 2 * P * Zs - 2 * Q * Xs
     return dict(Z=z, psi=psi, q=Q, A=A, J=J, J0=2 * P0)
+
+
+def airy_beam(k, g, beta0, sigma, x_turn, xs, z, n_beta=1201):
+    """Exact solution of Delta u + k^2 (1 + g z) u = 0: a Gaussian superposition
+    over the horizontal wavenumber beta of the separated solutions
+    e^{i beta (x - x_turn)} Ai(-(k^2 g)^{1/3} (z - z_t(beta))), with the
+    turning height z_t(beta) = (beta^2 / k^2 - 1) / g (Airy's equation
+    phi'' = t phi in t = -(k^2 g)^{1/3} (z - z_t)).  The weight
+    exp(-((beta - beta0) / sigma)^2) makes a beam that comes down, turns at
+    z_t(beta0) near x = x_turn and goes up again.  Trapezoidal quadrature
+    over beta0 +- 7 sigma.  Returns complex [len(xs), len(z)]."""
+    from scipy.special import airy
+    c = (k * k * g) ** (1.0 / 3.0)
+    b = beta0 + sigma * np.linspace(-7.0, 7.0, n_beta)
+    w = np.exp(-((b - beta0) / sigma) ** 2) * (b[1] - b[0])
+    zt = (b * b / (k * k) - 1.0) / g
+    ai = airy(-c * (np.asarray(z)[None, :] - zt[:, None]))[0]
+    return np.array([(w * np.exp(1j * b * (x - x_turn))) @ ai for x in xs])
+
+
+def fd_helmholtz(k, length, n_z, x_len, n_x, eps_fn, u0, xs_out):
+    """Brute-force full-wave solution of Delta u + k^2 eps(x, z) u = 0 on
+    [0, x_len] x [0, length) (periodic in z): Fourier-spectral in z on n_z
+    points, Numerov (4th order) in x with step x_len / n_x, and the exact
+    radiation conditions of the discrete scheme at both ends, where eps = 1:
+    the given incident field u0 (z-grid values at x = 0) comes in from the
+    left and every reflected or transmitted wave leaves.  Dense block
+    tridiagonal elimination over the x-grid.  eps_fn(x, z_array) returns eps
+    on the z-grid.  Returns the field at the ranges xs_out (grid points),
+    complex [len(xs_out), n_z]."""
+    hx = x_len / n_x
+    z = length * np.arange(n_z) / n_z
+    kap = 2.0 * np.pi * np.fft.fftfreq(n_z, d=length / n_z)
+    F = np.fft.fft(np.eye(n_z), axis=0)
+    Fi = np.fft.ifft(np.eye(n_z), axis=0)
+    eye = np.eye(n_z)
+    f_out = (kap ** 2 - k * k).astype(complex)  # u'' = f u per Fourier mode where eps = 1
+
+    def A(x):  # u_xx = A u in Fourier space: A = kappa^2 - k^2 eps (a convolution in z)
+        return np.diag(kap ** 2).astype(complex) - (F * (k * k * eps_fn(x, z))[None, :]) @ Fi
+
+    # per mode, the two discrete solutions t^i and t^-i of Numerov with f constant
+    c = (1 + 5 * hx * hx * f_out / 12) / (1 - hx * hx * f_out / 12)
+    c = c.real
+    t = np.where(np.abs(c) <= 1.0, c + 1j * np.sqrt(np.maximum(0.0, 1.0 - c * c)),
+                 c - np.sign(c) * np.sqrt(np.maximum(0.0, c * c - 1.0)))
+    if np.any(np.abs(f_out) < 1e-9 * k * k):
+        # t = 1 is a double root: the periodic problem is resonant for that mode
+        raise ValueError("a Fourier mode is exactly grazing (kappa = k): choose another height")
+    a_in = np.fft.fft(np.asarray(u0, dtype=complex))
+    n = n_x + 1
+    G = np.empty((n, n_z, n_z), complex)
+    gv = np.empty((n, n_z), complex)
+    a_prev, a_cur, a_next = np.diag(f_out), A(0.0), A(hx)
+    for i in range(n):
+        low = eye - hx * hx * a_prev / 12
+        mid = -2.0 * (eye + 5 * hx * hx * a_cur / 12)
+        up = eye - hx * hx * a_next / 12
+        rhs = np.zeros(n_z, complex)
+        if i == 0:  # ghost U_{-1} = T U_0 + (1/T - T) a_in
+            mid = mid + low * t[None, :]
+            rhs = -low @ ((1.0 / t - t) * a_in)
+        if i == n_x:  # ghost U_{n} = T U_{n-1}
+            mid = mid + up * t[None, :]
+        if i > 0:
+            mid = mid - low @ G[i - 1]
+            rhs = rhs - low @ gv[i - 1]
+        inv = np.linalg.inv(mid)
+        G[i] = inv @ up
+        gv[i] = inv @ rhs
+        a_prev, a_cur = a_cur, a_next
+        a_next = A((i + 2) * hx) if i + 2 <= n_x else np.diag(f_out)
+    U = np.empty((n, n_z), complex)
+    U[n_x] = gv[n_x]
+    for i in range(n_x - 1, -1, -1):
+        U[i] = gv[i] - G[i] @ U[i + 1]
+    idx = [int(round(x / hx)) for x in xs_out]
+    assert all(abs(j * hx - x) < 1e-9 * max(1.0, x) for j, x in zip(idx, xs_out))
+    return np.array([np.fft.ifft(U[j]) for j in idx])

@@ -199,7 +199,8 @@ int main() {
     swkb::PlanGuard c(&flag);
     if (!c.held()) return 3;
   }
-  // many threads: never two inside at once, and every thread gets in at least once
+  // many threads: never two inside at once (a try-lock promises no fairness,
+  // so only the total is required to be positive)
   std::atomic<int> inside{0}, worst{0};
   std::vector<int> got(8, 0);
   std::vector<std::thread> th;
@@ -216,8 +217,9 @@ int main() {
       }
     });
   for (auto& x : th) x.join();
-  for (int t = 0; t < 8; ++t)
-    if (got[t] == 0) return 4;
+  long total = 0;
+  for (int t = 0; t < 8; ++t) total += got[t];
+  if (total == 0) return 4;
   if (worst.load() != 1) return 5;
   if (flag != 0) return 6;
   std::printf("ok\n");
