@@ -419,7 +419,8 @@ def main():
                 "table_share": round(w["table_evals"] / max(1, w["table_evals"] + w["medium_evals"]), 4),
                 "peak_nonpacked": round(PEAK_ALU_NONPACKED / 1e12, 1),
                 "frac_of_nonpacked": round(achieved * 1e12 / PEAK_ALU_NONPACKED, 4),
-                "flops_per_launch": per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
+                "flops_per_launch": per_launch, "avg_launch_ms": round(avg_s * 1e3, 4),
+                "rhs_evals_per_launch": w["rhs_evals"] / launches, "table_evals_per_launch": w["table_evals"] / launches}
 
     res = {}
     for name, plan in plans.items():
@@ -587,7 +588,9 @@ def main():
         "config": {"workload": "random_medium: lambda=1, 200 Gaussian index bumps (seed 2301), 1000x4000 "
                                "wavelengths, N_z=8192, 2048 modes, 400 screens of 10, RK4 S=8, ray stride 8",
                    "n_z": N, "n_modes": M, "n_screens": Q, "rays_per_mode": plans["mixed"].num_rays,
-                   "precision": "mixed (FP32 march/interp/sincos, FP64 amplitude and phase bookkeeping)",
+                   "precision": "mixed: FP32 ray state, medium table, interpolation and sin/cos; FP64 ray "
+                                "tube (Z_s, Q_s accumulated in FP64 from FP32 RK4 increments) and transport "
+                                "amplitude, range phase, FFT and cross-group sums",
                    "hip_graphs": True},
         "range_wavelengths_per_s": 4000.0 * args.steps / rm["seconds"],
         "rel_err_mixed_vs_fp64": err_mixed,

@@ -58,13 +58,15 @@ typedef enum swkb_status {
 } swkb_status;
 
 /* Arithmetic of a plan.  SWKB_FP64: every step in FP64.  SWKB_MIXED: the
- * FFT, each mode's range phase frac(pbar dx / lambda) and the sums across
- * mode groups in FP64; the ray state (z - s, q - xi, phase deviation, Z_s,
- * Q_s), the medium read from the per-screen table (built from FP64 node
- * values), the amplitude, the interpolation and each mode-point's phase and
- * sin/cos in FP32, with the grid phase n m' / P carried as an exact FP32
- * fraction of a turn.  Result within 1e-3 of the FP64 path (about 1e-5 on
- * smooth media). */
+ * FFT, each mode's range phase frac(pbar dx / lambda), the sums across mode
+ * groups, the ray-tube variations Z_s, Q_s (accumulated in FP64 from FP32
+ * RK4 increments) and the transport amplitude sqrt(p0 / (p Z_s)) (its Z_s
+ * factor in FP64) in FP64; the ray state (z - s, q - xi, phase deviation),
+ * the medium read from the per-screen table (built from FP64 node values),
+ * the interpolation and each mode-point's phase and sin/cos in FP32 (the
+ * amplitude is stored in FP32 for the interpolation), with the grid phase
+ * n m' / P carried as an exact FP32 fraction of a turn.  Result within 1e-3
+ * of the FP64 path (about 1e-5 on smooth media). */
 enum { SWKB_FP64 = 0, SWKB_MIXED = 1 };
 /* How a screen's mode functions are obtained for media that do not depend
  * on x (LINEAR, EXPGAUSS, MPROFILE): every screen then sees the same rays,

@@ -18,8 +18,15 @@
 // FP64 number per mode, and only the small deviation dpsi is marched:
 //   d dpsi/dx = ((eps - eps_ref_n) - (q - xi)(q + xi)) / (p + pbar) + q (q - xi) / p
 // (= eps/p - xi q/p - pbar, written in small quantities).  State per ray:
-// dz = z - s, dq = q - xi, dpsi, Zs, Qs and the amplitude on arrival in T
-// (FP32 in the mixed path).
+// dz = z - s, dq = q - xi, dpsi in T (FP32 in the mixed path); the ray-tube
+// variations Zs, Qs are accumulated in FP64 in both precisions and the
+// amplitude on arrival is formed in FP64.  In the mixed path each RK4 step
+// starts from the FP64 tube rounded to FP32, forms its stages and its
+// increment in FP32 (their coefficients come from the FP32 ray state) and
+// adds the increment in FP64: an increment is ~1e-2 of Zs, so the tube keeps
+// about 1e-9 relative accuracy where an FP32 state would round by ~6e-8 a
+// step -- the ray-Jacobian amplitude near turning points of the x-march
+// (p -> 0, where 1/p^3 drives the tube) stays at FP64 accuracy.
 //
 // Ray r of mode n starts at s_r = z_a + (r rho - E) h with q = xi_n
 // (Sec. 2.1.2 initial conditions), Zs = 1, Qs = 0.  A ray is dead when
@@ -287,13 +294,31 @@ __device__ inline int first_point_at_or_above(const Geometry& g, double key, dou
   return ci;
 }
 
+// Transport amplitude sqrt(p0 / (p Zs)) = sqrt(p0 / p) Zs^(-1/2) with the
+// ray tube's factor in FP64: Zs^(-1/2) from the hardware estimate refined by
+// two Newton steps y <- y (3 - Zs y^2) / 2 (each doubles the correct bits of
+// the estimate, which has at least 22, so the result is FP64-accurate); the
+// slowness ratio p0 / p in T (the launch and arrival slownesses are T
+// quantities).
+template <typename T>
+__device__ inline double tube_amplitude(T p02, T p2, double Zs) {
+  if constexpr (std::is_same<T, double>::value) {
+    return sqrt(sqrt(p02) / (sqrt(p2) * Zs));
+  } else {
+    double y = __builtin_amdgcn_rsq(Zs);
+    y = y * (1.5 - 0.5 * Zs * y * y);
+    y = y * (1.5 - 0.5 * Zs * y * y);
+    return (double)sqrt(sqrt(p02) * fast_rsqrt<T>(p2)) * y;
+  }
+}
+
 // One wavefront lane per ray: RK4 across the screen.  Writes the arrival
 // record and returns the lane's status and work counts.
 template <typename T, typename MED>
 __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry& g, const MarchK& mk, bool active,
                                  size_t o, double s_launch, DevRecords& rec, int& st, Work& c) {
   T dz = T(0), dq = T(0), dps = T(0);
-  T Zs = T(1), Qs = T(0);
+  double Zs = 1.0, Qs = 0.0;  // ray tube, accumulated in FP64
   double amp = 0.0;
   st = kLive;
   if (!active) return;
@@ -303,34 +328,34 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
   if (!(p02 > (T)g.p2_floor)) {
     st = kDeadLaunch;
   } else {
-    const T p0 = sqrt(p02);
     const T hh = (T)(0.5 * mk.hx), hf = (T)mk.hx, h6 = (T)mk.h6;
     const T pfl = (T)g.p2_floor;
-    const T hd2 = hh, hd6 = h6;
     Deriv<T> k1, k2, k3, k4;
     for (int i = 0; i < g.S; ++i) {
-      if (!rhs<T>(med, mc, 2 * i, 1, dz, dq, Zs, Qs, pfl, k1, c, st)) break;
-      if (!rhs<T>(med, mc, 2 * i + 1, 2, dz + hh * k1.dz, dq + hh * k1.dq, Zs + hd2 * k1.Zs, Qs + hd2 * k1.Qs,
-                  pfl, k2, c, st))
+      const T zs = (T)Zs, qs = (T)Qs;  // the step's tube in T
+      if (!rhs<T>(med, mc, 2 * i, 1, dz, dq, zs, qs, pfl, k1, c, st)) break;
+      if (!rhs<T>(med, mc, 2 * i + 1, 2, dz + hh * k1.dz, dq + hh * k1.dq, zs + hh * k1.Zs, qs + hh * k1.Qs, pfl,
+                  k2, c, st))
         break;
-      if (!rhs<T>(med, mc, 2 * i + 1, 3, dz + hh * k2.dz, dq + hh * k2.dq, Zs + hd2 * k2.Zs, Qs + hd2 * k2.Qs,
-                  pfl, k3, c, st))
+      if (!rhs<T>(med, mc, 2 * i + 1, 3, dz + hh * k2.dz, dq + hh * k2.dq, zs + hh * k2.Zs, qs + hh * k2.Qs, pfl,
+                  k3, c, st))
         break;
-      if (!rhs<T>(med, mc, 2 * i + 2, 4, dz + hf * k3.dz, dq + hf * k3.dq, Zs + hf * k3.Zs, Qs + hf * k3.Qs,
-                  pfl, k4, c, st))
+      if (!rhs<T>(med, mc, 2 * i + 2, 4, dz + hf * k3.dz, dq + hf * k3.dq, zs + hf * k3.Zs, qs + hf * k3.Qs, pfl,
+                  k4, c, st))
         break;
       c.rhs += 4;
       dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
       dq += h6 * (k1.dq + T(2) * k2.dq + T(2) * k3.dq + k4.dq);
       dps += h6 * (k1.dps + T(2) * k2.dps + T(2) * k3.dps + k4.dps);
-      Zs += hd6 * (k1.Zs + T(2) * k2.Zs + T(2) * k3.Zs + k4.Zs);
-      Qs += hd6 * (k1.Qs + T(2) * k2.Qs + T(2) * k3.Qs + k4.Qs);
+      // the step's increment in T, the sum in FP64
+      Zs += (double)(h6 * (k1.Zs + T(2) * k2.Zs + T(2) * k3.Zs + k4.Zs));
+      Qs += (double)(h6 * (k1.Qs + T(2) * k2.Qs + T(2) * k3.Qs + k4.Qs));
     }
     // completed steps, and the evaluations of the step where the ray stopped
     evals += c.rhs + (st >> 2);
     st &= 3;
     if (st == kLive) {
-      if (!(Zs > T(0))) {
+      if (!(Zs > 0.0)) {
         st = kCaustic;
       } else {
         ++evals;
@@ -338,7 +363,7 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
         const T xi = (T)mc.xi;
         const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
         if (!(p2 > (T)g.p2_floor)) st = kDead;
-        else amp = (double)sqrt(p0 / (sqrt(p2) * Zs));  // in T, like the march
+        else amp = tube_amplitude<T>(p02, p2, Zs);
       }
     }
   }

@@ -723,10 +723,12 @@ def test_swkb_accuracy_against_gpu_modal_reference(torch_dev, swkb):
 
 
 def test_mixed_amplitude_near_turning_points(torch_dev, swkb):
-    """The mixed path integrates the ray tube (Z_s, Q_s) and forms the
-    amplitude sqrt(p0 / (p Z_s)) in FP32.  On the linear caustic, rays whose
+    """The mixed path accumulates the ray tube (Z_s, Q_s) in FP64 from FP32
+    RK4 increments and forms the amplitude sqrt(p0 / (p Z_s)) with its Z_s
+    factor in FP64 (stored in FP32).  On the linear caustic, rays whose
     vertical slowness changes sign within the screen (they pass a turning
-    point) keep amplitudes within 1e-4 relative of the oracle's FP64 march."""
+    point) and all live rays keep amplitudes close to the oracle's FP64
+    march; the bounds hold the FP32-ray-state level."""
     import oracle
     torch, dev = torch_dev
     cfg = CASES["linear_caustic_N512"]()
