@@ -108,8 +108,13 @@ def test_propagation_matches_oracle(torch_dev, swkb, oracle_runs, name, prec, pr
     got = hist.cpu().numpy()
     diag = plan.diagnostics()
     err = rel(got, ref)
-    say(f"[parity] {name} {prec} rel_l2={err:.3e} diag={diag} oracle={cnt}")
+    # screen by screen: max |difference| / max |oracle field| of that screen
+    # (at least 1e-3 of the run's largest value: the beam may leave the domain)
+    peak = np.abs(ref).max(axis=1)
+    mx = float((np.abs(got - ref).max(axis=1) / np.maximum(peak, 1e-3 * peak.max())).max())
+    say(f"[parity] {name} {prec} rel_l2={err:.3e} per-screen max-norm={mx:.3e} diag={diag} oracle={cnt}")
     assert err <= (FP64_TOL if prec == "fp64" else MIXED_TOL)
+    assert mx <= (FP64_TOL if prec == "fp64" else MIXED_TOL)
     if prec == "mixed":
         assert err <= MIXED_REGRESSION
     assert diag["screens"] == cfg["n_screens"]
