@@ -191,9 +191,11 @@ swkb_status swkb_propagate(swkb_plan_t plan, const void* u_in, int32_t q_begin, 
  * screens q_begin .. q_end-1 together: the rays, and for an x-invariant
  * medium the mode-function matrix, are shared, so each screen costs one
  * march (x-varying media) plus per-field FFTs and sums; with the matrix the
- * sums over modes of all fields form one complex matrix product (rocBLAS
- * GEMM on the matrix cores).  Results equal `batch` separate swkb_propagate
- * runs up to rounding.
+ * sums over modes of all fields form one complex matrix product on the
+ * matrix cores (the matrix is read once per screen for all fields; FP64
+ * instructions for SWKB_FP64, FP32 ones with FP64 cross-group sums for
+ * SWKB_MIXED).  Results equal `batch` separate swkb_propagate runs up to
+ * rounding.
  *   u_in:    device complex128[batch][N], fields on screen q_begin;
  *   history: device complex128[q_end - q_begin][batch][N] or NULL;
  *   u_out:   device complex128[batch][N], fields on screen q_end, or NULL.

@@ -13,8 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "swkb")
 LIB = os.path.join(HERE, "libswkb.so")
-SOURCES = ["api.hip", "fft.hip", "march.hip", "superpose.hip", "gemm.hip", "modal.hip", "serve.hip", "multi.hip", "patch.hip",
-           "static.hip"]
+SOURCES = ["api.hip", "fft.hip", "march.hip", "superpose.hip", "modal.hip", "serve.hip", "multi.hip", "patch.hip",
+           "static.hip", "batch.hip"]
 HEADERS = ["swkb_internal.h", "medium.h", "plan_guard.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -9,8 +9,6 @@
 #include <string>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "plan_guard.h"
 #include "swkb_internal.h"
 
@@ -139,7 +137,7 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, cf, cpol, part, tmat, hist,
+  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, pan, cpol, part, tmat, hist,
       counters;
   // one ray-record slot (offsets from its start); nslots of them from slot0
   size_t mtab, D, Pp, G, A, cz, cidx, tstart, mflag, mcaus, mdead, mwork, wcount;
@@ -208,9 +206,11 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.ub = take(B > 1 ? sizeof(double2) * g.N * B : 0);
   L.Y = take(sizeof(double2) * g.P * B);
   L.c = take(sizeof(double2) * g.M * B);
-  L.cf = take(B > 1 && use_matrix(p) && p->precision == SWKB_MIXED ? sizeof(float2) * g.M * B : 0);
+  L.pan = take(B > 1 && use_matrix(p) ? batch_panel_bytes(g, (int)B) : 0);
   L.cpol = take(p->precision == SWKB_MIXED ? sizeof(float2) * g.M : 0);
-  L.part = take(sizeof(double2) * (size_t)g.N * partial_groups(g) * B);
+  size_t part_bytes = sizeof(double2) * (size_t)g.N * partial_groups(g) * B;
+  if (B > 1 && use_matrix(p)) part_bytes = std::max(part_bytes, batch_part_bytes(g, p->precision, (int)B));
+  L.part = take(part_bytes);
   L.tmat = take(use_matrix(p) ? matrix_bytes(p) : 0);
   L.hist = take(p->keep_history ? sizeof(double2) * (size_t)g.N * (size_t)(p->n_screens + 1) : 0);
   L.counters = take(sizeof(unsigned long long) * 32);
@@ -637,12 +637,10 @@ swkb_status swkb::plan_impl(const swkb_params* p, void* workspace, size_t worksp
     pl->u = reinterpret_cast<double2*>(ws + L.u);
     // buffers of zero size share their offset with the next one: leave them unset
     pl->ub = p->max_batch > 1 ? reinterpret_cast<double2*>(ws + L.ub) : nullptr;
-    pl->cf = p->max_batch > 1 && use_matrix(p) && p->precision == SWKB_MIXED ? reinterpret_cast<float2*>(ws + L.cf)
-                                                                              : nullptr;
+    pl->pan = p->max_batch > 1 && use_matrix(p) ? static_cast<void*>(ws + L.pan) : nullptr;
     pl->cpol = p->precision == SWKB_MIXED ? reinterpret_cast<float2*>(ws + L.cpol) : nullptr;
     pl->max_batch = p->max_batch;
     pl->sum_fields = 1;
-    pl->blas = nullptr;
     pl->Y = reinterpret_cast<double2*>(ws + L.Y);
     pl->c = reinterpret_cast<double2*>(ws + L.c);
     pl->part = reinterpret_cast<double2*>(ws + L.part);
@@ -875,12 +873,6 @@ swkb_status swkb_propagate_batch(swkb_plan_t pl, const void* u_in, int32_t batch
       pl->cur_q = keep_q;
       return s;
     }
-    if (pl->use_matrix && !pl->blas) {
-      rocblas_handle h = nullptr;
-      if (rocblas_create_handle(&h) != rocblas_status_success)
-        return fail(SWKB_ERR_DEVICE, "rocblas_create_handle failed");
-      pl->blas = h;
-    }
     const double2* src = static_cast<const double2*>(u_in);
     pl->sum_fields = batch;
     auto fft = [&](int) { return timed(pl, kProfFft, st, [&] { return launch_fft_modes(*pl, src, batch, st); }); };
@@ -1092,7 +1084,6 @@ swkb_status swkb_profile_read(swkb_plan_t pl, void* hip_stream, swkb_timing* out
 
 void swkb_destroy(swkb_plan_t pl) {
   if (!pl) return;
-  if (pl->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(pl->blas));
   for (hipEvent_t ev : pl->ev_pool) (void)hipEventDestroy(ev);
   if (pl->cs) (void)hipStreamSynchronize(pl->cs);
   destroy_graphs(pl);

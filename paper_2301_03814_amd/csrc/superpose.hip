@@ -575,6 +575,25 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_c64_kernel(Geometry 
 constexpr int kFinThreads = 512;  // 128 points per workgroup, 4 threads per point
 constexpr int kFinWaves = kFinThreads / 64;
 
+// Energy of mode j summed over the batch in field order (the loads of eight
+// fields are issued before their terms are added).
+__device__ inline double batch_energy(const double2* __restrict__ c, int M, int j, int batch) {
+  double e = 0.0;
+  int bb = 0;
+  for (; bb + 8 <= batch; bb += 8) {
+    double2 cv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cv[u] = c[(size_t)(bb + u) * M + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e += cv[u].x * cv[u].x + cv[u].y * cv[u].y;
+  }
+  for (; bb < batch; ++bb) {
+    const double2 cv = c[(size_t)bb * M + j];
+    e += cv.x * cv.x + cv.y * cv.y;
+  }
+  return e;
+}
+
 template <typename PT>
 __device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, const double2* __restrict__ c,
                                      const PT* __restrict__ part, int groups, int batch, double2* __restrict__ out,
@@ -616,14 +635,7 @@ __device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, c
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double emax = 0.0;
 #pragma unroll 4
-  for (int j = threadIdx.x; j < g.M; j += kFinThreads) {
-    double e = 0.0;
-    for (int bb = 0; bb < batch; ++bb) {
-      const double2 cv = c[(size_t)bb * g.M + j];
-      e += cv.x * cv.x + cv.y * cv.y;
-    }
-    emax = fmax(emax, e);
-  }
+  for (int j = threadIdx.x; j < g.M; j += kFinThreads) emax = fmax(emax, batch_energy(c, g.M, j, batch));
   for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off, 64));
   if (lane == 0) sm[wv] = emax;
   __syncthreads();
@@ -639,11 +651,7 @@ __device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, c
     v[2] += f & 1;
     v[8] += (f >> 2) & 1;
     if (f) {
-      double e = 0.0;
-      for (int bb = 0; bb < batch; ++bb) {
-        const double2 cv = c[(size_t)bb * g.M + j];
-        e += cv.x * cv.x + cv.y * cv.y;
-      }
+      const double e = batch_energy(c, g.M, j, batch);
       if (e > thr) {
         if (f & 3) ++v[3];  // caustic or folded
         if (f & 4) ++v[9];  // no live ray
@@ -698,12 +706,6 @@ __global__ void __launch_bounds__(kFinThreads) finalize_multi(const MultiProblem
   double2* hist = p.hist ? p.hist + (size_t)step * p.g.N : nullptr;
   finalize_body<double2>(p.g, p.rec, p.c, p.part, p.groups, 1, p.u, hist, p.counters, p.ep, (int)(e & 0xfffff),
                          (p.g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, 0);
-}
-
-// c [batch][M] complex128 -> complex64 for the FP32 matrix product.
-__global__ void to_c64_kernel(const double2* __restrict__ c, float2* __restrict__ cf, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) cf[i] = make_float2((float)c[i].x, (float)c[i].y);
 }
 
 }  // namespace
@@ -868,20 +870,17 @@ hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* his
     return hipGetLastError();
   }
   // several fields: one complex matrix product U[b][m] = sum_j C[b][j] T[j][m]
-  hipError_t e = gemm_fields(pl, batch, st);
+  // on the matrix cores, mode-group partials summed in FP64 by the epilogue
+  int groups = 1;
+  hipError_t e = launch_batch_product(pl, batch, st, &groups);
   if (e != hipSuccess) return e;
+  const dim3 fin(finalize_blocks(g), batch);
   if (pl.precision == SWKB_FP64)
-    hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, batch), dim3(kFinThreads), 0, st, g, pl.rec,
-                       pl.c, pl.part, 1, batch, out, hist, pl.counters, ep);
+    hipLaunchKernelGGL(finalize_kernel<double2>, fin, dim3(kFinThreads), 0, st, g, pl.rec, pl.c, pl.part, groups,
+                       batch, out, hist, pl.counters, ep);
   else
-    hipLaunchKernelGGL(finalize_kernel<float2>, dim3((g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, batch), dim3(kFinThreads), 0, st, g, pl.rec,
-                       pl.c, reinterpret_cast<const float2*>(pl.part), 1, batch, out, hist, pl.counters, ep);
-  return hipGetLastError();
-}
-
-hipError_t launch_to_c64(const swkb_plan_s& pl, int batch, hipStream_t st) {
-  const int n = batch * pl.g.M;
-  hipLaunchKernelGGL(to_c64_kernel, dim3((n + 255) / 256), dim3(256), 0, st, pl.c, pl.cf, n);
+    hipLaunchKernelGGL(finalize_kernel<float2>, fin, dim3(kFinThreads), 0, st, g, pl.rec, pl.c,
+                       reinterpret_cast<const float2*>(pl.part), groups, batch, out, hist, pl.counters, ep);
   return hipGetLastError();
 }
 

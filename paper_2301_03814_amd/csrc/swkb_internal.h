@@ -120,12 +120,11 @@ struct swkb_plan_s {
   double2 *u, *ub;               // single field [N]; batch fields [B][N] (max_batch > 1)
   double2 *Y, *c;                // FFT scratch [B][P], modes [B][M]
   double2* part;                 // superposition partials [B][mode groups][N]
-  float2* cf;                    // modes as complex64 [B][M] (FP32 matrix product)
+  void* pan;                     // batched product's B operands per mode (matrix plans, max_batch > 1)
   float2* cpol;                  // one field's modes in polar form [M]: |c|, frac(arg c / (2 pi))
                                  // (FP32 interval sum; mixed-precision plans only)
   int max_batch;
   int sum_fields;                // fields summed per screen by the running propagation (march shape)
-  void* blas;                    // rocBLAS handle for batched matrix products (created on first use)
   int use_matrix;                // mode functions tabulated once (x-invariant medium)
   void* tmat;                    // T[mode][point], complex T (double2 or float2)
   swkb::DevRecords rec;
@@ -211,9 +210,13 @@ int superpose_groups(const Geometry& g);
 // Largest number of mode groups any superposition writes partial sums for.
 int partial_groups(const Geometry& g);
 hipError_t launch_build_matrix(const swkb_plan_s& pl, hipStream_t st);
-hipError_t launch_to_c64(const swkb_plan_s& pl, int batch, hipStream_t st);
-// U[b][m] = sum_j C[b][j] T[j][m] for batch > 1 into pl.part (rocBLAS GEMM)
-hipError_t gemm_fields(const swkb_plan_s& pl, int batch, hipStream_t st);
+// U[b][m] = sum_j C[b][j] T[j][m] for batch > 1: mode-group partial sums into
+// pl.part ([batch][groups][N], complex64 or complex128), groups written to
+// *groups (matrix cores, batch.hip).
+hipError_t launch_batch_product(const swkb_plan_s& pl, int batch, hipStream_t st, int* groups);
+int batch_groups(const Geometry& g, int precision, int B);
+size_t batch_part_bytes(const Geometry& g, int precision, int Bmax);
+size_t batch_panel_bytes(const Geometry& g, int B);
 hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st);
 // Multi-problem launches (tables and workgroup maps in device memory; map
 // entries are problem << 20 | local workgroup).

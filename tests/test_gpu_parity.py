@@ -760,3 +760,36 @@ def test_mixed_amplitude_near_turning_points(torch_dev, swkb):
     assert worst_turn <= 1e-4
     assert worst_all <= 1e-4
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,B", [("linear_caustic_N512", 9), ("linear_caustic_N512", 33),
+                                    ("linear_caustic_N512", 70), ("expgauss_N64_M2", 5)])
+def test_batch_product_shapes_equal_separate_runs(torch_dev, swkb, name, B, prec):
+    """The batched product on the matrix cores in every launch shape: one or
+    several column tiles (16 fields each in FP32, 8 in FP64), several passes
+    over T (more than 64 resp. 32 fields), a two-mode problem (one mode group
+    of one mode pair).  Every field equals its own single-field run."""
+    torch, dev = torch_dev
+    cfg = W.with_overrides(CASES[name](), max_batch=B)
+    assert cfg["medium_kind"] != W.MEDIUM_GAUSSSUM
+    P = swkb.FP64 if prec == "fp64" else swkb.MIXED
+    Q = min(cfg["n_screens"], 6)
+    rng = np.random.default_rng(B)
+    base = _sources(cfg, 3)
+    U0 = np.stack([base[b % 3] * np.exp(2j * np.pi * rng.uniform()) * rng.uniform(0.5, 2.0) for b in range(B)])
+    plan = swkb.Plan(cfg, precision=P, device=dev)
+    assert plan.uses_matrix
+    hist, last = plan.propagate_batch(torch.from_numpy(U0).to(dev), 0, Q)
+    hist = hist.cpu().numpy()
+    single = swkb.Plan(W.with_overrides(cfg, max_batch=1), precision=P, device=dev)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    worst = 0.0
+    for b in range(B):
+        ref = single.propagate(torch.from_numpy(U0[b]).to(dev), 0, Q).cpu().numpy()
+        worst = max(worst, rel(hist[:, b, :], ref))
+    say(f"[batch-shapes] {name} B={B} {prec}: worst field vs single run {worst:.2e}")
+    assert worst <= tol
+    assert torch.equal(last, torch.from_numpy(hist[-1]).to(dev))
+    plan.close()
+    single.close()
