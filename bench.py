@@ -268,9 +268,12 @@ def bench_multi(torch, np, W, Plan, Multi, MIXED, n_problems=64, graphs=True):
 def bench_patches(torch, np, W, Plan, PatchPlan, MIXED, n_patches=8):
     """Tall surface ducts (6 GHz, 1000 screens of 100 m, Dirichlet ground,
     mixed): 0-600 m (N_z = 32768, 8192 modes) by the single-domain step and by
-    the overlapping-patch step (8 patches, windows of 1 m, margins of 20 m),
-    and 0-1200 m (N_z = 65536, 16384 modes: beyond one plan's grid) by
-    patches only."""
+    the overlapping-patch steps (8 patches, partition of unity of scale 1 m,
+    margins of 20 m): the paper's Fourier-continuation patches and the
+    library's windowed pieces; 0-1200 m (N_z = 65536, 16384 modes: beyond one
+    plan's grid) by patches only."""
+    from paper_2301_03814_amd import PATCH_FC, PATCH_WINDOWED
+    methods = (("fourier_continuation", PATCH_FC), ("windowed", PATCH_WINDOWED))
     dev = torch.device("cuda:0")
 
     def timed(fn):
@@ -281,12 +284,12 @@ def bench_patches(torch, np, W, Plan, PatchPlan, MIXED, n_patches=8):
         torch.cuda.synchronize()
         return time.perf_counter() - t, r
 
-    def run_patches(cfg):
+    def run_patches(cfg, method):
         Q = cfg["n_screens"]
         u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pp = PatchPlan(cfg, n_patches, 1.0, 20.0, precision=MIXED)
+        pp = PatchPlan(cfg, n_patches, 1.0, 20.0, precision=MIXED, method=method)
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
         info = pp.info()
@@ -315,19 +318,21 @@ def bench_patches(torch, np, W, Plan, PatchPlan, MIXED, n_patches=8):
     ref = h[::50].cpu().numpy()
     del h
     full.close()
-    got, pat = run_patches(cfg)
+    runs = {name: run_patches(cfg, m) for name, m in methods}
     out = {"workload": "surface ducts: lambda=0.05 m, M-profile -0.3/+0.118 M/m, 1000 screens of 100 m (100 km), "
                        "Dirichlet ground, mixed; 0-600 m with N_z=32768, 8192 modes; 0-1200 m with N_z=65536, "
                        "16384 modes",
            "h600": {"single_domain": {"seconds": dt_full, "mode_points_per_screen": N * M,
                                       "plan_build_s": round(tb_full, 3), "range_km_per_s": 100.0 / dt_full,
                                       "mode_point_evals_per_s": N * M * Q / dt_full},
-                    "patches": pat,
-                    "speedup_patches_vs_single_domain": dt_full / pat["seconds"],
-                    "rel_diff_patches_vs_single_domain_every_50th_screen":
-                        float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}}
-    _, pat2 = run_patches(W.surface_duct(n_z=65536, n_modes=16384, height=1200.0))
-    out["h1200"] = {"patches": pat2, "single_domain": "beyond one plan's grid (n_z <= 32768)"}
+                    }}
+    for name, (got, pat) in runs.items():
+        pat["speedup_vs_single_domain"] = dt_full / pat["seconds"]
+        pat["rel_diff_vs_single_domain_every_50th_screen"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out["h600"][f"patches_{name}"] = pat
+    cfg2 = W.surface_duct(n_z=65536, n_modes=16384, height=1200.0)
+    pat2 = {f"patches_{name}": run_patches(cfg2, m)[1] for name, m in methods}
+    out["h1200"] = dict(pat2, single_domain="beyond one plan's grid (n_z <= 32768)")
     print(f"[bench] patches: {out}", file=sys.stderr, flush=True)
     return out
 

@@ -408,27 +408,42 @@ void swkb_multi_destroy(swkb_multi_t m);
 /* ---- overlapping patches ---------------------------------------------- */
 
 /* The screen step on overlapping patches (Sec. 2.4): the vertical interval
- * is covered by n_patches patches with cores [c_p, c_{p+1}],
+ * is covered by n_patches patches around the cores [c_p, c_{p+1}],
  * c_p = z_a + p K h (K = n_z / n_patches cells), blended by the smooth
  * partition of unity sigma_p(z) = erfc(-(z - c_p) / width) / 2,
  * S^0 = 1 - sigma_1, S^p = sigma_p - sigma_{p+1}, S^{P-1} = sigma_{P-1}.
- * A screen step windows the field (S^p u), runs the screen step of
- * swkb_propagate on each piece over a sub-domain of n_p points (a power of
- * two holding the core and e = ceil((6 width + margin) / h) cells on each
- * side, centred on the core; the bottom patch keeps the ground mirror and
- * starts at z_a), adds the pieces' outputs on the global grid in patch order
- * and applies the global exit taper.  Sub-domains keep the global largest
- * vertical slowness (n_modes_p = 2 floor(n_modes P_p / (2 P) + 1/2) with P_p, P
- * the FFT lengths) and have no absorbers.  The windowed pieces vanish near
- * their sub-domain ends, so the periodic step applies to them without the
- * paper's Fourier continuation; width sets how fast the windows' spectra
- * decay (exp(-(pi width xi / lambda)^2)) and margin must cover the drift of
- * the fields over one screen.  Cost per screen: the sum over patches of
- * n_modes_p n_p instead of n_modes n_z. */
+ *
+ * SWKB_PATCH_FC, the paper's FC-SWKB (eq. ifft_eq_phi_patches): patch p
+ * holds the grid points [a_p, b_p] = [p K - e, (p + 1) K + e], e =
+ * ceil(6 width / h), clipped to the grid.  Each screen the field on the patch
+ * is Fourier-continued (FC-Gram blend: 27 cells blending the 5 end samples to
+ * zero past each end) into one period of a power-of-two length (the patch,
+ * 2 x 27 blend cells and ceil(margin / h) cells of drift on each side); its
+ * DFT gives the patch's modes, whose rays start at the patch's points only,
+ * with initial amplitude S^p(z) w_j / N; the patches' mode sums are added on
+ * the global grid.  Over a ground (Sec. 2.5) the boundary patch is continued
+ * at its top only and keeps the ground mirror (odd or even extension,
+ * reflected medium, S^0 reflected), and every other patch's sum is reflected
+ * about z_a on each screen (eq. u_refl).
+ *
+ * SWKB_PATCH_WINDOWED, a variant of this library's: the field is windowed
+ * (S^p u) and each piece runs the screen step of swkb_propagate over a
+ * sub-domain holding the core and ceil((6 width + margin) / h) cells on each
+ * side (the bottom patch keeps the ground mirror and starts at z_a); the
+ * pieces carry the spectra of S^p u instead of launching S^p with each mode.
+ *
+ * Both: sub-domains keep the global largest vertical slowness (n_modes_p =
+ * 2 floor(n_modes P_p / (2 P) + 1/2) with P_p, P the FFT lengths) and have no
+ * absorbers; the global exit taper applies once after the sum; margin must
+ * cover the drift of the rays over one screen.  Cost per screen: the sum
+ * over patches of n_modes_p P_p instead of n_modes n_z. */
+#define SWKB_PATCH_FC 0
+#define SWKB_PATCH_WINDOWED 1
 typedef struct swkb_patch_config {
-  int32_t n_patches;  /* >= 1, divides n_z                        */
-  double width;       /* window scale (z units), > 0              */
-  double margin;      /* extra sub-domain cells' extent, >= 0 (z) */
+  int32_t n_patches;  /* >= 1, divides n_z                          */
+  double width;       /* partition of unity scale (z units), > 0    */
+  double margin;      /* drift room on each side, >= 0 (z units)    */
+  int32_t method;     /* SWKB_PATCH_FC or SWKB_PATCH_WINDOWED        */
 } swkb_patch_config;
 
 typedef struct swkb_patch_s* swkb_patch_t;

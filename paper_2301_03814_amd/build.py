@@ -15,7 +15,7 @@ OBJ = os.path.join(ROOT, "_build", "swkb")
 LIB = os.path.join(HERE, "libswkb.so")
 SOURCES = ["api.hip", "fft.hip", "march.hip", "superpose.hip", "modal.hip", "serve.hip", "multi.hip", "patch.hip",
            "static.hip", "batch.hip"]
-HEADERS = ["swkb_internal.h", "medium.h", "plan_guard.h"]
+HEADERS = ["swkb_internal.h", "medium.h", "plan_guard.h", "fc_gram.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -361,6 +361,33 @@ static swkb_status ensure_rays(swkb_plan_s* pl, int q, hipStream_t st) {
   return SWKB_OK;
 }
 
+namespace swkb {
+
+// Launch amplitude factors of a patch's rays (device array [R], or NULL),
+// set before the plan's first propagation.  A plan whose rays were marched
+// when it was built (media that do not depend on x, mode-function matrix)
+// marches them again with the factors and rebuilds its matrix; other plans
+// with cached rays drop them.
+swkb_status set_launch_window(swkb_plan_s* pl, const double* lw, hipStream_t st) {
+  pl->lwin = lw;
+  if (pl->use_matrix) {
+    select_slot(pl, 0);
+    hipError_t e = launch_march(*pl, 0, st);
+    if (e == hipSuccess) e = launch_scan(*pl, st);
+    if (e == hipSuccess) e = launch_build_matrix(*pl, st);
+    if (e != hipSuccess) {
+      set_slot_q(pl, 0, -1);
+      return hip_fail(e, "launch window: ray march");
+    }
+    set_slot_q(pl, 0, -2);
+  } else {
+    for (int k = 0; k < pl->nslots; ++k) set_slot_q(pl, k, -1);
+  }
+  return SWKB_OK;
+}
+
+}  // namespace swkb
+
 // Overlap march and sum on two streams: x-varying medium without profiling
 // (per-kernel event times need the kernels one after another).
 static bool overlap(const swkb_plan_s* pl) {

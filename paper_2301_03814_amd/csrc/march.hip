@@ -795,7 +795,7 @@ DevModes modes_of(const swkb_plan_s& pl) {
 
 int waves_per_mode(const Geometry& g) { return (g.R + 63) / 64; }
 
-hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
+static hipError_t launch_march_rays(const swkb_plan_s& pl, int q, hipStream_t st) {
   const Geometry& g = pl.g;
   const int wpm = waves_per_mode(g);
   const long long waves = (long long)wpm * g.M;
@@ -848,6 +848,40 @@ hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
   else
     hipLaunchKernelGGL(march_kernel<float>, grid, dim3(256), 0, st, g, mk, medium_for(pl, q), modes_of(pl),
                        pl.rec, wcount, x_q, wpm);
+  return hipGetLastError();
+}
+
+namespace {
+
+// Launch amplitudes of a patch (Sec. 2.4: initial amplitude S^p(z) w_j / N):
+// the transport factor of every live ray r of every mode times W[r]; a ray
+// with W[r] = 0 lies outside the patch and is not launched (dead at launch).
+template <typename T>
+__global__ void launch_window_kernel(T* __restrict__ A, const double* __restrict__ W, int R, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double w = W[i % (size_t)R];
+  const T a = A[i];
+  if (w > 0.0) {
+    if (a > T(0)) A[i] = (T)((double)a * w);
+  } else if (a > T(0)) {
+    A[i] = (T)(-kDeadLaunch);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st) {
+  const hipError_t e = launch_march_rays(pl, q, st);
+  if (e != hipSuccess || !pl.lwin) return e;
+  const size_t n = (size_t)pl.g.M * pl.g.R;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (pl.precision == SWKB_FP64)
+    hipLaunchKernelGGL(launch_window_kernel<double>, grid, dim3(256), 0, st, static_cast<double*>(pl.rec.A), pl.lwin,
+                       pl.g.R, n);
+  else
+    hipLaunchKernelGGL(launch_window_kernel<float>, grid, dim3(256), 0, st, static_cast<float*>(pl.rec.A), pl.lwin,
+                       pl.g.R, n);
   return hipGetLastError();
 }
 

@@ -1,26 +1,45 @@
-// Overlapping-patch screened WKB (Sec. 2.4): the vertical interval is
-// covered by P patches with cores [c_p, c_{p+1}], c_p = z_a + p K h
+// Overlapping-patch screened WKB (Sec. 2.4, FC-SWKB): the vertical interval
+// is covered by P patches around the cores [c_p, c_{p+1}], c_p = z_a + p K h
 // (K = N / P cells), blended by the smooth partition of unity
 //   sigma_p(z) = erfc(-(z - c_p) / w) / 2,
 //   S^0 = 1 - sigma_1,  S^p = sigma_p - sigma_{p+1},  S^{P-1} = sigma_{P-1},
 // which sums to one and falls below 1e-17 more than 6 w outside each core.
-// A screen step windows the field, u_p = S^p u, runs the ordinary screen
-// step (Sec. 2.1, with the ground mirror of Sec. 2.3 on the bottom patch;
-// for media that do not depend on x in mixed precision all patches' steps run
-// as one multi-problem group, one launch per stage)
-// on each piece over a sub-domain that holds the core plus e = ceil((6 w +
-// margin) / h) cells on each side (rounded up to a power of two, centred on
-// the core), adds the pieces' outputs on the global grid in patch order and
-// applies the global exit taper.  Each sub-domain keeps the global largest
-// vertical slowness (M_p = 2 floor(M P_p / (2 P_g) + 1/2), P_p and P_g the FFT
-// lengths) and has no absorbers of its own.  The per-screen cost is the sum
-// of the sub-domains' M_p n_p instead of M N.
+//
+// Fourier continuation (the paper's method, SWKB_PATCH_FC): patch p holds
+// the grid points [a_p, b_p] = [p K - e_w, (p + 1) K + e_w] (e_w =
+// ceil(6 w / h), clipped to the grid).  Each screen, the field on the patch
+// is continued past both ends by the FC-Gram blend (fc_gram.h: 27 values
+// blending the last 5 samples to zero) into one period of a power-of-two
+// length, the patch in its middle (eq. ifft_eq_phi_patches); that period is
+// the input of an ordinary periodic plan whose rays are launched only at the
+// patch's points with initial amplitude S^p(z) w_j / N (the plan's launch
+// window, applied after every march).  The patches' sums over their modes
+// are added on the global grid.  Over a ground (Sec. 2.5) the boundary
+// patch is continued only at its top and keeps the ground mirror of the
+// ordinary step (odd or even extension, medium reflected, launch amplitude
+// S^0 reflected), so it is never reflected afterwards; every other patch's
+// sum is reflected about z_a on each screen (eq. u_refl).
+//
+// Windowed pieces (SWKB_PATCH_WINDOWED, a variant of this library's): the
+// field is windowed, u_p = S^p u, and each piece runs the ordinary step on a
+// sub-domain holding the core plus e = ceil((6 w + margin) / h) cells on
+// each side, with the ground mirror on the bottom patch; the pieces carry the
+// spectrum of S^p u instead of launching S^p with each mode.
+//
+// Both: each sub-domain keeps the global largest vertical slowness (M_p =
+// 2 floor(M P_p / (2 P_g) + 1/2), P_p and P_g the FFT lengths), has no
+// absorbers of its own and has room for ceil(margin / h) cells of drift; the
+// global exit taper applies once after the sum; for media that do not depend
+// on x in mixed precision all patches' steps run as one multi-problem group
+// (one launch per stage).  The per-screen cost is the sum of the
+// sub-domains' M_p n_p instead of M N.
 #include <algorithm>
 #include <cmath>
 #include <new>
 #include <string>
 #include <vector>
 
+#include "fc_gram.h"
 #include "swkb_internal.h"
 
 namespace {
@@ -28,9 +47,14 @@ namespace {
 struct PatchView {
   int start, n;        // global index of the sub-domain's first point, its points
   const double2* f;    // the sub-plan's field after its screen step
-  const double* S;     // window at the sub-domain's points
-  double2* v;          // windowed field (the sub-plan's input)
+  const double* S;     // window at the sub-domain's points (windowed pieces)
+  double2* v;          // the sub-plan's input
+  int a, b;            // the patch's points [a, b] (Fourier continuation)
+  int cont_below;      // 1: continued below a as well (0: the boundary patch over a ground)
+  int reflect;         // 1: the sum is reflected about z_a (eq. u_refl)
 };
+
+__constant__ double c_blend[swkb::kFcCont][swkb::kFcMatch] = SWKB_FC_BLEND_INIT;
 
 swkb_status fail(swkb_status s, const std::string& msg) {
   swkb::set_error(msg);
@@ -42,21 +66,8 @@ swkb_status hip_fail(hipError_t e, const char* what) {
   return SWKB_ERR_DEVICE;
 }
 
-// v[i] = S[i] u[start + i] inside the global grid, 0 outside.
-__global__ void patch_window_kernel(const double2* __restrict__ u, int N, int start, int n,
-                                    const double* __restrict__ S, double2* __restrict__ v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int m = start + i;
-  double2 r = make_double2(0.0, 0.0);
-  if (m >= 0 && m < N) {
-    const double2 x = u[m];
-    r = make_double2(S[i] * x.x, S[i] * x.y);
-  }
-  v[i] = r;
-}
-
-// The same for every patch in one launch (patch blockIdx.y).
+// Windowed pieces of every patch (patch blockIdx.y): v[i] = S[i] u[start + i]
+// inside the global grid, 0 outside.
 __global__ void patch_window_all_kernel(const double2* __restrict__ u, int N, const PatchView* __restrict__ views) {
   const PatchView& pv = views[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -70,18 +81,60 @@ __global__ void patch_window_all_kernel(const double2* __restrict__ u, int N, co
   pv.v[i] = r;
 }
 
-// u'[m] = W[m] sum_p f_p[m - start_p] (patches in order), and the history row.
+// The sub-plans' inputs of every patch (patch blockIdx.y): the field on
+// [a, b] and its Fourier continuation, c + 1 cells past b the blend row c of
+// the last kFcMatch samples, c + 1 cells below a (cont_below) row c of the
+// first kFcMatch samples taken downwards, zero elsewhere in the period.
+__global__ void patch_fc_all_kernel(const double2* __restrict__ u, const PatchView* __restrict__ views) {
+  const PatchView& pv = views[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pv.n) return;
+  const int g = pv.start + i;
+  double re = 0.0, im = 0.0;
+  if (g >= pv.a && g <= pv.b) {
+    const double2 x = u[g];
+    re = x.x;
+    im = x.y;
+  } else if (g > pv.b && g <= pv.b + swkb::kFcCont) {
+    const int c = g - pv.b - 1;
+    for (int k = 0; k < swkb::kFcMatch; ++k) {
+      const double2 x = u[pv.b - swkb::kFcMatch + 1 + k];
+      re += c_blend[c][k] * x.x;
+      im += c_blend[c][k] * x.y;
+    }
+  } else if (pv.cont_below && g < pv.a && g >= pv.a - swkb::kFcCont) {
+    const int c = pv.a - g - 1;
+    for (int k = 0; k < swkb::kFcMatch; ++k) {
+      const double2 x = u[pv.a + swkb::kFcMatch - 1 - k];
+      re += c_blend[c][k] * x.x;
+      im += c_blend[c][k] * x.y;
+    }
+  }
+  pv.v[i] = make_double2(re, im);
+}
+
+// u'[m] = W[m] sum_p (f_p[m - start_p] + sgn f_p[-m - start_p] if reflected)
+// (patches in order), and the history row.
 __global__ void patch_add_kernel(const PatchView* __restrict__ views, int P, int N, const double* __restrict__ W,
-                                 double2* __restrict__ out, double2* __restrict__ hist) {
+                                 double sgn, double2* __restrict__ out, double2* __restrict__ hist) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= N) return;
   double re = 0.0, im = 0.0;
   for (int p = 0; p < P; ++p) {
-    const int i = m - views[p].start;
-    if (i >= 0 && i < views[p].n) {
-      const double2 x = views[p].f[i];
+    const PatchView& pv = views[p];
+    const int i = m - pv.start;
+    if (i >= 0 && i < pv.n) {
+      const double2 x = pv.f[i];
       re += x.x;
       im += x.y;
+    }
+    if (pv.reflect) {
+      const int j = -m - pv.start;
+      if (j >= 0 && j < pv.n) {
+        const double2 x = pv.f[j];
+        re += sgn * x.x;
+        im += sgn * x.y;
+      }
     }
   }
   const double2 r = make_double2(W[m] * re, W[m] * im);
@@ -101,14 +154,18 @@ struct swkb_patch_s {
   swkb_params p;
   std::vector<double> mparams;
   int P = 0, N = 0;
+  int method = SWKB_PATCH_FC;
   double width = 0.0, margin = 0.0, h = 0.0;
+  double sgn = 0.0;  // reflection of the non-boundary patches' sums: -1 Dirichlet, +1 Neumann, 0 none
   struct Sub {
     int start = 0, n = 0;
+    int a = 0, b = 0;      // the patch's points (Fourier continuation)
     swkb_params sp{};
     void* ws = nullptr;
     swkb_plan_t plan = nullptr;
-    double2* v = nullptr;  // windowed field [n]
-    double* S = nullptr;   // window at the sub-domain's points [n] (0 outside the grid)
+    double2* v = nullptr;  // the sub-plan's input [n]
+    double* S = nullptr;   // windowed pieces: window at the sub-domain's points [n] (0 outside the grid)
+    double* lw = nullptr;  // Fourier continuation: launch amplitude factor per ray of the sub-plan [R]
   };
   std::vector<Sub> subs;
   double2* u = nullptr;    // current field [N]
@@ -154,6 +211,7 @@ void destroy_patch(swkb_patch_s* pp) {
     if (s.ws) (void)hipFree(s.ws);
     if (s.v) (void)hipFree(s.v);
     if (s.S) (void)hipFree(s.S);
+    if (s.lw) (void)hipFree(s.lw);
   }
   if (pp->u) (void)hipFree(pp->u);
   if (pp->W) (void)hipFree(pp->W);
@@ -192,25 +250,27 @@ swkb_status enqueue_screens(swkb_patch_s* pp, const void* u_in, int q_begin, int
   if (u_in) e = hipMemcpyAsync(pp->u, u_in, sizeof(double2) * pp->N, hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: field copy");
   for (int q = q_begin; q < q_end; ++q) {
-    if (pp->grp) {
+    // every patch's input: its Fourier-continued period, or its windowed piece
+    if (pp->method == SWKB_PATCH_FC)
+      hipLaunchKernelGGL(patch_fc_all_kernel, dim3((pp->max_n + 255) / 256, pp->P), dim3(256), 0, st, pp->u,
+                         pp->views);
+    else
       hipLaunchKernelGGL(patch_window_all_kernel, dim3((pp->max_n + 255) / 256, pp->P), dim3(256), 0, st, pp->u,
                          pp->N, pp->views);
-      e = hipGetLastError();
-      if (e == hipSuccess) e = swkb::multi_step(pp->grp, q, st);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: patch inputs");
+    if (pp->grp) {
+      e = swkb::multi_step(pp->grp, q, st);
       if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: grouped step");
     } else {
       for (auto& s : pp->subs) {
-        hipLaunchKernelGGL(patch_window_kernel, dim3((s.n + 255) / 256), dim3(256), 0, st, pp->u, pp->N, s.start,
-                           s.n, s.S, s.v);
-        e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: window");
         const swkb_status ps = swkb::propagate_impl(s.plan, s.v, q, q + 1, nullptr, st);
         if (ps != SWKB_OK) return ps;
       }
     }
     double2* hist = history ? static_cast<double2*>(history) + (size_t)(q - q_begin) * pp->N : nullptr;
     hipLaunchKernelGGL(patch_add_kernel, dim3((pp->N + 255) / 256), dim3(256), 0, st, pp->views, pp->P, pp->N, pp->W,
-                       pp->u, hist);
+                       pp->sgn, pp->u, hist);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "swkb_patch_propagate: overlap-add");
   }
@@ -243,6 +303,8 @@ swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, v
   if (!(pc->width > 0.0) || !(pc->margin >= 0.0) || !std::isfinite(pc->width) || !std::isfinite(pc->margin))
     return fail(SWKB_ERR_ARG, "width must be > 0 and margin >= 0");
   if (p->max_batch != 1) return fail(SWKB_ERR_ARG, "patch plans carry one field (max_batch = 1)");
+  if (pc->method != SWKB_PATCH_FC && pc->method != SWKB_PATCH_WINDOWED)
+    return fail(SWKB_ERR_ARG, "method must be SWKB_PATCH_FC or SWKB_PATCH_WINDOWED");
   hipStream_t st = (hipStream_t)hip_stream;
   swkb_patch_s* pp = new (std::nothrow) swkb_patch_s();
   if (!pp) return fail(SWKB_ERR_NOMEM, "host allocation failed");
@@ -252,17 +314,42 @@ swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, v
     pp->p.medium_params = pp->mparams.data();
     pp->P = pc->n_patches;
     pp->N = p->n_z;
+    pp->method = pc->method;
     pp->width = pc->width;
     pp->margin = pc->margin;
     pp->h = (p->z_b - p->z_a) / p->n_z;
+    const bool ground = p->bc != SWKB_BC_PERIODIC;
+    pp->sgn = pc->method == SWKB_PATCH_FC && ground ? (p->bc == SWKB_BC_DIRICHLET ? -1.0 : 1.0) : 0.0;
     const int K = pp->N / pp->P;
     const int e = (int)std::ceil((6.0 * pc->width + pc->margin) / pp->h);
-    const int P_g = p->bc == SWKB_BC_PERIODIC ? pp->N : 2 * pp->N;
+    const int e_w = (int)std::ceil(6.0 * pc->width / pp->h);
+    const int e_m = (int)std::ceil(pc->margin / pp->h);
+    const int P_g = ground ? 2 * pp->N : pp->N;
     pp->subs.resize(pp->P);
     for (int q = 0; q < pp->P; ++q) {
       auto& s = pp->subs[q];
       s.sp = pp->p;
-      if (q == 0 && p->bc != SWKB_BC_PERIODIC) {
+      s.sp.launch_ext_cells = 0;
+      if (pc->method == SWKB_PATCH_FC) {
+        // the patch's points; its period holds 27 blend cells and the drift
+        // margin on both sides, the patch in the middle
+        s.a = std::max(0, q * K - e_w);
+        s.b = std::min(pp->N - 1, (q + 1) * K + e_w);
+        const int n = s.b - s.a + 1;
+        if (n < 2 * swkb::kFcMatch) {
+          delete pp;
+          return fail(SWKB_ERR_ARG, "a patch holds fewer than two matching stencils (10 points)");
+        }
+        if (q == 0 && ground) {
+          s.n = pow2_at_least(s.b + 1 + swkb::kFcCont + e_m);
+          s.start = 0;
+          s.sp.launch_ext_cells = e_m;  // rays of the mirror half that reach z_a
+        } else {
+          s.n = pow2_at_least(n + 2 * swkb::kFcCont + 2 * e_m);
+          s.start = s.a - (s.n - n) / 2;
+          s.sp.bc = SWKB_BC_PERIODIC;
+        }
+      } else if (q == 0 && ground) {
         s.n = pow2_at_least(K + e);
         s.start = 0;
       } else {
@@ -271,6 +358,7 @@ swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, v
         s.start = q * K - e - (s.n - need) / 2;
         s.sp.bc = SWKB_BC_PERIODIC;
       }
+      if (pc->method == SWKB_PATCH_WINDOWED) s.sp.launch_ext_cells = p->launch_ext_cells;
       const int P_p = s.sp.bc == SWKB_BC_PERIODIC ? s.n : 2 * s.n;
       s.sp.n_z = s.n;
       s.sp.n_modes = std::max(2, 2 * (int)std::floor((double)p->n_modes * P_p / (2.0 * P_g) + 0.5));
@@ -324,7 +412,31 @@ swkb_status swkb_patch_plan(const swkb_params* p, const swkb_patch_config* pc, v
       destroy_patch(pp);
       return hip_fail(e, "swkb_patch_plan: window upload");
     }
-    views[q] = PatchView{s.start, s.n, s.plan->u, s.S, s.v};
+    const bool ground_patch = q == 0 && p->bc != SWKB_BC_PERIODIC;
+    if (pp->method == SWKB_PATCH_FC) {
+      // launch amplitude S^p(s_r) of the sub-plan's rays (reflected about z_a
+      // on the mirror half of the boundary patch); 0 outside [a, b]
+      const int R = s.plan->g.R;
+      std::vector<double> lw(R, 0.0);
+      for (int r = 0; r < R; ++r) {
+        int gi = s.start + r * s.sp.ray_stride - s.sp.launch_ext_cells;
+        if (ground_patch && gi < 0) gi = -gi;
+        if (gi >= s.a && gi <= s.b) lw[r] = window(pp, q, p->z_a + (double)gi * pp->h);
+      }
+      e = hipMalloc(reinterpret_cast<void**>(&s.lw), sizeof(double) * R);
+      if (e == hipSuccess) e = hipMemcpy(s.lw, lw.data(), sizeof(double) * R, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        destroy_patch(pp);
+        return hip_fail(e, "swkb_patch_plan: launch window upload");
+      }
+      const swkb_status ws = swkb::set_launch_window(s.plan, s.lw, st);
+      if (ws != SWKB_OK) {
+        destroy_patch(pp);
+        return ws;
+      }
+    }
+    views[q] = PatchView{s.start, s.n, s.plan->u, s.S, s.v, s.a, s.b, ground_patch ? 0 : 1,
+                         pp->method == SWKB_PATCH_FC && p->bc != SWKB_BC_PERIODIC && !ground_patch ? 1 : 0};
     pp->max_n = std::max(pp->max_n, s.n);
   }
   std::vector<double> W(pp->N);

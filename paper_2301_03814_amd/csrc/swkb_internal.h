@@ -121,6 +121,8 @@ struct swkb_plan_s {
   double2 *Y, *c;                // FFT scratch [B][P], modes [B][M]
   double2* part;                 // superposition partials [B][mode groups][N]
   void* pan;                     // batched product's B operands per mode (matrix plans, max_batch > 1)
+  const double* lwin = nullptr;  // launch amplitude factor per ray [R] (a patch's S^p; 0: ray not launched), or
+                                 // NULL; device memory of the caller's, applied after every march
   float2* cpol;                  // one field's modes in polar form [M]: |c|, frac(arg c / (2 pi))
                                  // (FP32 interval sum; mixed-precision plans only)
   int max_batch;
@@ -203,6 +205,8 @@ hipError_t launch_fft_modes(const swkb_plan_s& pl, const double2* u, int batch, 
 // launch_march for the same screen.
 hipError_t launch_medium_table(const swkb_plan_s& pl, int q, hipStream_t st);
 hipError_t launch_march(const swkb_plan_s& pl, int q, hipStream_t st);
+// Launch amplitude factors per ray (overlapping patches); api.hip.
+swkb_status set_launch_window(swkb_plan_s* pl, const double* lw, hipStream_t st);
 hipError_t launch_scan(const swkb_plan_s& pl, hipStream_t st);
 // out [batch][N]; hist [batch][N] for this screen (or NULL).
 hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st);

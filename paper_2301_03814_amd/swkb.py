@@ -91,8 +91,12 @@ class MultiTuning(C.Structure):
                 ("apply_us", C.c_double * MULTI_MAX_CLASSES)]
 
 
+PATCH_FC, PATCH_WINDOWED = 0, 1
+
+
 class PatchConfig(C.Structure):
-    _fields_ = [("n_patches", C.c_int32), ("width", C.c_double), ("margin", C.c_double)]
+    _fields_ = [("n_patches", C.c_int32), ("width", C.c_double), ("margin", C.c_double),
+                ("method", C.c_int32)]
 
 
 REQ_PENDING, REQ_ACTIVE, REQ_DONE, REQ_FAILED = range(4)
@@ -487,16 +491,16 @@ class Multi:
 
 
 class PatchPlan:
-    """The screen step on overlapping patches (swkb_patch_*): the field is
-    windowed by a smooth partition of unity, each piece propagated on its own
-    sub-domain, the pieces added back."""
+    """The screen step on overlapping patches (swkb_patch_*): by default the
+    paper's Fourier-continuation patches (method=PATCH_FC), or the library's
+    windowed pieces (method=PATCH_WINDOWED)."""
 
-    def __init__(self, cfg, n_patches, width, margin, precision=FP64, stream=None):
+    def __init__(self, cfg, n_patches, width, margin, precision=FP64, stream=None, method=PATCH_FC):
         lib = load()
         self.cfg = cfg
         self.n_z = cfg["n_z"]
         self._params = make_params(cfg, precision)
-        pc = PatchConfig(n_patches=int(n_patches), width=float(width), margin=float(margin))
+        pc = PatchConfig(n_patches=int(n_patches), width=float(width), margin=float(margin), method=int(method))
         h = C.c_void_p()
         _check(lib.swkb_patch_plan(C.byref(self._params), C.byref(pc), _stream_handle(stream), C.byref(h)))
         self._h = h
