@@ -147,7 +147,9 @@ def bench_serving(torch, np, W, Plan, Server, FP64, MIXED, n_req=24):
 def bench_duct(args, torch, np, W, Plan, FP64, MIXED):
     """Surface duct at 6 GHz (N = 16384, M = 4096, 1000 screens of 100 m,
     Dirichlet ground mirror): an x-invariant medium, so the plan tabulates
-    the mode functions once and every screen is FFT + matrix product."""
+    the mode functions once and every screen is FFT + matrix product; beside
+    it the plain per-screen step (rays reused, interpolation and sum over
+    modes every screen)."""
     B = 16
     cfg = W.with_overrides(W.surface_duct(), max_batch=B)
     N, M, Q = cfg["n_z"], cfg["n_modes"], cfg["n_screens"]
@@ -189,6 +191,21 @@ def bench_duct(args, torch, np, W, Plan, FP64, MIXED):
                      f"batch{B}": {"mode_point_evals_per_s": B * M * N * Q / dtb, "ms_per_run": 1e3 * dtb,
                                    "note": f"{B} sources (heights 10-85 m) per screen as one complex matrix product on the matrix cores"}}
         plan.close()
+        # the plain per-screen step on the same workload
+        plain = Plan(W.with_overrides(cfg, propagator=2, max_batch=1), precision=prec, device=dev)
+        h = torch.empty((Q, N), dtype=torch.complex128, device=dev)
+        plain.propagate(u0, 0, Q, out=h)  # warm-up (marches the rays once)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain.propagate(u0, 0, Q, out=h)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        hp = h[::50].cpu().numpy()
+        del h
+        plain.close()
+        out[name]["plain_per_screen"] = {
+            "mode_point_evals_per_s": M * N * Q / dtp, "ms_per_run": 1e3 * dtp, "range_km_per_s": 100.0 / dtp,
+            "rel_diff_vs_matrix_every_50th_screen": float(np.linalg.norm(hp - hist[name]) / np.linalg.norm(hist[name]))}
     out["rel_err_mixed_vs_fp64_every_50th_screen"] = float(
         np.linalg.norm(hist["mixed"] - hist["fp64"]) / np.linalg.norm(hist["fp64"]))
     print(f"[bench] duct: {out}", file=sys.stderr, flush=True)

@@ -6,7 +6,8 @@ tests/golden/make_chained.py (which calls only the oracle):
 
 * the random medium (N = 8192, M = 2048), all 400 screens, every 25th;
 * the surface duct (N = 16384, M = 4096, Dirichlet ground), the first 20
-  screens (2 km), every 4th.
+  screens (2 km), every 4th, through the mode-function matrix and through
+  the plain per-screen step (interpolation and sum every screen).
 
 FP64 runs must stay within 1e-10 of the oracle, mixed runs within 1e-3, both
 as a relative L2 over the sampled screens and screen by screen as
@@ -51,6 +52,7 @@ def screen_max_rel(got, ref):
 CASES = {
     "random_medium": (lambda: W.random_medium(), 400),
     "surface_duct": (lambda: W.surface_duct(), 20),
+    "surface_duct_plain": (lambda: W.with_overrides(W.surface_duct(), propagator=2), 20),
 }
 TOL = {"fp64": 1e-10, "mixed": 1e-3}
 
@@ -62,9 +64,10 @@ def test_chain_matches_oracle_chain(torch_dev, name, prec):
     import paper_2301_03814_amd as pkg
     build, n_screens = CASES[name]
     cfg = build()
-    screens, ref, cnt = load_chain(name)
+    screens, ref, cnt = load_chain(name.replace("_plain", ""))
     say(f"[chain] {name} {prec}: {n_screens} screens on the GPU")
     plan = pkg.Plan(cfg, precision=pkg.FP64 if prec == "fp64" else pkg.MIXED, device=dev)
+    assert plan.uses_matrix == (name == "surface_duct")
     hist = plan.propagate(torch.from_numpy(W.incident_field(cfg)).to(dev), 0, n_screens)
     got = hist[torch.from_numpy(screens.astype(np.int64) - 1).to(dev)].cpu().numpy()
     diag = plan.diagnostics()
