@@ -342,7 +342,13 @@ int32_t swkb_uses_matrix(swkb_plan_t plan);
  * a device table.  Problems are ordered by screen count, so the problems
  * still running at step q are a prefix of the table and the launches of
  * step q cover exactly them.  With graphs enabled the whole sequence of
- * steps is captured once into a HIP graph and replayed as one launch.
+ * steps is captured once into a HIP graph and replayed as one launch.  With
+ * SWKB_MULTI_PERSISTENT it is one persistent launch instead: a cooperative
+ * grid of workgroups that are all resident at once walks every step's four
+ * stages in order, each workgroup taking every gridDim-th map entry of a
+ * stage, with a grid-wide barrier between stages; it runs the same device
+ * code item for item, so the fields equal those of the per-stage launches
+ * bit for bit.
  *
  * Requirements per plan: mode-function matrix in use (swkb_uses_matrix),
  * SWKB_MIXED precision, n_z a multiple of 512; at most 4095 plans, each
@@ -360,12 +366,13 @@ typedef struct swkb_multi_s* swkb_multi_t;
  * equal the single-problem path's choices, which makes every field
  * bit-identical to a separate swkb_propagate. */
 #define SWKB_MULTI_MAX_CLASSES 16
+#define SWKB_MULTI_PERSISTENT 2
 typedef struct swkb_multi_tuning {
   int32_t n_classes;                            /* distinct n_z, ascending   */
   int32_t class_n_z[SWKB_MULTI_MAX_CLASSES];
   int32_t fft_elems[SWKB_MULTI_MAX_CLASSES];
   int32_t apply_groups[SWKB_MULTI_MAX_CLASSES];
-  int32_t graphs;                               /* 1: capture and replay     */
+  int32_t graphs;                               /* 0: one launch per stage, 1: captured and replayed, SWKB_MULTI_PERSISTENT: one launch */
   double fft_us[SWKB_MULTI_MAX_CLASSES];        /* tuner: best FFT time of the class's screen (both passes) */
   double apply_us[SWKB_MULTI_MAX_CLASSES];      /* tuner: best product time of the class's screen           */
 } swkb_multi_tuning;

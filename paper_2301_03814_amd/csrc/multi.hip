@@ -51,6 +51,9 @@ struct swkb_multi_s {
   size_t lds_cols = 0, lds_rows = 0;
   // device memory
   MultiProblem* d_prob = nullptr;
+  int4* d_counts = nullptr;         // [qmax]: map entries of the four stages at each step
+  int* d_ctr = nullptr;             // [4 qmax]: the persistent launch's stage counters
+  int persist_blocks = 0;           // grid of the last persistent launch
   unsigned* d_map = nullptr;
   size_t map_cap = 0;               // entries
   size_t map_base[kKinds] = {0, 0, 0, 0};
@@ -177,6 +180,14 @@ hipError_t build_tables(swkb_multi_s* m) {
         map[m->map_base[k] + b] = ((unsigned)s << kMapShift) | (unsigned)(b - m->off[k][s]);
   e = hipMemcpy(m->d_map, map.data(), sizeof(unsigned) * entries, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->d_prob, m->hp.data(), sizeof(MultiProblem) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    std::vector<int4> cnt(m->qmax);
+    for (int q = 0; q < m->qmax; ++q) {
+      const int a = m->na[q];
+      cnt[q] = make_int4(m->off[kCols][a], m->off[kRows][a], m->off[kApply][a], m->off[kFin][a]);
+    }
+    e = hipMemcpy(m->d_counts, cnt.data(), sizeof(int4) * m->qmax, hipMemcpyHostToDevice);
+  }
   return e;
 }
 
@@ -202,6 +213,8 @@ void destroy_all(swkb_multi_s* m) {
   if (m->ev_done) (void)hipEventSynchronize(m->ev_done);
   drop_graph(m);
   if (m->d_prob) (void)hipFree(m->d_prob);
+  if (m->d_counts) (void)hipFree(m->d_counts);
+  if (m->d_ctr) (void)hipFree(m->d_ctr);
   if (m->d_map) (void)hipFree(m->d_map);
   if (m->d_part) (void)hipFree(m->d_part);
   if (m->h_stage) (void)hipHostFree(m->h_stage);
@@ -296,6 +309,8 @@ swkb_status swkb_multi_create(const swkb_plan_t* plans, int32_t n, swkb_multi_t*
     return fail(SWKB_ERR_NOMEM, "host allocation failed");
   }
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&m->d_prob), sizeof(MultiProblem) * n);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&m->d_counts), sizeof(int4) * m->qmax);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&m->d_ctr), sizeof(int) * 4 * m->qmax);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&m->h_stage), sizeof(MultiProblem) * n,
                                          hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_stage, hipEventDisableTiming);
@@ -331,6 +346,8 @@ swkb_status swkb_multi_set_tuning(swkb_multi_t m, const swkb_multi_tuning* t) {
     if (!valid_elems(t->fft_elems[c])) return fail(SWKB_ERR_ARG, "fft_elems must be 256, 512 or 1024");
     if (t->apply_groups[c] < 1) return fail(SWKB_ERR_ARG, "apply_groups must be >= 1");
   }
+  if (t->graphs < 0 || t->graphs > SWKB_MULTI_PERSISTENT)
+    return fail(SWKB_ERR_ARG, "graphs must be 0, 1 or SWKB_MULTI_PERSISTENT");
   const hipError_t e0 = hipEventSynchronize(m->ev_done);
   if (e0 != hipSuccess) return hip_fail(e0, "swkb_multi_set_tuning");
   drop_graph(m);
@@ -484,7 +501,12 @@ swkb_status swkb_multi_propagate(swkb_multi_t m, const void* const* u_in, void* 
   e = hipMemcpyAsync(m->d_prob, m->h_stage, sizeof(MultiProblem) * n, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipEventRecord(m->ev_stage, st);
   if (e != hipSuccess) return hip_fail(e, "swkb_multi_propagate: table upload");
-  if (m->tun.graphs) {
+  if (m->tun.graphs == SWKB_MULTI_PERSISTENT) {
+    const size_t lds = std::max(std::max(m->lds_cols, m->lds_rows), swkb::apply_lds_bytes());
+    e = swkb::launch_multi_persistent(m->d_prob, map_of(m, kCols), map_of(m, kRows), map_of(m, kApply),
+                                      map_of(m, kFin), m->d_counts, m->d_ctr, m->qmax, lds, 0, st,
+                                      &m->persist_blocks);
+  } else if (m->tun.graphs) {
     if (!m->exec) {
       e = hipStreamBeginCapture(m->cs, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "swkb_multi_propagate: capture");

@@ -14,6 +14,9 @@
 // medium, built once per plan).
 #include <type_traits>
 
+#include <hip/hip_cooperative_groups.h>
+
+#include "fft_body.h"
 #include "swkb_internal.h"
 
 namespace swkb {
@@ -515,12 +518,16 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_kernel(Geometry g,
 // The same product for complex64 T with 16-byte loads: lane l of a
 // wavefront reads points m0 + 128 u + 2 l and + 1 (two complex64 in one
 // float4), u < 4, so a workgroup covers 512 points and each load moves 1 KB
-// per wavefront.  The mode loop is not unrolled: at 57 VGPRs eight
-// wavefronts per SIMD keep enough loads in flight (unrolled by 4: 102 VGPRs,
-// four wavefronts, the 64-problem batch 1.486 -> 1.469 s without).  N % 512 == 0.
+// per wavefront.  In the per-stage kernels the mode loop is not unrolled
+// (U = 1): at 57 VGPRs eight wavefronts per SIMD keep enough loads in flight
+// (unrolled by 4: 102 VGPRs, four wavefronts, the 64-problem batch 1.486 ->
+// 1.469 s without).  The persistent kernel, whose other stages hold more
+// registers anyway, requests U modes' loads at once.  The terms are added in
+// the same order either way.  N % 512 == 0.
+template <int U>
 __device__ inline void apply_c64_body(const Geometry& g, const float4* __restrict__ tab,
                                       const double2* __restrict__ c, double2* __restrict__ part, int bx, int gi,
-                                      int groups, double2* red) {  // red: [kWaves][4][64][2] pairs of (re, im)
+                                      int groups, float2* red) {  // red: [kWaves][4][64][2] pairs of (re, im)
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int jstep = groups * kWaves;
@@ -528,8 +535,34 @@ __device__ inline void apply_c64_body(const Geometry& g, const float4* __restric
   float ar[4][2], ai[4][2];
   for (int u = 0; u < 4; ++u) ar[u][0] = ar[u][1] = ai[u][0] = ai[u][1] = 0.0f;
   const size_t row4 = (size_t)g.N / 2;  // float4 per row of T
+  int j = gi * kWaves + w;
+  if constexpr (U > 1) {
 #pragma unroll 1
-  for (int j = gi * kWaves + w; j < g.M; j += jstep) {
+    for (; j + (U - 1) * jstep < g.M; j += U * jstep) {
+      F4 v[U][4];
+      float cr[U], ci[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        const double2 cj = c[j + t * jstep];
+        cr[t] = (float)cj.x;
+        ci[t] = (float)cj.y;
+        const float4* col = tab + (size_t)(j + t * jstep) * row4 + m0 / 2 + lane;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[t][u] = __builtin_nontemporal_load(reinterpret_cast<const F4*>(col + u * 64));
+      }
+#pragma unroll
+      for (int t = 0; t < U; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ar[u][0] += cr[t] * v[t][u].x - ci[t] * v[t][u].y;
+          ai[u][0] += cr[t] * v[t][u].y + ci[t] * v[t][u].x;
+          ar[u][1] += cr[t] * v[t][u].z - ci[t] * v[t][u].w;
+          ai[u][1] += cr[t] * v[t][u].w + ci[t] * v[t][u].z;
+        }
+    }
+  }
+#pragma unroll 1
+  for (; j < g.M; j += jstep) {
     const double2 cj = c[j];
     const float cr = (float)cj.x, ci = (float)cj.y;
     const float4* col = tab + (size_t)j * row4 + m0 / 2 + lane;
@@ -544,16 +577,16 @@ __device__ inline void apply_c64_body(const Geometry& g, const float4* __restric
   }
   for (int u = 0; u < 4; ++u)
     for (int h = 0; h < 2; ++h)
-      red[((w * 4 + u) * 64 + lane) * 2 + h] = make_double2((double)ar[u][h], (double)ai[u][h]);
+      red[((w * 4 + u) * 64 + lane) * 2 + h] = make_float2(ar[u][h], ai[u][h]);
   __syncthreads();
-  // points m0 + 128 u + 2 l + h, summed over the wavefronts in order
+  // points m0 + 128 u + 2 l + h, summed over the wavefronts in order (in FP64)
   for (int idx = threadIdx.x; idx < 512; idx += blockDim.x) {
     const int u = idx >> 7, l = (idx >> 1) & 63, h = idx & 1;
     double sr = 0.0, si = 0.0;
     for (int k = 0; k < kWaves; ++k) {
-      const double2 v = red[((k * 4 + u) * 64 + l) * 2 + h];
-      sr += v.x;
-      si += v.y;
+      const float2 v = red[((k * 4 + u) * 64 + l) * 2 + h];
+      sr += (double)v.x;
+      si += (double)v.y;
     }
     part[(size_t)gi * g.N + m0 + idx] = make_double2(sr, si);
   }
@@ -563,7 +596,7 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_c64_kernel(Geometry 
                                                                        const double2* __restrict__ c,
                                                                        double2* __restrict__ part) {
   extern __shared__ double2 red[];
-  apply_c64_body(g, tab, c, part, blockIdx.x, blockIdx.y, gridDim.y, red);
+  apply_c64_body<1>(g, tab, c, part, blockIdx.x, blockIdx.y, gridDim.y, reinterpret_cast<float2*>(red));
 }
 
 // Sum of the mode-group partials in a fixed order (four threads per point,
@@ -574,6 +607,10 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_c64_kernel(Geometry 
 // energy summed over the batch exceeds caustic_tol^2 times the largest.
 constexpr int kFinThreads = 512;  // 128 points per workgroup, 4 threads per point
 constexpr int kFinWaves = kFinThreads / 64;
+// Threads per workgroup of the persistent multi-problem kernel: the FFT and
+// product bodies' own workgroup size (the epilogue body takes any).
+constexpr int kPersistThreads = 64 * kWaves;
+constexpr int kPersistUnroll = 4;  // modes of the product whose loads a wavefront issues together
 
 // Energy of mode j summed over the batch in field order (the loads of eight
 // fields are issued before their terms are added).
@@ -601,50 +638,53 @@ __device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, c
                                      const Epi& ep, int bx, int nbx, int b) {
   if (bx + 1 < nbx) {
     const int sub = threadIdx.x & 3;
-    const int m = bx * (kFinThreads / 4) + (threadIdx.x >> 2);
     const PT* pb = part + (size_t)b * groups * g.N;
-    double sr = 0.0, si = 0.0;
-    if (m < g.N) {
+    // the workgroup's kFinThreads / 4 points, blockDim.x / 4 at a time
+    for (int p0 = 0; p0 < kFinThreads / 4; p0 += (int)blockDim.x / 4) {
+      const int m = bx * (kFinThreads / 4) + p0 + (threadIdx.x >> 2);
+      double sr = 0.0, si = 0.0;
+      if (m < g.N) {
 #pragma unroll 4
-      for (int k = sub; k < groups; k += 4) {
-        const PT v = pb[(size_t)k * g.N + m];
-        sr += (double)v.x;
-        si += (double)v.y;
+        for (int k = sub; k < groups; k += 4) {
+          const PT v = pb[(size_t)k * g.N + m];
+          sr += (double)v.x;
+          si += (double)v.y;
+        }
       }
-    }
-    // combine the four partial sums in the order 0, 1, 2, 3
-    const double r1 = __shfl_down(sr, 1, 4), i1 = __shfl_down(si, 1, 4);
-    const double r2 = __shfl_down(sr, 2, 4), i2 = __shfl_down(si, 2, 4);
-    const double r3 = __shfl_down(sr, 3, 4), i3 = __shfl_down(si, 3, 4);
-    if (sub == 0 && m < g.N) {
-      const double tr = ((sr + r1) + r2) + r3, ti = ((si + i1) + i2) + i3;
-      const double wz = taper(g, ep, g.z_a + (double)m * g.h);
-      const double2 val = make_double2(wz * tr, wz * ti);
-      out[(size_t)b * g.N + m] = val;
-      if (hist) hist[(size_t)b * g.N + m] = val;
+      // combine the four partial sums in the order 0, 1, 2, 3
+      const double r1 = __shfl_down(sr, 1, 4), i1 = __shfl_down(si, 1, 4);
+      const double r2 = __shfl_down(sr, 2, 4), i2 = __shfl_down(si, 2, 4);
+      const double r3 = __shfl_down(sr, 3, 4), i3 = __shfl_down(si, 3, 4);
+      if (sub == 0 && m < g.N) {
+        const double tr = ((sr + r1) + r2) + r3, ti = ((si + i1) + i2) + i3;
+        const double wz = taper(g, ep, g.z_a + (double)m * g.h);
+        const double2 val = make_double2(wz * tr, wz * ti);
+        out[(size_t)b * g.N + m] = val;
+        if (hist) hist[(size_t)b * g.N + m] = val;
+      }
     }
     return;
   }
   if (b != 0) return;
-  // Diagnostics of the screen (last workgroup of field 0, 512 threads so
-  // that each loop below is one or two rounds of independent loads): the
+  // Diagnostics of the screen (last workgroup of field 0, up to 512 threads
+  // so that each loop below is one or two rounds of independent loads): the
   // largest mode energy (summed over the batch), then the counts, with
   // wavefront reductions and the wavefronts combined in order.
   __shared__ double sm[kFinWaves];
   __shared__ unsigned long long cnt[kFinWaves][10];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
   double emax = 0.0;
 #pragma unroll 4
-  for (int j = threadIdx.x; j < g.M; j += kFinThreads) emax = fmax(emax, batch_energy(c, g.M, j, batch));
+  for (int j = threadIdx.x; j < g.M; j += (int)blockDim.x) emax = fmax(emax, batch_energy(c, g.M, j, batch));
   for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off, 64));
   if (lane == 0) sm[wv] = emax;
   __syncthreads();
   emax = 0.0;
-  for (int k = 0; k < kFinWaves; ++k) emax = fmax(emax, sm[k]);
+  for (int k = 0; k < nw; ++k) emax = fmax(emax, sm[k]);
   const double thr = ep.caustic_tol * ep.caustic_tol * emax;
   unsigned v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // a thread's sums fit 32 bits; 64-bit from the wavefront on
 #pragma unroll 4
-  for (int j = threadIdx.x; j < g.M; j += kFinThreads) {
+  for (int j = threadIdx.x; j < g.M; j += (int)blockDim.x) {
     const int f = rec.mflag[j];
     v[0] += rec.mcaus[j];
     v[1] += rec.mdead[j];
@@ -670,7 +710,7 @@ __device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, c
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int w = 0; w < kFinWaves; ++w)
+    for (int w = 0; w < nw; ++w)
       for (int k = 0; k < 10; ++k) t[k] += cnt[w][k];
     for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], t[k]);
     atomicAdd(&counters[4], 1ull);
@@ -696,7 +736,7 @@ __global__ void __launch_bounds__(64 * kWaves) apply_c64_multi(const MultiProble
   const unsigned e = map[blockIdx.x];
   const MultiProblem& p = mp[e >> 20];
   const int local = (int)(e & 0xfffff), nx = p.g.N >> 9;
-  apply_c64_body(p.g, p.tmat, p.c, p.part, local % nx, local / nx, p.groups, red);
+  apply_c64_body<1>(p.g, p.tmat, p.c, p.part, local % nx, local / nx, p.groups, reinterpret_cast<float2*>(red));
 }
 
 __global__ void __launch_bounds__(kFinThreads) finalize_multi(const MultiProblem* __restrict__ mp,
@@ -706,6 +746,78 @@ __global__ void __launch_bounds__(kFinThreads) finalize_multi(const MultiProblem
   double2* hist = p.hist ? p.hist + (size_t)step * p.g.N : nullptr;
   finalize_body<double2>(p.g, p.rec, p.c, p.part, p.groups, 1, p.u, hist, p.counters, p.ep, (int)(e & 0xfffff),
                          (p.g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, 0);
+}
+
+// Every screen step of every problem of a group in one launch: a grid of
+// workgroups that are all resident at once (cooperative launch) walks the
+// stages of each step in order (FFT columns, FFT rows, matrix product,
+// epilogue), with a grid-wide barrier between stages.  Within a stage the
+// workgroups take the stage's map entries one at a time from a counter
+// (ctr[4 q + stage], zero at the start), so that entries of unequal cost
+// (problems of different sizes) spread as they do over a launch's
+// workgroups.  n[q] holds the number of map entries of each stage at step
+// q.  The same device bodies as the per-stage kernels, entry for entry, so
+// the fields are those of the per-stage launches bit for bit.
+template <typename F>
+__device__ inline void take_items(int* __restrict__ ctr, int count, F&& body) {
+  __shared__ int item;
+  for (;;) {
+    if (threadIdx.x == 0) item = atomicAdd(ctr, 1);
+    __syncthreads();
+    const int i = item;
+    __syncthreads();  // every thread has read item before it changes
+    if (i >= count) break;  // uniform over the workgroup
+    body(i);
+    __syncthreads();  // the LDS of this entry is free for the next one
+  }
+}
+
+__global__ void __launch_bounds__(kPersistThreads) multi_persistent(const MultiProblem* __restrict__ mp,
+                                                                    const unsigned* __restrict__ map_cols,
+                                                                    const unsigned* __restrict__ map_rows,
+                                                                    const unsigned* __restrict__ map_apply,
+                                                                    const unsigned* __restrict__ map_fin,
+                                                                    const int4* __restrict__ n, int* __restrict__ ctr,
+                                                                    int qmax) {
+  extern __shared__ double2 L[];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int q = 0; q < qmax; ++q) {
+    const int4 cnt = n[q];
+    take_items(ctr + 4 * q, cnt.x, [&](int i) {
+      const unsigned e = map_cols[i];
+      const MultiProblem& p = mp[e >> 20];
+      fftb::fft_cols_body(q == 0 ? p.u_in : p.u, p.Y, p.tw, p.g.N, p.g.bc, p.g.P, p.g.P1, p.g.P2, p.logP1, p.CA,
+                          (int)(e & 0xfffff), L);
+    });
+    grid.sync();
+    take_items(ctr + 4 * q + 1, cnt.y, [&](int i) {
+      const unsigned e = map_rows[i];
+      const MultiProblem& p = mp[e >> 20];
+      fftb::fft_rows_body(p.Y, p.c, p.tw, p.g.P, p.g.P1, p.g.P2, p.logP2, p.RB, p.g.M, (int)(e & 0xfffff), L);
+    });
+    grid.sync();
+    take_items(ctr + 4 * q + 2, cnt.z, [&](int i) {
+      const unsigned e = map_apply[i];
+      const MultiProblem& p = mp[e >> 20];
+      const int local = (int)(e & 0xfffff), nx = p.g.N >> 9;
+      apply_c64_body<kPersistUnroll>(p.g, p.tmat, p.c, p.part, local % nx, local / nx, p.groups,
+                                     reinterpret_cast<float2*>(L));
+    });
+    grid.sync();
+    take_items(ctr + 4 * q + 3, cnt.w, [&](int i) {
+      const unsigned e = map_fin[i];
+      const MultiProblem& p = mp[e >> 20];
+      double2* hist = p.hist ? p.hist + (size_t)q * p.g.N : nullptr;
+      finalize_body<double2>(p.g, p.rec, p.c, p.part, p.groups, 1, p.u, hist, p.counters, p.ep, (int)(e & 0xfffff),
+                             (p.g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, 0);
+    });
+    grid.sync();
+  }
+}
+
+__global__ void zero_ints(int* __restrict__ a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
 }
 
 }  // namespace
@@ -845,7 +957,7 @@ hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* his
   if (batch == 1 && pl.precision != SWKB_FP64 && g.N % 512 == 0) {
     const int groups = c64_groups(g);  // 512-point workgroups
     hipLaunchKernelGGL(apply_matrix_c64_kernel, dim3(g.N / 512, groups), dim3(64 * kWaves),
-                       sizeof(double2) * kWaves * 4 * 64 * 2, st, g, static_cast<const float4*>(pl.tmat), pl.c,
+                       sizeof(float2) * kWaves * 4 * 64 * 2, st, g, static_cast<const float4*>(pl.tmat), pl.c,
                        pl.part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -891,7 +1003,7 @@ int apply_multi_groups(const Geometry& g) { return c64_groups(g); }
 hipError_t launch_apply_multi(const MultiProblem* mp, const unsigned* map_apply, int n_apply,
                               const unsigned* map_fin, int n_fin, int step, hipStream_t st) {
   if (n_apply > 0) {
-    hipLaunchKernelGGL(apply_c64_multi, dim3(n_apply), dim3(64 * kWaves), sizeof(double2) * kWaves * 4 * 64 * 2, st,
+    hipLaunchKernelGGL(apply_c64_multi, dim3(n_apply), dim3(64 * kWaves), sizeof(float2) * kWaves * 4 * 64 * 2, st,
                        mp, map_apply);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -902,5 +1014,37 @@ hipError_t launch_apply_multi(const MultiProblem* mp, const unsigned* map_apply,
   }
   return hipSuccess;
 }
+
+
+// One cooperative launch for every screen step of a group (see
+// multi_persistent): the largest grid whose workgroups all fit on the device
+// at once, at most max_blocks; *blocks_out gets the grid size.  ctr: 4 qmax
+// ints of device memory for the stage counters.
+hipError_t launch_multi_persistent(const MultiProblem* mp, const unsigned* map_cols, const unsigned* map_rows,
+                                   const unsigned* map_apply, const unsigned* map_fin, const int4* n, int* ctr,
+                                   int qmax, size_t lds, int max_blocks, hipStream_t st, int* blocks_out) {
+  int dev = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(multi_persistent),
+                                                     kPersistThreads, lds);
+  if (e != hipSuccess) return e;
+  int blocks = per_cu * prop.multiProcessorCount;
+  if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
+  if (blocks < 1) return hipErrorInvalidConfiguration;
+  if (blocks_out) *blocks_out = blocks;
+  // the stage counters start at zero (a kernel, not a memset: callers may capture this)
+  hipLaunchKernelGGL(zero_ints, dim3((4 * qmax + 255) / 256), dim3(256), 0, st, ctr, 4 * qmax);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  void* args[] = {(void*)&mp, (void*)&map_cols, (void*)&map_rows, (void*)&map_apply, (void*)&map_fin, (void*)&n,
+                  (void*)&ctr, (void*)&qmax};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(multi_persistent), dim3(blocks),
+                                    dim3(kPersistThreads), args, (unsigned)lds, st);
+}
+
+size_t apply_lds_bytes() { return sizeof(float2) * kWaves * 4 * 64 * 2; }
 
 }  // namespace swkb

@@ -231,6 +231,12 @@ int finalize_blocks(const Geometry& g);
 int apply_multi_groups(const Geometry& g);
 hipError_t launch_fft_multi(const MultiProblem* mp, const unsigned* map_cols, int n_cols, const unsigned* map_rows,
                             int n_rows, int first, size_t lds_cols, size_t lds_rows, hipStream_t st);
+// Every screen step of a multi-problem group in one cooperative launch
+// (superpose.hip); n[q] = map entries of the four stages at step q.
+hipError_t launch_multi_persistent(const MultiProblem* mp, const unsigned* map_cols, const unsigned* map_rows,
+                                   const unsigned* map_apply, const unsigned* map_fin, const int4* n, int* ctr,
+                                   int qmax, size_t lds, int max_blocks, hipStream_t st, int* blocks_out);
+size_t apply_lds_bytes();
 hipError_t launch_apply_multi(const MultiProblem* mp, const unsigned* map_apply, int n_apply,
                               const unsigned* map_fin, int n_fin, int step, hipStream_t st);
 // Inside the library: a multi-problem group whose problems read their fields

@@ -34,6 +34,7 @@ EXPORTS = ["swkb_workspace_bytes", "swkb_plan", "swkb_propagate", "swkb_field", 
            "swkb_propagate_static"]
 
 MULTI_MAX_CLASSES = 16
+MULTI_PERSISTENT = 2  # swkb_multi_tuning.graphs: one persistent launch
 
 
 class Params(C.Structure):
@@ -428,7 +429,8 @@ class Multi:
     def _tuning_dict(t):
         n = t.n_classes
         return {"n_z": list(t.class_n_z[:n]), "fft_elems": list(t.fft_elems[:n]),
-                "apply_groups": list(t.apply_groups[:n]), "graphs": bool(t.graphs),
+                "apply_groups": list(t.apply_groups[:n]), "graphs": t.graphs == 1,
+                "persistent": t.graphs == MULTI_PERSISTENT,
                 "fft_us": list(t.fft_us[:n]), "apply_us": list(t.apply_us[:n])}
 
     def tuning(self):
@@ -436,8 +438,10 @@ class Multi:
         _check(_lib.swkb_multi_get_tuning(self._h, C.byref(t)))
         return self._tuning_dict(t)
 
-    def set_tuning(self, fft_elems=None, apply_groups=None, graphs=None):
-        """Change launch shapes: per-class lists (ascending n_z) or None to keep."""
+    def set_tuning(self, fft_elems=None, apply_groups=None, graphs=None, persistent=None):
+        """Change launch shapes: per-class lists (ascending n_z) or None to
+        keep; graphs: capture and replay the per-stage launches; persistent:
+        one cooperative launch for every step instead."""
         t = MultiTuning()
         _check(_lib.swkb_multi_get_tuning(self._h, C.byref(t)))
         for name, vals in (("fft_elems", fft_elems), ("apply_groups", apply_groups)):
@@ -448,6 +452,10 @@ class Multi:
                     getattr(t, name)[i] = int(v)
         if graphs is not None:
             t.graphs = 1 if graphs else 0
+        if persistent:
+            t.graphs = MULTI_PERSISTENT
+        elif persistent is not None and t.graphs == MULTI_PERSISTENT:
+            t.graphs = 0
         _check(_lib.swkb_multi_set_tuning(self._h, C.byref(t)))
 
     def tune(self, reps=10, stream=None):

@@ -109,6 +109,51 @@ def test_graph_replays_equal_eager(env):
     close(plans, m)
 
 
+def test_persistent_launch_equals_separate_runs(env):
+    """One cooperative launch for every step of every problem (grid-wide
+    barriers between the stages) gives each problem's history and
+    diagnostics of a separate swkb_propagate bit for bit, on two calls in a
+    row."""
+    torch, dev, pkg = env
+    cfgs = uneven()
+    ref = [standalone(torch, dev, pkg, c) for c in cfgs]
+    plans, u0s, m = group(torch, dev, pkg, cfgs)
+    m.set_tuning(persistent=True)
+    assert m.tuning()["persistent"]
+    for r in range(2):
+        say(f"[multi] persistent launch, call {r}")
+        before = [p.diagnostics() for p in plans]
+        hists = m.propagate(u0s, history=True)
+        torch.cuda.synchronize()
+        for i, (c, p) in enumerate(zip(cfgs, plans)):
+            assert np.array_equal(hists[i].cpu().numpy(), ref[i][0]), (r, c["name"])
+            assert torch.equal(p.field(), hists[i][-1])
+            if r == 0:
+                assert p.diagnostics() == ref[i][1], c["name"]
+            else:  # counters accumulate over calls
+                d = p.diagnostics()
+                assert d["screens"] == before[i]["screens"] + c["n_screens"], c["name"]
+    close(plans, m)
+
+
+def test_persistent_launch_equals_stage_launches_tuned(env):
+    """With autotuned shapes the persistent launch equals the per-stage
+    launches of the same tuning bit for bit."""
+    torch, dev, pkg = env
+    cfgs = uneven()
+    plans, u0s, m = group(torch, dev, pkg, cfgs)
+    t = m.tune(reps=2)
+    say(f"[multi] tuned {t['fft_elems']} {t['apply_groups']}")
+    m.set_tuning(graphs=False, persistent=False)
+    want = [h.cpu().numpy() for h in m.propagate(u0s, history=True)]
+    m.set_tuning(persistent=True)
+    got = m.propagate(u0s, history=True)
+    torch.cuda.synchronize()
+    for i in range(len(cfgs)):
+        assert np.array_equal(got[i].cpu().numpy(), want[i]), i
+    close(plans, m)
+
+
 def test_autotuned_shapes(env):
     torch, dev, pkg = env
     cfgs = uneven()
