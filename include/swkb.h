@@ -351,8 +351,9 @@ int32_t swkb_uses_matrix(swkb_plan_t plan);
  * bit for bit.
  *
  * Requirements per plan: mode-function matrix in use (swkb_uses_matrix),
- * SWKB_MIXED precision, n_z a multiple of 512; at most 4095 plans, each
- * listed once.  The plans stay owned by the caller, must outlive the group
+ * n_z a multiple of 512; at most 4095 plans, each listed once.  SWKB_MIXED
+ * and SWKB_FP64 plans may share a group; an FP64 problem's product keeps the
+ * single-problem blocking (apply_groups shapes the complex64 products).  The plans stay owned by the caller, must outlive the group
  * and must not be used otherwise while a group call is in flight.  The
  * group allocates its own device memory (hipMalloc: a problem table, the
  * workgroup maps and the partial sums of the product). */

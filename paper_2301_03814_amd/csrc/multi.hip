@@ -81,14 +81,12 @@ int class_of(const swkb_multi_s* m, int n_z) {
 int max_groups(const Geometry& g) { return (g.M + 3) / 4; }
 
 // Workgroups of stage `kind` for a problem with the given shapes.
-int stage_blocks(int kind, const Geometry& g, int fft_elems, int groups) {
-  int CA, RB;
-  swkb::fft_blocking(g, fft_elems, &CA, &RB);
+int stage_blocks(int kind, const MultiProblem& p) {
   switch (kind) {
-    case kCols: return g.P2 / CA;
-    case kRows: return g.P1 / RB;
-    case kApply: return (g.N / 512) * groups;
-    default: return swkb::finalize_blocks(g);
+    case kCols: return p.g.P2 / p.CA;
+    case kRows: return p.g.P1 / p.RB;
+    case kApply: return p.fp64 ? (p.g.T / p.sub) * p.groups : (p.g.N / 512) * p.groups;
+    default: return swkb::finalize_blocks(p.g);
   }
 }
 
@@ -138,7 +136,11 @@ hipError_t build_tables(swkb_multi_s* m) {
     const swkb_plan_s* pl = m->plans[m->order[s]];
     const Geometry& g = pl->g;
     const int c = m->cls[s];
-    const int fe = m->tun.fft_elems[c], gr = std::min(m->tun.apply_groups[c], max_groups(g));
+    const bool fp64 = pl->precision == SWKB_FP64;
+    // FP64 problems keep the single-problem product blocking (the tuning
+    // shapes the complex64 products)
+    const int fe = m->tun.fft_elems[c];
+    const int gr = fp64 ? swkb::apply_f64_groups(g) : std::min(m->tun.apply_groups[c], max_groups(g));
     MultiProblem& p = m->hp[s];
     p.g = g;
     p.ep = swkb::epi_of(*pl);
@@ -146,7 +148,10 @@ hipError_t build_tables(swkb_multi_s* m) {
     p.tw = pl->tw;
     p.Y = pl->Y;
     p.c = pl->c;
-    p.tmat = static_cast<const float4*>(pl->tmat);
+    p.fp64 = fp64 ? 1 : 0;
+    p.sub = fp64 ? swkb::apply_f64_sub(g) : 0;
+    p.tmat = fp64 ? nullptr : static_cast<const float4*>(pl->tmat);
+    p.tmat64 = fp64 ? static_cast<const double2*>(pl->tmat) : nullptr;
     p.part = nullptr;  // set below
     p.u = pl->u;
     p.u_in = nullptr;
@@ -158,7 +163,7 @@ hipError_t build_tables(swkb_multi_s* m) {
     p.groups = gr;
     m->lds_cols = std::max(m->lds_cols, sizeof(double2) * (size_t)(p.CA * g.P1 + g.P1 / 2));
     m->lds_rows = std::max(m->lds_rows, sizeof(double2) * (size_t)(p.RB * g.P2 + g.P2 / 2));
-    for (int k = 0; k < kKinds; ++k) m->off[k][s + 1] = m->off[k][s] + stage_blocks(k, g, fe, gr);
+    for (int k = 0; k < kKinds; ++k) m->off[k][s + 1] = m->off[k][s] + stage_blocks(k, p);
     part_elems += (size_t)gr * g.N;
   }
   size_t entries = 0;
@@ -250,9 +255,8 @@ swkb_status swkb_multi_create(const swkb_plan_t* plans, int32_t n, swkb_multi_t*
   for (int i = 0; i < n; ++i) {
     const swkb_plan_s* pl = plans[i];
     if (!pl) return fail(SWKB_ERR_ARG, "plan " + std::to_string(i) + " is NULL");
-    if (!pl->use_matrix || pl->precision != SWKB_MIXED || pl->g.N % 512 != 0)
-      return fail(SWKB_ERR_ARG, "plan " + std::to_string(i) +
-                                    " must use the mode-function matrix, SWKB_MIXED and n_z % 512 == 0");
+    if (!pl->use_matrix || pl->g.N % 512 != 0)
+      return fail(SWKB_ERR_ARG, "plan " + std::to_string(i) + " must use the mode-function matrix and n_z % 512 == 0");
     if (pl->H) return fail(SWKB_ERR_ARG, "plan " + std::to_string(i) + " keeps its history (keep_history = 1)");
     for (int j = 0; j < i; ++j)
       if (plans[j] == pl) return fail(SWKB_ERR_ARG, "plan listed twice");
@@ -296,9 +300,12 @@ swkb_status swkb_multi_create(const swkb_plan_t* plans, int32_t n, swkb_multi_t*
       const swkb_plan_s* pl = m->plans[m->order[s]];
       const int c = class_of(m, pl->g.N);
       m->cls[s] = c;
+      if (pl->precision == SWKB_FP64) continue;  // FP64 products keep their own blocking
       const int d = swkb::apply_multi_groups(pl->g);
       if (m->tun.apply_groups[c] == 0 || d > m->tun.apply_groups[c]) m->tun.apply_groups[c] = d;
     }
+    for (int c = 0; c < m->tun.n_classes; ++c)
+      if (m->tun.apply_groups[c] == 0) m->tun.apply_groups[c] = 1;  // a class of FP64 problems only
     // one n_z can come with different n_modes: the default is the largest
     // single-problem choice among them, clamped to (n_modes + 3) / 4 per
     // problem, which gives each problem its own single-problem choice
@@ -404,7 +411,7 @@ swkb_status swkb_multi_tune(swkb_multi_t m, int32_t reps, void* hip_stream, swkb
       mp->clear();
       for (int s : slots) {
         const MultiProblem& p = m->hp[s];
-        const int nb = kind == kCols ? p.g.P2 / p.CA : kind == kRows ? p.g.P1 / p.RB : (p.g.N / 512) * p.groups;
+        const int nb = stage_blocks(kind, p);
         for (int b = 0; b < nb; ++b) mp->push_back(((unsigned)s << kMapShift) | (unsigned)b);
       }
     };
@@ -455,7 +462,8 @@ swkb_status swkb_multi_tune(swkb_multi_t m, int32_t reps, void* hip_stream, swkb
     double best_apply = 1e30;
     for (int gr : cand[c]) {
       if (e != hipSuccess) break;
-      for (int s : slots) m->hp[s].groups = std::min(gr, max_groups(m->hp[s].g));
+      for (int s : slots)
+        if (!m->hp[s].fp64) m->hp[s].groups = std::min(gr, max_groups(m->hp[s].g));
       sub_map(kApply, &ma);
       mb.clear();
       e = upload(ma, mb);

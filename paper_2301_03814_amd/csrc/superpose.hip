@@ -467,16 +467,12 @@ __global__ void __launch_bounds__(64 * kWaves, (std::is_same<T, float>::value ? 
 // group's modes of c_j T[j][m], in the same grid/partial layout as the
 // superposition (a streaming read of T, coalesced along m).
 template <typename T>
-__global__ void __launch_bounds__(64 * kWaves) apply_matrix_kernel(Geometry g,
-                                                                   const typename CplxOf<T>::type* __restrict__ tab,
-                                                                   const double2* __restrict__ c,
-                                                                   double2* __restrict__ part, int sub) {
-  extern __shared__ double2 red[];
+__device__ inline void apply_matrix_body(const Geometry& g, const typename CplxOf<T>::type* __restrict__ tab,
+                                         const double2* __restrict__ c, double2* __restrict__ part, int sb, int gi,
+                                         int groups, int sub, double2* red) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int sb = blockIdx.x;
-  const int gi = blockIdx.y;
-  const int jstep = (int)gridDim.y * kWaves;
+  const int jstep = groups * kWaves;
   const int m0 = sb * sub * 64;
   T acc_re[kSub], acc_im[kSub];
   for (int u = 0; u < kSub; ++u) acc_re[u] = acc_im[u] = T(0);
@@ -513,6 +509,15 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_kernel(Geometry g,
       part[(size_t)gi * g.N + m0 + u * 64 + lane] = make_double2(sr, si);
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kWaves) apply_matrix_kernel(Geometry g,
+                                                                   const typename CplxOf<T>::type* __restrict__ tab,
+                                                                   const double2* __restrict__ c,
+                                                                   double2* __restrict__ part, int sub) {
+  extern __shared__ double2 red[];
+  apply_matrix_body<T>(g, tab, c, part, blockIdx.x, blockIdx.y, gridDim.y, sub, red);
 }
 
 // The same product for complex64 T with 16-byte loads: lane l of a
@@ -735,8 +740,14 @@ __global__ void __launch_bounds__(64 * kWaves) apply_c64_multi(const MultiProble
   extern __shared__ double2 red[];
   const unsigned e = map[blockIdx.x];
   const MultiProblem& p = mp[e >> 20];
-  const int local = (int)(e & 0xfffff), nx = p.g.N >> 9;
-  apply_c64_body<1>(p.g, p.tmat, p.c, p.part, local % nx, local / nx, p.groups, reinterpret_cast<float2*>(red));
+  const int local = (int)(e & 0xfffff);
+  if (p.fp64) {
+    const int nsb = p.g.T / p.sub;
+    apply_matrix_body<double>(p.g, p.tmat64, p.c, p.part, local % nsb, local / nsb, p.groups, p.sub, red);
+  } else {
+    const int nx = p.g.N >> 9;
+    apply_c64_body<1>(p.g, p.tmat, p.c, p.part, local % nx, local / nx, p.groups, reinterpret_cast<float2*>(red));
+  }
 }
 
 __global__ void __launch_bounds__(kFinThreads) finalize_multi(const MultiProblem* __restrict__ mp,
@@ -799,9 +810,15 @@ __global__ void __launch_bounds__(kPersistThreads) multi_persistent(const MultiP
     take_items(ctr + 4 * q + 2, cnt.z, [&](int i) {
       const unsigned e = map_apply[i];
       const MultiProblem& p = mp[e >> 20];
-      const int local = (int)(e & 0xfffff), nx = p.g.N >> 9;
-      apply_c64_body<kPersistUnroll>(p.g, p.tmat, p.c, p.part, local % nx, local / nx, p.groups,
-                                     reinterpret_cast<float2*>(L));
+      const int local = (int)(e & 0xfffff);
+      if (p.fp64) {
+        const int nsb = p.g.T / p.sub;
+        apply_matrix_body<double>(p.g, p.tmat64, p.c, p.part, local % nsb, local / nsb, p.groups, p.sub, L);
+      } else {
+        const int nx = p.g.N >> 9;
+        apply_c64_body<kPersistUnroll>(p.g, p.tmat, p.c, p.part, local % nx, local / nx, p.groups,
+                                       reinterpret_cast<float2*>(L));
+      }
     });
     grid.sync();
     take_items(ctr + 4 * q + 3, cnt.w, [&](int i) {
@@ -1003,7 +1020,7 @@ int apply_multi_groups(const Geometry& g) { return c64_groups(g); }
 hipError_t launch_apply_multi(const MultiProblem* mp, const unsigned* map_apply, int n_apply,
                               const unsigned* map_fin, int n_fin, int step, hipStream_t st) {
   if (n_apply > 0) {
-    hipLaunchKernelGGL(apply_c64_multi, dim3(n_apply), dim3(64 * kWaves), sizeof(float2) * kWaves * 4 * 64 * 2, st,
+    hipLaunchKernelGGL(apply_c64_multi, dim3(n_apply), dim3(64 * kWaves), apply_lds_bytes(), st,
                        mp, map_apply);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1045,6 +1062,14 @@ hipError_t launch_multi_persistent(const MultiProblem* mp, const unsigned* map_c
                                     dim3(kPersistThreads), args, (unsigned)lds, st);
 }
 
-size_t apply_lds_bytes() { return sizeof(float2) * kWaves * 4 * 64 * 2; }
+size_t apply_lds_bytes() {
+  const size_t c64 = sizeof(float2) * kWaves * 4 * 64 * 2, f64 = sizeof(double2) * 64 * kWaves * kSub;
+  return c64 > f64 ? c64 : f64;
+}
+
+// The FP64 product's single-problem blocking: 64-point tiles per workgroup
+// and mode groups.
+int apply_f64_sub(const Geometry& g) { return superpose_sub(g); }
+int apply_f64_groups(const Geometry& g) { return superpose_groups(g); }
 
 }  // namespace swkb

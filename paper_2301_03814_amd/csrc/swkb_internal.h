@@ -86,7 +86,9 @@ struct MultiProblem {
   const double2* tw;
   double2* Y;
   double2* c;
-  const float4* tmat;    // complex64 mode-function matrix [M][N]
+  const float4* tmat;    // complex64 mode-function matrix [M][N] (mixed precision)
+  const double2* tmat64; // complex128 mode-function matrix [M][N] (FP64)
+  int fp64, sub;         // FP64 problem; its product's 64-point tiles per workgroup
   double2* part;         // [groups][N] partial sums of the product
   double2* u;            // the problem's field
   const double2* u_in;   // field on the problem's first screen
@@ -237,6 +239,8 @@ hipError_t launch_multi_persistent(const MultiProblem* mp, const unsigned* map_c
                                    const unsigned* map_apply, const unsigned* map_fin, const int4* n, int* ctr,
                                    int qmax, size_t lds, int max_blocks, hipStream_t st, int* blocks_out);
 size_t apply_lds_bytes();
+int apply_f64_sub(const Geometry& g);
+int apply_f64_groups(const Geometry& g);
 hipError_t launch_apply_multi(const MultiProblem* mp, const unsigned* map_apply, int n_apply,
                               const unsigned* map_fin, int n_fin, int step, hipStream_t st);
 // Inside the library: a multi-problem group whose problems read their fields

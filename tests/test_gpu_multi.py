@@ -50,8 +50,8 @@ def uneven():
     return out
 
 
-def standalone(torch, dev, pkg, cfg):
-    p = pkg.Plan(cfg, precision=pkg.MIXED, device=dev)
+def standalone(torch, dev, pkg, cfg, prec=None):
+    p = pkg.Plan(cfg, precision=pkg.MIXED if prec is None else prec, device=dev)
     h = p.propagate(torch.from_numpy(W.incident_field(cfg)).to(dev), 0, cfg["n_screens"])
     d = p.diagnostics()
     p.close()
@@ -154,6 +154,28 @@ def test_persistent_launch_equals_stage_launches_tuned(env):
     close(plans, m)
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_fp64_and_mixed_problems_in_one_group(env, persistent):
+    """FP64 and mixed plans share a group: with the default shapes, by
+    per-stage launches and by the persistent launch, each history equals its
+    separate swkb_propagate bit for bit (FP64 products keep their blocking)."""
+    torch, dev, pkg = env
+    cfgs = uneven()
+    precs = [pkg.FP64 if i % 2 == 0 else pkg.MIXED for i in range(len(cfgs))]
+    ref = [standalone(torch, dev, pkg, c, pr)[0] for c, pr in zip(cfgs, precs)]
+    plans = [pkg.Plan(c, precision=pr, device=dev) for c, pr in zip(cfgs, precs)]
+    u0s = [torch.from_numpy(W.incident_field(c)).to(dev) for c in cfgs]
+    m = pkg.Multi(plans)
+    if persistent:
+        m.set_tuning(persistent=True)
+    say(f"[multi] FP64 and mixed, persistent={persistent}")
+    hists = m.propagate(u0s, history=True)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cfgs):
+        assert np.array_equal(hists[i].cpu().numpy(), ref[i]), (c["name"], precs[i])
+    close(plans, m)
+
+
 def test_autotuned_shapes(env):
     torch, dev, pkg = env
     cfgs = uneven()
@@ -209,12 +231,11 @@ def test_small_problems_match_oracle(env):
 def test_rejects_plans_it_cannot_carry(env):
     torch, dev, pkg = env
     c = uneven()[0]
-    p64 = pkg.Plan(c, precision=pkg.FP64, device=dev)
     rec = pkg.Plan(W.with_overrides(c, propagator=2), precision=pkg.MIXED, device=dev)
     small = pkg.Plan(W.with_overrides(W.linear_caustic(n_screens=2), n_z=256, n_modes=64), precision=pkg.MIXED,
                      device=dev)
     ok = pkg.Plan(c, precision=pkg.MIXED, device=dev)
-    for bad in ([p64], [rec], [small], [ok, ok]):
+    for bad in ([rec], [small], [ok, ok]):
         with pytest.raises(pkg.SwkbError) as ei:
             pkg.Multi(bad)
         assert ei.value.status == 1
@@ -225,7 +246,7 @@ def test_rejects_plans_it_cannot_carry(env):
     with pytest.raises(ValueError):
         m.set_tuning(fft_elems=[512, 512])
     m.close()
-    for p in (p64, rec, small, ok):
+    for p in (rec, small, ok):
         p.close()
 
 
