@@ -34,6 +34,13 @@
 // stage; dead and caustic rays do not contribute.
 #include "medium.h"
 
+// The compiler's indexed buffer load of four dwords (descriptor, index,
+// byte offset, scalar byte offset, cache bits), named by its intrinsic.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ f32x4 struct_buffer_load_f32x4(i32x4 rsrc, int vindex, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.buffer.load.v4f32");
+
 namespace swkb {
 namespace {
 
@@ -88,6 +95,10 @@ struct GenericMedium {
   DevMedium md;
   double x_q, hx2;  // stage k sits at x_q + k * hx2
   double s;         // launch height of this lane's ray
+  // stage heights are carried as the displacement dz itself
+  __device__ static T pos(T dz) { return dz; }
+  __device__ static T pos_scale(T h) { return h; }
+  __device__ static T advance(T p, T hs, T kdz) { return p + hs * kdz; }
   __device__ Med<T> eval(int k, T dz, Work& c) const {
     ++c.med;
     return medium_eval<T>(md, x_q + k * hx2, s, dz, c.terms);
@@ -141,6 +152,9 @@ struct GaussMedium {
   int nl;
   T zl0;  // launch height of this lane's ray relative to the wavefront reference
   const double* __restrict__ pow2_64 = nullptr;  // FP64: 2^(j/64), j < 64, in LDS
+  __device__ static T pos(T dz) { return dz; }
+  __device__ static T pos_scale(T h) { return h; }
+  __device__ static T advance(T p, T hs, T kdz) { return p + hs * kdz; }
   __device__ inline void bump(T z, T c, T2<T> ac, T2<T> tk, T& dn, T& nz, T& nzz, int& nterms) const {
     const T ddz = z - c;
     const T d2 = ddz * ddz;
@@ -193,21 +207,45 @@ struct GaussMedium {
 // only enters the ray-tube amplitude, within 1e-4 relative.  Heights
 // outside the table fall back to the direct evaluation.
 //
+// The table row of a stage is wavefront-uniform; an interval's entry is read
+// by a buffer load indexed by the interval (the descriptor: the row's base,
+// a 16-byte stride and the row length as the record count), which takes the
+// interval index as it is, without a per-lane address computation, and whose
+// hardware range check agrees with the caller's own test.
+constexpr int kBufferWord3 = 0x00020000;  // 32-bit data format, CDNA buffer descriptor word 3
+
+__device__ inline f32x4 row_load(const float4* row, unsigned n, unsigned i) {
+  const unsigned long long a = (unsigned long long)row;
+  i32x4 r;
+  r.x = (int)(unsigned)a;
+  r.y = (int)((unsigned)(a >> 32) | (16u << 16));  // base bits 32..47, stride 16 bytes
+  r.z = (int)n;
+  r.w = kBufferWord3;
+  return struct_buffer_load_f32x4(r, (int)i, 0, 0, 0);
+}
+
 // eval returns hz = p' and hzz = p''/2 in node units; hz_scale() and
 // hzz_scale() take them to eps_z / 2 and eps_zz / 2, so that the scales
 // ride on products the right-hand side forms anyway.
+//
+// Stage heights are carried as the table coordinate t = dz / dz_t + tl
+// itself (node spacings above node j0): a stage's height is then one FMA
+// from the step's first, t + (h / dz_t) k_dz, and the direct evaluation
+// recovers dz = (t - tl) dz_t.
 struct TableMedium {
   static constexpr bool kTableReads = true;
   const float4* __restrict__ ta;  // [(2S+1)][ni]
   unsigned ni;                    // intervals
   float inv_dz, half_inv_dz;      // 1/dz_t, 1/(2 dz_t)
   float inv_dz2;                  // 1/dz_t^2
-  float two_dz, dz_sq;            // 2 dz_t, dz_t^2 (direct values into node units)
+  float dzt, two_dz, dz_sq;       // dz_t, 2 dz_t, dz_t^2 (direct values into node units)
   int j0;      // node at or below the wavefront's reference height z_w
   float tl;    // this lane's launch height above node j0, in node spacings
   GaussMedium<float> direct;
-  __device__ Med<float> eval(int k, float dz, Work& c) const {
-    const float t = dz * inv_dz + tl;
+  __device__ float pos(float dz) const { return dz * inv_dz + tl; }
+  __device__ float pos_scale(float h) const { return h * inv_dz; }
+  __device__ static float advance(float t, float hs, float kdz) { return t + hs * kdz; }
+  __device__ Med<float> eval(int k, float t, Work& c) const {
     // node index floor(t) in one instruction (a saturating conversion, like
     // the one of floorf(t) to int) and the offset t - floor(t) in another
     int ti;
@@ -215,14 +253,13 @@ struct TableMedium {
     // unsigned wrap sends heights below the table (and saturated conversions) out of range too
     const unsigned iv = (unsigned)j0 + (unsigned)ti;
     if (!(iv < ni)) {
-      Med<float> m = direct.eval(k, dz, c);
+      Med<float> m = direct.eval(k, (t - tl) * dzt, c);
       m.hz *= two_dz;
       m.hzz *= dz_sq;
       return m;
     }
     const float u = __builtin_amdgcn_fractf(t);
-    const size_t o = (size_t)k * ni + iv;
-    const float4 a = ta[o];
+    const f32x4 a = row_load(ta + (size_t)k * ni, ni, iv);
     // Horner for p, p' and p''/2 together
     float p = a.w * u + a.z;
     float d1 = a.w * u + p;         // 2 c3 u + c2
@@ -240,22 +277,23 @@ struct TableMedium {
   __device__ float hzz_scale() const { return inv_dz2; }
 };
 
-// Right-hand side at stage k, the n-th evaluation of its RK4 step.
-// Returns false when the ray stops there, with st = kCaustic (Z_s <= 0 at
-// the stage) or else kDead (p^2 <= p2_floor), plus 4 n; the medium is
-// evaluated in either case, so that both tests are taken on one branch
-// that a wavefront of live rays skips.
-template <typename T, typename MED>
-__device__ inline bool rhs(const MED& med, const ModeC& mc, int k, int n, T dz, T dq, T Zs, T Qs, T p2_floor,
-                          Deriv<T>& d, Work& c, int& st) {
-  const Med<T> m = med.eval(k, dz, c);
+// Right-hand side at stage k, the n-th evaluation (n = 1..4) of RK4 step i,
+// at the stage height pos (in the medium's coordinate).  Returns false when
+// the ray stops there, with st = kCaustic (Z_s <= 0 at the stage) or else
+// kDead (p^2 <= p2_floor), plus 4 (4 i + n - 1); the medium is evaluated in
+// either case, so that both tests are taken on one branch that a wavefront
+// of live rays skips.
+template <typename T, typename MED, typename POS>
+__device__ inline bool rhs(const MED& med, const ModeC& mc, int k, int n, int i, POS pos, T dq, T Zs, T Qs,
+                          T p2_floor, Deriv<T>& d, Work& c, int& st) {
+  const Med<T> m = med.eval(k, pos, c);
   const T xi = (T)mc.xi;
   const T w = dq * (T(2) * xi + dq);          // q^2 - xi^2
   const T num = (m.e1 - (T)mc.e1r) - w;       // p^2 - pbar^2, in small quantities
   const T p2 = num + (T)mc.pb2;
   const bool ok = (Zs > T(0)) & (p2 > p2_floor);
   if (__builtin_expect(!ok, 0)) {
-    st = (Zs > T(0) ? kDead : kCaustic) + 4 * n;
+    st = (Zs > T(0) ? kDead : kCaustic) + 4 * (4 * i + n - 1);
     return false;
   }
   const T ip = fast_rsqrt<T>(p2);
@@ -316,34 +354,35 @@ __device__ inline double tube_amplitude(T p02, T p2, double Zs) {
 // record and returns the lane's status and work counts.
 template <typename T, typename MED>
 __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry& g, const MarchK& mk, bool active,
-                                 size_t o, double s_launch, DevRecords& rec, int& st, Work& c) {
+                                 size_t o, double s_launch, const DevRecords& rec, int& st, Work& c) {
   T dz = T(0), dq = T(0), dps = T(0);
   double Zs = 1.0, Qs = 0.0;  // ray tube, accumulated in FP64
   double amp = 0.0;
   st = kLive;
   if (!active) return;
-  const Med<T> m0 = med.eval(0, T(0), c);
+  const Med<T> m0 = med.eval(0, med.pos(T(0)), c);
   int evals = 1;  // medium evaluations of this ray
   const T p02 = (T)mc.omx2 + m0.e1;
   if (!(p02 > (T)g.p2_floor)) {
     st = kDeadLaunch;
   } else {
     const T hh = (T)(0.5 * mk.hx), hf = (T)mk.hx, h6 = (T)mk.h6;
+    const auto hh_p = med.pos_scale(hh), hf_p = med.pos_scale(hf);  // stage offsets in the medium's coordinate
     const T pfl = (T)g.p2_floor;
     Deriv<T> k1, k2, k3, k4;
     for (int i = 0; i < g.S; ++i) {
       const T zs = (T)Zs, qs = (T)Qs;  // the step's tube in T
-      if (!rhs<T>(med, mc, 2 * i, 1, dz, dq, zs, qs, pfl, k1, c, st)) break;
-      if (!rhs<T>(med, mc, 2 * i + 1, 2, dz + hh * k1.dz, dq + hh * k1.dq, zs + hh * k1.Zs, qs + hh * k1.Qs, pfl,
-                  k2, c, st))
+      const auto p1 = med.pos(dz);
+      if (!rhs<T>(med, mc, 2 * i, 1, i, p1, dq, zs, qs, pfl, k1, c, st)) break;
+      if (!rhs<T>(med, mc, 2 * i + 1, 2, i, med.advance(p1, hh_p, k1.dz), dq + hh * k1.dq, zs + hh * k1.Zs,
+                  qs + hh * k1.Qs, pfl, k2, c, st))
         break;
-      if (!rhs<T>(med, mc, 2 * i + 1, 3, dz + hh * k2.dz, dq + hh * k2.dq, zs + hh * k2.Zs, qs + hh * k2.Qs, pfl,
-                  k3, c, st))
+      if (!rhs<T>(med, mc, 2 * i + 1, 3, i, med.advance(p1, hh_p, k2.dz), dq + hh * k2.dq, zs + hh * k2.Zs,
+                  qs + hh * k2.Qs, pfl, k3, c, st))
         break;
-      if (!rhs<T>(med, mc, 2 * i + 2, 4, dz + hf * k3.dz, dq + hf * k3.dq, zs + hf * k3.Zs, qs + hf * k3.Qs, pfl,
-                  k4, c, st))
+      if (!rhs<T>(med, mc, 2 * i + 2, 4, i, med.advance(p1, hf_p, k3.dz), dq + hf * k3.dq, zs + hf * k3.Zs,
+                  qs + hf * k3.Qs, pfl, k4, c, st))
         break;
-      c.rhs += 4;
       dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
       dq += h6 * (k1.dq + T(2) * k2.dq + T(2) * k3.dq + k4.dq);
       dps += h6 * (k1.dps + T(2) * k2.dps + T(2) * k3.dps + k4.dps);
@@ -351,15 +390,22 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
       Zs += (double)(h6 * (k1.Zs + T(2) * k2.Zs + T(2) * k3.Zs + k4.Zs));
       Qs += (double)(h6 * (k1.Qs + T(2) * k2.Qs + T(2) * k3.Qs + k4.Qs));
     }
-    // completed steps, and the evaluations of the step where the ray stopped
-    evals += c.rhs + (st >> 2);
-    st &= 3;
+    // completed steps (4 evaluations each), and the evaluations of the step
+    // where the ray stopped
+    if (st == kLive) {
+      c.rhs = 4 * g.S;
+      evals += c.rhs;
+    } else {
+      c.rhs = (st >> 2) & ~3;
+      evals += (st >> 2) + 1;
+      st &= 3;
+    }
     if (st == kLive) {
       if (!(Zs > 0.0)) {
         st = kCaustic;
       } else {
         ++evals;
-        const Med<T> m1 = med.eval(2 * g.S, dz, c);
+        const Med<T> m1 = med.eval(2 * g.S, med.pos(dz), c);
         const T xi = (T)mc.xi;
         const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
         if (!(p2 > (T)g.p2_floor)) st = kDead;
@@ -543,8 +589,8 @@ __global__ void __launch_bounds__(kTabNodes) medium_table_kernel(const double* _
 }
 
 // Mixed-path Gaussian-sum march through the screen's medium table.
-__device__ inline void march_table_body(const Geometry& g, const MarchK& mk, const GaussTabs<float>& tabs,
-                                        const MedTab& mt, const DevModes& modes, DevRecords& rec,
+__device__ __forceinline__ void march_table_body(const Geometry& g, const MarchK& mk, const GaussTabs<float>& tabs,
+                                        const MedTab& mt, const DevModes& modes, const DevRecords& rec,
                                         int* __restrict__ wcount, int waves_per_mode) {
   const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int lane = threadIdx.x & 63;
@@ -565,6 +611,7 @@ __device__ inline void march_table_body(const Geometry& g, const MarchK& mk, con
   med.inv_dz = mk.inv_dz;
   med.half_inv_dz = mk.half_inv_dz;
   med.inv_dz2 = mk.inv_dz2;
+  med.dzt = 0.5f * mk.two_dz;
   med.two_dz = mk.two_dz;
   med.dz_sq = mk.dz_sq;
   const double rel = (g.z_a + (double)(w * 64 * g.rho - g.E) * g.h) - mt.z_lo;  // z_w above the table's base
@@ -585,16 +632,35 @@ __device__ inline void march_table_body(const Geometry& g, const MarchK& mk, con
 // owner-map kernel, 4 wavefronts per SIMD) the march at 8 wavefronts per
 // SIMD crowds that sum out of the CUs it shares, so there the compiler's own
 // choice runs: 4 fields, 80.2 -> 71.6 ms per 400 screens.
-__global__ void __launch_bounds__(256, 8) march_table_kernel(Geometry g, MarchK mk, GaussTabs<float> tabs,
-                                                             MedTab mt, DevModes modes, DevRecords rec,
-                                                             int* __restrict__ wcount, int waves_per_mode) {
-  march_table_body(g, mk, tabs, mt, modes, rec, wcount, waves_per_mode);
+//
+// Both take their arguments as one structure and read each field where it
+// is used, through the argument segment: the compiler loads by-value kernel
+// arguments on entry, which would hold the record pointers and the count
+// buffer (used only after the march) in scalar registers across it and, at
+// 8 wavefronts per SIMD, spill them to vector lanes.
+struct TableMarchArgs {
+  Geometry g;
+  MarchK mk;
+  GaussTabs<float> tabs;
+  MedTab mt;
+  DevModes modes;
+  DevRecords rec;
+  int* wcount;
+  int waves_per_mode;
+};
+
+__device__ inline const TableMarchArgs& table_args() {
+  return *(const TableMarchArgs*)__builtin_amdgcn_kernarg_segment_ptr();
 }
 
-__global__ void __launch_bounds__(256) march_table_batch_kernel(Geometry g, MarchK mk, GaussTabs<float> tabs,
-                                                                MedTab mt, DevModes modes, DevRecords rec,
-                                                                int* __restrict__ wcount, int waves_per_mode) {
-  march_table_body(g, mk, tabs, mt, modes, rec, wcount, waves_per_mode);
+__global__ void __launch_bounds__(256, 8) march_table_kernel(TableMarchArgs) {
+  const TableMarchArgs& a = table_args();
+  march_table_body(a.g, a.mk, a.tabs, a.mt, a.modes, a.rec, a.wcount, a.waves_per_mode);
+}
+
+__global__ void __launch_bounds__(256) march_table_batch_kernel(TableMarchArgs) {
+  const TableMarchArgs& a = table_args();
+  march_table_body(a.g, a.mk, a.tabs, a.mt, a.modes, a.rec, a.wcount, a.waves_per_mode);
 }
 
 // One workgroup per mode: running maximum of live arrival heights (search
@@ -827,12 +893,11 @@ static hipError_t launch_march_rays(const swkb_plan_s& pl, int q, hipStream_t st
                          reinterpret_cast<const T2<float>*>(pl.gterm) + off,
                          static_cast<const float*>(pl.gczl) + off * wpm, nl};
       // reads the table launch_medium_table built for screen q
+      const TableMarchArgs a{g, mk, t, pl.mtab, modes_of(pl), pl.rec, wcount, wpm};
       if (pl.sum_fields > 1)
-        hipLaunchKernelGGL(march_table_batch_kernel, grid, dim3(256), 0, st, g, mk, t, pl.mtab, modes_of(pl),
-                           pl.rec, wcount, wpm);
+        hipLaunchKernelGGL(march_table_batch_kernel, grid, dim3(256), 0, st, a);
       else
-        hipLaunchKernelGGL(march_table_kernel, grid, dim3(256), 0, st, g, mk, t, pl.mtab, modes_of(pl), pl.rec,
-                           wcount, wpm);
+        hipLaunchKernelGGL(march_table_kernel, grid, dim3(256), 0, st, a);
     } else {
       GaussTabs<float> t{reinterpret_cast<const T2<float>*>(pl.gstage) + off * nst,
                          reinterpret_cast<const T2<float>*>(pl.gterm) + off,
