@@ -319,13 +319,13 @@ __device__ inline int first_point_at_or_above(const Geometry& g, double key, dou
   int ci = x <= 0.0 ? 0 : (x >= (double)(g.N + 1) ? g.N + 1 : (int)ceil(x));
   // exact decisions with the same arithmetic as z_m = z_a + m h.  The
   // estimate's rounding is a few 1e-11 grid steps here (|x| <= 2^17), so it
-  // is at most one step off while |z_a| / h stays far below 2^48: one
-  // correction either way, a check, and the stepping loops only for a
-  // geometry that needs more
+  // is exact unless x lies that close to an integer: the two neighbouring
+  // decisions confirm it, and the stepping loops (z_m increases with m)
+  // correct it otherwise
   auto reaches = [&](int m) { return g.z_a + (double)m * g.h >= key; };
-  if (ci > 0 && reaches(ci - 1)) --ci;
-  else if (ci <= g.N && !reaches(ci)) ++ci;
-  if (__builtin_expect(!((ci == 0 || !reaches(ci - 1)) && (ci > g.N || reaches(ci))), 0)) {
+  const bool high = ci > 0 && reaches(ci - 1);
+  const bool low = ci <= g.N && !reaches(ci);
+  if (__builtin_expect(high || low, 0)) {
     while (ci > 0 && reaches(ci - 1)) --ci;
     while (ci <= g.N && !reaches(ci)) ++ci;
   }
@@ -337,7 +337,8 @@ __device__ inline int first_point_at_or_above(const Geometry& g, double key, dou
 // two Newton steps y <- y (3 - Zs y^2) / 2 (each doubles the correct bits of
 // the estimate, which has at least 22, so the result is FP64-accurate); the
 // slowness ratio p0 / p in T (the launch and arrival slownesses are T
-// quantities).
+// quantities; in FP32 from the hardware square root and reciprocal square
+// root, within a few ulp, as the FP32 amplitude that is stored).
 template <typename T>
 __device__ inline double tube_amplitude(T p02, T p2, double Zs) {
   if constexpr (std::is_same<T, double>::value) {
@@ -346,7 +347,7 @@ __device__ inline double tube_amplitude(T p02, T p2, double Zs) {
     double y = __builtin_amdgcn_rsq(Zs);
     y = y * (1.5 - 0.5 * Zs * y * y);
     y = y * (1.5 - 0.5 * Zs * y * y);
-    return (double)sqrt(sqrt(p02) * fast_rsqrt<T>(p2)) * y;
+    return (double)__builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(p02) * fast_rsqrt<T>(p2)) * y;
   }
 }
 
@@ -367,6 +368,7 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
     st = kDeadLaunch;
   } else {
     const T hh = (T)(0.5 * mk.hx), hf = (T)mk.hx, h6 = (T)mk.h6;
+    const double h6d = (double)h6;
     const auto hh_p = med.pos_scale(hh), hf_p = med.pos_scale(hf);  // stage offsets in the medium's coordinate
     const T pfl = (T)g.p2_floor;
     Deriv<T> k1, k2, k3, k4;
@@ -386,9 +388,10 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
       dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
       dq += h6 * (k1.dq + T(2) * k2.dq + T(2) * k3.dq + k4.dq);
       dps += h6 * (k1.dps + T(2) * k2.dps + T(2) * k3.dps + k4.dps);
-      // the step's increment in T, the sum in FP64
-      Zs += (double)(h6 * (k1.Zs + T(2) * k2.Zs + T(2) * k3.Zs + k4.Zs));
-      Qs += (double)(h6 * (k1.Qs + T(2) * k2.Qs + T(2) * k3.Qs + k4.Qs));
+      // the step's weighted slope sum in T; its product with h/6 (exact in
+      // FP64 for T = float) and the sum in FP64
+      Zs = fma(h6d, (double)(k1.Zs + T(2) * k2.Zs + T(2) * k3.Zs + k4.Zs), Zs);
+      Qs = fma(h6d, (double)(k1.Qs + T(2) * k2.Qs + T(2) * k3.Qs + k4.Qs), Qs);
     }
     // completed steps (4 evaluations each), and the evaluations of the step
     // where the ray stopped
