@@ -88,6 +88,17 @@ __device__ inline double fast_rcp<double>(double x) { return 1.0 / x; }
 template <>
 __device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Mode constants of the march in T (wavefront-uniform: one mode per wavefront).
+template <typename T>
+struct ModeT {
+  T xi, e1r, pb2, pbar, omx2;
+};
+
+template <typename T>
+__device__ inline ModeT<T> mode_in(const ModeC& mc) {
+  return ModeT<T>{(T)mc.xi, (T)mc.e1r, (T)mc.pb2, (T)mc.pbar, (T)mc.omx2};
+}
+
 // Medium evaluated through the generic device function (any kind, mirror).
 template <typename T>
 struct GenericMedium {
@@ -232,6 +243,7 @@ __device__ inline f32x4 row_load(const float4* row, unsigned n, unsigned i) {
 // itself (node spacings above node j0): a stage's height is then one FMA
 // from the step's first, t + (h / dz_t) k_dz, and the direct evaluation
 // recovers dz = (t - tl) dz_t.
+template <bool kHold>
 struct TableMedium {
   static constexpr bool kTableReads = true;
   const float4* __restrict__ ta;  // [(2S+1)][ni]
@@ -245,6 +257,16 @@ struct TableMedium {
   __device__ float pos(float dz) const { return dz * inv_dz + tl; }
   __device__ float pos_scale(float h) const { return h * inv_dz; }
   __device__ static float advance(float t, float hs, float kdz) { return t + hs * kdz; }
+  // kHold: keep the entry last read (interval held_iv of the previous
+  // evaluation's row, ~0 if none).  RK4 stages 2 and 3 share a range
+  // position, and so do stage 4 and the next step's stage 1 (and the launch
+  // with the first stage, the last stage with the arrival); between such
+  // stages a ray moves by far less than a table interval, so the second
+  // usually finds its entry held and a wavefront reads only for the lanes
+  // that do not.
+  mutable f32x4 held;
+  mutable unsigned held_iv = ~0u;
+  template <bool kSameRow>
   __device__ Med<float> eval(int k, float t, Work& c) const {
     // node index floor(t) in one instruction (a saturating conversion, like
     // the one of floorf(t) to int) and the offset t - floor(t) in another
@@ -253,13 +275,18 @@ struct TableMedium {
     // unsigned wrap sends heights below the table (and saturated conversions) out of range too
     const unsigned iv = (unsigned)j0 + (unsigned)ti;
     if (!(iv < ni)) {
+      held_iv = ~0u;
       Med<float> m = direct.eval(k, (t - tl) * dzt, c);
       m.hz *= two_dz;
       m.hzz *= dz_sq;
       return m;
     }
     const float u = __builtin_amdgcn_fractf(t);
-    const f32x4 a = row_load(ta + (size_t)k * ni, ni, iv);
+    if (!(kHold && kSameRow) || iv != held_iv) {
+      held = row_load(ta + (size_t)k * ni, ni, iv);
+      held_iv = iv;
+    }
+    const f32x4 a = held;
     // Horner for p, p' and p''/2 together
     float p = a.w * u + a.z;
     float d1 = a.w * u + p;         // 2 c3 u + c2
@@ -283,14 +310,22 @@ struct TableMedium {
 // kDead (p^2 <= p2_floor), plus 4 (4 i + n - 1); the medium is evaluated in
 // either case, so that both tests are taken on one branch that a wavefront
 // of live rays skips.
-template <typename T, typename MED, typename POS>
-__device__ inline bool rhs(const MED& med, const ModeC& mc, int k, int n, int i, POS pos, T dq, T Zs, T Qs,
+// Medium at stage k; kSameRow: the previous evaluation was on the same row
+// (same range position), which a table medium may use.
+template <bool kSameRow, typename MED, typename POS>
+__device__ inline auto eval_medium(const MED& med, int k, POS pos, Work& c) {
+  if constexpr (MED::kTableReads) return med.template eval<kSameRow>(k, pos, c);
+  else return med.eval(k, pos, c);
+}
+
+template <bool kSameRow, typename T, typename MED, typename POS>
+__device__ inline bool rhs(const MED& med, const ModeT<T>& mc, int k, int n, int i, POS pos, T dq, T Zs, T Qs,
                           T p2_floor, Deriv<T>& d, Work& c, int& st) {
-  const Med<T> m = med.eval(k, pos, c);
-  const T xi = (T)mc.xi;
+  const Med<T> m = eval_medium<kSameRow>(med, k, pos, c);
+  const T xi = mc.xi;
   const T w = dq * (T(2) * xi + dq);          // q^2 - xi^2
-  const T num = (m.e1 - (T)mc.e1r) - w;       // p^2 - pbar^2, in small quantities
-  const T p2 = num + (T)mc.pb2;
+  const T num = (m.e1 - mc.e1r) - w;          // p^2 - pbar^2, in small quantities
+  const T p2 = num + mc.pb2;
   const bool ok = (Zs > T(0)) & (p2 > p2_floor);
   if (__builtin_expect(!ok, 0)) {
     st = (Zs > T(0) ? kDead : kCaustic) + 4 * (4 * i + n - 1);
@@ -299,7 +334,7 @@ __device__ inline bool rhs(const MED& med, const ModeC& mc, int k, int n, int i,
   const T ip = fast_rsqrt<T>(p2);
   const T q = xi + dq;
   d.dz = q * ip;
-  d.dps = num * fast_rcp<T>(p2 * ip + (T)mc.pbar) + dq * d.dz;
+  d.dps = num * fast_rcp<T>(p2 * ip + mc.pbar) + dq * d.dz;
   d.dq = m.hz * (med.hz_scale() * ip);        // (eps_z/2) / p
   // ray-tube variations:
   //   Z_s' = (eps Q_s - q (eps_z/2) Z_s) / p^3,
@@ -361,29 +396,31 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
   double amp = 0.0;
   st = kLive;
   if (!active) return;
-  const Med<T> m0 = med.eval(0, med.pos(T(0)), c);
+  const ModeT<T> mt = mode_in<T>(mc);
+  const Med<T> m0 = eval_medium<false>(med, 0, med.pos(T(0)), c);
   int evals = 1;  // medium evaluations of this ray
-  const T p02 = (T)mc.omx2 + m0.e1;
-  if (!(p02 > (T)g.p2_floor)) {
+  const T p02 = mt.omx2 + m0.e1;
+  const T pfl = (T)g.p2_floor;
+  if (!(p02 > pfl)) {
     st = kDeadLaunch;
   } else {
     const T hh = (T)(0.5 * mk.hx), hf = (T)mk.hx, h6 = (T)mk.h6;
     const double h6d = (double)h6;
-    const auto hh_p = med.pos_scale(hh), hf_p = med.pos_scale(hf);  // stage offsets in the medium's coordinate
-    const T pfl = (T)g.p2_floor;
+    // stage offsets in the medium's coordinate
+    const auto hh_p = med.pos_scale(hh), hf_p = med.pos_scale(hf);
     Deriv<T> k1, k2, k3, k4;
     for (int i = 0; i < g.S; ++i) {
       const T zs = (T)Zs, qs = (T)Qs;  // the step's tube in T
       const auto p1 = med.pos(dz);
-      if (!rhs<T>(med, mc, 2 * i, 1, i, p1, dq, zs, qs, pfl, k1, c, st)) break;
-      if (!rhs<T>(med, mc, 2 * i + 1, 2, i, med.advance(p1, hh_p, k1.dz), dq + hh * k1.dq, zs + hh * k1.Zs,
-                  qs + hh * k1.Qs, pfl, k2, c, st))
+      if (!rhs<true, T>(med, mt, 2 * i, 1, i, p1, dq, zs, qs, pfl, k1, c, st)) break;
+      if (!rhs<false, T>(med, mt, 2 * i + 1, 2, i, med.advance(p1, hh_p, k1.dz), dq + hh * k1.dq, zs + hh * k1.Zs,
+                         qs + hh * k1.Qs, pfl, k2, c, st))
         break;
-      if (!rhs<T>(med, mc, 2 * i + 1, 3, i, med.advance(p1, hh_p, k2.dz), dq + hh * k2.dq, zs + hh * k2.Zs,
-                  qs + hh * k2.Qs, pfl, k3, c, st))
+      if (!rhs<true, T>(med, mt, 2 * i + 1, 3, i, med.advance(p1, hh_p, k2.dz), dq + hh * k2.dq, zs + hh * k2.Zs,
+                        qs + hh * k2.Qs, pfl, k3, c, st))
         break;
-      if (!rhs<T>(med, mc, 2 * i + 2, 4, i, med.advance(p1, hf_p, k3.dz), dq + hf * k3.dq, zs + hf * k3.Zs,
-                  qs + hf * k3.Qs, pfl, k4, c, st))
+      if (!rhs<false, T>(med, mt, 2 * i + 2, 4, i, med.advance(p1, hf_p, k3.dz), dq + hf * k3.dq, zs + hf * k3.Zs,
+                         qs + hf * k3.Qs, pfl, k4, c, st))
         break;
       dz += h6 * (k1.dz + T(2) * k2.dz + T(2) * k3.dz + k4.dz);
       dq += h6 * (k1.dq + T(2) * k2.dq + T(2) * k3.dq + k4.dq);
@@ -408,10 +445,10 @@ __device__ inline void march_ray(const MED& med, const ModeC& mc, const Geometry
         st = kCaustic;
       } else {
         ++evals;
-        const Med<T> m1 = med.eval(2 * g.S, med.pos(dz), c);
-        const T xi = (T)mc.xi;
-        const T p2 = (T)mc.omx2 + m1.e1 - dq * (T(2) * xi + dq);
-        if (!(p2 > (T)g.p2_floor)) st = kDead;
+        const Med<T> m1 = eval_medium<true>(med, 2 * g.S, med.pos(dz), c);
+        const T xi = mt.xi;
+        const T p2 = mt.omx2 + m1.e1 - dq * (T(2) * xi + dq);
+        if (!(p2 > pfl)) st = kDead;
         else amp = tube_amplitude<T>(p02, p2, Zs);
       }
     }
@@ -592,6 +629,7 @@ __global__ void __launch_bounds__(kTabNodes) medium_table_kernel(const double* _
 }
 
 // Mixed-path Gaussian-sum march through the screen's medium table.
+template <bool kHold>
 __device__ __forceinline__ void march_table_body(const Geometry& g, const MarchK& mk, const GaussTabs<float>& tabs,
                                         const MedTab& mt, const DevModes& modes, const DevRecords& rec,
                                         int* __restrict__ wcount, int waves_per_mode) {
@@ -603,7 +641,7 @@ __device__ __forceinline__ void march_table_body(const Geometry& g, const MarchK
   const int r = w * 64 + lane;
   const bool active = r < g.R;
   const ModeC mc = load_mode(modes, j);
-  TableMedium med;
+  TableMedium<kHold> med;
   med.direct.stage = tabs.stage;
   med.direct.term = tabs.term;
   med.direct.czl = tabs.czl + (size_t)w * tabs.nl;
@@ -627,20 +665,23 @@ __device__ __forceinline__ void march_table_body(const Geometry& g, const MarchK
   wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c, g.S);
 }
 
-// Two launch shapes of the same march.  Every stage waits on its table
-// read, so beside the one-field FP32 sum the march asks for 8 wavefronts
-// per SIMD (the compiler then keeps to 64 VGPRs and fewer SGPRs; at its own
-// choice, 106 SGPRs, the SGPR file allows 7): random medium N = 8192, step
-// 58.0 -> 56.7 ms per 400 screens.  Beside the sum of several fields (the
-// owner-map kernel, 4 wavefronts per SIMD) the march at 8 wavefronts per
-// SIMD crowds that sum out of the CUs it shares, so there the compiler's own
-// choice runs: 4 fields, 80.2 -> 71.6 ms per 400 screens.
+// Two launch shapes of the same march.  Beside the one-field FP32 sum the
+// march keeps the table entry it last read (half the table reads of a step;
+// the reads, about 27 cache lines per wavefront load, kept the texture data
+// path 82 % busy) and asks for 7 wavefronts per SIMD: 67 VGPRs without
+// spills (at 8, the held entry and the RK4 slopes spill to scratch inside the
+// step loop): random medium N = 8192, march 94.5 -> 88.5 us, step 53.6 ->
+// 52.3 ms per 400 screens.  Beside the sum of several fields (the owner-map
+// kernel, 4 wavefronts per SIMD) the march crowds that sum out of the CUs it
+// shares when it asks for more wavefronts or holds more registers, so there
+// the compiler's own choice runs without the held entry: 4 fields, 80.2 ->
+// 71.6 ms per 400 screens (held entry: 73.3 ms).
 //
 // Both take their arguments as one structure and read each field where it
 // is used, through the argument segment: the compiler loads by-value kernel
 // arguments on entry, which would hold the record pointers and the count
-// buffer (used only after the march) in scalar registers across it and, at
-// 8 wavefronts per SIMD, spill them to vector lanes.
+// buffer (used only after the march) in scalar registers across it and
+// spill them to vector lanes.
 struct TableMarchArgs {
   Geometry g;
   MarchK mk;
@@ -656,14 +697,14 @@ __device__ inline const TableMarchArgs& table_args() {
   return *(const TableMarchArgs*)__builtin_amdgcn_kernarg_segment_ptr();
 }
 
-__global__ void __launch_bounds__(256, 8) march_table_kernel(TableMarchArgs) {
+__global__ void __launch_bounds__(256, 7) march_table_kernel(TableMarchArgs) {
   const TableMarchArgs& a = table_args();
-  march_table_body(a.g, a.mk, a.tabs, a.mt, a.modes, a.rec, a.wcount, a.waves_per_mode);
+  march_table_body<true>(a.g, a.mk, a.tabs, a.mt, a.modes, a.rec, a.wcount, a.waves_per_mode);
 }
 
 __global__ void __launch_bounds__(256) march_table_batch_kernel(TableMarchArgs) {
   const TableMarchArgs& a = table_args();
-  march_table_body(a.g, a.mk, a.tabs, a.mt, a.modes, a.rec, a.wcount, a.waves_per_mode);
+  march_table_body<false>(a.g, a.mk, a.tabs, a.mt, a.modes, a.rec, a.wcount, a.waves_per_mode);
 }
 
 // One workgroup per mode: running maximum of live arrival heights (search
