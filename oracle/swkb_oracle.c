@@ -19,7 +19,7 @@
  *      eikonal phase psi and the transport amplitude A (eqs.
  *      first_order_system_1/2);
  *   3. interpolation of psi_n and A_n from the ray arrivals to the uniform grid
- *      of the next screen (Sec. 2.1.2, "standard interpolation");
+ *      of the next screen (Sec. 2.1.2, which leaves the scheme open);
  *   4. the sum over modes (eq. ray_bundle_q_plus_1), repeated per screen.
  *
  * Readings taken where the paper is silent or garbled (listed with reasons
