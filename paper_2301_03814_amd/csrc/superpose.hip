@@ -39,6 +39,11 @@ template <typename T>
 __device__ inline T wave_shfl(T v, int src) { return __shfl(v, src, 64); }
 
 constexpr int kWaves = 4;  // wavefronts per workgroup
+// Bytes of a wavefront's one-field accumulator row: 9 per point (a padding
+// point every 8), at most 7 tiles of 64 points, rounded up to a power of two.
+constexpr unsigned kPolarTiles = 7;
+constexpr unsigned kPolarStride = 4096;
+static_assert(9 * 64 * kPolarTiles <= kPolarStride, "one-field accumulator row");
 constexpr int kSub = 4;    // 64-point tiles per super-tile of the matrix product
 
 template <typename T>
@@ -179,6 +184,9 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
                                                                    int sub, int batch) {
   constexpr bool POLAR = std::is_same<T, float>::value && NB == 1 && !TABLE;
   extern __shared__ double2 lds_raw[];
+  // one-field accumulators: kWaves rows of kPolarStride bytes at a fixed
+  // LDS offset (so that a row address is one and-or of the point counter)
+  __shared__ __align__(16) char polar_acc[POLAR ? kWaves * kPolarStride : 16];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int gi = blockIdx.y;
@@ -191,7 +199,10 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
   const int m0 = t0 * 64;                                // its first grid point
   const int row = sub * 64 + sub * 8;
   using C2 = typename CplxOf<T>::type;
-  C2* acc = reinterpret_cast<C2*>(lds_raw) + (size_t)w * NB * row;  // [NB][row] (re, im)
+  // POLAR: wavefront w's row starts at byte w * kPolarStride of polar_acc
+  const unsigned wstride = POLAR ? kPolarStride : 0u;
+  C2* acc = POLAR ? reinterpret_cast<C2*>(polar_acc + (size_t)w * wstride)
+                  : reinterpret_cast<C2*>(lds_raw) + (size_t)w * NB * row;  // [NB][row] (re, im)
   if constexpr (!TABLE)
     for (int i = lane; i < NB * row; i += 64) {
       acc[i].x = T(0);
@@ -268,6 +279,28 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
         e2 = c2 * il;
         e3 = c3 * il;
       }
+      if constexpr (POLAR) {
+        // point m of the row sits at byte 8 (m + m / 8) = (9 m) & ~7 (the
+        // padding every 8 points keeps a step's lanes, about rho points
+        // apart, in different banks): the loop counts 9 m, and the wave's
+        // row offset is OR-ed in
+        char* const lds_b = reinterpret_cast<char*>(polar_acc);
+        const unsigned wb = (unsigned)w * wstride;
+        const unsigned m9e = 9u * (unsigned)mhi;
+        for (unsigned m9 = 9u * (unsigned)mlo; m9 < m9e; m9 += 9u, tau += hstep) {
+          const float turns = __builtin_amdgcn_fractf(gt + (((e3 * tau + e2) * tau + e1) * tau + e0));
+          const float sn = __builtin_amdgcn_sinf(turns);  // argument in revolutions
+          const float cs = __builtin_amdgcn_cosf(turns);
+          gt = __builtin_amdgcn_fractf(gt + gstep);
+          const T a = ((q3 * tau + q2) * tau + q1) * tau + q0;
+          C2* const pa = reinterpret_cast<C2*>(lds_b + ((m9 & ~7u) | wb));
+          C2 v = *pa;
+          v.x = fma_t(a, cs, v.x);
+          v.y = fma_t(a, sn, v.y);
+          *pa = v;
+        }
+        continue;
+      }
       for (int m = mlo; m < mhi; ++m, tau += hstep) {
         T sn, cs;
         if constexpr (kF64) {
@@ -291,13 +324,6 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
           continue;
         }
         const int pm = m + (m >> 3);
-        if constexpr (POLAR) {
-          C2 v = acc[pm];
-          v.x = fma_t(a, cs, v.x);
-          v.y = fma_t(a, sn, v.y);
-          acc[pm] = v;
-          continue;
-        }
         for (int bb = 0; bb < NB; ++bb) {
           // lanes of one step own different points; LDS keeps the wavefront's accesses in order
           C2 v = acc[bb * row + pm];
@@ -310,13 +336,13 @@ __global__ void __launch_bounds__(64 * kWaves) superpose_iv_kernel(Geometry g, D
   }
   if constexpr (TABLE) return;
   __syncthreads();
-  const C2* acc0 = reinterpret_cast<const C2*>(lds_raw);
+  const C2* acc0 = POLAR ? reinterpret_cast<const C2*>(polar_acc) : reinterpret_cast<const C2*>(lds_raw);
   for (int bb = 0; bb < nb; ++bb) {
     for (int m = threadIdx.x; m < npts; m += blockDim.x) {
       const int pm = m + (m >> 3);
       double sr = 0.0, si = 0.0;
       for (int k = 0; k < kWaves; ++k) {
-        const C2 v = acc0[((size_t)k * NB + bb) * row + pm];
+        const C2 v = POLAR ? acc0[(size_t)k * (wstride / sizeof(C2)) + pm] : acc0[((size_t)k * NB + bb) * row + pm];
         sr += (double)v.x;
         si += (double)v.y;
       }
@@ -859,11 +885,11 @@ int superpose_groups(const Geometry& g) { return groups_for(g, superpose_sub(g))
 // about 56 ray spacings (rho points each): most lanes own an interval and
 // the tile still fits one pass unless rays crowd (random medium, N = 8192:
 // 39.2 us per screen against 42.2 us at 48 spacings, 45.7 at 40 and 49.6 at
-// 64, where a second pass is common); at most 512 points (FP32) or 256
-// (FP64) for the LDS accumulators.
+// 64, where a second pass is common); at most 448 points (FP32: the one-field
+// accumulator rows) or 256 (FP64) for the LDS accumulators.
 static int iv_sub(const Geometry& g, int precision) {
   int s = (56 * g.rho) / 64;
-  const int smax = precision == SWKB_FP64 ? 4 : 8;
+  const int smax = precision == SWKB_FP64 ? 4 : (int)kPolarTiles;
   if (s > smax) s = smax;
   if (s < 1) s = 1;
   return g.T < s ? g.T : s;
@@ -896,9 +922,9 @@ static void launch_sum(const swkb_plan_s& pl, const dim3& grid, const DevModes& 
                        hipStream_t st) {
   if constexpr (std::is_same<T, float>::value && NB == 1) {
     if (!pl.cpol) return;  // reported by launch_superpose
-    const int row = sub * 64 + sub * 8;
-    const size_t shmem = sizeof(T) * (size_t)kWaves * 2 * NB * row;
-    hipLaunchKernelGGL((superpose_iv_kernel<T, NB, false>), dim3(grid.x, grid.y, 1), dim3(64 * kWaves), shmem, st,
+    // the accumulator rows are the kernel's static LDS (at most kPolarTiles
+    // tiles: launch_superpose checks)
+    hipLaunchKernelGGL((superpose_iv_kernel<T, NB, false>), dim3(grid.x, grid.y, 1), dim3(64 * kWaves), 0, st,
                        pl.g, md, pl.rec, pl.c, pl.cpol, pl.part, static_cast<typename CplxOf<T>::type*>(nullptr), ep,
                        sub, batch);
   } else {
@@ -925,11 +951,13 @@ Epi epi_of(const swkb_plan_s& pl) {
 hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, int batch, hipStream_t st) {
   const Geometry& g = pl.g;
   const Epi ep = epi_of(pl);
-  // the one-field FP32 sum reads the modes in polar form
+  // the one-field FP32 sum reads the modes in polar form and accumulates in
+  // rows of at most kPolarTiles tiles
   if (pl.precision != SWKB_FP64 && batch == 1 && !pl.cpol) return hipErrorInvalidValue;
   // batches keep the accumulators of NB fields in LDS: 256-point super-tiles
   int sub = iv_sub(g, pl.precision);
   if (batch > 1 && sub > 4) sub = 4;
+  if (pl.precision != SWKB_FP64 && batch == 1 && sub > (int)kPolarTiles) return hipErrorInvalidValue;
   const int groups = groups_for(g, sub);
   DevModes md{pl.xi, pl.pbar, pl.e1r, pl.frac};
   const dim3 grid((g.T + sub - 1) / sub, groups);
