@@ -490,7 +490,7 @@ def main():
                                                 "screens")}
         res[name] = dict(seconds=t1 - t0, prof=prof, work=work, diag=diag,
                          lat_ms=sorted(a.elapsed_time(b) for a, b in lat))
-        if name == "mixed":
+        if name == "mixed" and not args.profile_only:
             # the same steps replayed from a captured HIP graph (reported beside the value)
             plan.graphs(True)
             step(name)  # capture
