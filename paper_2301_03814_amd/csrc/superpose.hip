@@ -638,6 +638,7 @@ __global__ void __launch_bounds__(64 * kWaves) apply_matrix_c64_kernel(Geometry 
 // energy summed over the batch exceeds caustic_tol^2 times the largest.
 constexpr int kFinThreads = 512;  // 128 points per workgroup, 4 threads per point
 constexpr int kFinWaves = kFinThreads / 64;
+constexpr int kDiagSlots = 8;  // modes per thread and chunk in the diagnostics
 // Threads per workgroup of the persistent multi-problem kernel: the FFT and
 // product bodies' own workgroup size (the epilogue body takes any).
 constexpr int kPersistThreads = 64 * kWaves;
@@ -660,6 +661,91 @@ __device__ inline double batch_energy(const double2* __restrict__ c, int M, int 
     e += cv.x * cv.x + cv.y * cv.y;
   }
   return e;
+}
+
+// Diagnostics of a screen, by one workgroup: the largest mode energy
+// (summed over the batch), then the counts, with wavefront reductions and
+// the wavefronts combined in order.  A thread takes modes j0 + k *
+// blockDim.x, k < kDiagSlots, of each chunk of kDiagSlots * blockDim.x
+// modes, with the loads of all of them issued together (kOne, one field:
+// the energy is one load); when one chunk covers the M modes (M <= 4096 at
+// 512 threads), their energies and flags stay in registers for the count of
+// significant modes, so the workgroup waits for memory about once instead of
+// once per loop round.
+template <bool kOne>
+__device__ inline void diag_body(const Geometry& g, const DevRecords& rec, const double2* __restrict__ c, int batch,
+                                 unsigned long long* __restrict__ counters, const Epi& ep) {
+  __shared__ double sm[kFinWaves];
+  __shared__ unsigned long long cnt[kFinWaves][10];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nt = (int)blockDim.x, nw = nt >> 6;
+  unsigned v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // a thread's sums fit 32 bits; 64-bit from the wavefront on
+  double emax = 0.0, e[kDiagSlots];
+  int fl[kDiagSlots];
+  for (int j0 = 0; j0 < g.M; j0 += kDiagSlots * nt) {
+#pragma unroll
+    for (int k = 0; k < kDiagSlots; ++k) {
+      const int j = j0 + k * nt + (int)threadIdx.x;
+      int f = 0;
+      double ej = 0.0;
+      if (j < g.M) {
+        f = rec.mflag[j];
+        const int4 w = *reinterpret_cast<const int4*>(rec.mwork + 4 * (size_t)j);  // 16-byte aligned rows
+        v[0] += rec.mcaus[j];
+        v[1] += rec.mdead[j];
+        v[2] += f & 1;
+        v[8] += (f >> 2) & 1;
+        v[4] += (unsigned)w.x;
+        v[5] += (unsigned)w.y;
+        v[6] += (unsigned)w.z;
+        v[7] += (unsigned)w.w;
+        if constexpr (kOne) {
+          const double2 cj = c[j];
+          ej = cj.x * cj.x + cj.y * cj.y;
+        } else {
+          ej = batch_energy(c, g.M, j, batch);
+        }
+      }
+      e[k] = ej;
+      fl[k] = f;
+      emax = fmax(emax, ej);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off, 64));
+  if (lane == 0) sm[wv] = emax;
+  __syncthreads();
+  emax = 0.0;
+  for (int k = 0; k < nw; ++k) emax = fmax(emax, sm[k]);
+  const double thr = ep.caustic_tol * ep.caustic_tol * emax;
+  if (g.M <= kDiagSlots * nt) {
+#pragma unroll
+    for (int k = 0; k < kDiagSlots; ++k)
+      if (fl[k] && e[k] > thr) {
+        if (fl[k] & 3) ++v[3];  // caustic or folded
+        if (fl[k] & 4) ++v[9];  // no live ray
+      }
+  } else {
+    for (int j = threadIdx.x; j < g.M; j += nt) {
+      const int f = rec.mflag[j];
+      if (f && batch_energy(c, g.M, j, kOne ? 1 : batch) > thr) {
+        if (f & 3) ++v[3];
+        if (f & 4) ++v[9];
+      }
+    }
+  }
+  for (int k = 0; k < 10; ++k) {
+    unsigned long long w64 = v[k];
+    for (int off = 32; off > 0; off >>= 1) w64 += __shfl_xor(w64, off, 64);
+    if (lane == 0) cnt[wv][k] = w64;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int w = 0; w < nw; ++w)
+      for (int k = 0; k < 10; ++k) t[k] += cnt[w][k];
+    for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], t[k]);
+    atomicAdd(&counters[4], 1ull);
+    for (int k = 4; k < 10; ++k) atomicAdd(&counters[k + 1], t[k]);
+  }
 }
 
 template <typename PT>
@@ -697,56 +783,11 @@ __device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, c
     return;
   }
   if (b != 0) return;
-  // Diagnostics of the screen (last workgroup of field 0, up to 512 threads
-  // so that each loop below is one or two rounds of independent loads): the
-  // largest mode energy (summed over the batch), then the counts, with
-  // wavefront reductions and the wavefronts combined in order.
-  __shared__ double sm[kFinWaves];
-  __shared__ unsigned long long cnt[kFinWaves][10];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
-  double emax = 0.0;
-#pragma unroll 4
-  for (int j = threadIdx.x; j < g.M; j += (int)blockDim.x) emax = fmax(emax, batch_energy(c, g.M, j, batch));
-  for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off, 64));
-  if (lane == 0) sm[wv] = emax;
-  __syncthreads();
-  emax = 0.0;
-  for (int k = 0; k < nw; ++k) emax = fmax(emax, sm[k]);
-  const double thr = ep.caustic_tol * ep.caustic_tol * emax;
-  unsigned v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // a thread's sums fit 32 bits; 64-bit from the wavefront on
-#pragma unroll 4
-  for (int j = threadIdx.x; j < g.M; j += (int)blockDim.x) {
-    const int f = rec.mflag[j];
-    v[0] += rec.mcaus[j];
-    v[1] += rec.mdead[j];
-    v[2] += f & 1;
-    v[8] += (f >> 2) & 1;
-    if (f) {
-      const double e = batch_energy(c, g.M, j, batch);
-      if (e > thr) {
-        if (f & 3) ++v[3];  // caustic or folded
-        if (f & 4) ++v[9];  // no live ray
-      }
-    }
-    v[4] += (unsigned)rec.mwork[4 * j];
-    v[5] += (unsigned)rec.mwork[4 * j + 1];
-    v[6] += (unsigned)rec.mwork[4 * j + 2];
-    v[7] += (unsigned)rec.mwork[4 * j + 3];
-  }
-  for (int k = 0; k < 10; ++k) {
-    unsigned long long w64 = v[k];
-    for (int off = 32; off > 0; off >>= 1) w64 += __shfl_xor(w64, off, 64);
-    if (lane == 0) cnt[wv][k] = w64;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int w = 0; w < nw; ++w)
-      for (int k = 0; k < 10; ++k) t[k] += cnt[w][k];
-    for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], t[k]);
-    atomicAdd(&counters[4], 1ull);
-    for (int k = 4; k < 10; ++k) atomicAdd(&counters[k + 1], t[k]);
-  }
+  // the last workgroup of field 0: the screen's diagnostics
+  if (batch == 1)
+    diag_body<true>(g, rec, c, 1, counters, ep);
+  else
+    diag_body<false>(g, rec, c, batch, counters, ep);
 }
 
 template <typename PT>
