@@ -678,7 +678,9 @@ __device__ inline void diag_body(const Geometry& g, const DevRecords& rec, const
   __shared__ double sm[kFinWaves];
   __shared__ unsigned long long cnt[kFinWaves][10];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nt = (int)blockDim.x, nw = nt >> 6;
-  unsigned v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // a thread's sums fit 32 bits; 64-bit from the wavefront on
+  // a thread's sums fit 32 bits, 64-bit from the wavefront on; counts 3 and
+  // 9 (significant modes) wait for the threshold below
+  unsigned v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   double emax = 0.0, e[kDiagSlots];
   int fl[kDiagSlots];
   for (int j0 = 0; j0 < g.M; j0 += kDiagSlots * nt) {
@@ -710,41 +712,67 @@ __device__ inline void diag_body(const Geometry& g, const DevRecords& rec, const
       emax = fmax(emax, ej);
     }
   }
-  for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off, 64));
-  if (lane == 0) sm[wv] = emax;
+  // Wavefront sums: the eight counts that do not depend on the threshold go
+  // through the shuffle steps together with the largest energy, the two that
+  // do (each at most M: 32 bits) after it.  The chains of one step are
+  // independent, so a step costs one LDS round trip (one chain after another
+  // took about 3 us per screen).
+  constexpr int kFree[8] = {0, 1, 2, 4, 5, 6, 7, 8};
+  unsigned long long w64[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) w64[i] = v[kFree[i]];
+  for (int off = 32; off > 0; off >>= 1) {
+    emax = fmax(emax, __shfl_xor(emax, off, 64));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w64[i] += __shfl_xor(w64[i], off, 64);
+  }
+  if (lane == 0) {
+    sm[wv] = emax;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cnt[wv][kFree[i]] = w64[i];
+  }
   __syncthreads();
   emax = 0.0;
   for (int k = 0; k < nw; ++k) emax = fmax(emax, sm[k]);
   const double thr = ep.caustic_tol * ep.caustic_tol * emax;
+  unsigned sig = 0, sig_dead = 0;
   if (g.M <= kDiagSlots * nt) {
 #pragma unroll
     for (int k = 0; k < kDiagSlots; ++k)
       if (fl[k] && e[k] > thr) {
-        if (fl[k] & 3) ++v[3];  // caustic or folded
-        if (fl[k] & 4) ++v[9];  // no live ray
+        if (fl[k] & 3) ++sig;       // caustic or folded
+        if (fl[k] & 4) ++sig_dead;  // no live ray
       }
   } else {
     for (int j = threadIdx.x; j < g.M; j += nt) {
       const int f = rec.mflag[j];
       if (f && batch_energy(c, g.M, j, kOne ? 1 : batch) > thr) {
-        if (f & 3) ++v[3];
-        if (f & 4) ++v[9];
+        if (f & 3) ++sig;
+        if (f & 4) ++sig_dead;
       }
     }
   }
-  for (int k = 0; k < 10; ++k) {
-    unsigned long long w64 = v[k];
-    for (int off = 32; off > 0; off >>= 1) w64 += __shfl_xor(w64, off, 64);
-    if (lane == 0) cnt[wv][k] = w64;
+  for (int off = 32; off > 0; off >>= 1) {
+    sig += __shfl_xor(sig, off, 64);
+    sig_dead += __shfl_xor(sig_dead, off, 64);
+  }
+  if (lane == 0) {
+    cnt[wv][3] = sig;
+    cnt[wv][9] = sig_dead;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int w = 0; w < nw; ++w)
-      for (int k = 0; k < 10; ++k) t[k] += cnt[w][k];
-    for (int k = 0; k < 4; ++k) atomicAdd(&counters[k], t[k]);
-    atomicAdd(&counters[4], 1ull);
-    for (int k = 4; k < 10; ++k) atomicAdd(&counters[k + 1], t[k]);
+  // counters[0..3]: count 0..3; [4]: screens; [5..10]: count 4..9 (one
+  // lane each, one atomic instruction)
+  if ((int)threadIdx.x <= 10) {
+    const int k = threadIdx.x;
+    unsigned long long t = 0;
+    if (k == 4) {
+      t = 1;
+    } else {
+      const int src = k < 4 ? k : k - 1;
+      for (int w = 0; w < nw; ++w) t += cnt[w][src];
+    }
+    atomicAdd(&counters[k], t);
   }
 }
 
