@@ -19,6 +19,10 @@
 #include "fft_body.h"
 #include "swkb_internal.h"
 
+// wavefront reductions of the device library (cross-lane DPP steps)
+extern "C" __device__ unsigned long long __ockl_wfred_add_u64(unsigned long long);
+extern "C" __device__ double __ockl_wfred_max_f64(double);
+
 namespace swkb {
 namespace {
 
@@ -712,20 +716,15 @@ __device__ inline void diag_body(const Geometry& g, const DevRecords& rec, const
       emax = fmax(emax, ej);
     }
   }
-  // Wavefront sums: the eight counts that do not depend on the threshold go
-  // through the shuffle steps together with the largest energy, the two that
-  // do (each at most M: 32 bits) after it.  The chains of one step are
-  // independent, so a step costs one LDS round trip (one chain after another
-  // took about 3 us per screen).
+  // Wavefront reductions (cross-lane DPP steps, no LDS round trips): the
+  // largest energy and the eight counts that do not depend on the threshold
+  // first, the two that do (each at most M: 32 bits) after it.  As 64-bit
+  // shuffle chains one after another they took about 3 us per screen.
   constexpr int kFree[8] = {0, 1, 2, 4, 5, 6, 7, 8};
   unsigned long long w64[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) w64[i] = v[kFree[i]];
-  for (int off = 32; off > 0; off >>= 1) {
-    emax = fmax(emax, __shfl_xor(emax, off, 64));
-#pragma unroll
-    for (int i = 0; i < 8; ++i) w64[i] += __shfl_xor(w64[i], off, 64);
-  }
+  for (int i = 0; i < 8; ++i) w64[i] = __ockl_wfred_add_u64(v[kFree[i]]);
+  emax = __ockl_wfred_max_f64(emax);
   if (lane == 0) {
     sm[wv] = emax;
 #pragma unroll
@@ -752,10 +751,8 @@ __device__ inline void diag_body(const Geometry& g, const DevRecords& rec, const
       }
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    sig += __shfl_xor(sig, off, 64);
-    sig_dead += __shfl_xor(sig_dead, off, 64);
-  }
+  sig = __ockl_wfred_add_u32(sig);
+  sig_dead = __ockl_wfred_add_u32(sig_dead);
   if (lane == 0) {
     cnt[wv][3] = sig;
     cnt[wv][9] = sig_dead;
