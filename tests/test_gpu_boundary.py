@@ -1,8 +1,9 @@
 """GPU tests of the C ABI's contract beyond the numerics: a batch of one field
 on a plan without a batch buffer, HIP-graph replays after calls that change
 the plan's rays or field buffer, the single-stream rule (SWKB_ERR_BUSY), the
-field of any screen (swkb_field with keep_history) and the report of a
-significant evanescent mode (SWKB_ERR_EVANESCENT)."""
+field of any screen (swkb_field with keep_history), the report of a
+significant evanescent mode (SWKB_ERR_EVANESCENT) and the diagnostics of a
+batch against those of one field."""
 import sys
 
 import numpy as np
@@ -196,3 +197,31 @@ def test_evanescent_mode_is_reported(torch_dev, swkb, prec):
     err = float(np.linalg.norm(hist - ref) / np.linalg.norm(ref))
     assert err <= (1e-10 if prec == "fp64" else 1e-3)
     plan.close()
+
+
+@pytest.mark.parametrize("prop", [0, 2])
+@pytest.mark.parametrize("n_z,n_modes,stride", [(512, 128, 1), (16384, 8192, 8)])
+def test_batch_diagnostics_equal_one_field(torch_dev, swkb, n_z, n_modes, stride, prop):
+    """The epilogue's diagnostics have a one-field path (each thread holds
+    its modes' energies in registers while M <= 4096, and makes a second
+    pass over the modes above that) and a several-field path (energies summed
+    over the batch).  Two copies of one field double every mode energy and
+    the largest one exactly, so every count of the batch equals the
+    one-field count; the wide screen makes caustic modes significant."""
+    torch, dev = torch_dev
+    cfg = W.with_overrides(W.linear_caustic(n_screens=2), n_z=n_z, n_modes=n_modes, ray_stride=stride, dx=300.0,
+                           rk4_steps=64, absorber_top=0.0, absorber_bot=0.0, caustic_tol=1e-3, propagator=prop)
+    u0 = torch.from_numpy(W.incident_field(cfg)).to(dev)
+    say(f"[diag] N={n_z} M={n_modes} prop={prop}: one field")
+    one = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
+    one.propagate(u0, 0, 2)
+    d1 = one.diagnostics()
+    one.close()
+    say(f"[diag] N={n_z} M={n_modes} prop={prop}: batch of two, one-field counts {d1}")
+    two = swkb.Plan(W.with_overrides(cfg, max_batch=2), precision=swkb.MIXED, device=dev)
+    two.propagate_batch(torch.stack([u0, u0]).contiguous(), 0, 2)
+    d2 = two.diagnostics()
+    two.close()
+    say(f"[diag] batch counts {d2}")
+    assert d1["screens"] == 2 and d1["significant"] > 0
+    assert d1 == d2
