@@ -137,7 +137,7 @@ std::vector<int> gauss_lists(const swkb_params* p, std::vector<int>* off) {
 }
 
 struct Layout {
-  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, pan, cpol, part, tmat, hist,
+  size_t xi, pbar, e1r, frac, frac_st, tw, mprm, glist, gstage, gterm, gczl, u, ub, Y, c, pan, menergy, cpol, part, tmat, hist,
       counters;
   // one ray-record slot (offsets from its start); nslots of them from slot0
   size_t mtab, D, Pp, G, A, cz, cidx, tstart, mflag, mcaus, mdead, mwork, wcount;
@@ -207,6 +207,7 @@ Layout layout(const swkb_params* p, const Geometry& g, size_t nlist, bool gfast)
   L.Y = take(sizeof(double2) * g.P * B);
   L.c = take(sizeof(double2) * g.M * B);
   L.pan = take(B > 1 && use_matrix(p) ? batch_panel_bytes(g, (int)B) : 0);
+  L.menergy = take(B > 1 && use_matrix(p) ? sizeof(double) * g.M : 0);
   L.cpol = take(p->precision == SWKB_MIXED ? sizeof(float2) * g.M : 0);
   size_t part_bytes = sizeof(double2) * (size_t)g.N * partial_groups(g) * B;
   if (B > 1 && use_matrix(p)) part_bytes = std::max(part_bytes, batch_part_bytes(g, p->precision, (int)B));
@@ -665,6 +666,7 @@ swkb_status swkb::plan_impl(const swkb_params* p, void* workspace, size_t worksp
     // buffers of zero size share their offset with the next one: leave them unset
     pl->ub = p->max_batch > 1 ? reinterpret_cast<double2*>(ws + L.ub) : nullptr;
     pl->pan = p->max_batch > 1 && use_matrix(p) ? static_cast<void*>(ws + L.pan) : nullptr;
+    pl->menergy = p->max_batch > 1 && use_matrix(p) ? reinterpret_cast<double*>(ws + L.menergy) : nullptr;
     pl->cpol = p->precision == SWKB_MIXED ? reinterpret_cast<float2*>(ws + L.cpol) : nullptr;
     pl->max_batch = p->max_batch;
     pl->sum_fields = 1;

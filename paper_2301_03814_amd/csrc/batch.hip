@@ -49,10 +49,25 @@ __device__ inline double panel_value(const double2 cv, int cc, int cp) {
   return cc == cp ? cv.x : (cc == 0 ? cv.y : -cv.y);
 }
 
+// The panel kernels' last ceil(M / 256) workgroups (when energy is given):
+// each mode's energy summed over the B fields, for the epilogue's
+// diagnostics, which then read M values instead of B M coefficients in one
+// workgroup.  Workgroup e takes modes 256 e + thread.
+__device__ inline void mode_energies(const double2* __restrict__ c, int M, int B, unsigned e,
+                                     double* __restrict__ energy) {
+  const int j = (int)(e * blockDim.x + threadIdx.x);
+  if (j < M) energy[j] = batch_energy(c, M, j, B);
+}
+
 // FP32 panel [mode pair p][cc][tile][lane]: lane l = n + 32 k holds row k =
 // mode 2 p + k (component cc of T), column n; tile t covers fields 16 t ..
 // 16 t + 15.
-__global__ void panel_f32_kernel(const double2* __restrict__ c, int M, int B, int tiles, float* __restrict__ pan) {
+__global__ void panel_f32_kernel(const double2* __restrict__ c, int M, int B, int tiles, float* __restrict__ pan,
+                                 unsigned pblocks, double* __restrict__ energy) {
+  if (blockIdx.x >= pblocks) {
+    mode_energies(c, M, B, blockIdx.x - pblocks, energy);
+    return;
+  }
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)M * tiles * 64) return;
   const int l = (int)(i & 63), t = (int)((i >> 6) % tiles);
@@ -65,7 +80,12 @@ __global__ void panel_f32_kernel(const double2* __restrict__ c, int M, int B, in
 // FP64 panel [mode quad q][cc][tile][lane]: lane l = n + 16 k holds row k =
 // mode 4 q + k (zero past the last mode), column n; tile t covers fields
 // 8 t .. 8 t + 7.
-__global__ void panel_f64_kernel(const double2* __restrict__ c, int M, int B, int tiles, double* __restrict__ pan) {
+__global__ void panel_f64_kernel(const double2* __restrict__ c, int M, int B, int tiles, double* __restrict__ pan,
+                                 unsigned pblocks, double* __restrict__ energy) {
+  if (blockIdx.x >= pblocks) {
+    mode_energies(c, M, B, blockIdx.x - pblocks, energy);
+    return;
+  }
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int quads = (M + 3) / 4;
   if (i >= (size_t)quads * 2 * tiles * 64) return;
@@ -277,6 +297,10 @@ size_t batch_panel_bytes(const Geometry& g, int B) {
   return (size_t)ceil_div(g.M, 4) * 2 * panel_tiles(SWKB_FP64, B) * 64 * sizeof(double);
 }
 
+static unsigned energy_blocks(const swkb_plan_s& pl) {
+  return pl.menergy ? (unsigned)ceil_div(pl.g.M, 256) : 0u;
+}
+
 hipError_t launch_batch_product(const swkb_plan_s& pl, int batch, hipStream_t st, int* groups_out) {
   const Geometry& g = pl.g;
   const int prec = pl.precision;
@@ -289,8 +313,9 @@ hipError_t launch_batch_product(const swkb_plan_s& pl, int batch, hipStream_t st
   if (prec == SWKB_FP64) {
     const int quads = ceil_div(g.M, 4);
     const size_t n = (size_t)quads * 2 * tiles * 64;
-    hipLaunchKernelGGL(panel_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pl.c, g.M, batch, tiles,
-                       static_cast<double*>(pl.pan));
+    const unsigned pb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(panel_f64_kernel, dim3(pb + energy_blocks(pl)), dim3(256), 0, st, pl.c, g.M, batch, tiles,
+                       static_cast<double*>(pl.pan), pb, pl.menergy);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const doublex2* T = static_cast<const doublex2*>(pl.tmat);
@@ -306,8 +331,9 @@ hipError_t launch_batch_product(const swkb_plan_s& pl, int batch, hipStream_t st
   }
   const int pairs = g.M / 2;
   const size_t n = (size_t)g.M * tiles * 64;
-  hipLaunchKernelGGL(panel_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pl.c, g.M, batch, tiles,
-                     static_cast<float*>(pl.pan));
+  const unsigned pb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(panel_f32_kernel, dim3(pb + energy_blocks(pl)), dim3(256), 0, st, pl.c, g.M, batch, tiles,
+                     static_cast<float*>(pl.pan), pb, pl.menergy);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const floatx2* T = static_cast<const floatx2*>(pl.tmat);

@@ -648,37 +648,21 @@ constexpr int kDiagSlots = 8;  // modes per thread and chunk in the diagnostics
 constexpr int kPersistThreads = 64 * kWaves;
 constexpr int kPersistUnroll = 4;  // modes of the product whose loads a wavefront issues together
 
-// Energy of mode j summed over the batch in field order (the loads of eight
-// fields are issued before their terms are added).
-__device__ inline double batch_energy(const double2* __restrict__ c, int M, int j, int batch) {
-  double e = 0.0;
-  int bb = 0;
-  for (; bb + 8 <= batch; bb += 8) {
-    double2 cv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) cv[u] = c[(size_t)(bb + u) * M + j];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) e += cv[u].x * cv[u].x + cv[u].y * cv[u].y;
-  }
-  for (; bb < batch; ++bb) {
-    const double2 cv = c[(size_t)bb * M + j];
-    e += cv.x * cv.x + cv.y * cv.y;
-  }
-  return e;
-}
-
 // Diagnostics of a screen, by one workgroup: the largest mode energy
 // (summed over the batch), then the counts, with wavefront reductions and
 // the wavefronts combined in order.  A thread takes modes j0 + k *
 // blockDim.x, k < kDiagSlots, of each chunk of kDiagSlots * blockDim.x
 // modes, with the loads of all of them issued together (kOne, one field:
-// the energy is one load); when one chunk covers the M modes (M <= 4096 at
+// the energy is one load; several fields: energy, the modes' energies
+// summed over the batch by the panel kernels of the batched product, when
+// given, else the sums here); when one chunk covers the M modes (M <= 4096 at
 // 512 threads), their energies and flags stay in registers for the count of
 // significant modes, so the workgroup waits for memory about once instead of
 // once per loop round.
 template <bool kOne>
 __device__ inline void diag_body(const Geometry& g, const DevRecords& rec, const double2* __restrict__ c, int batch,
-                                 unsigned long long* __restrict__ counters, const Epi& ep) {
+                                 unsigned long long* __restrict__ counters, const Epi& ep,
+                                 const double* __restrict__ energy) {
   __shared__ double sm[kFinWaves];
   __shared__ unsigned long long cnt[kFinWaves][10];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nt = (int)blockDim.x, nw = nt >> 6;
@@ -708,7 +692,7 @@ __device__ inline void diag_body(const Geometry& g, const DevRecords& rec, const
           const double2 cj = c[j];
           ej = cj.x * cj.x + cj.y * cj.y;
         } else {
-          ej = batch_energy(c, g.M, j, batch);
+          ej = energy ? energy[j] : batch_energy(c, g.M, j, batch);
         }
       }
       e[k] = ej;
@@ -745,7 +729,7 @@ __device__ inline void diag_body(const Geometry& g, const DevRecords& rec, const
   } else {
     for (int j = threadIdx.x; j < g.M; j += nt) {
       const int f = rec.mflag[j];
-      if (f && batch_energy(c, g.M, j, kOne ? 1 : batch) > thr) {
+      if (f && (!kOne && energy ? energy[j] : batch_energy(c, g.M, j, kOne ? 1 : batch)) > thr) {
         if (f & 3) ++sig;
         if (f & 4) ++sig_dead;
       }
@@ -777,7 +761,8 @@ template <typename PT>
 __device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, const double2* __restrict__ c,
                                      const PT* __restrict__ part, int groups, int batch, double2* __restrict__ out,
                                      double2* __restrict__ hist, unsigned long long* __restrict__ counters,
-                                     const Epi& ep, int bx, int nbx, int b) {
+                                     const Epi& ep, int bx, int nbx, int b,
+                                     const double* __restrict__ energy = nullptr) {
   if (bx + 1 < nbx) {
     const int sub = threadIdx.x & 3;
     const PT* pb = part + (size_t)b * groups * g.N;
@@ -810,9 +795,9 @@ __device__ inline void finalize_body(const Geometry& g, const DevRecords& rec, c
   if (b != 0) return;
   // the last workgroup of field 0: the screen's diagnostics
   if (batch == 1)
-    diag_body<true>(g, rec, c, 1, counters, ep);
+    diag_body<true>(g, rec, c, 1, counters, ep, nullptr);
   else
-    diag_body<false>(g, rec, c, batch, counters, ep);
+    diag_body<false>(g, rec, c, batch, counters, ep, energy);
 }
 
 template <typename PT>
@@ -820,8 +805,10 @@ __global__ void __launch_bounds__(kFinThreads) finalize_kernel(Geometry g, DevRe
                                                                const double2* __restrict__ c,
                                                                const PT* __restrict__ part, int groups, int batch,
                                                                double2* __restrict__ out, double2* __restrict__ hist,
-                                                               unsigned long long* __restrict__ counters, Epi ep) {
-  finalize_body<PT>(g, rec, c, part, groups, batch, out, hist, counters, ep, blockIdx.x, gridDim.x, blockIdx.y);
+                                                               unsigned long long* __restrict__ counters, Epi ep,
+                                                               const double* __restrict__ energy) {
+  finalize_body<PT>(g, rec, c, part, groups, batch, out, hist, counters, ep, blockIdx.x, gridDim.x, blockIdx.y,
+                    energy);
 }
 
 // The matrix product and the epilogue of one screen for many problems, one
@@ -1037,7 +1024,7 @@ hipError_t launch_superpose(const swkb_plan_s& pl, double2* out, double2* hist, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, batch), dim3(kFinThreads), 0, st, g, pl.rec, pl.c,
-                     pl.part, groups, batch, out, hist, pl.counters, ep);
+                     pl.part, groups, batch, out, hist, pl.counters, ep, nullptr);
   return hipGetLastError();
 }
 
@@ -1073,7 +1060,7 @@ hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* his
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, 1), dim3(kFinThreads), 0, st, g, pl.rec, pl.c,
-                       pl.part, groups, 1, out, hist, pl.counters, ep);
+                       pl.part, groups, 1, out, hist, pl.counters, ep, nullptr);
     return hipGetLastError();
   }
   if (batch == 1) {
@@ -1089,7 +1076,7 @@ hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* his
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel<double2>, dim3((g.N + kFinThreads / 4 - 1) / (kFinThreads / 4) + 1, 1), dim3(kFinThreads), 0, st, g, pl.rec, pl.c,
-                       pl.part, groups, 1, out, hist, pl.counters, ep);
+                       pl.part, groups, 1, out, hist, pl.counters, ep, nullptr);
     return hipGetLastError();
   }
   // several fields: one complex matrix product U[b][m] = sum_j C[b][j] T[j][m]
@@ -1100,10 +1087,11 @@ hipError_t launch_apply_matrix(const swkb_plan_s& pl, double2* out, double2* his
   const dim3 fin(finalize_blocks(g), batch);
   if (pl.precision == SWKB_FP64)
     hipLaunchKernelGGL(finalize_kernel<double2>, fin, dim3(kFinThreads), 0, st, g, pl.rec, pl.c, pl.part, groups,
-                       batch, out, hist, pl.counters, ep);
+                       batch, out, hist, pl.counters, ep, pl.menergy);
   else
     hipLaunchKernelGGL(finalize_kernel<float2>, fin, dim3(kFinThreads), 0, st, g, pl.rec, pl.c,
-                       reinterpret_cast<const float2*>(pl.part), groups, batch, out, hist, pl.counters, ep);
+                       reinterpret_cast<const float2*>(pl.part), groups, batch, out, hist, pl.counters, ep,
+                       pl.menergy);
   return hipGetLastError();
 }
 

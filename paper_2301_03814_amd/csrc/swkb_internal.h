@@ -97,6 +97,25 @@ struct MultiProblem {
   int logP1, logP2, CA, RB, groups;
 };
 
+// Energy of mode j summed over the batch in field order (the loads of eight
+// fields are issued before their terms are added).
+__device__ inline double batch_energy(const double2* __restrict__ c, int M, int j, int batch) {
+  double e = 0.0;
+  int bb = 0;
+  for (; bb + 8 <= batch; bb += 8) {
+    double2 cv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cv[u] = c[(size_t)(bb + u) * M + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e += cv[u].x * cv[u].x + cv[u].y * cv[u].y;
+  }
+  for (; bb < batch; ++bb) {
+    const double2 cv = c[(size_t)bb * M + j];
+    e += cv.x * cv.x + cv.y * cv.y;
+  }
+  return e;
+}
+
 }  // namespace swkb
 
 struct swkb_plan_s {
@@ -123,6 +142,7 @@ struct swkb_plan_s {
   double2 *Y, *c;                // FFT scratch [B][P], modes [B][M]
   double2* part;                 // superposition partials [B][mode groups][N]
   void* pan;                     // batched product's B operands per mode (matrix plans, max_batch > 1)
+  double* menergy;               // batched product: each mode's energy summed over the batch [M] (same plans)
   const double* lwin = nullptr;  // launch amplitude factor per ray [R] (a patch's S^p; 0: ray not launched), or
                                  // NULL; device memory of the caller's, applied after every march
   float2* cpol;                  // one field's modes in polar form [M]: |c|, frac(arg c / (2 pi))

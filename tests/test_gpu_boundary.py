@@ -206,7 +206,8 @@ def test_batch_diagnostics_equal_one_field(torch_dev, swkb, n_z, n_modes, stride
     its modes' energies in registers while M <= 4096, and makes a second
     pass over the modes above that) and a several-field path (energies summed
     over the batch).  Two copies of one field double every mode energy and
-    the largest one exactly, so every count of the batch equals the
+    the largest one (to within rounding, which could move only a mode lying
+    at the threshold itself), so every count of the batch equals the
     one-field count; the wide screen makes caustic modes significant."""
     torch, dev = torch_dev
     cfg = W.with_overrides(W.linear_caustic(n_screens=2), n_z=n_z, n_modes=n_modes, ray_stride=stride, dx=300.0,
