@@ -29,13 +29,40 @@ __device__ inline double2 extended(const double2* __restrict__ u, int i, int N, 
 // nb sequences of length len (power of two) stored at L[b * len + i] in
 // bit-reversed order; in-place radix-2 decimation in time.  The twiddle of
 // butterfly k at half-size hs is e^{-2 pi i k / (2 hs)} = wl[k * len / (2 hs)],
-// wl[k] = e^{-2 pi i k / len} (k < len / 2) staged in LDS.
+// wl[k] = e^{-2 pi i k / len} (k < len / 2) staged in LDS.  Two consecutive
+// stages (half-sizes hs and 2 hs) run together from registers: a thread
+// takes the four elements base + {0, 1, 2, 3} hs that the two stages' four
+// butterflies connect, so each pair of stages costs one LDS round trip and
+// one barrier; the butterflies and their twiddles are those of the radix-2
+// stages (a last stage runs alone when the number of stages is odd).
 __device__ inline void lds_fft(double2* L, int nb, int len, const double2* wl) {
-  const int half = len >> 1;
-  const int nbf = nb * half;
-  for (int hs = 1; hs < len; hs <<= 1) {
+  int hs = 1;
+  for (; 4 * hs <= len; hs <<= 2) {
+    const int quarter = len >> 2;
+    const int ta = len / (2 * hs), tb = ta >> 1;  // twiddle strides of the two stages
+    for (int q = threadIdx.x; q < nb * quarter; q += blockDim.x) {
+      const int seq = q / quarter, r = q - seq * quarter;
+      const int grp = r / hs, kk = r - grp * hs;
+      const int i0 = seq * len + grp * 4 * hs + kk;
+      const double2 wa = wl[kk * ta], wb0 = wl[kk * tb], wb1 = wl[(kk + hs) * tb];
+      const double2 x0 = L[i0], x1 = cmul(L[i0 + hs], wa);
+      const double2 x2 = L[i0 + 2 * hs], x3 = cmul(L[i0 + 3 * hs], wa);
+      // half-size hs: (i0, i0 + hs) and (i0 + 2 hs, i0 + 3 hs)
+      const double2 a0 = make_double2(x0.x + x1.x, x0.y + x1.y), a1 = make_double2(x0.x - x1.x, x0.y - x1.y);
+      const double2 a2 = make_double2(x2.x + x3.x, x2.y + x3.y), a3 = make_double2(x2.x - x3.x, x2.y - x3.y);
+      // half-size 2 hs: (i0, i0 + 2 hs) at k = kk, (i0 + hs, i0 + 3 hs) at k = kk + hs
+      const double2 b2 = cmul(a2, wb0), b3 = cmul(a3, wb1);
+      L[i0] = make_double2(a0.x + b2.x, a0.y + b2.y);
+      L[i0 + 2 * hs] = make_double2(a0.x - b2.x, a0.y - b2.y);
+      L[i0 + hs] = make_double2(a1.x + b3.x, a1.y + b3.y);
+      L[i0 + 3 * hs] = make_double2(a1.x - b3.x, a1.y - b3.y);
+    }
+    __syncthreads();
+  }
+  if (hs < len) {  // one radix-2 stage left (hs = len / 2)
+    const int half = len >> 1;
     const int tstride = len / (2 * hs);
-    for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
+    for (int b = threadIdx.x; b < nb * half; b += blockDim.x) {
       const int seq = b / half, bb = b - seq * half;
       const int grp = bb / hs, kk = bb - grp * hs;
       const int i0 = seq * len + grp * 2 * hs + kk, i1 = i0 + hs;
