@@ -497,6 +497,86 @@ __device__ inline void wave_counts(int* __restrict__ wcount, size_t slot, int la
   }
 }
 
+// Wavefronts of the Gaussian-sum marches.  A mode's first F = R / 64
+// wavefront positions are full (64 rays each).  Its last T = R mod 64 rays
+// start at the launch heights of position F whatever the mode, so the tails
+// of floor(64 / T) modes share one wavefront, mode after mode in segments of
+// T lanes (random medium: R = 1091, a mode's eighteenth wavefront would
+// otherwise march 3 rays on 64 lanes, 5.6 % of all wavefronts).  Every ray
+// takes the same arithmetic either way; only its mode index becomes a lane
+// value on a tail wavefront.
+__host__ __device__ inline long long packed_march_waves(const Geometry& g) {
+  const int T = g.R & 63;
+  const long long full = (long long)g.M * (g.R >> 6);
+  if (!T) return full;
+  const int per = 64 / T;
+  return full + (g.M + per - 1) / per;
+}
+
+// A lane's ray on the packed layout: mode j, wavefront position w, ray
+// rl within the position (r = 64 w + rl).
+struct RayLane {
+  int j, w, rl;
+  bool active;
+  bool lead;  // tail wavefront: first lane of its mode's segment
+};
+
+// Counts of a tail wavefront: the first lane of each segment sums its T
+// lanes (T - 1 lane reads each) and writes its mode's slot of position F.
+__device__ inline void tail_counts(int* __restrict__ wcount, int wpm, const RayLane& rl, int lane, int T, int st,
+                                   Work c) {
+  const unsigned long long bc = __ballot(rl.active && st == kCaustic);
+  const unsigned long long bd = __ballot(rl.active && (st == kDead || st == kDeadLaunch));
+  int v0 = c.rhs, v1 = c.med, v2 = c.terms, v3 = c.tab;
+  for (int k = 1; k < T; ++k) {
+    v0 += __shfl(c.rhs, lane + k);
+    v1 += __shfl(c.med, lane + k);
+    v2 += __shfl(c.terms, lane + k);
+    v3 += __shfl(c.tab, lane + k);
+  }
+  if (rl.lead && rl.active) {
+    const unsigned long long seg = (1ull << T) - 1;
+    int* wc = wcount + kWaveCounts * ((size_t)rl.j * wpm + rl.w);
+    wc[0] = __popcll((bc >> lane) & seg);
+    wc[1] = __popcll((bd >> lane) & seg);
+    wc[2] = v0;
+    wc[3] = v1;
+    wc[4] = v2;
+    wc[5] = v3;
+  }
+}
+
+// Wavefront `wave` of the packed layout: full positions first, then the
+// tails.  Returns false when the wavefront has no ray (uniform).  One march
+// body serves both kinds, the mode index a lane value: inlined once per kind,
+// the march's register allocation spilled inside the step loop.
+__device__ inline bool ray_lane(const Geometry& g, int wave, int lane, RayLane& rl, bool& tail) {
+  const int F = g.R >> 6;
+  tail = wave >= g.M * F;
+  if (!tail) {
+    const int j = wave / F;
+    rl.j = j;
+    rl.w = wave - j * F;
+    rl.rl = lane;
+    rl.active = true;
+    rl.lead = lane == 0;
+    return true;
+  }
+  const int T = g.R & 63;
+  if (!T) return false;
+  const int per = 64 / T;
+  const int tw = wave - g.M * F;
+  if (tw * per >= g.M) return false;
+  const int seg = lane / T;
+  rl.j = tw * per + seg;
+  rl.w = F;
+  rl.rl = lane - seg * T;
+  rl.active = seg < per && rl.j < g.M;
+  rl.lead = rl.rl == 0;
+  if (!rl.active) rl.j = g.M - 1;  // loads stay in range; nothing is marched or written
+  return true;
+}
+
 __device__ inline ModeC load_mode(const DevModes& modes, int j) {
   ModeC mc;
   mc.xi = modes.xi[j];
@@ -548,6 +628,32 @@ struct GaussTabs {
 // the bump loop; at the compiler's choice 101 VGPRs and 4): random medium,
 // 1448 -> 1404 us per screen.
 template <typename T>
+__device__ __forceinline__ void march_gauss_lane(const Geometry& g, const MarchK& mk, const GaussTabs<T>& tabs,
+                                                 const DevModes& modes, const DevRecords& rec,
+                                                 int* __restrict__ wcount, int waves_per_mode,
+                                                 const double* pow2_64, int wave, int lane) {
+  RayLane rl;
+  bool tail;
+  if (!ray_lane(g, wave, lane, rl, tail)) return;  // uniform per wavefront
+  const int w = __builtin_amdgcn_readfirstlane(rl.w);
+  const int r = w * 64 + rl.rl;
+  const ModeC mc = load_mode(modes, rl.j);
+  GaussMedium<T> med;
+  med.pow2_64 = pow2_64;
+  med.stage = tabs.stage;
+  med.term = tabs.term;
+  med.czl = tabs.czl + (size_t)w * tabs.nl;
+  med.nl = tabs.nl;
+  med.zl0 = (T)((double)(rl.rl * g.rho) * g.h);
+  int st;
+  Work c;
+  march_ray<T>(med, mc, g, mk, rl.active, (size_t)rl.j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec,
+               st, c);
+  if (tail) tail_counts(wcount, waves_per_mode, rl, lane, g.R & 63, st, c);
+  else wave_counts(wcount, (size_t)__builtin_amdgcn_readfirstlane(rl.j) * waves_per_mode + w, lane, true, st, c, g.S);
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256, (std::is_same<T, double>::value ? 5 : 1)) march_gauss_kernel(Geometry g, MarchK mk, GaussTabs<T> tabs,
                                                           DevModes modes, DevRecords rec, int* __restrict__ wcount,
                                                           int waves_per_mode) {
@@ -558,23 +664,7 @@ __global__ void __launch_bounds__(256, (std::is_same<T, double>::value ? 5 : 1))
   }
   const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int lane = threadIdx.x & 63;
-  const int j = wave / waves_per_mode;
-  if (j >= g.M) return;  // uniform per wavefront
-  const int w = wave - j * waves_per_mode;
-  const int r = w * 64 + lane;
-  const bool active = r < g.R;
-  const ModeC mc = load_mode(modes, j);
-  GaussMedium<T> med;
-  med.pow2_64 = pow2_64;
-  med.stage = tabs.stage;
-  med.term = tabs.term;
-  med.czl = tabs.czl + (size_t)w * tabs.nl;
-  med.nl = tabs.nl;
-  med.zl0 = (T)((double)(lane * g.rho) * g.h);
-  int st;
-  Work c;
-  march_ray<T>(med, mc, g, mk, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec, st, c);
-  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c, g.S);
+  march_gauss_lane<T>(g, mk, tabs, modes, rec, wcount, waves_per_mode, pow2_64, wave, lane);
 }
 
 // Per-screen medium table of the mixed Gaussian-sum march.  Node values at
@@ -630,23 +720,21 @@ __global__ void __launch_bounds__(kTabNodes) medium_table_kernel(const double* _
 
 // Mixed-path Gaussian-sum march through the screen's medium table.
 template <bool kHold>
-__device__ __forceinline__ void march_table_body(const Geometry& g, const MarchK& mk, const GaussTabs<float>& tabs,
-                                        const MedTab& mt, const DevModes& modes, const DevRecords& rec,
-                                        int* __restrict__ wcount, int waves_per_mode) {
-  const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-  const int lane = threadIdx.x & 63;
-  const int j = wave / waves_per_mode;
-  if (j >= g.M) return;  // uniform per wavefront
-  const int w = wave - j * waves_per_mode;
-  const int r = w * 64 + lane;
-  const bool active = r < g.R;
+__device__ __forceinline__ void march_table_lane(const Geometry& g, const MarchK& mk, const GaussTabs<float>& tabs,
+                                                 const MedTab& mt, const DevModes& modes, const DevRecords& rec,
+                                                 int* __restrict__ wcount, int waves_per_mode, int wave, int lane) {
+  RayLane rl;
+  bool tail;
+  if (!ray_lane(g, wave, lane, rl, tail)) return;  // uniform per wavefront
+  const int j = rl.j, w = __builtin_amdgcn_readfirstlane(rl.w);
+  const int r = w * 64 + rl.rl;
   const ModeC mc = load_mode(modes, j);
   TableMedium<kHold> med;
   med.direct.stage = tabs.stage;
   med.direct.term = tabs.term;
   med.direct.czl = tabs.czl + (size_t)w * tabs.nl;
   med.direct.nl = tabs.nl;
-  med.direct.zl0 = (float)((double)(lane * g.rho) * g.h);
+  med.direct.zl0 = (float)((double)(rl.rl * g.rho) * g.h);
   med.ni = (unsigned)(mt.n - 1);
   med.ta = mt.tab;
   med.inv_dz = mk.inv_dz;
@@ -657,12 +745,22 @@ __device__ __forceinline__ void march_table_body(const Geometry& g, const MarchK
   med.dz_sq = mk.dz_sq;
   const double rel = (g.z_a + (double)(w * 64 * g.rho - g.E) * g.h) - mt.z_lo;  // z_w above the table's base
   med.j0 = (int)floor(rel * mk.inv_dzt);
-  med.tl = (float)((rel - (double)med.j0 * mt.dz + (double)(lane * g.rho) * g.h) * mk.inv_dzt);
+  med.tl = (float)((rel - (double)med.j0 * mt.dz + (double)(rl.rl * g.rho) * g.h) * mk.inv_dzt);
   int st;
   Work c;
-  march_ray<float>(med, mc, g, mk, active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec,
+  march_ray<float>(med, mc, g, mk, rl.active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec,
                    st, c);
-  wave_counts(wcount, (size_t)j * waves_per_mode + w, lane, active, st, c, g.S);
+  if (tail) tail_counts(wcount, waves_per_mode, rl, lane, g.R & 63, st, c);
+  else wave_counts(wcount, (size_t)__builtin_amdgcn_readfirstlane(j) * waves_per_mode + w, lane, true, st, c, g.S);
+}
+
+template <bool kHold>
+__device__ __forceinline__ void march_table_body(const Geometry& g, const MarchK& mk, const GaussTabs<float>& tabs,
+                                        const MedTab& mt, const DevModes& modes, const DevRecords& rec,
+                                        int* __restrict__ wcount, int waves_per_mode) {
+  const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const int lane = threadIdx.x & 63;
+  march_table_lane<kHold>(g, mk, tabs, mt, modes, rec, wcount, waves_per_mode, wave, lane);
 }
 
 // Two launch shapes of the same march.  Beside the one-field FP32 sum the
@@ -910,6 +1008,8 @@ static hipError_t launch_march_rays(const swkb_plan_s& pl, int q, hipStream_t st
   const int wpm = waves_per_mode(g);
   const long long waves = (long long)wpm * g.M;
   const dim3 grid((unsigned)((waves + 3) / 4));
+  // the Gaussian-sum marches share tail wavefronts between modes
+  const dim3 pgrid((unsigned)((packed_march_waves(g) + 3) / 4));
   const double x_q = pl.p.x0 + q * pl.p.dx;
   int* wcount = pl.wcount;
   MarchK mk;
@@ -930,7 +1030,7 @@ static hipError_t launch_march_rays(const swkb_plan_s& pl, int q, hipStream_t st
       GaussTabs<double> t{reinterpret_cast<const T2<double>*>(pl.gstage) + off * nst,
                           reinterpret_cast<const T2<double>*>(pl.gterm) + off,
                           static_cast<const double*>(pl.gczl) + off * wpm, nl};
-      hipLaunchKernelGGL(march_gauss_kernel<double>, grid, dim3(256), 0, st, g, mk, t, modes_of(pl), pl.rec,
+      hipLaunchKernelGGL(march_gauss_kernel<double>, pgrid, dim3(256), 0, st, g, mk, t, modes_of(pl), pl.rec,
                          wcount, wpm);
     } else if (pl.mtab.tab) {
       GaussTabs<float> t{reinterpret_cast<const T2<float>*>(pl.gstage) + off * nst,
@@ -939,14 +1039,14 @@ static hipError_t launch_march_rays(const swkb_plan_s& pl, int q, hipStream_t st
       // reads the table launch_medium_table built for screen q
       const TableMarchArgs a{g, mk, t, pl.mtab, modes_of(pl), pl.rec, wcount, wpm};
       if (pl.sum_fields > 1)
-        hipLaunchKernelGGL(march_table_batch_kernel, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(march_table_batch_kernel, pgrid, dim3(256), 0, st, a);
       else
-        hipLaunchKernelGGL(march_table_kernel, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(march_table_kernel, pgrid, dim3(256), 0, st, a);
     } else {
       GaussTabs<float> t{reinterpret_cast<const T2<float>*>(pl.gstage) + off * nst,
                          reinterpret_cast<const T2<float>*>(pl.gterm) + off,
                          static_cast<const float*>(pl.gczl) + off * wpm, nl};
-      hipLaunchKernelGGL(march_gauss_kernel<float>, grid, dim3(256), 0, st, g, mk, t, modes_of(pl), pl.rec,
+      hipLaunchKernelGGL(march_gauss_kernel<float>, pgrid, dim3(256), 0, st, g, mk, t, modes_of(pl), pl.rec,
                          wcount, wpm);
     }
     return hipGetLastError();
