@@ -546,11 +546,27 @@ __device__ inline void tail_counts(int* __restrict__ wcount, int wpm, const RayL
   }
 }
 
-// Wavefront `wave` of the packed layout: full positions first, then the
-// tails.  Returns false when the wavefront has no ray (uniform).  One march
-// body serves both kinds, the mode index a lane value: inlined once per kind,
-// the march's register allocation spilled inside the step loop.
-__device__ inline bool ray_lane(const Geometry& g, int wave, int lane, RayLane& rl, bool& tail) {
+// Wavefront `wave` of the packed layout (kPack: full positions first, then
+// the tails) or of one mode per wavefront position (ceil(R / 64) per mode).
+// Returns false when the wavefront has no ray (uniform).  One march body
+// serves full and tail wavefronts, the mode index a lane value: inlined once
+// per kind, the table march's register allocation spilled inside the step
+// loop.  The FP64 march keeps one mode per wavefront: with the mode index a
+// lane value it spilled 56 bytes a lane inside its step loop (HBM writes per
+// launch 80 -> 176 MB).
+template <bool kPack>
+__device__ inline bool ray_lane(const Geometry& g, int wave, int lane, int wpm, RayLane& rl, bool& tail) {
+  if constexpr (!kPack) {
+    tail = false;
+    const int j = wave / wpm;
+    if (j >= g.M) return false;
+    rl.j = j;
+    rl.w = wave - j * wpm;
+    rl.rl = lane;
+    rl.active = rl.w * 64 + lane < g.R;
+    rl.lead = lane == 0;
+    return true;
+  }
   const int F = g.R >> 6;
   tail = wave >= g.M * F;
   if (!tail) {
@@ -576,6 +592,10 @@ __device__ inline bool ray_lane(const Geometry& g, int wave, int lane, RayLane& 
   if (!rl.active) rl.j = g.M - 1;  // loads stay in range; nothing is marched or written
   return true;
 }
+
+// Packed layout for the FP32 marches only.
+template <typename T>
+constexpr bool packs_tails() { return !std::is_same<T, double>::value; }
 
 __device__ inline ModeC load_mode(const DevModes& modes, int j) {
   ModeC mc;
@@ -634,7 +654,7 @@ __device__ __forceinline__ void march_gauss_lane(const Geometry& g, const MarchK
                                                  const double* pow2_64, int wave, int lane) {
   RayLane rl;
   bool tail;
-  if (!ray_lane(g, wave, lane, rl, tail)) return;  // uniform per wavefront
+  if (!ray_lane<packs_tails<T>()>(g, wave, lane, waves_per_mode, rl, tail)) return;  // uniform per wavefront
   const int w = __builtin_amdgcn_readfirstlane(rl.w);
   const int r = w * 64 + rl.rl;
   const ModeC mc = load_mode(modes, rl.j);
@@ -650,7 +670,8 @@ __device__ __forceinline__ void march_gauss_lane(const Geometry& g, const MarchK
   march_ray<T>(med, mc, g, mk, rl.active, (size_t)rl.j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec,
                st, c);
   if (tail) tail_counts(wcount, waves_per_mode, rl, lane, g.R & 63, st, c);
-  else wave_counts(wcount, (size_t)__builtin_amdgcn_readfirstlane(rl.j) * waves_per_mode + w, lane, true, st, c, g.S);
+  else wave_counts(wcount, (size_t)__builtin_amdgcn_readfirstlane(rl.j) * waves_per_mode + w, lane, rl.active, st, c,
+                   g.S);
 }
 
 template <typename T>
@@ -725,7 +746,7 @@ __device__ __forceinline__ void march_table_lane(const Geometry& g, const MarchK
                                                  int* __restrict__ wcount, int waves_per_mode, int wave, int lane) {
   RayLane rl;
   bool tail;
-  if (!ray_lane(g, wave, lane, rl, tail)) return;  // uniform per wavefront
+  if (!ray_lane<true>(g, wave, lane, waves_per_mode, rl, tail)) return;  // uniform per wavefront
   const int j = rl.j, w = __builtin_amdgcn_readfirstlane(rl.w);
   const int r = w * 64 + rl.rl;
   const ModeC mc = load_mode(modes, j);
@@ -1008,7 +1029,7 @@ static hipError_t launch_march_rays(const swkb_plan_s& pl, int q, hipStream_t st
   const int wpm = waves_per_mode(g);
   const long long waves = (long long)wpm * g.M;
   const dim3 grid((unsigned)((waves + 3) / 4));
-  // the Gaussian-sum marches share tail wavefronts between modes
+  // the FP32 Gaussian-sum marches share tail wavefronts between modes
   const dim3 pgrid((unsigned)((packed_march_waves(g) + 3) / 4));
   const double x_q = pl.p.x0 + q * pl.p.dx;
   int* wcount = pl.wcount;
@@ -1030,7 +1051,7 @@ static hipError_t launch_march_rays(const swkb_plan_s& pl, int q, hipStream_t st
       GaussTabs<double> t{reinterpret_cast<const T2<double>*>(pl.gstage) + off * nst,
                           reinterpret_cast<const T2<double>*>(pl.gterm) + off,
                           static_cast<const double*>(pl.gczl) + off * wpm, nl};
-      hipLaunchKernelGGL(march_gauss_kernel<double>, pgrid, dim3(256), 0, st, g, mk, t, modes_of(pl), pl.rec,
+      hipLaunchKernelGGL(march_gauss_kernel<double>, grid, dim3(256), 0, st, g, mk, t, modes_of(pl), pl.rec,
                          wcount, wpm);
     } else if (pl.mtab.tab) {
       GaussTabs<float> t{reinterpret_cast<const T2<float>*>(pl.gstage) + off * nst,
