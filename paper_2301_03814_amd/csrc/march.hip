@@ -593,7 +593,7 @@ __device__ inline bool ray_lane(const Geometry& g, int wave, int lane, int wpm, 
   return true;
 }
 
-// Packed layout for the FP32 marches only.
+// Packed layout for the FP32 Gaussian-sum march without the table.
 template <typename T>
 constexpr bool packs_tails() { return !std::is_same<T, double>::value; }
 
@@ -740,13 +740,13 @@ __global__ void __launch_bounds__(kTabNodes) medium_table_kernel(const double* _
 }
 
 // Mixed-path Gaussian-sum march through the screen's medium table.
-template <bool kHold>
+template <bool kHold, bool kPack>
 __device__ __forceinline__ void march_table_lane(const Geometry& g, const MarchK& mk, const GaussTabs<float>& tabs,
                                                  const MedTab& mt, const DevModes& modes, const DevRecords& rec,
                                                  int* __restrict__ wcount, int waves_per_mode, int wave, int lane) {
   RayLane rl;
   bool tail;
-  if (!ray_lane<true>(g, wave, lane, waves_per_mode, rl, tail)) return;  // uniform per wavefront
+  if (!ray_lane<kPack>(g, wave, lane, waves_per_mode, rl, tail)) return;  // uniform per wavefront
   const int j = rl.j, w = __builtin_amdgcn_readfirstlane(rl.w);
   const int r = w * 64 + rl.rl;
   const ModeC mc = load_mode(modes, j);
@@ -772,16 +772,17 @@ __device__ __forceinline__ void march_table_lane(const Geometry& g, const MarchK
   march_ray<float>(med, mc, g, mk, rl.active, (size_t)j * g.R + r, g.z_a + (double)(r * g.rho - g.E) * g.h, rec,
                    st, c);
   if (tail) tail_counts(wcount, waves_per_mode, rl, lane, g.R & 63, st, c);
-  else wave_counts(wcount, (size_t)__builtin_amdgcn_readfirstlane(j) * waves_per_mode + w, lane, true, st, c, g.S);
+  else wave_counts(wcount, (size_t)__builtin_amdgcn_readfirstlane(j) * waves_per_mode + w, lane, kPack || rl.active,
+                   st, c, g.S);
 }
 
-template <bool kHold>
+template <bool kHold, bool kPack>
 __device__ __forceinline__ void march_table_body(const Geometry& g, const MarchK& mk, const GaussTabs<float>& tabs,
                                         const MedTab& mt, const DevModes& modes, const DevRecords& rec,
                                         int* __restrict__ wcount, int waves_per_mode) {
   const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int lane = threadIdx.x & 63;
-  march_table_lane<kHold>(g, mk, tabs, mt, modes, rec, wcount, waves_per_mode, wave, lane);
+  march_table_lane<kHold, kPack>(g, mk, tabs, mt, modes, rec, wcount, waves_per_mode, wave, lane);
 }
 
 // Two launch shapes of the same march.  Beside the one-field FP32 sum the
@@ -794,7 +795,9 @@ __device__ __forceinline__ void march_table_body(const Geometry& g, const MarchK
 // kernel, 4 wavefronts per SIMD) the march crowds that sum out of the CUs it
 // shares when it asks for more wavefronts or holds more registers, so there
 // the compiler's own choice runs without the held entry: 4 fields, 80.2 ->
-// 71.6 ms per 400 screens (held entry: 73.3 ms).
+// 71.6 ms per 400 screens (held entry: 73.3 ms).  That shape also keeps one
+// mode per wavefront: the packed tails took it from 62 to 67 VGPRs, 7
+// wavefronts per SIMD instead of 8 (4 fields: 67.9 -> 74.5 ms).
 //
 // Both take their arguments as one structure and read each field where it
 // is used, through the argument segment: the compiler loads by-value kernel
@@ -818,12 +821,12 @@ __device__ inline const TableMarchArgs& table_args() {
 
 __global__ void __launch_bounds__(256, 7) march_table_kernel(TableMarchArgs) {
   const TableMarchArgs& a = table_args();
-  march_table_body<true>(a.g, a.mk, a.tabs, a.mt, a.modes, a.rec, a.wcount, a.waves_per_mode);
+  march_table_body<true, true>(a.g, a.mk, a.tabs, a.mt, a.modes, a.rec, a.wcount, a.waves_per_mode);
 }
 
 __global__ void __launch_bounds__(256) march_table_batch_kernel(TableMarchArgs) {
   const TableMarchArgs& a = table_args();
-  march_table_body<false>(a.g, a.mk, a.tabs, a.mt, a.modes, a.rec, a.wcount, a.waves_per_mode);
+  march_table_body<false, false>(a.g, a.mk, a.tabs, a.mt, a.modes, a.rec, a.wcount, a.waves_per_mode);
 }
 
 // One workgroup per mode: running maximum of live arrival heights (search
@@ -1060,7 +1063,7 @@ static hipError_t launch_march_rays(const swkb_plan_s& pl, int q, hipStream_t st
       // reads the table launch_medium_table built for screen q
       const TableMarchArgs a{g, mk, t, pl.mtab, modes_of(pl), pl.rec, wcount, wpm};
       if (pl.sum_fields > 1)
-        hipLaunchKernelGGL(march_table_batch_kernel, pgrid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(march_table_batch_kernel, grid, dim3(256), 0, st, a);
       else
         hipLaunchKernelGGL(march_table_kernel, pgrid, dim3(256), 0, st, a);
     } else {
