@@ -172,6 +172,47 @@ def test_stage_rays_match_oracle(torch_dev, swkb, name):
     plan.close()
 
 
+# (launch extension, ray stride) -> rays per mode R on the 1024-point random
+# medium: the FP32 Gaussian-sum march fills a mode's first R // 64 wavefronts
+# and packs the last R mod 64 rays of several modes into shared wavefronts
+# (64 // (R mod 64) modes each).  R = 192: no tail; 33: tails only, one mode
+# per wavefront; 100: one full wavefront and a 36-ray tail; 70: ten 6-ray
+# tails per wavefront, the last wavefront part-filled (256 modes); 129: one
+# ray of each of 64 modes per wavefront.
+RAY_LAYOUTS = {192: (250, 8), 33: (0, 32), 100: (280, 16), 70: (40, 16), 129: (0, 8)}
+
+
+@pytest.mark.parametrize("R", sorted(RAY_LAYOUTS))
+def test_mixed_march_ray_layouts(torch_dev, swkb, R):
+    import oracle
+    torch, dev = torch_dev
+    ext, stride = RAY_LAYOUTS[R]
+    cfg = W.with_overrides(small_random(n_screens=3), launch_ext_cells=ext, ray_stride=stride)
+    say(f"[layout] R={R} ext={ext} stride={stride}")
+    plan = swkb.Plan(cfg, precision=swkb.MIXED, device=dev)
+    assert plan.num_rays == R
+    u0 = W.incident_field(cfg)
+    # one screen: the diagnostics' ray counts (per-wavefront sums, per-mode
+    # totals) equal the flags of that screen's rays
+    plan.propagate(torch.from_numpy(u0).to(dev), 0, 1)
+    d = plan.diagnostics()
+    flag = plan.stage_rays(0)["flag"].cpu().numpy()
+    assert d["caustic_rays"] == int((flag == 3).sum())
+    assert d["dead_rays"] == int(((flag != 0) & (flag != 3)).sum())
+    # the whole run against the oracle
+    oracle.build()
+    ref, cnt = oracle.run(cfg, u0)
+    got = plan.propagate(torch.from_numpy(u0).to(dev), 0, cfg["n_screens"]).cpu().numpy()
+    err = rel(got, ref)
+    peak = np.abs(ref).max(axis=1)
+    mx = float((np.abs(got - ref).max(axis=1) / np.maximum(peak, 1e-3 * peak.max())).max())
+    say(f"[layout] R={R} rel_l2={err:.3e} per-screen max-norm={mx:.3e} caustic={d['caustic_rays']} "
+        f"dead={d['dead_rays']}")
+    assert err <= MIXED_REGRESSION
+    assert mx <= MIXED_TOL
+    plan.close()
+
+
 def test_resume_and_determinism(torch_dev, swkb):
     """Resuming from screen q equals an uninterrupted run bit for bit, and
     two runs are bitwise identical (fixed-order reductions, no atomics on
